@@ -1,0 +1,324 @@
+"""FP64 oracle for the exact Gaussian ray renderer (3DGEER, arXiv 2505.24053).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library never loads it; it shares no code with ``paper_2505_24053_amd``
+except the seeded input generators of ``paper_2505_24053_amd.synth``.
+
+The heavy lifting is in ``geer_oracle.c`` (plain C, FP64, brute force over
+every ray-Gaussian pair, OpenMP over rays).  This module compiles it with gcc
+on first use, marshals arguments, and adds the pieces that are easiest to
+state with library primitives:
+
+* ``tile_list``: the (tile, depth key, index) ordering of the association
+  list, done with ``numpy.lexsort`` (the paper's global sort by
+  FrustumID + depth, Alg. 1);
+* ``valid_mask``: BEAP rays that land on the native sensor through the
+  pinhole or Kannala-Brandt projection (App. E).
+
+Every function here follows the passage cited in its docstring.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "geer_oracle.c")
+LIB = os.path.join(HERE, "libgeer_oracle.so")
+
+MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2}
+DEFAULT_OPTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, lambda_mode=0, lambda_fixed=3.0)
+
+
+class View(C.Structure):
+    _fields_ = [("model", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("pad_", C.c_int32),
+                ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("k", C.c_double * 4), ("fov_x", C.c_double), ("fov_y", C.c_double),
+                ("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
+                ("lambda_fixed", C.c_double), ("lambda_mode", C.c_int32), ("pad_", C.c_int32)]
+
+
+class SceneC(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("pad_", C.c_int32),
+                ("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+ASSOC_DT = np.dtype([("hx0", np.int32), ("hx1", np.int32), ("hy0", np.int32), ("hy1", np.int32),
+                     ("count", np.uint32), ("key", np.uint32), ("culled", np.int32), ("pad_", np.int32)])
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (no fused multiply-add, no fast math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=gnu11",
+                               "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = C.CDLL(LIB)
+            P = C.POINTER
+            L.orc_assoc_fp32.argtypes = [P(SceneC), P(View), P(Opts), C.c_void_p]
+            L.orc_render.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+            L.orc_render_backward.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.c_int]
+            L.orc_sh_basis.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+            L.orc_pair.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p]
+            L.orc_edges.argtypes = [P(View), C.c_void_p, C.c_void_p, P(C.c_int), P(C.c_int)]
+            L.orc_lambda2_hat.argtypes = [C.c_float, C.c_float, C.c_int, C.c_double]
+            L.orc_lambda2_hat.restype = C.c_float
+            L.orc_contrib_mask.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p]
+            _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def make_view(cam: dict) -> View:
+    v = View()
+    v.model = MODELS[cam["model"]]
+    v.width, v.height = int(cam["width"]), int(cam["height"])
+    v.fx, v.fy, v.cx, v.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    for i in range(4):
+        v.k[i] = float(cam["k"][i])
+    v.fov_x, v.fov_y = float(cam["fov_x"]), float(cam["fov_y"])
+    R = np.asarray(cam["R"], dtype=np.float64).reshape(9)
+    t = np.asarray(cam["t"], dtype=np.float64).reshape(3)
+    for i in range(9):
+        v.R[i] = R[i]
+    for i in range(3):
+        v.t[i] = t[i]
+    return v
+
+
+def make_opts(**kw) -> Opts:
+    d = dict(DEFAULT_OPTS)
+    d.update(kw)
+    o = Opts()
+    o.alpha_min, o.alpha_max, o.t_min = float(d["alpha_min"]), float(d["alpha_max"]), float(d["t_min"])
+    o.lambda_fixed, o.lambda_mode = float(d["lambda_fixed"]), int(d["lambda_mode"])
+    return o
+
+
+class _SceneRef:
+    """Keeps contiguous FP64 copies (exact for FP32 inputs) alive while C
+    holds their pointers."""
+
+    def __init__(self, scene):
+        self.arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in scene.arrays()]
+        s = SceneC()
+        s.n = scene.n
+        s.sh_degree = scene.sh_degree
+        s.mean, s.scale, s.quat, s.opacity, s.sh = (a.ctypes.data for a in self.arrs)
+        self.c = s
+
+
+def assoc_fp32(scene, cam, **opts):
+    """FP32 association reference (particle bounding frustum against the
+    camera sub-frusta, Sec. 3.2 / App. D): per Gaussian the half-tile
+    rectangle, tile count, depth key and 3-sigma cull flag."""
+    L = lib()
+    ref = _SceneRef(scene)
+    out = np.zeros(scene.n, dtype=ASSOC_DT)
+    L.orc_assoc_fp32(C.byref(ref.c), C.byref(make_view(cam)), C.byref(make_opts(**opts)), _ptr(out))
+    return out
+
+
+def tile_grid(cam):
+    tw = (int(cam["width"]) + 15) // 16
+    th = (int(cam["height"]) + 15) // 16
+    return tw, th
+
+
+def tile_list(assoc, cam):
+    """Expand each visible Gaussian to every 16x16 tile of its rectangle and
+    order the entries by (tile id, depth key, Gaussian index) -- the
+    DuplicateWithKeys / SortByKeys / IdentifyFrustumRanges steps of Alg. 1.
+    Returns (tile ids, Gaussian ids, ranges[ntiles + 1])."""
+    tw, th = tile_grid(cam)
+    vis = np.nonzero(assoc["count"] > 0)[0]
+    tiles, gids, keys = [], [], []
+    for g in vis:
+        a = assoc[g]
+        tx0, tx1, ty0, ty1 = a["hx0"] // 2, a["hx1"] // 2, a["hy0"] // 2, a["hy1"] // 2
+        yy, xx = np.mgrid[ty0:ty1 + 1, tx0:tx1 + 1]
+        t = (yy * tw + xx).ravel()
+        tiles.append(t)
+        gids.append(np.full(t.size, g, dtype=np.int64))
+        keys.append(np.full(t.size, a["key"], dtype=np.uint64))
+    if not tiles:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(tw * th + 1, np.int64)
+    tiles = np.concatenate(tiles).astype(np.int64)
+    gids = np.concatenate(gids)
+    keys = np.concatenate(keys)
+    order = np.lexsort((gids, keys, tiles))
+    tiles, gids = tiles[order], gids[order]
+    ranges = np.searchsorted(tiles, np.arange(tw * th + 1), side="left")
+    return tiles, gids, ranges
+
+
+def render(scene, cam, pix=None, nthreads: int = 0, **opts):
+    """Brute-force FP64 render of BEAP pixels (all when ``pix`` is None).
+    Returns dict(rgb [P,3], depth [P], trans [P], ncomp [P], amb [P], pix)."""
+    L = lib()
+    w, h = int(cam["width"]), int(cam["height"])
+    if pix is None:
+        pix = np.arange(w * h, dtype=np.int64)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    n = pix.size
+    rgb = np.zeros((n, 3))
+    depth = np.zeros(n)
+    trans = np.zeros(n)
+    ncomp = np.zeros(n, np.int32)
+    amb = np.zeros(n, np.int32)
+    ref = _SceneRef(scene)
+    rc = L.orc_render(C.byref(ref.c), C.byref(make_view(cam)), C.byref(make_opts(**opts)), n, _ptr(pix),
+                      _ptr(rgb), _ptr(depth), _ptr(trans), _ptr(ncomp), _ptr(amb), int(nthreads))
+    if rc != 0:
+        raise MemoryError("oracle render failed")
+    return dict(rgb=rgb, depth=depth, trans=trans, ncomp=ncomp, amb=amb.astype(bool), pix=pix)
+
+
+def render_backward(scene, cam, pix, dl_drgb, nthreads: int = 0, **opts):
+    """FP64 gradients of L (given dL/dRGB [P,3] on ``pix``) with respect to
+    mean [3,N], scale [3,N], raw quaternion [4,N], opacity [N], SH [K*3,N]
+    (App. C, with the corrected cross-product signs)."""
+    L = lib()
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    g = np.ascontiguousarray(dl_drgb, dtype=np.float64).reshape(-1, 3)
+    assert g.shape[0] == pix.size
+    n = scene.n
+    K = (scene.sh_degree + 1) ** 2
+    out = dict(mean=np.zeros((3, n)), scale=np.zeros((3, n)), quat=np.zeros((4, n)), opacity=np.zeros(n),
+               sh=np.zeros((K * 3, n)))
+    ref = _SceneRef(scene)
+    rc = L.orc_render_backward(C.byref(ref.c), C.byref(make_view(cam)), C.byref(make_opts(**opts)), pix.size,
+                               _ptr(pix), _ptr(g), _ptr(out["mean"]), _ptr(out["scale"]), _ptr(out["quat"]),
+                               _ptr(out["opacity"]), _ptr(out["sh"]), int(nthreads))
+    if rc != 0:
+        raise MemoryError("oracle backward failed")
+    return out
+
+
+def contrib_mask(scene, cam, pix=None, **opts):
+    """Brute-force [P, N] boolean mask of contributing (pixel, Gaussian) pairs
+    under the contribution rule, without early termination (tiny inputs)."""
+    w, h = int(cam["width"]), int(cam["height"])
+    if pix is None:
+        pix = np.arange(w * h, dtype=np.int64)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    mask = np.zeros((pix.size, scene.n), np.uint8)
+    ref = _SceneRef(scene)
+    lib().orc_contrib_mask(C.byref(ref.c), C.byref(make_view(cam)), C.byref(make_opts(**opts)), pix.size,
+                           _ptr(pix), _ptr(mask))
+    return mask.astype(bool)
+
+
+def sh_basis(deg: int, dirs):
+    """Real SH basis (Condon-Shortley phase) and its R^3 gradient at ``dirs``."""
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    K = (deg + 1) ** 2
+    Y = np.zeros((d.shape[0], K))
+    dY = np.zeros((d.shape[0], K, 3))
+    lib().orc_sh_basis(deg, d.shape[0], _ptr(d), _ptr(Y), _ptr(dY))
+    return Y, dY
+
+
+def pair(scene, cam, g: int, d, **opts):
+    """(kappa, t*, sigma exp(-kappa/2), lambda_i^2) of one pair, FP64."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros(4)
+    ref = _SceneRef(scene)
+    lib().orc_pair(C.byref(ref.c), C.byref(make_view(cam)), C.byref(make_opts(**opts)), int(g), _ptr(d),
+                   _ptr(out))
+    return out
+
+
+def edges(cam):
+    """Half-tile edge tables: mirrored tan(theta/2) columns, tan(phi) rows."""
+    w, h = int(cam["width"]), int(cam["height"])
+    ex = np.zeros(w // 8 + 2, np.float32)
+    ey = np.zeros(h // 8 + 2, np.float32)
+    nx, ny = C.c_int(), C.c_int()
+    lib().orc_edges(C.byref(make_view(cam)), _ptr(ex), _ptr(ey), C.byref(nx), C.byref(ny))
+    return ex[:nx.value + 1], ey[:ny.value + 1]
+
+
+def lambda2_hat(sigma: float, alpha_min: float = 1 / 255, mode: int = 0, lam_fixed: float = 3.0) -> float:
+    return float(lib().orc_lambda2_hat(float(sigma), float(alpha_min), int(mode), float(lam_fixed)))
+
+
+def pixel_dirs_camera(cam, pix):
+    """FP64 camera-space unit directions of BEAP pixel centres (App. E)."""
+    w, h = int(cam["width"]), int(cam["height"])
+    pix = np.asarray(pix, dtype=np.int64)
+    px, py = pix % w, pix // w
+    th = -cam["fov_x"] / 2 + (px + 0.5) * cam["fov_x"] / w
+    ph = -cam["fov_y"] / 2 + (py + 0.5) * cam["fov_y"] / h
+    d = np.stack([np.sin(th) * np.cos(ph), np.cos(th) * np.sin(ph), np.cos(th) * np.cos(ph)], -1)
+    return d / np.linalg.norm(d, axis=-1, keepdims=True)
+
+
+def pixel_dirs_world(cam, pix):
+    R = np.asarray(cam["R"], dtype=np.float64).reshape(3, 3)
+    return pixel_dirs_camera(cam, pix) @ R
+
+
+def valid_mask(cam):
+    """BEAP rays whose native projection lands on the sensor (App. E).  The
+    incidence angle is atan2(sqrt(x^2+y^2), z) so rays beyond 90 degrees are
+    handled; pinhole rays need z > 0."""
+    w, h = int(cam["width"]), int(cam["height"])
+    d = pixel_dirs_camera(cam, np.arange(w * h)).reshape(h, w, 3)
+    x, y, z = d[..., 0], d[..., 1], d[..., 2]
+    rxy = np.hypot(x, y)
+    if cam["model"] == "pinhole":
+        with np.errstate(divide="ignore", invalid="ignore"):
+            u = cam["fx"] * x / z + cam["cx"]
+            v = cam["fy"] * y / z + cam["cy"]
+        ok = z > 0
+    else:
+        inc = np.arctan2(rxy, z)
+        k = cam["k"]
+        td = inc * (1 + k[0] * inc**2 + k[1] * inc**4 + k[2] * inc**6 + k[3] * inc**8)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            cx_ = np.where(rxy > 0, x / rxy, 0.0)
+            cy_ = np.where(rxy > 0, y / rxy, 0.0)
+        u = cam["fx"] * td * cx_ + cam["cx"]
+        v = cam["fy"] * td * cy_ + cam["cy"]
+        ok = np.ones_like(z, dtype=bool)
+    return ok & (u >= 0) & (u < w) & (v >= 0) & (v < h)
+
+
+def opts_dict(**kw):
+    d = dict(DEFAULT_OPTS)
+    d.update(kw)
+    return d
+
+
+__all__ = ["build", "assoc_fp32", "tile_list", "render", "render_backward", "sh_basis", "pair", "edges",
+           "lambda2_hat", "contrib_mask", "valid_mask", "pixel_dirs_camera", "pixel_dirs_world", "DEFAULT_OPTS"]

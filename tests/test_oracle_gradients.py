@@ -1,0 +1,183 @@
+"""Pins of the oracle's analytic gradients (App. C, two-stage chain).
+
+* central finite differences of the oracle's own FP64 forward (the scene
+  arrays are FP64 so perturbations below FP32 resolution are possible);
+* an independent torch.float64 autograd implementation of the same defined
+  quantity (vectorised brute force written here from the equations, with
+  the rotation built from the quaternion in torch and the 3DGS real-SH
+  polynomials);
+* the cross-product sign reading: with m_u = o_u x d_u, central differences
+  agree with dkappa/do_u = d_u x g_m and dkappa/dd_u = -(2 kappa/|d_u|^2) d_u
+  + g_m x o_u, and disagree with the printed orientation of both cross terms.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2505_24053_amd import synth
+
+OPTS = dict(oracle.DEFAULT_OPTS)
+
+
+def slice_problem(seed=0, n=200, res=32, model="kb"):
+    scene = synth.scene_slice(n, seed)
+    if model == "kb":
+        cam = synth.camera_kb(res, res, 190.0, seed=seed)
+    else:
+        cam = synth.camera_pinhole(res, res, 70.0)
+    rng = np.random.default_rng(seed + 99)
+    pix = np.arange(res * res)
+    G = rng.normal(size=(pix.size, 3))
+    return scene, cam, pix, G
+
+
+def as64(scene):
+    return synth.Scene(*(a.astype(np.float64) for a in scene.arrays()), scene.sh_degree)
+
+
+def loss(scene, cam, pix, G):
+    r = oracle.render(scene, cam, pix=pix)
+    return float(np.sum(r["rgb"] * G))
+
+
+def test_finite_differences(oracle_lib):
+    scene, cam, pix, G = slice_problem()
+    s64 = as64(scene)
+    grads = oracle.render_backward(s64, cam, pix, G)
+    rng = np.random.default_rng(1)
+    live = np.nonzero(np.abs(grads["opacity"]) > 1e-6)[0]
+    assert live.size > 20
+    checks = 0
+    for group, rows, h in (("mean", 3, 1e-6), ("scale", 3, 1e-8), ("quat", 4, 1e-6), ("opacity", 1, 1e-6),
+                           ("sh", 48, 1e-5)):
+        for _ in range(8):
+            g = int(rng.choice(live))
+            r = int(rng.integers(rows))
+            arr = getattr(s64, group)
+            idx = (r, g) if arr.ndim == 2 else (g,)
+            x0 = arr[idx]
+            arr[idx] = x0 + h
+            lp = loss(s64, cam, pix, G)
+            arr[idx] = x0 - h
+            lm = loss(s64, cam, pix, G)
+            arr[idx] = x0
+            fd = (lp - lm) / (2 * h)
+            an = grads[group][idx]
+            scale_ref = max(abs(an), 1e-3 * np.abs(grads[group]).max())
+            assert abs(fd - an) <= 2e-4 * scale_ref + 1e-7, (group, idx, fd, an)
+            checks += 1
+    assert checks == 40
+
+
+# ----------------------------------------------------------- torch autograd --
+
+SH = [0.28209479177387814, 0.4886025119029199, 1.0925484305920792, -1.0925484305920792,
+      0.31539156525252005, -1.0925484305920792, 0.5462742152960396, -0.5900435899266435,
+      2.890611442640554, -0.4570457994644658, 0.3731763325901154, -0.4570457994644658,
+      1.445305721320277, -0.5900435899266435]
+
+
+def sh_eval(deg, v, coef):
+    """3DGS real SH polynomials; v [N,3] unit, coef [K,3,N] -> [N,3]."""
+    x, y, z = v[:, 0], v[:, 1], v[:, 2]
+    basis = [torch.full_like(x, SH[0])]
+    if deg > 0:
+        basis += [-SH[1] * y, SH[1] * z, -SH[1] * x]
+    if deg > 1:
+        xx, yy, zz = x * x, y * y, z * z
+        basis += [SH[2] * x * y, SH[3] * y * z, SH[4] * (2 * zz - xx - yy), SH[5] * x * z, SH[6] * (xx - yy)]
+    if deg > 2:
+        basis += [SH[7] * y * (3 * xx - yy), SH[8] * x * y * z, SH[9] * y * (4 * zz - xx - yy),
+                  SH[10] * z * (2 * zz - 3 * xx - 3 * yy), SH[11] * x * (4 * zz - xx - yy),
+                  SH[12] * z * (xx - yy), SH[13] * x * (xx - 3 * yy)]
+    B = torch.stack(basis, 0)  # [K, N]
+    return torch.einsum("kn,kcn->nc", B, coef)
+
+
+def torch_render(params, scene, cam, pix, G):
+    mean, scale, quat, opac, sh = params
+    n = mean.shape[1]
+    K = (scene.sh_degree + 1) ** 2
+    q = quat / quat.norm(dim=0, keepdim=True)
+    r, i, j, k = q
+    R = torch.stack([
+        torch.stack([1 - 2 * (j * j + k * k), 2 * (i * j - r * k), 2 * (i * k + r * j)], -1),
+        torch.stack([2 * (i * j + r * k), 1 - 2 * (i * i + k * k), 2 * (j * k - r * i)], -1),
+        torch.stack([2 * (i * k - r * j), 2 * (j * k + r * i), 1 - 2 * (i * i + j * j)], -1)], -2)  # [N,3,3]
+    W = R.transpose(1, 2) / scale.T[:, :, None]
+    Rc = torch.tensor(np.asarray(cam["R"]), dtype=torch.float64)
+    tc = torch.tensor(np.asarray(cam["t"]), dtype=torch.float64)
+    o = -(Rc.T @ tc)
+    ou = torch.einsum("nab,nb->na", W, o[None, :] - mean.T)
+    d = torch.tensor(oracle.pixel_dirs_world(cam, pix))
+    u = torch.einsum("nab,pb->pna", W, d)
+    m = torch.cross(ou[None].expand_as(u), u, dim=-1)
+    uu = (u * u).sum(-1)
+    kappa = (m * m).sum(-1) / uu
+    v = mean.T - o[None, :]
+    v = v / v.norm(dim=1, keepdim=True)
+    col = torch.clamp(sh_eval(scene.sh_degree, v, sh.reshape(K, 3, n)) + 0.5, min=0.0)
+    alpha = torch.clamp(opac[None, :] * torch.exp(-0.5 * kappa), max=OPTS["alpha_max"])
+    mask = oracle.contrib_mask(scene, cam, pix=pix)
+    key = oracle.assoc_fp32(scene, cam)["key"].astype(np.int64)
+    total = 0.0
+    for p in range(pix.size):
+        idx = np.nonzero(mask[p])[0]
+        idx = idx[np.lexsort((idx, key[idx]))]
+        a = alpha[p, idx]
+        T = 1.0
+        keep = []
+        Td = 1.0
+        for t in range(idx.size):
+            if Td * (1 - float(a[t].detach())) < OPTS["t_min"]:
+                break
+            Td *= 1 - float(a[t].detach())
+            keep.append(t)
+        if not keep:
+            continue
+        a = a[keep]
+        T = torch.cat([torch.ones(1, dtype=torch.float64), torch.cumprod(1 - a, 0)[:-1]])
+        C = ((a * T)[:, None] * col[idx[keep]]).sum(0)
+        total = total + (C * torch.tensor(G[p])).sum()
+    return total
+
+
+def test_independent_torch_autograd(oracle_lib):
+    scene, cam, pix, G = slice_problem(seed=2, n=120, res=24)
+    s64 = as64(scene)
+    grads = oracle.render_backward(s64, cam, pix, G)
+    params = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in s64.arrays()]
+    L = torch_render(params, s64, cam, pix, G)
+    L.backward()
+    assert float(L) == pytest.approx(loss(s64, cam, pix, G), rel=1e-12)
+    for name, p in zip(("mean", "scale", "quat", "opacity", "sh"), params):
+        ref = p.grad.numpy()
+        got = grads[name]
+        err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+        assert err < 1e-9, (name, err)
+
+
+def test_cross_product_sign_reading():
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        o = rng.normal(size=3) * 3
+        u = rng.normal(size=3)
+
+        def kap(o_, u_):
+            m_ = np.cross(o_, u_)
+            return m_ @ m_ / (u_ @ u_)
+
+        h = 1e-6
+        fd_o = np.array([(kap(o + h * e, u) - kap(o - h * e, u)) / (2 * h) for e in np.eye(3)])
+        fd_u = np.array([(kap(o, u + h * e) - kap(o, u - h * e)) / (2 * h) for e in np.eye(3)])
+        m = np.cross(o, u)
+        gm = 2 * m / (u @ u)
+        k = kap(o, u)
+        np.testing.assert_allclose(np.cross(u, gm), fd_o, rtol=1e-6, atol=1e-8)
+        np.testing.assert_allclose(-(2 * k / (u @ u)) * u + np.cross(gm, o), fd_u, rtol=1e-6, atol=1e-8)
+        # the printed orientation fails unless the cross terms vanish
+        printed_o = np.cross(gm, u)
+        assert np.linalg.norm(printed_o - fd_o) > 1e-3 * np.linalg.norm(fd_o)
