@@ -1,0 +1,192 @@
+/*
+ * geer.h -- C ABI of the MI355X exact Gaussian ray renderer.
+ *
+ * The library implements the rendering hot path of 3DGEER (arXiv 2505.24053):
+ *   (a) per-Gaussian particle bounding frustum (PBF) as a rectangle of BEAP
+ *       tiles (Sec. 3.2 and App. D: Eq. planeTrans, ellipsoid_tangent,
+ *       solve_tan, pbf-cov3d, tan_sol, and the xi = 1 mirror of Eq. aabb),
+ *   (b) tile/Gaussian key generation and a per-tile depth sort
+ *       (Alg. 1: DuplicateWithKeys, SortByKeys, IdentifyFrustumRanges),
+ *   (c) per-pixel front-to-back compositing (Eq. color) with the closed-form
+ *       ray opacity sigma exp(-kappa/2), kappa = |o_u x d_u|^2 / |d_u|^2
+ *       (Eq. transmit / trans:cano / mahdist_comp),
+ * over BEAP rays (Sec. 3.3, App. E), and its gradient (App. C).
+ *
+ * Conventions shared by every call:
+ *   - All array pointers named "device" are HIP device pointers owned by the
+ *     caller; the library never frees them and never keeps them after the
+ *     call returns (a frame keeps its own copies of what the backward needs).
+ *   - Scene arrays are FP32 structure-of-arrays, row-major, N = scene->n:
+ *       mean [3][N], scale [3][N] (linear standard deviations),
+ *       quat [4][N] as (r, i, j, k), any non-zero norm (normalised inside),
+ *       opacity [N] in (0, 1], sh [(deg+1)^2 * 3][N] with row k*3 + channel.
+ *   - Image outputs are planar FP32. For V views of sizes W_v x H_v they are
+ *     concatenated view after view: rgb holds 3*W_v*H_v floats per view
+ *     ([3][H][W]), depth and trans hold W_v*H_v floats per view ([H][W]).
+ *   - Cameras: BEAP grid of width x height pixels spanning fov_x x fov_y
+ *     radians; pixel (i, j) looks along theta_i = -fov_x/2 + (i+1/2) fov_x/w,
+ *     phi_j = -fov_y/2 + (j+1/2) fov_y/h, direction (sin t cos p, cos t sin p,
+ *     cos t cos p) normalised, in OpenCV camera axes; pose x_cam = R x + t.
+ *     Requirements: 0 < fov_x <= 2 pi, 0 < fov_y <= pi (phi is the principal
+ *     angle atan(y / z), so its grid spans at most the open half-turn).
+ *   - Every call returns a geer_status and never aborts. Argument errors are
+ *     detected on the host before any launch. Work is enqueued on `stream`
+ *     (a hipStream_t, 0 for the default stream) unless a call says it
+ *     synchronises.
+ */
+#ifndef GEER_H
+#define GEER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GEER_OK = 0,
+  GEER_ERR_INVALID_ARG = 1, /* bad pointer, size, camera or option */
+  GEER_ERR_OOM = 2,         /* device or host allocation failed */
+  GEER_ERR_CAPACITY = 3,    /* association list larger than 2^32 - 1 entries */
+  GEER_ERR_HIP = 4,         /* a HIP runtime call failed; see geer_last_error */
+  GEER_ERR_UNSUPPORTED = 5  /* feature not available in this build */
+} geer_status;
+
+typedef enum { GEER_CAM_PINHOLE = 0, GEER_CAM_EQUIDISTANT = 1, GEER_CAM_KB = 2 } geer_cam_model;
+
+/* One view: camera model, native intrinsics (used for the valid-ray mask of
+ * the loss), BEAP grid, pose.  The camera models are those of App. E
+ * (pinhole; Kannala-Brandt with k1..k4; equidistant = KB with k = 0). */
+typedef struct {
+  int32_t model;         /* geer_cam_model */
+  int32_t width, height; /* BEAP grid in pixels, 1 .. 65536 */
+  int32_t reserved;      /* must be 0 */
+  double fx, fy, cx, cy; /* native pinhole / fisheye intrinsics */
+  double k[4];           /* KB distortion k1..k4 (0 for pinhole, equidistant) */
+  double fov_x, fov_y;   /* BEAP angular extents in radians */
+  double R[9];           /* world-to-camera rotation, row-major */
+  double t[3];           /* world-to-camera translation */
+} geer_view;
+
+/* A scene resident in device memory (not copied; layout in the header). */
+typedef struct {
+  int64_t n;         /* number of Gaussians, 0 .. 2^28 */
+  int32_t sh_degree; /* 0 .. 3 */
+  int32_t reserved;  /* must be 0 */
+  const float* mean;    /* device [3][n] */
+  const float* scale;   /* device [3][n], > 0 */
+  const float* quat;    /* device [4][n] */
+  const float* opacity; /* device [n] */
+  const float* sh;      /* device [(deg+1)^2*3][n] */
+} geer_scene;
+
+/* Rendering options.  A pair (ray, Gaussian) contributes iff the camera is
+ * outside the Gaussian's 3-sigma ellipsoid (culling, App. B), the closest
+ * approach lies in front of the camera, and
+ *   lambda_mode 0 (default): alpha_raw = sigma exp(-kappa/2) >= alpha_min,
+ *     i.e. kappa <= 2 ln(sigma / alpha_min); the PBF uses that lambda;
+ *   lambda_mode 1: kappa <= lambda_fixed^2 and alpha_raw >= alpha_min; the
+ *     PBF uses lambda_fixed (the paper's "typically 3").
+ * alpha = min(alpha_raw, alpha_max); compositing stops before the first
+ * Gaussian that would take the transmittance below t_min (t_min = 0: never). */
+typedef struct {
+  float alpha_min;    /* default 1/255, in (0, 1) */
+  float alpha_max;    /* default 0.99, in [alpha_min, 1) */
+  float t_min;        /* default 1e-4, in [0, 1) */
+  float lambda_fixed; /* default 3, > 0 */
+  int32_t lambda_mode;
+  int32_t reserved; /* must be 0 */
+} geer_opts;
+
+typedef struct geer_ctx geer_ctx;     /* per-device library state */
+typedef struct geer_frame geer_frame; /* forward state kept for the backward */
+
+/* Statistics of one forward, counted on the device. */
+typedef struct {
+  int64_t n_items;     /* Gaussians x views */
+  int64_t n_visible;   /* items whose PBF meets at least one tile */
+  int64_t n_entries;   /* (tile, Gaussian) pairs of the association list */
+  int64_t n_tiles;     /* 16x16 tiles over all views */
+  int64_t n_pixels;    /* rays over all views */
+  int64_t n_evaluated; /* (ray, entry) pairs evaluated by the render kernel */
+  int64_t n_composited;/* (ray, Gaussian) pairs blended */
+} geer_frame_stats;
+
+/* Association buffers a frame can export (for parity checks). */
+typedef enum {
+  GEER_BUF_RECT = 0,   /* uint32 [items][2]: hx0 | hx1 << 16, hy0 | hy1 << 16 (8-px half-tiles) */
+  GEER_BUF_COUNT = 1,  /* uint32 [items]: tiles covered, 0 = not visible */
+  GEER_BUF_KEY = 2,    /* uint32 [items]: depth key (bits of FP32 squared camera distance) */
+  GEER_BUF_LIST = 3,   /* uint32 [entries]: item id (view * n + gaussian), tile-major, depth order */
+  GEER_BUF_RANGES = 4, /* uint32 [tiles + 1]: start of each tile's run in LIST */
+  GEER_BUF_NLAST = 5   /* uint32 [pixels]: one past the last LIST index blended by each ray */
+} geer_buffer;
+
+/* Creates the library state on HIP device `device`.  *out is set on success. */
+geer_status geer_create(int32_t device, geer_ctx** out);
+/* Releases every device buffer of the context (frames must be released first). */
+void geer_destroy(geer_ctx* ctx);
+/* Last error message of the context (static storage, valid until the next call). */
+const char* geer_last_error(const geer_ctx* ctx);
+/* Fills the defaults listed with geer_opts. */
+void geer_default_opts(geer_opts* opts);
+
+/*
+ * Forward render of n_views views of one scene (Alg. 1).  All views share one
+ * association list (a global tile space), so a batch of views reads the scene
+ * once.  rgb, depth, trans: device outputs laid out as in the header; any of
+ * depth / trans may be NULL.  If `frame` is not NULL a frame is created and
+ * returned that holds what geer_render_backward needs; the caller releases it.
+ * Synchronises `stream` once (to size the association list).
+ */
+geer_status geer_render(geer_ctx* ctx, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                        const geer_opts* opts, float* rgb, float* depth, float* trans, geer_frame** frame,
+                        void* stream);
+
+/*
+ * Gradient of a scalar loss given dL/dRGB (device, same layout as rgb) with
+ * respect to mean, scale (linear), raw quaternion, opacity and SH
+ * coefficients (App. C, with m_u = o_u x d_u).  Gradient arrays are device
+ * buffers in the scene layout; accumulate = 0 overwrites them, 1 adds.
+ * The scene passed to geer_render must be unchanged.
+ */
+geer_status geer_render_backward(geer_ctx* ctx, const geer_frame* frame, const float* dl_drgb,
+                                 float* g_mean, float* g_scale, float* g_quat, float* g_opacity,
+                                 float* g_sh, int32_t accumulate, void* stream);
+
+/* Frees the frame's device state (after any pending backward has completed). */
+void geer_frame_release(geer_frame* frame);
+
+/* Device-counted statistics of the frame's forward.  Synchronises. */
+geer_status geer_frame_get_stats(const geer_frame* frame, geer_frame_stats* out);
+
+/* Size in bytes of an exportable frame buffer. */
+int64_t geer_frame_buffer_bytes(const geer_frame* frame, int32_t which);
+
+/* Copies a frame buffer to host memory `dst` of `bytes` (>= the size above).
+ * Synchronises. */
+geer_status geer_frame_export(const geer_frame* frame, int32_t which, void* dst, int64_t bytes);
+
+/*
+ * Valid-ray mask of a view (host): mask[j * width + i] = 1 iff BEAP ray (i, j)
+ * projects onto the native sensor [0, width) x [0, height) through the view's
+ * camera model (App. E, with the incidence angle atan2(|xy|, z) so that rays
+ * beyond 90 degrees are defined).  `mask` is host memory of width*height bytes.
+ */
+geer_status geer_valid_mask(const geer_view* view, uint8_t* mask);
+
+/*
+ * L1 loss over valid rays and its gradient (device):
+ *   L = sum_{valid rays, channels} |rgb - target| / (3 * n_valid),
+ *   dl_drgb = sign(rgb - target) / (3 * n_valid) on valid rays, 0 elsewhere.
+ * rgb, target, dl_drgb: [3][pixels]; mask: uint8 [pixels] (device, 1 = valid);
+ * loss: device float, written.  n_valid is counted on the device.
+ */
+geer_status geer_l1_loss(geer_ctx* ctx, int64_t pixels, const float* rgb, const float* target,
+                         const uint8_t* mask, float* dl_drgb, float* loss, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEER_H */

@@ -80,7 +80,7 @@ def lib():
             P = C.POINTER
             L.orc_assoc_fp32.argtypes = [P(SceneC), P(View), P(Opts), C.c_void_p]
             L.orc_render.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p,
-                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
             L.orc_render_backward.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p,
                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_int]
@@ -161,20 +161,18 @@ def tile_list(assoc, cam):
     Returns (tile ids, Gaussian ids, ranges[ntiles + 1])."""
     tw, th = tile_grid(cam)
     vis = np.nonzero(assoc["count"] > 0)[0]
-    tiles, gids, keys = [], [], []
-    for g in vis:
-        a = assoc[g]
-        tx0, tx1, ty0, ty1 = a["hx0"] // 2, a["hx1"] // 2, a["hy0"] // 2, a["hy1"] // 2
-        yy, xx = np.mgrid[ty0:ty1 + 1, tx0:tx1 + 1]
-        t = (yy * tw + xx).ravel()
-        tiles.append(t)
-        gids.append(np.full(t.size, g, dtype=np.int64))
-        keys.append(np.full(t.size, a["key"], dtype=np.uint64))
-    if not tiles:
-        return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(tw * th + 1, np.int64)
-    tiles = np.concatenate(tiles).astype(np.int64)
-    gids = np.concatenate(gids)
-    keys = np.concatenate(keys)
+    a = assoc[vis]
+    tx0, tx1 = a["hx0"].astype(np.int64) // 2, a["hx1"].astype(np.int64) // 2
+    ty0, ty1 = a["hy0"].astype(np.int64) // 2, a["hy1"].astype(np.int64) // 2
+    wt = tx1 - tx0 + 1
+    cnt = wt * (ty1 - ty0 + 1)
+    assert np.all(cnt == a["count"].astype(np.int64))
+    total = int(cnt.sum())
+    owner = np.repeat(np.arange(vis.size), cnt)
+    local = np.arange(total) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    tiles = (ty0[owner] + local // wt[owner]) * tw + tx0[owner] + local % wt[owner]
+    gids = vis[owner].astype(np.int64)
+    keys = a["key"][owner].astype(np.uint64)
     order = np.lexsort((gids, keys, tiles))
     tiles, gids = tiles[order], gids[order]
     ranges = np.searchsorted(tiles, np.arange(tw * th + 1), side="left")
@@ -183,7 +181,10 @@ def tile_list(assoc, cam):
 
 def render(scene, cam, pix=None, nthreads: int = 0, **opts):
     """Brute-force FP64 render of BEAP pixels (all when ``pix`` is None).
-    Returns dict(rgb [P,3], depth [P], trans [P], ncomp [P], amb [P], pix)."""
+    Returns dict(rgb [P,3], depth [P], trans [P], ncomp [P], amb [P], amb_tol [P],
+    pix): ``amb`` marks rays with a pair within the FP32 error band of a
+    contribution or termination decision, ``amb_tol`` bounds how much those
+    decisions can move the ray's colour."""
     L = lib()
     w, h = int(cam["width"]), int(cam["height"])
     if pix is None:
@@ -195,12 +196,13 @@ def render(scene, cam, pix=None, nthreads: int = 0, **opts):
     trans = np.zeros(n)
     ncomp = np.zeros(n, np.int32)
     amb = np.zeros(n, np.int32)
+    amb_tol = np.zeros(n)
     ref = _SceneRef(scene)
     rc = L.orc_render(C.byref(ref.c), C.byref(make_view(cam)), C.byref(make_opts(**opts)), n, _ptr(pix),
-                      _ptr(rgb), _ptr(depth), _ptr(trans), _ptr(ncomp), _ptr(amb), int(nthreads))
+                      _ptr(rgb), _ptr(depth), _ptr(trans), _ptr(ncomp), _ptr(amb), _ptr(amb_tol), int(nthreads))
     if rc != 0:
         raise MemoryError("oracle render failed")
-    return dict(rgb=rgb, depth=depth, trans=trans, ncomp=ncomp, amb=amb.astype(bool), pix=pix)
+    return dict(rgb=rgb, depth=depth, trans=trans, ncomp=ncomp, amb=amb.astype(bool), amb_tol=amb_tol, pix=pix)
 
 
 def render_backward(scene, cam, pix, dl_drgb, nthreads: int = 0, **opts):

@@ -542,6 +542,7 @@ typedef struct {
   int64_t g;
   double alpha, araw, kappa, tstar;
   double u[3], m[3], uu;
+  double band; /* FP32 error bound of kappa for this pair */
   int clamped;
 } contrib;
 
@@ -552,22 +553,46 @@ static int contrib_cmp(const void* a, const void* b) {
   return x->g < y->g ? -1 : (x->g > y->g ? 1 : 0);
 }
 
-/* Per-Gaussian bound on the FP32 error of kappa: one FP32 unit of the ray
- * direction moves the closest approach by dist * 2^-22 metres, i.e. by
- * dist * 2^-22 / s_min in Mahalanobis units. */
-static double kappa_band(const gprep* p) {
-  double smin = p->s[0] < p->s[1] ? p->s[0] : p->s[1];
-  smin = smin < p->s[2] ? smin : p->s[2];
-  double dm = 8.0 * p->dist * 0x1p-23 / smin;
-  double rl = p->lam2 > 0 ? sqrt(p->lam2) : 0;
-  return 4.0 * rl * dm + dm * dm + 1e-5 * (p->lam2 > 1 ? p->lam2 : 1);
+/* First-order bound on how far FP32 evaluation can move kappa: the ray
+ * direction carries a few units in the last place (|grad_d kappa| * 2^-21),
+ * the camera-space mean a few ulps of |mu| + |o| (|grad_mu kappa| * that),
+ * plus a relative floor.  Both gradients come from the chain of the
+ * cookbook appendix (dkappa/dd_u, dkappa/do_u) mapped through W^T. */
+static double kappa_band(const gprep* p, const double u[3], const double m[3], double uu, double kappa,
+                         const double o[3]) {
+  const double* ou = p->ou;
+  const double* W = p->W;
+  double gm[3] = {2 * m[0] / uu, 2 * m[1] / uu, 2 * m[2] / uu};
+  double dku[3] = {gm[1] * ou[2] - gm[2] * ou[1], gm[2] * ou[0] - gm[0] * ou[2], gm[0] * ou[1] - gm[1] * ou[0]};
+  double kk = 2 * kappa / uu;
+  for (int a = 0; a < 3; ++a) dku[a] -= kk * u[a];
+  double dko[3] = {u[1] * gm[2] - u[2] * gm[1], u[2] * gm[0] - u[0] * gm[2], u[0] * gm[1] - u[1] * gm[0]};
+  double gd2 = 0, gmu2 = 0;
+  for (int q = 0; q < 3; ++q) {
+    double a = W[0 * 3 + q] * dku[0] + W[1 * 3 + q] * dku[1] + W[2 * 3 + q] * dku[2];
+    double b = W[0 * 3 + q] * dko[0] + W[1 * 3 + q] * dko[1] + W[2 * 3 + q] * dko[2];
+    gd2 += a * a;
+    gmu2 += b * b;
+  }
+  double mu_mag = p->dist + sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+  return 0x1p-20 * sqrt(gd2) + 0x1p-20 * mu_mag * sqrt(gmu2) + 1e-6 * (p->lam2 > 1 ? p->lam2 : 1);
 }
 
 /* Collect the contributors of one ray in order; returns the count. */
-static int64_t gather(const gprep* P, int64_t n, const orc_opts* op, const double d[3],
-                      contrib** buf, int64_t* cap, int* amb) {
+static double cmax_of(const gprep* p) {
+  double c = p->col[0] > p->col[1] ? p->col[0] : p->col[1];
+  return c > p->col[2] ? c : p->col[2];
+}
+
+/* *amb is set when some pair lies within the FP32 error band of a decision;
+ * *tol accumulates how much flipping those decisions can change the colour
+ * (2 alpha_raw max(c) per pair: the pair's own term and the occlusion it
+ * adds to what lies behind). */
+static int64_t gather(const gprep* P, int64_t n, const orc_opts* op, const double o[3], const double d[3],
+                      contrib** buf, int64_t* cap, int* amb, double* tol) {
   int64_t cnt = 0;
   *amb = 0;
+  *tol = 0;
   for (int64_t g = 0; g < n; ++g) {
     const gprep* p = &P[g];
     if (!p->active) continue;
@@ -580,17 +605,20 @@ static int64_t gather(const gprep* P, int64_t n, const orc_opts* op, const doubl
     double kappa = (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / uu;
     double od = ou[0] * u[0] + ou[1] * u[1] + ou[2] * u[2];
     double tstar = -od / uu;
-    double band = kappa_band(p);
-    if (fabs(kappa - p->lam2) <= band && tstar > 0) *amb = 1;
+    double band = kappa_band(p, u, m, uu, kappa, o);
+    int flag = 0;
+    if (fabs(kappa - p->lam2) <= band && tstar > 0) flag = 1;
     if (fabs(od) <= 1e-4 * sqrt(uu) * sqrt(ou[0] * ou[0] + ou[1] * ou[1] + ou[2] * ou[2]) && kappa <= p->lam2 + band)
+      flag = 1;
+    double araw = p->sigma * exp(-0.5 * kappa);
+    if (op->lambda_mode == 1 && fabs(araw - op->alpha_min) <= 1e-3 * op->alpha_min) flag = 1;
+    if (flag) {
       *amb = 1;
+      *tol += 2.0 * p->sigma * exp(-0.5 * (kappa - band > 0 ? kappa - band : 0)) * (cmax_of(p) + 1e-3);
+    }
     if (!(tstar > 0)) continue;
     if (!(kappa <= p->lam2)) continue;
-    double araw = p->sigma * exp(-0.5 * kappa);
-    if (op->lambda_mode == 1) {
-      if (fabs(araw - op->alpha_min) <= 1e-3 * op->alpha_min) *amb = 1;
-      if (!(araw >= op->alpha_min)) continue;
-    }
+    if (op->lambda_mode == 1 && !(araw >= op->alpha_min)) continue;
     if (cnt == *cap) {
       *cap = *cap ? *cap * 2 : 256;
       *buf = (contrib*)realloc(*buf, sizeof(contrib) * (size_t)*cap);
@@ -603,6 +631,7 @@ static int64_t gather(const gprep* P, int64_t n, const orc_opts* op, const doubl
     c->alpha = c->clamped ? op->alpha_max : araw;
     c->kappa = kappa;
     c->tstar = tstar;
+    c->band = band;
     for (int a = 0; a < 3; ++a) { c->u[a] = u[a]; c->m[a] = m[a]; }
     c->uu = uu;
   }
@@ -622,7 +651,7 @@ static void camera_centre(const orc_view* v, double o[3]) {
  */
 int orc_render(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64_t npix,
                const int64_t* pix, double* rgb, double* depth, double* trans, int32_t* ncomp,
-               int32_t* amb, int nthreads) {
+               int32_t* amb, double* amb_tol, int nthreads) {
   int64_t n = sc->n;
   orc_assoc* as = (orc_assoc*)malloc(sizeof(orc_assoc) * (size_t)(n > 0 ? n : 1));
   gprep* P = (gprep*)malloc(sizeof(gprep) * (size_t)(n > 0 ? n : 1));
@@ -644,14 +673,27 @@ int orc_render(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64
       double d[3];
       pixel_dir(v, px, py, d);
       int a_flag;
-      int64_t cnt = gather(P, n, op, d, &buf, &cap, &a_flag);
+      double tol;
+      int64_t cnt = gather(P, n, op, o, d, &buf, &cap, &a_flag, &tol);
+      double cmax_all = 0;
+      for (int64_t i = 0; i < cnt; ++i) {
+        double cm = cmax_of(&P[buf[i].g]);
+        cmax_all = cm > cmax_all ? cm : cmax_all;
+      }
       double T = 1, C[3] = {0, 0, 0}, D = 0;
+      double trel = 0; /* first-order relative FP32 error of the transmittance */
       int32_t nc = 0;
       for (int64_t i = 0; i < cnt; ++i) {
         const contrib* c = &buf[i];
         double Tn = T * (1 - c->alpha);
+        trel += (c->clamped ? 0.0 : c->alpha * 0.5 * c->band) / (1 - c->alpha) + 0x1p-22;
         if (op->t_min > 0) {
-          if (fabs(Tn - op->t_min) <= 2e-3 * op->t_min) a_flag = 1;
+          if (fabs(Tn - op->t_min) <= (trel + 0x1p-20) * Tn) {
+            /* termination may happen one step earlier or later: the step's
+               own term plus everything behind it */
+            a_flag = 1;
+            tol += T * (c->alpha + 1.0) * (cmax_all + 1e-3);
+          }
           if (Tn < op->t_min) break;
         }
         double w = c->alpha * T;
@@ -666,6 +708,7 @@ int orc_render(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64
       trans[t] = T;
       ncomp[t] = nc;
       amb[t] = a_flag;
+      amb_tol[t] = a_flag ? tol : 0.0;
     }
     free(buf);
   }
@@ -719,7 +762,8 @@ int orc_render_backward(const orc_scene* sc, const orc_view* v, const orc_opts* 
       double d[3];
       pixel_dir(v, px, py, d);
       int a_flag;
-      int64_t cnt = gather(P, n, op, d, &buf, &cap, &a_flag);
+      double tol_unused;
+      int64_t cnt = gather(P, n, op, o, d, &buf, &cap, &a_flag, &tol_unused);
       if (cnt > tcap) { tcap = cnt; Tb = (double*)realloc(Tb, sizeof(double) * (size_t)tcap); }
       /* forward pass storing T before each composited Gaussian */
       double T = 1;
@@ -876,6 +920,8 @@ int orc_contrib_mask(const orc_scene* sc, const orc_view* v, const orc_opts* op,
   if (!as || !P) { free(as); free(P); return -1; }
   orc_assoc_fp32(sc, v, op, as);
   prep_gaussians(sc, v, op, P, as);
+  double o[3];
+  camera_centre(v, o);
 #pragma omp parallel
   {
     contrib* buf = NULL;
@@ -886,7 +932,8 @@ int orc_contrib_mask(const orc_scene* sc, const orc_view* v, const orc_opts* op,
       double d[3];
       pixel_dir(v, px, py, d);
       int a_flag;
-      int64_t cnt = gather(P, n, op, d, &buf, &cap, &a_flag);
+      double tol_unused;
+      int64_t cnt = gather(P, n, op, o, d, &buf, &cap, &a_flag, &tol_unused);
       memset(mask + (size_t)t * (size_t)n, 0, (size_t)n);
       for (int64_t i = 0; i < cnt; ++i) mask[(size_t)t * (size_t)n + (size_t)buf[i].g] = 1;
     }

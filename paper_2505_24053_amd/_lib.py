@@ -1,0 +1,131 @@
+"""ctypes binding of libgeer.so (declarations in include/geer.h).
+
+Argument marshalling only: every step of the render runs in the HIP library.
+Loading fails loudly when the library has not been built; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgeer.so")
+
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = range(6)
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "CAPACITY", 4: "HIP", 5: "UNSUPPORTED"}
+MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2}
+BUF_RECT, BUF_COUNT, BUF_KEY, BUF_LIST, BUF_RANGES, BUF_NLAST = range(6)
+
+# every symbol include/geer.h declares
+EXPORTS = ["geer_create", "geer_destroy", "geer_last_error", "geer_default_opts", "geer_render",
+           "geer_render_backward", "geer_frame_release", "geer_frame_get_stats", "geer_frame_buffer_bytes",
+           "geer_frame_export", "geer_valid_mask", "geer_l1_loss"]
+
+
+class GeerView(C.Structure):
+    _fields_ = [("model", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("reserved", C.c_int32),
+                ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("k", C.c_double * 4), ("fov_x", C.c_double), ("fov_y", C.c_double),
+                ("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class GeerScene(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32),
+                ("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class GeerOpts(C.Structure):
+    _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
+                ("lambda_fixed", C.c_float), ("lambda_mode", C.c_int32), ("reserved", C.c_int32)]
+
+
+class GeerFrameStats(C.Structure):
+    _fields_ = [("n_items", C.c_int64), ("n_visible", C.c_int64), ("n_entries", C.c_int64),
+                ("n_tiles", C.c_int64), ("n_pixels", C.c_int64), ("n_evaluated", C.c_int64),
+                ("n_composited", C.c_int64)]
+
+
+class GeerError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("geer %s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgeer.so is not built (%s); run `python -m paper_2505_24053_amd.build` "
+                               "or __graft_entry__.build()" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        P, V = C.POINTER, C.c_void_p
+        L.geer_create.argtypes = [C.c_int32, P(V)]
+        L.geer_destroy.argtypes = [V]
+        L.geer_destroy.restype = None
+        L.geer_last_error.argtypes = [V]
+        L.geer_last_error.restype = C.c_char_p
+        L.geer_default_opts.argtypes = [P(GeerOpts)]
+        L.geer_default_opts.restype = None
+        L.geer_render.argtypes = [V, P(GeerScene), C.c_int32, P(GeerView), P(GeerOpts), V, V, V, P(V), V]
+        L.geer_render_backward.argtypes = [V, V, V, V, V, V, V, V, C.c_int32, V]
+        L.geer_frame_release.argtypes = [V]
+        L.geer_frame_release.restype = None
+        L.geer_frame_get_stats.argtypes = [V, P(GeerFrameStats)]
+        L.geer_frame_buffer_bytes.argtypes = [V, C.c_int32]
+        L.geer_frame_buffer_bytes.restype = C.c_int64
+        L.geer_frame_export.argtypes = [V, C.c_int32, V, C.c_int64]
+        L.geer_valid_mask.argtypes = [P(GeerView), V]
+        L.geer_l1_loss.argtypes = [V, C.c_int64, V, V, V, V, V, V]
+        _lib = L
+        return L
+
+
+def make_view(cam: dict) -> GeerView:
+    v = GeerView()
+    v.model = MODELS[cam["model"]]
+    v.width, v.height, v.reserved = int(cam["width"]), int(cam["height"]), 0
+    v.fx, v.fy, v.cx, v.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    for i in range(4):
+        v.k[i] = float(cam["k"][i])
+    v.fov_x, v.fov_y = float(cam["fov_x"]), float(cam["fov_y"])
+    R = np.asarray(cam["R"], dtype=np.float64).reshape(9)
+    t = np.asarray(cam["t"], dtype=np.float64).reshape(3)
+    for i in range(9):
+        v.R[i] = R[i]
+    for i in range(3):
+        v.t[i] = t[i]
+    return v
+
+
+def make_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, lambda_mode=0, lambda_fixed=3.0) -> GeerOpts:
+    o = GeerOpts()
+    o.alpha_min, o.alpha_max, o.t_min = float(alpha_min), float(alpha_max), float(t_min)
+    o.lambda_fixed, o.lambda_mode, o.reserved = float(lambda_fixed), int(lambda_mode), 0
+    return o
+
+
+def check(status, ctx=None):
+    if status != OK:
+        msg = load().geer_last_error(ctx).decode() if ctx else ""
+        raise GeerError(status, msg)
+
+
+def valid_mask(cam: dict) -> np.ndarray:
+    v = make_view(cam)
+    out = np.zeros(int(cam["height"]) * int(cam["width"]), np.uint8)
+    check(load().geer_valid_mask(C.byref(v), C.c_void_p(out.ctypes.data)))
+    return out.reshape(int(cam["height"]), int(cam["width"])).astype(bool)
+
+
+__all__ = ["load", "make_view", "make_opts", "check", "valid_mask", "GeerError", "EXPORTS"]

@@ -1,0 +1,52 @@
+// Internal layouts shared by the host code and the gfx950 kernels of libgeer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace geer {
+
+constexpr int kTile = 16;      // CSF tile edge (pixels)
+constexpr int kHalf = 8;       // half-tile edge: one wave64 covers an 8x8 half-tile
+constexpr int kLamShift = 17;  // lambda^2 table: buckets of 2^17 float bit patterns
+
+// Per-view constants, uploaded once per render call.
+struct ViewDev {
+  float Rc[9];        // world-to-camera rotation (FP32)
+  float tc[3];        // world-to-camera translation (FP32)
+  float campos[3];    // camera centre in world space (SH view direction)
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  int32_t nhx, nhy;   // half-tile columns / rows
+  int32_t tile_base;  // first global tile id of this view
+  int32_t pix_base;   // first pixel of this view in the concatenated outputs
+  int32_t ex_off, ey_off;  // offsets of the edge tables in the edge buffer
+  int32_t dx_off, dy_off;  // offsets of the direction tables (2 floats per entry)
+  int32_t pad_[5];
+};
+static_assert(sizeof(ViewDev) % 16 == 0, "ViewDev alignment");
+
+// Render record of one (Gaussian, view) item: 64 bytes, read wave-uniformly.
+//   G rows (9): r e1^T Wc, r e2^T Wc, -o_u^T Wc   (rotated canonical frame)
+//   c0 = -r^2 log2(e) / 2, lsig = log2(sigma), c1 = r^2
+//   rgb (3), qmax (kappa / r^2 bound of the fixed-lambda mode, +inf otherwise)
+struct alignas(16) Record {
+  float g[9];
+  float c0, lsig, c1;
+  float rgb[3];
+  float qmax;
+};
+static_assert(sizeof(Record) == 64, "Record is 64 bytes");
+
+struct Opts {
+  float alpha_min, alpha_max, t_min, lambda_fixed;
+  int32_t lambda_mode;
+  float lam2_fixed;   // conservative lambda_fixed^2 for the PBF
+  float kmax_fixed;   // lambda_fixed^2 for the contribution test
+  int32_t lam_lo;     // first bucket index of the lambda^2 table
+  int32_t lam_n;      // number of buckets
+  int32_t pad_[3];
+};
+
+__host__ __device__ inline uint32_t pack16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+}  // namespace geer

@@ -1,0 +1,46 @@
+// Host-side tables and kernel launchers of libgeer (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "geer.h"
+#include "geer_common.h"
+
+namespace geer {
+
+// tables.cpp
+void lambda_table(float alpha_min, std::vector<float>& tab, int& lo, int& n);
+float lambda_fixed_hat(float lambda_fixed);
+void edge_tables(const geer_view& v, std::vector<float>& ex, std::vector<float>& ey);
+void direction_tables(const geer_view& v, std::vector<float>& dx, std::vector<float>& dy);
+void view_constants(const geer_view& v, ViewDev& d);
+void valid_mask(const geer_view& v, uint8_t* mask);
+
+// preprocess.hip
+void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
+                       const float* scale, const float* quat, const float* opacity, const float* sh,
+                       const ViewDev* views, const Opts& op, const float* lam_tab, const float* edges,
+                       Record* recs, uint2* rects, uint32_t* keys, uint32_t* counts, unsigned long long* totals);
+
+// sort.hip
+int64_t scan_scratch_words(int64_t n);
+void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch);
+int64_t radix_hist_words(int64_t n);
+void radix_pass(hipStream_t st, const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* filter,
+                int64_t n, int shift, uint32_t* keys_out, uint32_t* vals_out, uint32_t* hist,
+                uint32_t* scan_scratch);
+void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m, const uint32_t* counts, uint32_t* out);
+void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m, int64_t total,
+                   const uint2* rects, const ViewDev* views, int64_t n, uint32_t* tiles_out, uint32_t* items_out);
+void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total, int64_t ntiles, uint32_t* ranges);
+void launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v);
+
+// render.hip
+void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const ViewDev* views, int nviews,
+                   const float2* dtab, const uint32_t* ranges, const uint32_t* list, const uint2* rects,
+                   const Record* recs, const Opts& op, float* rgb, float* depth, float* trans, uint32_t* nlast,
+                   float* tfinal, unsigned long long* stats);
+
+}  // namespace geer

@@ -1,0 +1,128 @@
+"""Torch-facing API of the HIP renderer: device tensors in, device tensors out.
+
+PyTorch supplies device memory and streams; every computation runs in
+libgeer.so.  Scene tensors use the library layout (float32, CUDA/HIP device,
+contiguous): mean [3,N], scale [3,N], quat [4,N], opacity [N], sh [K*3,N].
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_contexts = {}
+
+
+def context(device: int = 0):
+    """The per-device library context (created on first use)."""
+    if device not in _contexts:
+        L = _lib.load()
+        h = C.c_void_p()
+        _lib.check(L.geer_create(int(device), C.byref(h)))
+        _contexts[device] = h
+    return _contexts[device]
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_scene(scene: dict):
+    n = scene["mean"].shape[1]
+    deg = int(scene["sh_degree"])
+    shapes = {"mean": (3, n), "scale": (3, n), "quat": (4, n), "opacity": (n,), "sh": ((deg + 1) ** 2 * 3, n)}
+    for k, shp in shapes.items():
+        t = scene[k]
+        if tuple(t.shape) != shp or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("scene[%r] must be a contiguous float32 device tensor of shape %s, got %s %s %s"
+                             % (k, shp, tuple(t.shape), t.dtype, t.device))
+    return n, deg
+
+
+def scene_from_numpy(s, device="cuda") -> dict:
+    """Upload a host scene (the layout of the synthetic-scene module)."""
+    return dict(mean=torch.as_tensor(s.mean, device=device).contiguous(),
+                scale=torch.as_tensor(s.scale, device=device).contiguous(),
+                quat=torch.as_tensor(s.quat, device=device).contiguous(),
+                opacity=torch.as_tensor(s.opacity, device=device).contiguous(),
+                sh=torch.as_tensor(s.sh, device=device).contiguous(),
+                sh_degree=int(s.sh_degree))
+
+
+class Frame:
+    """Forward state kept by the library for the backward (geer_frame)."""
+
+    def __init__(self, handle, ctx, cams):
+        self.handle = handle
+        self.ctx = ctx
+        self.cams = cams
+
+    def stats(self) -> dict:
+        st = _lib.GeerFrameStats()
+        _lib.check(_lib.load().geer_frame_get_stats(self.handle, C.byref(st)), self.ctx)
+        return {k: int(getattr(st, k)) for k, _ in _lib.GeerFrameStats._fields_}
+
+    def export(self, which: int) -> np.ndarray:
+        L = _lib.load()
+        nbytes = int(L.geer_frame_buffer_bytes(self.handle, which))
+        out = np.zeros(max(nbytes // 4, 1), np.uint32)
+        _lib.check(L.geer_frame_export(self.handle, which, C.c_void_p(out.ctypes.data), nbytes), self.ctx)
+        return out[: nbytes // 4]
+
+    def release(self):
+        if self.handle:
+            _lib.load().geer_frame_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def view_pixels(cams):
+    return [int(c["width"]) * int(c["height"]) for c in cams]
+
+
+def render(scene: dict, cams, opts: dict | None = None, keep_frame: bool = False, out=None, want_depth=True,
+           want_trans=True):
+    """Render the views `cams` (list of camera dicts).  Returns
+    (rgb [sum 3*H*W], depth [sum H*W] | None, trans | None, Frame | None) as
+    flat concatenations in view order (see views_of to split them)."""
+    n, deg = _check_scene(scene)
+    dev = scene["mean"].device
+    ctx = context(dev.index or 0)
+    npix = sum(view_pixels(cams))
+    if out is None:
+        rgb = torch.empty(3 * npix, device=dev, dtype=torch.float32)
+        depth = torch.empty(npix, device=dev, dtype=torch.float32) if want_depth else None
+        trans = torch.empty(npix, device=dev, dtype=torch.float32) if want_trans else None
+    else:
+        rgb, depth, trans = out
+    views = (_lib.GeerView * len(cams))(*[_lib.make_view(c) for c in cams])
+    sc = _lib.GeerScene()
+    sc.n, sc.sh_degree, sc.reserved = n, deg, 0
+    sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh = (scene[k].data_ptr() for k in
+                                                    ("mean", "scale", "quat", "opacity", "sh"))
+    op = _lib.make_opts(**(opts or {}))
+    fh = C.c_void_p()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    _lib.check(_lib.load().geer_render(ctx, C.byref(sc), len(cams), views, C.byref(op), _ptr(rgb), _ptr(depth),
+                                       _ptr(trans), C.byref(fh) if keep_frame else None, C.c_void_p(stream)), ctx)
+    frame = Frame(fh, ctx, cams) if keep_frame else None
+    return rgb, depth, trans, frame
+
+
+def views_of(flat: torch.Tensor, cams, channels: int):
+    """Split a flat concatenated output into per-view [C,H,W] tensors."""
+    outs, off = [], 0
+    for c in cams:
+        hw = int(c["width"]) * int(c["height"])
+        outs.append(flat[off: off + channels * hw].view(channels, int(c["height"]), int(c["width"])))
+        off += channels * hw
+    return outs

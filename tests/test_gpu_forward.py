@@ -1,0 +1,231 @@
+"""GPU forward parity against the oracle, through the C ABI.
+
+* association (stage a/b): rectangles, tile counts, depth keys, the sorted
+  list and the tile ranges are compared bit for bit with the oracle's FP32
+  association reference and its (tile, key, index) sort;
+* render (stage c): RGB, depth and transmittance against the FP64 brute force,
+  RGB max-abs <= 2e-4 on every ray the oracle does not flag as within the
+  FP32 error band of a contribution / termination threshold (flagged rays are
+  counted and held to a loose bound); full images at small sizes, sampled rays
+  at the full workload sizes;
+* edge cases: empty scene, ragged grids, a 1x1 grid, all Gaussians culled,
+  fixed-lambda mode, no early termination, multi-view batches equal to
+  single-view renders, bit-identical repeats.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import adversarial_scene
+from paper_2505_24053_amd import _lib, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RGB_TOL = 2e-4
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_24053_amd import renderer
+
+    if not __import__("os").path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    return renderer
+
+
+def gpu_render(R, scene, cams, **opts):
+    sc = R.scene_from_numpy(scene)
+    rgb, depth, trans, frame = R.render(sc, cams, opts=opts or None, keep_frame=True)
+    torch.cuda.synchronize()
+    out = []
+    for v, (c3, d1, t1) in enumerate(zip(R.views_of(rgb, cams, 3), R.views_of(depth, cams, 1),
+                                         R.views_of(trans, cams, 1))):
+        out.append(dict(rgb=c3.reshape(3, -1).T.double().cpu().numpy(), depth=d1.reshape(-1).double().cpu().numpy(),
+                        trans=t1.reshape(-1).double().cpu().numpy()))
+    return out, frame
+
+
+def check_association(frame, scene, cams, **opts):
+    n = scene.n
+    rect = frame.export(_lib.BUF_RECT).reshape(-1, 2)
+    count = frame.export(_lib.BUF_COUNT)
+    key = frame.export(_lib.BUF_KEY)
+    lst = frame.export(_lib.BUF_LIST)
+    ranges = frame.export(_lib.BUF_RANGES)
+    all_items, tile_base, e_base, all_ranges = [], 0, 0, []
+    for v, cam in enumerate(cams):
+        a = oracle.assoc_fp32(scene, cam, **opts)
+        sl = slice(v * n, (v + 1) * n)
+        np.testing.assert_array_equal(count[sl], a["count"])
+        np.testing.assert_array_equal(key[sl], a["key"])
+        vis = a["count"] > 0
+        gr = rect[sl]
+        np.testing.assert_array_equal(gr[vis, 0] & 0xFFFF, a["hx0"][vis])
+        np.testing.assert_array_equal(gr[vis, 0] >> 16, a["hx1"][vis])
+        np.testing.assert_array_equal(gr[vis, 1] & 0xFFFF, a["hy0"][vis])
+        np.testing.assert_array_equal(gr[vis, 1] >> 16, a["hy1"][vis])
+        tiles, gids, rng = oracle.tile_list(a, cam)
+        all_items.append(gids + v * n)
+        all_ranges.append(rng[:-1] + e_base)
+        e_base += tiles.size
+        tw, th = oracle.tile_grid(cam)
+        tile_base += tw * th
+    all_ranges.append(np.array([e_base]))
+    np.testing.assert_array_equal(lst, np.concatenate(all_items))
+    np.testing.assert_array_equal(ranges, np.concatenate(all_ranges))
+    st = frame.stats()
+    assert st["n_entries"] == e_base
+    return e_base
+
+
+def compare_render(got, ref, pix=None, rgb_tol=RGB_TOL):
+    """RGB within rgb_tol on unflagged rays; a flagged ray may also differ by
+    the oracle's bound on the decisions that fall within FP32 error."""
+    sel = slice(None) if pix is None else pix
+    g_rgb, g_d, g_t = got["rgb"][sel], got["depth"][sel], got["trans"][sel]
+    amb = ref["amb"]
+    ok = ~amb
+    err = np.abs(g_rgb - ref["rgb"]).max(axis=1)
+    assert err[ok].max(initial=0) <= rgb_tol, "max |rgb| err %g at %s" % (err[ok].max(), np.argmax(np.where(ok, err, 0)))
+    over = err[amb] - (rgb_tol + ref["amb_tol"][amb])
+    assert over.max(initial=-1) <= 0, "flagged ray beyond its bound by %g" % over.max()
+    terr = np.abs(g_t - ref["trans"])
+    assert terr[ok].max(initial=0) <= rgb_tol
+    derr = np.abs(g_d - ref["depth"]) / (1.0 + np.abs(ref["depth"]))
+    assert derr[ok].max(initial=0) <= 1e-3
+    assert amb.mean() < 0.10
+    print("rays %d, flagged %d (%.2f%%), flagged beyond %.0e: %d, max err unflagged %.3g"
+          % (amb.size, amb.sum(), 100 * amb.mean(), rgb_tol, int((err[amb] > rgb_tol).sum()), err[ok].max(initial=0)))
+    return float(err[ok].max(initial=0)), int(amb.sum())
+
+
+def test_small_workload_bit_exact_association_and_render(R):
+    scene, cams = synth.workload_small()
+    got, frame = gpu_render(R, scene, cams)
+    e = check_association(frame, scene, cams)
+    assert e > 1000
+    ref = oracle.render(scene, cams[0])
+    compare_render(got[0], ref)
+    frame.release()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_adversarial_multiview_batch(R, seed):
+    rng = np.random.default_rng(300 + seed)
+    scene = adversarial_scene(seed)
+    cams = []
+    for k, make in enumerate([lambda R_, c: synth.camera_pinhole(37, 23, 60.0, R_, c),
+                              lambda R_, c: synth.camera_equidistant(40, 40, 180.0, R_, c),
+                              lambda R_, c: synth.camera_kb(48, 24, 190.0, seed=1, R=R_, position=c),
+                              lambda R_, c: synth.camera_kb(40, 24, 200.0, seed=2, R=R_, position=c)]):
+        Rm, c = synth.random_pose(rng, half=1.0) if k % 2 else (None, None)
+        cams.append(make(Rm, c))
+    got, frame = gpu_render(R, scene, cams)
+    check_association(frame, scene, cams)
+    for v, cam in enumerate(cams):
+        compare_render(got[v], oracle.render(scene, cam))
+    frame.release()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_lambda_modes_and_no_termination(R, mode):
+    scene = synth.scene_box(3000, seed=5, half=4.0)
+    cam = synth.camera_equidistant(96, 80, 180.0)
+    opts = dict(lambda_mode=mode, t_min=0.0 if mode else 1e-4)
+    got, frame = gpu_render(R, scene, [cam], **opts)
+    check_association(frame, scene, [cam], **opts)
+    compare_render(got[0], oracle.render(scene, cam, **opts))
+    frame.release()
+
+
+def test_fisheye_reduced_full_image(R):
+    scene, cams = synth.workload_fisheye_forward(seed=1, n=20000, width=256)
+    got, frame = gpu_render(R, scene, cams)
+    check_association(frame, scene, cams)
+    err, namb = compare_render(got[0], oracle.render(scene, cams[0]))
+    print("fisheye 20k/256^2: max err %.3g, ambiguous rays %d" % (err, namb))
+    frame.release()
+
+
+def test_fisheye_full_size_sampled(R):
+    """100k Gaussians SH3, equidistant 180 deg, 1024x1024: association bit-exact
+    on the whole frame, rendering on 2048 sampled rays."""
+    scene, cams = synth.workload_fisheye_forward(seed=0)
+    cam = cams[0]
+    got, frame = gpu_render(R, scene, cams)
+    check_association(frame, scene, cams)
+    pix = np.random.default_rng(0).choice(cam["width"] * cam["height"], 2048, replace=False)
+    ref = oracle.render(scene, cam, pix=pix)
+    err, namb = compare_render(got[0], ref, pix=pix)
+    print("fisheye 100k/1024^2 sampled: max err %.3g, ambiguous %d" % (err, namb))
+    frame.release()
+
+
+def test_kb190_full_size_sampled(R):
+    """500k Gaussians SH3, Kannala-Brandt 190 deg 1280x960."""
+    scene, cams, _ = synth.workload_kb_train(seed=0)
+    cam = cams[0]
+    got, frame = gpu_render(R, scene, cams)
+    check_association(frame, scene, cams)
+    pix = np.random.default_rng(1).choice(cam["width"] * cam["height"], 1024, replace=False)
+    ref = oracle.render(scene, cam, pix=pix)
+    err, namb = compare_render(got[0], ref, pix=pix)
+    print("kb190 500k sampled: max err %.3g, ambiguous %d" % (err, namb))
+    frame.release()
+
+
+def test_empty_and_degenerate_inputs(R):
+    cam = synth.camera_pinhole(37, 23, 60.0)
+    empty = synth.scene_small(1).subset(np.arange(0))
+    got, frame = gpu_render(R, empty, [cam])
+    assert np.all(got[0]["rgb"] == 0) and np.all(got[0]["trans"] == 1) and np.all(got[0]["depth"] == 0)
+    assert frame.stats()["n_entries"] == 0
+    frame.release()
+    # a 1x1 grid
+    scene, _ = synth.workload_small()
+    one = synth.camera_pinhole(1, 1, 10.0)
+    got, frame = gpu_render(R, scene, [one])
+    check_association(frame, scene, [one])
+    compare_render(got[0], oracle.render(scene, one))
+    frame.release()
+    # every Gaussian contains the camera: all culled
+    big = synth.scene_small(50)
+    big.mean[:] = 0.0
+    big.scale[:] = 1.0
+    got, frame = gpu_render(R, big, [cam])
+    assert frame.stats()["n_visible"] == 0 and np.all(got[0]["rgb"] == 0)
+    frame.release()
+
+
+def test_batch_equals_single_views_and_repeats(R):
+    scene = synth.scene_box(20000, seed=2, half=6.0)
+    rng = np.random.default_rng(5)
+    cams = [synth.camera_pinhole(64, 48, 60.0, *synth.random_pose(rng, 3.0)),
+            synth.camera_equidistant(80, 80, 180.0, *synth.random_pose(rng, 3.0)),
+            synth.camera_kb(96, 54, 200.0, seed=3, R=synth.random_rotation(rng), position=rng.uniform(-3, 3, 3))]
+    sc = R.scene_from_numpy(scene)
+    rgb_b, d_b, t_b, _ = R.render(sc, cams)
+    rgb_b2, _, _, _ = R.render(sc, cams)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb_b, rgb_b2)
+    for v, cam in enumerate(cams):
+        rgb_s, d_s, t_s, _ = R.render(sc, [cam])
+        torch.cuda.synchronize()
+        assert torch.equal(R.views_of(rgb_b, cams, 3)[v].reshape(-1), rgb_s)
+        assert torch.equal(R.views_of(t_b, cams, 1)[v].reshape(-1), t_s)
+
+
+def test_invalid_arguments_rejected(R):
+    scene, cams = synth.workload_small()
+    sc = R.scene_from_numpy(scene)
+    with pytest.raises(_lib.GeerError):
+        R.render(sc, [dict(cams[0], fov_y=3.5)])
+    with pytest.raises(_lib.GeerError):
+        R.render(sc, cams, opts=dict(alpha_min=0.0))
+    with pytest.raises(ValueError):
+        R.render(dict(sc, mean=sc["mean"].double()), cams)

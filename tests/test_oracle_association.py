@@ -21,6 +21,7 @@ import pytest
 from scipy.spatial.transform import Rotation
 
 import oracle
+from helpers import adversarial_scene
 from paper_2505_24053_amd import synth
 
 CAMS = {
@@ -29,46 +30,6 @@ CAMS = {
     "kb190": lambda R=None, c=None: synth.camera_kb(32, 24, 190.0, seed=1, R=R, position=c),
     "kb200": lambda R=None, c=None: synth.camera_kb(40, 24, 200.0, seed=2, R=R, position=c),
 }
-
-
-def adversarial_scene(seed, n=48):
-    """Camera at the origin looking down +z; Gaussians placed where the
-    association is hard."""
-    rng = np.random.default_rng(seed)
-    mu = np.zeros((3, n))
-    s = np.exp(rng.uniform(np.log(0.01), np.log(0.6), (3, n)))
-    kinds = rng.integers(0, 8, n)
-    for g in range(n):
-        k = kinds[g]
-        if k == 0:  # anywhere around the camera, including behind
-            d = rng.normal(size=3)
-            mu[:, g] = d / np.linalg.norm(d) * rng.uniform(0.4, 5.0)
-        elif k == 1:  # straddling the z = 0 plane
-            mu[:, g] = [rng.uniform(-3, 3), rng.uniform(-3, 3), rng.uniform(-0.3, 0.3)]
-        elif k == 2:  # near the camera y axis (theta pencil)
-            mu[:, g] = [rng.normal(0, 0.2), rng.uniform(-3, 3), rng.normal(0, 0.2)]
-        elif k == 3:  # near the camera x axis (phi pencil)
-            mu[:, g] = [rng.uniform(-3, 3), rng.normal(0, 0.2), rng.normal(0, 0.2)]
-        elif k == 4:  # disk: one tiny scale
-            mu[:, g] = [rng.uniform(-2, 2), rng.uniform(-2, 2), rng.uniform(0.5, 4)]
-            s[rng.integers(0, 3), g] = 1e-6 * s[:, g].max()
-        elif k == 5:  # needle: two tiny scales
-            mu[:, g] = [rng.uniform(-2, 2), rng.uniform(-2, 2), rng.uniform(-1, 4)]
-            a = rng.permutation(3)[:2]
-            s[a, g] = 1e-6 * s[:, g].max()
-        elif k == 6:  # camera just outside 3 sigma
-            d = rng.normal(size=3)
-            d /= np.linalg.norm(d)
-            s[:, g] = rng.uniform(0.3, 0.8)
-            mu[:, g] = d * s[0, g] * rng.uniform(3.0, 3.6)
-        else:  # beside the camera, large
-            mu[:, g] = [rng.uniform(-2, 2), rng.uniform(-2, 2), rng.uniform(-2, 2)]
-            s[:, g] = rng.uniform(0.2, 1.0, 3)
-    q = rng.standard_normal((4, n))
-    sig = rng.uniform(0.02, 0.99, n)
-    sh = rng.normal(0, 0.3, (3, n))
-    return synth.Scene(mu.astype(np.float32), s.astype(np.float32), q.astype(np.float32),
-                       sig.astype(np.float32), sh.astype(np.float32), 0)
 
 
 def check_superset(scene, cam, **opts):
