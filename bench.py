@@ -1,0 +1,181 @@
+#!/usr/bin/env python
+"""Throughput of the exact Gaussian ray renderer on one MI355X.
+
+One step = one full forward (preprocess + PBF, association sort, render) of a
+synthetic scene shaped like the forward-only workload: 100,000 Gaussians
+with SH degree 3 in a 20 m box around the camera, an equidistant 180-degree
+fisheye, a 1024 x 1024 BEAP ray grid, 16 x 16 tiles.  Inputs are resident in
+HBM before the timed region; outputs are preallocated.
+
+Printed (one JSON line on stdout):
+  value          rays rendered per second (Mrays/s, whole job)
+  roofline       the render kernel (dominant) against the FP32 VALU peak,
+                 timed with HIP events on its own stream inside the library
+  cpu_baseline   the FP64 oracle on a bounded sample of the same rays,
+                 on the host cores, with the GPU's RGB error on that sample
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s fwd and fwd+bwd vs plain, p50/p99 frame latency, RGB err vs FP64"
+# Render kernel work per evaluated (ray, entry) pair, in FP32 operations of its
+# formulation (FMA = 2): g = G d (15), |g_perp|^2 (3), |g|^2 (2), 1/|g|^2 (1),
+# q (1), exponent and exp2 (3), alpha clamp (1), T(1 - alpha) (2), weight (1),
+# colour (6), depth (4).
+FLOP_PER_PAIR = 39
+# FP32 vector peak without packed FP32 (which the build disables): 256 CUs x
+# 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz.
+PEAK_TFLOPS = 78.6432
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_record(kernel_src):
+    """HBM bytes per render launch from the committed rocprofv3 PMC summary,
+    or None when the kernel source changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "render_fisheye100k_pmc.json")
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    if rec.get("render_src_sha") != source_hash(kernel_src):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-rays", type=int, default=16384, help="oracle sample size (0: skip)")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after timing, copy this many MiB device-to-device once (a plain copy kernel of known "
+                         "size that calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE in the same run)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2505_24053_amd import _lib, renderer, synth
+
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    dev = torch.device("cuda:0")
+    scene_np, cams = synth.workload_fisheye_forward(seed=args.seed)
+    cam = cams[0]
+    W, H = cam["width"], cam["height"]
+    rays = W * H
+    sc = renderer.scene_from_numpy(scene_np, device=dev)
+    out = (torch.empty(3 * rays, device=dev), torch.empty(rays, device=dev), torch.empty(rays, device=dev))
+    torch.cuda.synchronize()
+
+    renderer.set_profiling(True)
+    for _ in range(args.warmup):
+        renderer.render(sc, cams, out=out)
+    torch.cuda.synchronize()
+    renderer.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        renderer.render(sc, cams, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs = renderer.profile_read(max(args.steps, 1))
+    renderer.set_profiling(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = rays / (ms_step * 1e-3) / 1e6
+
+    ms_render = statistics.mean(r["ms_render"] for r in recs)
+    ms_prep = statistics.mean(r["ms_preprocess"] for r in recs)
+    ms_sort = statistics.mean(r["ms_sort"] for r in recs)
+    ms_total = statistics.mean(r["ms_total"] for r in recs)
+    n_eval = recs[-1]["n_evaluated"]
+    n_entries = recs[-1]["n_entries"]
+    achieved = FLOP_PER_PAIR * n_eval / (ms_render * 1e-3) / 1e12
+    _, _, _, frame = renderer.render(sc, cams, keep_frame=True)
+    ranges = frame.export(_lib.BUF_RANGES).astype(np.int64)
+    st = frame.stats()
+    frame.release()
+    per_tile = np.diff(ranges)
+    traffic = traffic_record(os.path.join(ROOT, "paper_2505_24053_amd", "csrc", "render.hip"))
+    roofline = {"kernel": "render_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS, 4),
+                "traffic": traffic, "launch_ms": round(ms_render, 4), "evaluated_pairs": int(n_eval),
+                "flop_per_pair": FLOP_PER_PAIR}
+
+    if args.copy_probe > 0:
+        nb = args.copy_probe << 20
+        src = torch.empty(nb // 4, device=dev)
+        dst = torch.empty(nb // 4, device=dev)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    cpu = None
+    rgb_err = None
+    if args.cpu_rays > 0:
+        import oracle
+
+        threads = len(os.sched_getaffinity(0))
+        if os.environ.get("OMP_NUM_THREADS"):
+            threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+        pix = np.random.default_rng(args.seed + 1).choice(rays, args.cpu_rays, replace=False)
+        oracle.lib()
+        c0 = time.perf_counter()
+        ref = oracle.render(scene_np, cam, pix=pix, nthreads=threads)
+        c1 = time.perf_counter()
+        cpu = {"value": round(args.cpu_rays / (c1 - c0) / 1e6, 6), "unit": "Mrays/s", "cores": threads,
+               "kind": "oracle", "seconds": round(c1 - c0, 2),
+               "sample": "%d seeded random rays of the same 1024x1024 frame, FP64 brute force over all %d "
+                         "Gaussians" % (args.cpu_rays, scene_np.n)}
+        got = out[0].view(3, rays).T[torch.as_tensor(pix, device=dev)].double().cpu().numpy()
+        err = np.abs(got - ref["rgb"]).max(axis=1)
+        okm = ~ref["amb"]
+        rgb_err = {"max_abs_unflagged": float(err[okm].max()), "rays": int(args.cpu_rays),
+                   "flagged_frac": round(float(ref["amb"].mean()), 5),
+                   "flagged_within_bound": bool(np.all(err[~okm] <= 2e-4 + ref["amb_tol"][~okm]))}
+
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "forward_fisheye180_100k_sh3_1024x1024", "gaussians": scene_np.n, "sh_degree": 3,
+                   "camera": "equidistant 180 deg", "beap_grid": [W, H], "tile": 16, "rays": rays},
+        "stages_ms": {"preprocess": round(ms_prep, 4), "sort": round(ms_sort, 4), "render": round(ms_render, 4),
+                      "device_total": round(ms_total, 4)},
+        "association": {"entries": int(n_entries), "visible": int(st["n_visible"]),
+                        "entries_per_tile_mean": round(float(per_tile.mean()), 1),
+                        "entries_per_tile_std": round(float(per_tile.std()), 1)},
+        "rgb_err_vs_fp64": rgb_err,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

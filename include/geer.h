@@ -185,6 +185,29 @@ geer_status geer_valid_mask(const geer_view* view, uint8_t* mask);
 geer_status geer_l1_loss(geer_ctx* ctx, int64_t pixels, const float* rgb, const float* target,
                          const uint8_t* mask, float* dl_drgb, float* loss, void* stream);
 
+/*
+ * Stage timing.  While enabled, every geer_render records HIP events on its
+ * stream around its stages (the preprocess / PBF kernel; the sort, expansion
+ * and ranges; the render kernel) and copies its device counters; up to 64
+ * records are kept, oldest overwritten.  These are the Prep / Dup+Sort /
+ * Render stages of the paper's timing tables.
+ */
+typedef struct {
+  float ms_preprocess; /* stage (a) kernel */
+  float ms_sort;       /* stage (b): depth sort, count scan, expansion, tile sort, ranges */
+  float ms_render;     /* stage (c) render kernel */
+  float ms_total;      /* first event to last, including the host read-back of the list size */
+  int64_t n_entries;   /* association list length */
+  int64_t n_evaluated; /* (ray, entry) pairs evaluated by the render kernel */
+} geer_profile_record;
+
+/* Turns stage timing on (1) or off (0) for the context. */
+geer_status geer_set_profiling(geer_ctx* ctx, int32_t enable);
+/* Copies the most recent min(max, available) records to `out`, oldest
+ * first, and returns how many were copied (negative on error).  Waits for
+ * the recorded work to finish.  Clears the records. */
+int32_t geer_profile_read(geer_ctx* ctx, geer_profile_record* out, int32_t max);
+
 #ifdef __cplusplus
 }
 #endif

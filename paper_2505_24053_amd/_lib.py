@@ -23,7 +23,7 @@ BUF_RECT, BUF_COUNT, BUF_KEY, BUF_LIST, BUF_RANGES, BUF_NLAST = range(6)
 # every symbol include/geer.h declares
 EXPORTS = ["geer_create", "geer_destroy", "geer_last_error", "geer_default_opts", "geer_render",
            "geer_render_backward", "geer_frame_release", "geer_frame_get_stats", "geer_frame_buffer_bytes",
-           "geer_frame_export", "geer_valid_mask", "geer_l1_loss"]
+           "geer_frame_export", "geer_valid_mask", "geer_l1_loss", "geer_set_profiling", "geer_profile_read"]
 
 
 class GeerView(C.Structure):
@@ -48,6 +48,11 @@ class GeerFrameStats(C.Structure):
     _fields_ = [("n_items", C.c_int64), ("n_visible", C.c_int64), ("n_entries", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_pixels", C.c_int64), ("n_evaluated", C.c_int64),
                 ("n_composited", C.c_int64)]
+
+
+class GeerProfileRecord(C.Structure):
+    _fields_ = [("ms_preprocess", C.c_float), ("ms_sort", C.c_float), ("ms_render", C.c_float),
+                ("ms_total", C.c_float), ("n_entries", C.c_int64), ("n_evaluated", C.c_int64)]
 
 
 class GeerError(RuntimeError):
@@ -87,6 +92,9 @@ def load():
         L.geer_frame_export.argtypes = [V, C.c_int32, V, C.c_int64]
         L.geer_valid_mask.argtypes = [P(GeerView), V]
         L.geer_l1_loss.argtypes = [V, C.c_int64, V, V, V, V, V, V]
+        L.geer_set_profiling.argtypes = [V, C.c_int32]
+        L.geer_profile_read.argtypes = [V, P(GeerProfileRecord), C.c_int32]
+        L.geer_profile_read.restype = C.c_int32
         _lib = L
         return L
 

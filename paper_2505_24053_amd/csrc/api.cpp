@@ -29,8 +29,16 @@ struct Block {
 
 }  // namespace
 
+struct ProfSlot {
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  uint64_t* host_stats = nullptr;  // pinned copy of the frame's device counters
+};
+
 struct geer_ctx {
   int device = 0;
+  bool profiling = false;
+  std::vector<ProfSlot> prof;  // ring of stage-timing records
+  int prof_next = 0, prof_count = 0;
   std::mutex mu;
   std::vector<Block> cache;  // released device blocks, reusable on the same stream
   std::string err;
@@ -193,6 +201,18 @@ void free_frame_buffers(geer_frame* f) {
     release(c, *b);
 }
 
+ProfSlot* prof_slot(geer_ctx* c) {
+  if (!c->profiling || c->prof.empty()) return nullptr;
+  ProfSlot* s = &c->prof[c->prof_next];
+  c->prof_next = (c->prof_next + 1) % (int)c->prof.size();
+  c->prof_count = std::min<int>(c->prof_count + 1, (int)c->prof.size());
+  return s;
+}
+
+void prof_mark(ProfSlot* s, int i, hipStream_t st) {
+  if (s) (void)hipEventRecord(s->ev[i], st);
+}
+
 int bytes_for_tiles(int64_t max_tile) {
   int passes = 0;
   while (max_tile > 0) {
@@ -237,6 +257,11 @@ void geer_destroy(geer_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (auto& b : c->cache) (void)hipFree(b.p);
+  for (auto& ps : c->prof) {
+    for (auto& e : ps.ev)
+      if (e) (void)hipEventDestroy(e);
+    if (ps.host_stats) (void)hipHostFree(ps.host_stats);
+  }
   if (c->lam_dev) (void)hipFree(c->lam_dev);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
@@ -362,10 +387,13 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   TRY(acquire(c, 64, st, f->stats));  // [0] entries, [1] visible, [2] evaluated, [3] spare
   uint64_t* d_stats = (uint64_t*)f->stats.p;
   launch_fill_u32(st, (uint32_t*)d_stats, 8, 0u);
+  ProfSlot* ps = prof_slot(c);
+  prof_mark(ps, 0, st);
   launch_preprocess(st, n, n_views, scene->sh_degree, scene->mean, scene->scale, scene->quat, scene->opacity,
                     scene->sh, d_views, op, c->lam_dev, d_edges, (Record*)f->recs.p, (uint2*)f->rects.p,
                     (uint32_t*)f->keys.p, (uint32_t*)f->counts.p, (unsigned long long*)d_stats);
   HTRY(hipGetLastError());
+  prof_mark(ps, 1, st);
   HTRY(hipMemcpyAsync(c->pinned, d_stats, 16, hipMemcpyDeviceToHost, st));
   HTRY(hipStreamSynchronize(st));
   uint64_t totals[2];
@@ -392,6 +420,7 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   TRY(acquire(c, 4 * (e1 + 8), st, f->list));
   TRY(acquire(c, 4 * (e1 + 8), st, items_b));
   TRY(acquire(c, 4 * (ntiles + 1), st, f->ranges));
+  prof_mark(ps, 2, st);
   uint32_t* H = (uint32_t*)hist.p;
   uint32_t* SC = (uint32_t*)scratch.p;
   if (nvis > 0) {
@@ -438,11 +467,14 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
     TRY(acquire(c, 4 * npix, st, f->nlast));
     TRY(acquire(c, 4 * npix, st, f->tfinal));
   }
+  prof_mark(ps, 3, st);
   launch_render(st, op.lambda_mode == 1, ntiles, d_views, n_views, d_dtab, (const uint32_t*)f->ranges.p,
                 (const uint32_t*)f->list.p, (const uint2*)f->rects.p, (const Record*)f->recs.p, op, rgb, depth,
                 trans, keep ? (uint32_t*)f->nlast.p : nullptr, keep ? (float*)f->tfinal.p : nullptr,
                 (unsigned long long*)(d_stats + 2));
   HTRY(hipGetLastError());
+  prof_mark(ps, 4, st);
+  if (ps) HTRY(hipMemcpyAsync(ps->host_stats, d_stats, 32, hipMemcpyDeviceToHost, st));
   cleanup(GEER_OK);
   if (keep) {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -528,6 +560,48 @@ geer_status geer_frame_export(const geer_frame* f, int32_t which, void* dst, int
   HIP_TRY(c, hipMemcpyAsync(dst, b->p, (size_t)need, hipMemcpyDeviceToHost, f->stream));
   HIP_TRY(c, hipStreamSynchronize(f->stream));
   return GEER_OK;
+}
+
+geer_status geer_set_profiling(geer_ctx* c, int32_t enable) {
+  if (!c) return GEER_ERR_INVALID_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (enable && c->prof.empty()) {
+    c->prof.resize(64);
+    for (auto& ps : c->prof) {
+      for (auto& e : ps.ev) HIP_TRY(c, hipEventCreate(&e));
+      HIP_TRY(c, hipHostMalloc((void**)&ps.host_stats, 32, hipHostMallocDefault));
+    }
+  }
+  c->profiling = enable != 0;
+  c->prof_next = 0;
+  c->prof_count = 0;
+  return GEER_OK;
+}
+
+int32_t geer_profile_read(geer_ctx* c, geer_profile_record* out, int32_t max) {
+  if (!c || !out || max < 0) return -GEER_ERR_INVALID_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return -GEER_ERR_HIP;
+  int n = std::min<int>(max, c->prof_count);
+  int size = (int)c->prof.size();
+  for (int i = 0; i < n; ++i) {
+    // oldest of the last n records first
+    int idx = ((c->prof_next - n + i) % size + size) % size;
+    ProfSlot& ps = c->prof[idx];
+    if (hipEventSynchronize(ps.ev[4]) != hipSuccess) return -GEER_ERR_HIP;
+    float t01 = 0, t23 = 0, t34 = 0, t04 = 0;
+    (void)hipEventElapsedTime(&t01, ps.ev[0], ps.ev[1]);
+    (void)hipEventElapsedTime(&t23, ps.ev[2], ps.ev[3]);
+    (void)hipEventElapsedTime(&t34, ps.ev[3], ps.ev[4]);
+    (void)hipEventElapsedTime(&t04, ps.ev[0], ps.ev[4]);
+    out[i].ms_preprocess = t01;
+    out[i].ms_sort = t23;
+    out[i].ms_render = t34;
+    out[i].ms_total = t04;
+    out[i].n_entries = (int64_t)ps.host_stats[0];
+    out[i].n_evaluated = (int64_t)ps.host_stats[2];
+  }
+  c->prof_count = 0;
+  return n;
 }
 
 geer_status geer_valid_mask(const geer_view* v, uint8_t* mask) {

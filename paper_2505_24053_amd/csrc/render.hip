@@ -2,12 +2,14 @@
 // with the closed-form ray opacity alpha = sigma exp(-kappa/2).
 //
 // Mapping: one 256-lane workgroup per 16x16 tile (camera sub-frustum), one
-// wave64 per 8x8 half-tile, one lane per ray.  Each wave walks its tile's
-// depth-ordered list on its own: the list index, the Gaussian's rectangle and
-// its 64-byte record are wave-uniform (scalar loads into SGPRs, used directly
-// as VALU operands), entries whose rectangle misses the wave's half-tile are
-// skipped with a scalar branch, and the wave leaves the loop as soon as all of
-// its rays have terminated.  No LDS, no barriers.
+// wave64 per 8x8 half-tile, one lane per ray.  The workgroup walks its tile's
+// depth-ordered list in batches of 256 entries: each lane fetches one entry's
+// 64-byte record (vector loads, the next batch prefetched into registers
+// while the current one blends) and stages it in LDS; wave ballots publish,
+// per half-tile, which staged entries its rectangle meets.  Each wave then
+// visits only its own hits, reading records from LDS as broadcasts, and skips
+// the batch entirely once all of its rays have terminated; the tile stops
+// when all four waves have.
 //
 // Per pair, kappa = |o_u x d_u|^2 / |d_u|^2 is evaluated in a canonical frame
 // rotated so that o_u lies on its third axis (the canonical Gaussian is
@@ -59,6 +61,8 @@ __device__ __forceinline__ void blend_one(const Record& R, bool enable, float dx
   last = blend ? e + 1 : last;
 }
 
+constexpr int kBatch = 256;  // list entries staged per workgroup pass (one per lane)
+
 template <bool kFixed>
 __global__ __launch_bounds__(256) void render_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
@@ -66,18 +70,22 @@ __global__ __launch_bounds__(256) void render_kernel(
     const Record* __restrict__ recs, Opts op, float* __restrict__ rgb, float* __restrict__ depth,
     float* __restrict__ trans, uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
     unsigned long long* __restrict__ stats) {
+  __shared__ float4 s_rec[kBatch][4];     // 16 KB of records, one batch
+  __shared__ uint64_t s_hit[4][kBatch / 64];  // per half-tile: which staged entries meet it
+
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   int v = 0;
   while (v + 1 < nviews && tile >= views[v + 1].tile_base) ++v;
   const ViewDev& V = views[v];
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
   const int hx = 2 * tx + (wv & 1), hy = 2 * ty + (wv >> 1);
-  if (hx >= V.nhx || hy >= V.nhy) return;  // half-tile outside a ragged image
+  const bool wave_live = hx < V.nhx && hy < V.nhy;  // half-tile inside a ragged image
   const int px = hx * kHalf + (lane & 7), py = hy * kHalf + (lane >> 3);
-  const bool valid = px < V.width && py < V.height;
+  const bool valid = wave_live && px < V.width && py < V.height;
 
   const float2 cth = dtab[V.dx_off + min(px, V.width - 1)];  // (sin, cos) theta
   const float2 cph = dtab[V.dy_off + min(py, V.height - 1)]; // (sin, cos) phi
@@ -90,43 +98,61 @@ __global__ __launch_bounds__(256) void render_kernel(
   uint32_t last = start;
   uint64_t evals = 0;
   bool done = !valid;
-  const uint32_t hxu = (uint32_t)hx, hyu = (uint32_t)hy;
+  // the four half-tiles of this tile, for the per-entry hit bits
+  const uint32_t hx0 = 2u * tx, hy0 = 2u * ty;
 
-  // Batches of 8 list entries from an 8-aligned base (the list is padded with
-  // a valid id): 8 ids -> 8 rectangles (all loads in flight together) -> mask
-  // of entries meeting this half-tile -> their records two at a time, both
-  // scalar loads issued before the single wait.
-  for (uint32_t base = start & ~7u; base < end; base += 8) {
-    const uint4 i0 = *reinterpret_cast<const uint4*>(list + base);
-    const uint4 i1 = *reinterpret_cast<const uint4*>(list + base + 4);
-    const uint32_t ids[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
-    uint2 rc[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) rc[k] = rects[ids[k]];
-    uint32_t mask = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const bool hit = (hxu >= (rc[k].x & 0xffffu)) & (hxu <= (rc[k].x >> 16)) & (hyu >= (rc[k].y & 0xffffu)) &
-                       (hyu <= (rc[k].y >> 16));
-      mask |= (uint32_t)hit << k;
+  // Prefetch of one batch into registers: entry start + k goes to lane k.
+  float4 p0, p1, p2, p3;
+  uint2 prc;
+  auto fetch = [&](uint32_t b) {
+    const uint32_t e = b + tid;
+    if (e < end) {
+      const uint32_t item = list[e];
+      prc = rects[item];
+      const float4* r = reinterpret_cast<const float4*>(recs + item);
+      p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
+    } else {
+      prc = make_uint2(1u, 0u);  // empty rectangle: meets no half-tile
     }
-    const uint32_t lo = start > base ? start - base : 0u;
-    const uint32_t hi = end - base < 8u ? end - base : 8u;
-    mask &= (0xffu << lo) & (0xffu >> (8u - hi));
-    while (mask) {
-      const int k0 = __builtin_ctz(mask);
-      mask &= mask - 1;
-      const bool two = mask != 0;
-      const int k1 = two ? __builtin_ctz(mask) : k0;
-      mask &= two ? mask - 1 : mask;
-      const Record R0 = recs[ids[k0]];
-      const Record R1 = recs[ids[k1]];
-      evals += (uint64_t)__popcll(__ballot(!done));
-      blend_one<kFixed>(R0, true, dx, dy, dz, op, base + k0, done, T, cr, cg, cb, D, last);
-      if (two) evals += (uint64_t)__popcll(__ballot(!done));
-      blend_one<kFixed>(R1, two, dx, dy, dz, op, base + k1, done, T, cr, cg, cb, D, last);
+  };
+  if (start < end) fetch(start);
+
+  for (uint32_t base = start; base < end; base += kBatch) {
+    // stage the prefetched batch (the barrier closing the previous pass made
+    // the LDS free) and publish each half-tile's hit mask
+    s_rec[tid][0] = p0; s_rec[tid][1] = p1; s_rec[tid][2] = p2; s_rec[tid][3] = p3;
+    const uint32_t rx0 = prc.x & 0xffffu, rx1 = prc.x >> 16, ry0 = prc.y & 0xffffu, ry1 = prc.y >> 16;
+    const bool cx0 = rx0 <= hx0 && hx0 <= rx1, cx1 = rx0 <= hx0 + 1 && hx0 + 1 <= rx1;
+    const bool cy0 = ry0 <= hy0 && hy0 <= ry1, cy1 = ry0 <= hy0 + 1 && hy0 + 1 <= ry1;
+    const uint64_t b00 = __ballot(cx0 && cy0), b10 = __ballot(cx1 && cy0);
+    const uint64_t b01 = __ballot(cx0 && cy1), b11 = __ballot(cx1 && cy1);
+    if (lane == 0) {
+      s_hit[0][wv] = b00; s_hit[1][wv] = b10; s_hit[2][wv] = b01; s_hit[3][wv] = b11;
     }
-    if (__ballot(!done) == 0) break;
+    if (base + kBatch < end) fetch(base + kBatch);  // in flight while this batch blends
+    __syncthreads();
+    if (__ballot(!done) != 0) {
+      const uint32_t nb = min((uint32_t)kBatch, end - base);
+#pragma unroll
+      for (int g = 0; g < kBatch / 64; ++g) {
+        if ((uint32_t)(g * 64) >= nb) break;
+        const uint64_t mv = s_hit[wv][g];  // same value in every lane: move it to SGPRs
+        // (readfirstlane returns int: go through uint32_t so nothing sign-extends)
+        uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32)) << 32) |
+                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mv);
+        while (m) {
+          const int k = g * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          Record R;
+          float4* rr = reinterpret_cast<float4*>(&R);
+          rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
+          evals += (uint64_t)__popcll(__ballot(!done));
+          blend_one<kFixed>(R, true, dx, dy, dz, op, base + k, done, T, cr, cg, cb, D, last);
+        }
+      }
+    }
+    // every wave done -> the whole tile is done; the barrier also frees the LDS
+    if (__syncthreads_and(done ? 1 : 0)) break;
   }
 
   if (valid) {
@@ -142,7 +168,7 @@ __global__ __launch_bounds__(256) void render_kernel(
     if (nlast) nlast[gp] = last;
     if (tfinal) tfinal[gp] = T;
   }
-  if (stats && lane == 0) atomicAdd(&stats[0], (unsigned long long)evals);
+  if (stats && lane == 0 && evals) atomicAdd(&stats[0], (unsigned long long)evals);
 }
 
 void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const ViewDev* views, int nviews,

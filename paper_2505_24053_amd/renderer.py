@@ -27,6 +27,19 @@ def context(device: int = 0):
     return _contexts[device]
 
 
+def set_profiling(enable: bool, device: int = 0):
+    _lib.check(_lib.load().geer_set_profiling(context(device), 1 if enable else 0), context(device))
+
+
+def profile_read(max_records: int = 64, device: int = 0):
+    """Stage timings of the most recent renders (oldest first)."""
+    recs = (_lib.GeerProfileRecord * max_records)()
+    n = _lib.load().geer_profile_read(context(device), recs, max_records)
+    if n < 0:
+        raise _lib.GeerError(-n, "profile read failed")
+    return [{k: getattr(recs[i], k) for k, _ in _lib.GeerProfileRecord._fields_} for i in range(n)]
+
+
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 

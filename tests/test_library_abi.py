@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "geer.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:geer_status|void|const char\*|int64_t)\s+(geer_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:geer_status|void|const char\*|int64_t|int32_t)\s+(geer_\w+)\s*\(", src, re.M)))
 
 
 @pytest.fixture(scope="module")
