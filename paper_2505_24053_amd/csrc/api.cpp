@@ -57,6 +57,7 @@ struct geer_frame {
   Opts op{};
   int32_t nviews = 0;
   int64_t n = 0, items = 0, ntiles = 0, npix = 0, entries = 0, visible = 0;
+  size_t edges_off = 0, dtab_off = 0;  // sub-buffers of meta
   std::vector<geer_view> views;
   std::vector<ViewDev> hviews;
   Block meta, recs, rects, keys, counts, list, ranges, nlast, tfinal, stats;
@@ -374,6 +375,8 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   std::memcpy((char*)c->pinned + edges_off, edges.data(), edges.size() * sizeof(float));
   std::memcpy((char*)c->pinned + dtab_off, dtab.data(), dtab.size() * sizeof(float));
   HTRY(hipMemcpyAsync(f->meta.p, c->pinned, meta_bytes, hipMemcpyHostToDevice, st));
+  f->edges_off = edges_off;
+  f->dtab_off = dtab_off;
   const ViewDev* d_views = (const ViewDev*)f->meta.p;
   const float* d_edges = (const float*)((char*)f->meta.p + edges_off);
   const float2* d_dtab = (const float2*)((char*)f->meta.p + dtab_off);
@@ -492,9 +495,35 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
 geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* dl_drgb, float* g_mean,
                                  float* g_scale, float* g_quat, float* g_opacity, float* g_sh, int32_t accumulate,
                                  void* stream) {
-  (void)f; (void)dl_drgb; (void)g_mean; (void)g_scale; (void)g_quat; (void)g_opacity; (void)g_sh;
-  (void)accumulate; (void)stream;
-  return fail(c, GEER_ERR_UNSUPPORTED, "backward not built yet");
+  if (!c) return GEER_ERR_INVALID_ARG;
+  if (!f || f->ctx != c) return fail(c, GEER_ERR_INVALID_ARG, "frame missing or from another context");
+  if (!dl_drgb) return fail(c, GEER_ERR_INVALID_ARG, "null dL/dRGB");
+  if (f->n > 0 && (!g_mean || !g_scale || !g_quat || !g_opacity || !g_sh))
+    return fail(c, GEER_ERR_INVALID_ARG, "null gradient array");
+  if (!f->nlast.p || !f->tfinal.p) return fail(c, GEER_ERR_INVALID_ARG, "frame holds no forward state");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if ((f->op.lambda_mode == 0) && (!c->lam_dev || c->lam_amin != f->op.alpha_min)) {
+    geer_status s = lambda_dev(c, f->op.alpha_min, st);
+    if (s != GEER_OK) return s;
+  }
+  Block acc;
+  geer_status s = acquire(c, sizeof(float) * 16 * (size_t)std::max<int64_t>(f->items, 1), st, acc);
+  if (s != GEER_OK) return s;
+  const char* meta = (const char*)f->meta.p;
+  const ViewDev* d_views = (const ViewDev*)meta;
+  const float* d_edges = (const float*)(meta + f->edges_off);
+  const float2* d_dtab = (const float2*)(meta + f->dtab_off);
+  const geer_scene& sc = f->scene;
+  launch_backward(st, f->op.lambda_mode == 1, f->ntiles, f->n, f->nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat,
+                  sc.opacity, sc.sh, d_views, d_dtab, d_edges, c->lam_dev, f->op, (const uint32_t*)f->ranges.p,
+                  (const uint32_t*)f->list.p, (const uint2*)f->rects.p, (const Record*)f->recs.p,
+                  (const uint32_t*)f->nlast.p, (const float*)f->tfinal.p, dl_drgb, (float*)acc.p, accumulate != 0,
+                  g_mean, g_scale, g_quat, g_opacity, g_sh);
+  hipError_t e = hipGetLastError();
+  release(c, acc);
+  if (e != hipSuccess) return fail(c, GEER_ERR_HIP, "backward launch: %s", hipGetErrorString(e));
+  return GEER_OK;
 }
 
 void geer_frame_release(geer_frame* f) {
@@ -614,8 +643,22 @@ geer_status geer_valid_mask(const geer_view* v, uint8_t* mask) {
 
 geer_status geer_l1_loss(geer_ctx* c, int64_t pixels, const float* rgb, const float* target, const uint8_t* mask,
                          float* dl_drgb, float* loss, void* stream) {
-  (void)pixels; (void)rgb; (void)target; (void)mask; (void)dl_drgb; (void)loss; (void)stream;
-  return fail(c, GEER_ERR_UNSUPPORTED, "loss not built yet");
+  if (!c) return GEER_ERR_INVALID_ARG;
+  if (pixels < 0 || (pixels > 0 && (!rgb || !target || !mask || !dl_drgb)) || !loss)
+    return fail(c, GEER_ERR_INVALID_ARG, "bad loss arguments");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(c, hipSetDevice(c->device));
+  Block scratch;
+  const int64_t nb = l1_partial_count(pixels);
+  geer_status s = acquire(c, sizeof(float2) * (size_t)(nb + 1) + 16, st, scratch);
+  if (s != GEER_OK) return s;
+  float2* partial = (float2*)scratch.p;
+  float* scale = (float*)(partial + nb + 1);
+  launch_l1(st, pixels, rgb, target, mask, dl_drgb, loss, partial, scale);
+  hipError_t e = hipGetLastError();
+  release(c, scratch);
+  if (e != hipSuccess) return fail(c, GEER_ERR_HIP, "loss launch: %s", hipGetErrorString(e));
+  return GEER_OK;
 }
 
 }  // extern "C"

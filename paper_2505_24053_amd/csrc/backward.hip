@@ -1,0 +1,378 @@
+// Gradient of the render (App. C, two-stage propagation).
+//
+// Render backward (ray-wise, "RenderCUDA" stage): one workgroup per tile, the
+// same 256-entry LDS batches as the forward but walked back to front from
+// each ray's saved final transmittance and last blended entry.  A pair is
+// replayed only if the forward blended it (same rectangle skip, same
+// evaluation functions, bit-identical decisions); the transmittance before it
+// is recovered as T / (1 - alpha) (no per-sample state is stored).  Per pair:
+//   dL/dc     = alpha T G,           dL/dalpha = T (c - C_behind) . G,
+//   dL/dkappa = -alpha / 2 dL/dalpha,
+// and, in the canonical frame rotated so that o_u = (0, 0, r) (u' = Q Wc d,
+// g = r (u'x, u'y, -u'z), ss = |g|^2, mm = gx^2 + gy^2), the corrected-sign
+// chain  dkappa/do_u = d_u x g_m,  dkappa/dd_u = -(2 kappa/|d_u|^2) d_u
+// + g_m x o_u  (g_m = 2 m_u / |d_u|^2, m_u = o_u x d_u) reads
+//   dkappa/do_u' = (2 r / ss) (gx gz, gy gz, mm),
+//   dkappa/du'   = (2 r / ss) (r^2 / ss) (gz^2 gx, gz^2 gy, mm gz).
+// Each wave reduces its 16 per-pair partials (dlog sigma, dc[3], do_u'[3],
+// du' d^T [9]) with a value-splitting butterfly (17 shuffles) and 16 lanes
+// add them to the item's accumulator.
+//
+// Preprocess backward (Gaussian-wise, "PreprocessCUDA" stage): one lane per
+// Gaussian, summing over views: dWc = Q^T dP', do_u = Q^T do_u';
+// dW = dWc Rc + do_u (o - mu)^T (Eq. b9), dmu = -W^T do_u (mean gradient) plus
+// the SH view-direction term; ds_k = -sum_j dW_kj R_jk / s_k^2 (Eq. scaling);
+// dq through the four dW/dq matrices (Eq. rotation) and the normalisation.
+#include <hip/hip_runtime.h>
+
+#include "geer_common.h"
+#include "geer_device.h"
+
+namespace geer {
+
+constexpr int kBatchB = 256;
+constexpr int kAcc = 16;  // accumulator floats per (Gaussian, view) item
+
+// Sum v[0..15] over the wave; lanes with (lane & 3) == 0 end up holding the
+// total of value index idx and add it to dst[idx].
+__device__ __forceinline__ void wave_reduce16_add(const float v[16], float* __restrict__ dst) {
+  const int lane = threadIdx.x & 63;
+  const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8, h4 = lane & 4;
+  float a8[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float send = h32 ? v[j] : v[8 + j];
+    const float keep = h32 ? v[8 + j] : v[j];
+    a8[j] = keep + __shfl_xor(send, 32);
+  }
+  float a4[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float send = h16 ? a8[j] : a8[4 + j];
+    const float keep = h16 ? a8[4 + j] : a8[j];
+    a4[j] = keep + __shfl_xor(send, 16);
+  }
+  float a2[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float send = h8 ? a4[j] : a4[2 + j];
+    const float keep = h8 ? a4[2 + j] : a4[j];
+    a2[j] = keep + __shfl_xor(send, 8);
+  }
+  float a1 = (h4 ? a2[1] : a2[0]) + __shfl_xor(h4 ? a2[0] : a2[1], 4);
+  a1 += __shfl_xor(a1, 2);
+  a1 += __shfl_xor(a1, 1);
+  const int idx = (h32 ? 8 : 0) + (h16 ? 4 : 0) + (h8 ? 2 : 0) + (h4 ? 1 : 0);
+  if ((lane & 3) == 0 && a1 != 0.0f) unsafeAtomicAdd(dst + idx, a1);
+}
+
+template <bool kFixed>
+__global__ __launch_bounds__(256) void render_backward_kernel(
+    const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
+    const Record* __restrict__ recs, Opts op, const uint32_t* __restrict__ nlast, const float* __restrict__ tfinal,
+    const float* __restrict__ dl_drgb, float* __restrict__ acc) {
+  __shared__ float4 s_rec[kBatchB][4];
+  __shared__ uint32_t s_item[kBatchB];
+  __shared__ uint64_t s_hit[4][kBatchB / 64];
+  __shared__ uint32_t s_last[4];
+
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  int v = 0;
+  while (v + 1 < nviews && tile >= views[v + 1].tile_base) ++v;
+  const ViewDev& V = views[v];
+  const int lt = tile - V.tile_base;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int tid = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int hx = 2 * tx + (wv & 1), hy = 2 * ty + (wv >> 1);
+  const bool wave_live = hx < V.nhx && hy < V.nhy;
+  const int px = hx * kHalf + (lane & 7), py = hy * kHalf + (lane >> 3);
+  const bool valid = wave_live && px < V.width && py < V.height;
+  float dx, dy, dz;
+  pixel_direction(V, dtab, px, py, dx, dy, dz);
+
+  const uint32_t start = ranges[tile];
+  const int64_t hw = (int64_t)V.width * V.height;
+  const int64_t p = (int64_t)py * V.width + px;
+  const int64_t gp = (int64_t)V.pix_base + p;
+  float T = 1.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
+  uint32_t last = start;
+  if (valid) {
+    T = tfinal[gp];
+    last = nlast[gp];
+    const float* g = dl_drgb + 3 * (int64_t)V.pix_base;
+    G0 = g[p];
+    G1 = g[hw + p];
+    G2 = g[2 * hw + p];
+  }
+  float cb0 = 0.0f, cb1 = 0.0f, cb2 = 0.0f;  // colour of everything behind, as seen just in front of it
+
+  // the tile's replay range is [start, max over its rays of last)
+  uint32_t wmax = last;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, off));
+  if (lane == 0) s_last[wv] = wmax;
+  __syncthreads();
+  const uint32_t top = max(max(s_last[0], s_last[1]), max(s_last[2], s_last[3]));
+
+  float4 p0, p1, p2, p3;
+  uint2 prc;
+  uint32_t pitem = 0;
+  auto fetch = [&](uint32_t b, uint32_t e_end) {
+    const uint32_t e = b + tid;
+    if (e < e_end) {
+      pitem = list[e];
+      prc = rects[pitem];
+      const float4* r = reinterpret_cast<const float4*>(recs + pitem);
+      p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
+    } else {
+      prc = make_uint2(1u, 0u);
+    }
+  };
+  const uint32_t hx0 = 2u * tx, hy0 = 2u * ty;
+  uint32_t bend = top;
+  uint32_t bbase = bend > start + kBatchB ? bend - kBatchB : start;
+  if (start < top) fetch(bbase, bend);
+
+  while (bend > start) {
+    s_rec[tid][0] = p0; s_rec[tid][1] = p1; s_rec[tid][2] = p2; s_rec[tid][3] = p3;
+    s_item[tid] = pitem;
+    const uint32_t rx0 = prc.x & 0xffffu, rx1 = prc.x >> 16, ry0 = prc.y & 0xffffu, ry1 = prc.y >> 16;
+    const bool cx0 = rx0 <= hx0 && hx0 <= rx1, cx1 = rx0 <= hx0 + 1 && hx0 + 1 <= rx1;
+    const bool cy0 = ry0 <= hy0 && hy0 <= ry1, cy1 = ry0 <= hy0 + 1 && hy0 + 1 <= ry1;
+    const uint64_t b00 = __ballot(cx0 && cy0), b10 = __ballot(cx1 && cy0);
+    const uint64_t b01 = __ballot(cx0 && cy1), b11 = __ballot(cx1 && cy1);
+    if (lane == 0) {
+      s_hit[0][wv] = b00; s_hit[1][wv] = b10; s_hit[2][wv] = b01; s_hit[3][wv] = b11;
+    }
+    const uint32_t base = bbase;
+    const uint32_t nb = bend - bbase;
+    // prefetch the batch in front of this one
+    bend = bbase;
+    bbase = bend > start + kBatchB ? bend - kBatchB : start;
+    if (bend > start) fetch(bbase, bend);
+    __syncthreads();
+    if (__ballot(valid && last > base) != 0) {
+      for (int g = (int)((nb + 63) / 64) - 1; g >= 0; --g) {
+        const uint64_t mv = s_hit[wv][g];
+        uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32)) << 32) |
+                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mv);
+        if (g == (int)((nb - 1) / 64)) m &= (nb % 64 == 0) ? ~0ull : ((1ull << (nb % 64)) - 1);
+        while (m) {
+          const int bit = 63 - __builtin_clzll(m);
+          m &= ~(1ull << bit);
+          const int k = g * 64 + bit;
+          const uint32_t e = base + (uint32_t)k;
+          Record R;
+          float4* rr = reinterpret_cast<float4*>(&R);
+          rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
+          const PairEval E = eval_pair(R, dx, dy, dz);
+          const bool on = valid & (e < last) & pair_contributes<kFixed>(R, E, op);
+          if (__ballot(on) == 0) continue;
+          const float a = clamp_alpha(E.a_raw, op);
+          const bool clamped = !(E.a_raw < op.alpha_max);
+          const float Tb = on ? T / (1.0f - a) : T;  // transmittance in front of this Gaussian
+          const float w = on ? a * Tb : 0.0f;
+          float part[kAcc];
+          part[1] = w * G0;
+          part[2] = w * G1;
+          part[3] = w * G2;
+          const float dla = on ? Tb * ((R.rgb[0] - cb0) * G0 + (R.rgb[1] - cb1) * G1 + (R.rgb[2] - cb2) * G2) : 0.0f;
+          cb0 = on ? fmaf(a, R.rgb[0] - cb0, cb0) : cb0;
+          cb1 = on ? fmaf(a, R.rgb[1] - cb1, cb1) : cb1;
+          cb2 = on ? fmaf(a, R.rgb[2] - cb2, cb2) : cb2;
+          T = Tb;
+          const float dlk = clamped ? 0.0f : -0.5f * a * dla;  // dL/dkappa
+          part[0] = clamped ? 0.0f : dla * a;                  // dL/dlog(sigma)
+          const float r = sqrtf(R.c1);
+          const float f = 2.0f * r * E.inv * dlk;               // dL/dkappa * 2 r / ss
+          part[4] = f * E.gx * E.gz;
+          part[5] = f * E.gy * E.gz;
+          part[6] = f * E.mm;
+          const float h = f * (R.c1 * E.inv);
+          const float gz2 = E.gz * E.gz;
+          const float du0 = h * gz2 * E.gx, du1 = h * gz2 * E.gy, du2 = h * E.mm * E.gz;
+          part[7] = du0 * dx; part[8] = du0 * dy; part[9] = du0 * dz;
+          part[10] = du1 * dx; part[11] = du1 * dy; part[12] = du1 * dz;
+          part[13] = du2 * dx; part[14] = du2 * dy; part[15] = du2 * dz;
+          wave_reduce16_add(part, acc + (int64_t)s_item[k] * kAcc);
+        }
+      }
+    }
+    __syncthreads();  // the next pass overwrites the staged batch
+  }
+}
+
+// ------------------------------------------------------------------------
+// Gaussian-wise stage
+
+template <int kDeg>
+__global__ __launch_bounds__(256) void preprocess_backward_kernel(
+    int64_t n, int32_t n_views, const float* __restrict__ mean, const float* __restrict__ scale,
+    const float* __restrict__ quat, const float* __restrict__ opacity, const float* __restrict__ sh,
+    const ViewDev* __restrict__ views, Opts op, const float* __restrict__ lam_tab, const float* __restrict__ edges,
+    const float* __restrict__ acc, int accumulate, float* __restrict__ g_mean, float* __restrict__ g_scale,
+    float* __restrict__ g_quat, float* __restrict__ g_opacity, float* __restrict__ g_sh) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const float mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
+  const float s[3] = {scale[g], scale[n + g], scale[2 * n + g]};
+  const float q[4] = {quat[g], quat[n + g], quat[2 * n + g], quat[3 * n + g]};
+  const float sigma = opacity[g];
+  constexpr int K = (kDeg + 1) * (kDeg + 1);
+  float dmu[3] = {0, 0, 0}, dW[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dsig = 0.0f;
+  float dsh[K * 3];
+#pragma unroll
+  for (int i = 0; i < K * 3; ++i) dsh[i] = 0.0f;
+  float R[9], qh[4] = {1, 0, 0, 0}, qn = 1.0f;
+  bool any = false;
+  for (int v = 0; v < n_views; ++v) {
+    const int64_t item = (int64_t)v * n + g;
+    const float4* ap = reinterpret_cast<const float4*>(acc + item * kAcc);
+    const float4 A0 = ap[0], A1 = ap[1], A2 = ap[2], A3 = ap[3];
+    const float a[16] = {A0.x, A0.y, A0.z, A0.w, A1.x, A1.y, A1.z, A1.w,
+                         A2.x, A2.y, A2.z, A2.w, A3.x, A3.y, A3.z, A3.w};
+    bool nz = false;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) nz |= a[i] != 0.0f;
+    if (!nz) continue;
+    const ViewDev& Vw = views[v];
+    AssocOut As;
+    associate(mu, s, q, sigma, Vw, op, lam_tab, edges, As);
+    Frame3 F;
+    canonical_frame(As, s, F);
+    any = true;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = As.R[i];
+    qh[0] = As.qh[0]; qh[1] = As.qh[1]; qh[2] = As.qh[2]; qh[3] = As.qh[3];
+    qn = As.qn;
+    const float* Q0 = F.e1;
+    const float* Q1 = F.e2;
+    const float* Q2 = F.nn;
+    // dWc = Q^T dP',  do_u = Q^T do_u'
+    float dWc[9], dou[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dWc[k * 3 + i] = Q0[k] * a[7 + i] + Q1[k] * a[10 + i] + Q2[k] * a[13 + i];
+      dou[k] = Q0[k] * a[4] + Q1[k] * a[5] + Q2[k] * a[6];
+    }
+    // Wc = W Rc^T  =>  dW += dWc Rc ;  o_u = W (o - mu)  =>  dW += do_u (o - mu)^T
+    const float om[3] = {Vw.campos[0] - mu[0], Vw.campos[1] - mu[1], Vw.campos[2] - mu[2]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        dW[k * 3 + j] += dWc[k * 3 + 0] * Vw.Rc[0 * 3 + j] + dWc[k * 3 + 1] * Vw.Rc[1 * 3 + j] +
+                         dWc[k * 3 + 2] * Vw.Rc[2 * 3 + j] + dou[k] * om[j];
+    // dmu = -W^T do_u, W[k][j] = R[j][k] / s_k
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      dmu[j] -= R[j * 3 + 0] / s[0] * dou[0] + R[j * 3 + 1] / s[1] * dou[1] + R[j * 3 + 2] / s[2] * dou[2];
+    dsig += a[0] / sigma;
+    // colour: SH coefficients (unless the channel was clamped) and view direction
+    const float dv[3] = {mu[0] - Vw.campos[0], mu[1] - Vw.campos[1], mu[2] - Vw.campos[2]};
+    const float dist = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    const float vd[3] = {dv[0] / dist, dv[1] / dist, dv[2] / dist};
+    float B[16], dB[16][3];
+    sh_basis(kDeg, vd, B, dB);
+    float gv[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float raw = 0.5f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) raw = fmaf(B[k], sh[(int64_t)(k * 3 + c) * n + g], raw);
+      const float dc = raw > 0.0f ? a[1 + c] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        dsh[k * 3 + c] += B[k] * dc;
+        const float cf = sh[(int64_t)(k * 3 + c) * n + g] * dc;
+        gv[0] += cf * dB[k][0];
+        gv[1] += cf * dB[k][1];
+        gv[2] += cf * dB[k][2];
+      }
+    }
+    const float vg = vd[0] * gv[0] + vd[1] * gv[1] + vd[2] * gv[2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dmu[j] += (gv[j] - vd[j] * vg) / dist;
+  }
+  float ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0};
+  if (any) {
+    // W[i][j] = R[j][i] / s_i  =>  ds_i = -sum_j dW_ij R_ji / s_i^2
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      ds[i] = -(dW[i * 3 + 0] * R[0 * 3 + i] + dW[i * 3 + 1] * R[1 * 3 + i] + dW[i * 3 + 2] * R[2 * 3 + i]) /
+              (s[i] * s[i]);
+    // X_ij = dW_ij / s_i, contracted with the four dW/dq matrices of the unit quaternion
+    float X[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) X[i * 3 + j] = dW[i * 3 + j] / s[i];
+    const float qr = qh[0], qi = qh[1], qj = qh[2], qk = qh[3];
+    float dh[4];
+    dh[0] = 2.0f * (X[1] * qk - X[2] * qj - X[3] * qk + X[5] * qi + X[6] * qj - X[7] * qi);
+    dh[1] = 2.0f * (X[1] * qj + X[2] * qk + X[3] * qj - 2.0f * X[4] * qi + X[5] * qr + X[6] * qk - X[7] * qr -
+                    2.0f * X[8] * qi);
+    dh[2] = 2.0f * (-2.0f * X[0] * qj + X[1] * qi - X[2] * qr + X[3] * qi + X[5] * qk + X[6] * qr + X[7] * qk -
+                    2.0f * X[8] * qj);
+    dh[3] = 2.0f * (-2.0f * X[0] * qk + X[1] * qr + X[2] * qi - X[3] * qr - 2.0f * X[4] * qk + X[5] * qj +
+                    X[6] * qi + X[7] * qj);
+    const float proj = dh[0] * qr + dh[1] * qi + dh[2] * qj + dh[3] * qk;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dq[c] = (dh[c] - qh[c] * proj) / qn;
+  }
+  auto put = [&](float* dst, int64_t idx, float val) { dst[idx] = accumulate ? dst[idx] + val : val; };
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    put(g_mean, j * n + g, dmu[j]);
+    put(g_scale, j * n + g, ds[j]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) put(g_quat, c * n + g, dq[c]);
+  put(g_opacity, g, dsig);
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) put(g_sh, (int64_t)k * n + g, dsh[k]);
+}
+
+__global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t n, int32_t n_views,
+                     int32_t sh_degree, const float* mean, const float* scale, const float* quat,
+                     const float* opacity, const float* sh, const ViewDev* views, const float2* dtab,
+                     const float* edges, const float* lam_tab, const Opts& op, const uint32_t* ranges,
+                     const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
+                     const float* tfinal, const float* dl_drgb, float* acc, int accumulate, float* g_mean,
+                     float* g_scale, float* g_quat, float* g_opacity, float* g_sh) {
+  const int64_t nacc = n * n_views * kAcc;
+  if (nacc > 0)
+    hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nacc + 255) / 256)), dim3(256), 0, st, acc, nacc);
+  if (ntiles > 0) {
+    if (fixed_lambda)
+      hipLaunchKernelGGL(render_backward_kernel<true>, dim3((unsigned)ntiles), dim3(256), 0, st, views, n_views,
+                         dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc);
+    else
+      hipLaunchKernelGGL(render_backward_kernel<false>, dim3((unsigned)ntiles), dim3(256), 0, st, views, n_views,
+                         dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc);
+  }
+  if (n > 0) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+#define GEER_PB(D)                                                                                              \
+  hipLaunchKernelGGL(preprocess_backward_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, scale, quat, opacity, \
+                     sh, views, op, lam_tab, edges, acc, accumulate, g_mean, g_scale, g_quat, g_opacity, g_sh)
+    switch (sh_degree) {
+      case 0: GEER_PB(0); break;
+      case 1: GEER_PB(1); break;
+      case 2: GEER_PB(2); break;
+      default: GEER_PB(3); break;
+    }
+#undef GEER_PB
+  }
+}
+
+}  // namespace geer

@@ -1,0 +1,398 @@
+// Device functions shared by the forward and the backward kernels of libgeer:
+// the bit-exact FP32 association, the render record, the SH basis and the
+// per-pair evaluation.  The backward recomputes with these same functions so
+// that every decision it replays is bit-identical to the forward's.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "geer_common.h"
+
+namespace geer {
+
+__device__ __forceinline__ float f_max(float a, float b) { return a > b ? a : b; }
+__device__ __forceinline__ float f_min(float a, float b) { return a < b ? a : b; }
+
+// first cell h in [0, n) whose closed interval [e[h], e[h+1]] can meet [a, ...]
+__device__ __forceinline__ int first_cell(const float* __restrict__ e, int n, float a) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (e[mid + 1] >= a) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+// last cell h in [0, n) with e[h] <= b (-1 if none)
+__device__ __forceinline__ int last_cell(const float* __restrict__ e, int n, float b) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (e[mid] <= b) lo = mid + 1; else hi = mid;
+  }
+  return lo - 1;
+}
+
+__device__ __forceinline__ float pad_of(float x) {
+#pragma clang fp contract(off)
+  float ax = fabsf(x);
+  float s = 1.0f + ax;
+  return s * 0x1p-14f;
+}
+
+__device__ __forceinline__ bool pieces_range(const float* __restrict__ e, int n, int np, const float* a,
+                                             const float* b, int& c0, int& c1) {
+  int lo = n, hi = -1;
+  bool any = false;
+  for (int p = 0; p < np; ++p) {
+    int x0 = first_cell(e, n, a[p]);
+    int x1 = last_cell(e, n, b[p]);
+    if (x0 <= x1) {
+      any = true;
+      lo = min(lo, x0);
+      hi = max(hi, x1);
+    }
+  }
+  c0 = lo;
+  c1 = hi;
+  return any;
+}
+
+struct AssocOut {
+  float R[9];   // local-to-world rotation of the unit quaternion
+  float qh[4];  // unit quaternion
+  float qn;     // |q|
+  float A[9];   // Rc R
+  float mc[3];  // camera-space mean
+  float vou[3]; // S^-1 A^T mu_c = -o_u
+  uint32_t key;
+  int hx0, hx1, hy0, hy1;
+  bool visible;
+};
+
+// The FP32 association.  Each statement is one IEEE single operation.
+__device__ __forceinline__ void associate(const float mu[3], const float s[3], const float q[4], float sigma,
+                                          const ViewDev& V, const Opts& op, const float* __restrict__ lam_tab,
+                                          const float* __restrict__ edges, AssocOut& o) {
+#pragma clang fp contract(off)
+  o.visible = false;
+  o.hx0 = 1; o.hx1 = 0; o.hy0 = 1; o.hy1 = 0;
+
+  float qq = q[0] * q[0];
+  qq = qq + q[1] * q[1];
+  qq = qq + q[2] * q[2];
+  qq = qq + q[3] * q[3];
+  float qn = __builtin_sqrtf(qq);
+  float r = q[0] / qn, i = q[1] / qn, j = q[2] / qn, k = q[3] / qn;
+  o.qn = qn;
+  o.qh[0] = r; o.qh[1] = i; o.qh[2] = j; o.qh[3] = k;
+
+  float xx = i * i, yy = j * j, zz = k * k, xy = i * j, xz = i * k, yz = j * k;
+  float rx = r * i, ry = r * j, rz = r * k;
+  float* R = o.R;
+  R[0] = 1.0f - 2.0f * (yy + zz); R[1] = 2.0f * (xy - rz);        R[2] = 2.0f * (xz + ry);
+  R[3] = 2.0f * (xy + rz);        R[4] = 1.0f - 2.0f * (xx + zz); R[5] = 2.0f * (yz - rx);
+  R[6] = 2.0f * (xz - ry);        R[7] = 2.0f * (yz + rx);        R[8] = 1.0f - 2.0f * (xx + yy);
+
+  float M[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      float t0 = V.Rc[a * 3 + 0] * R[0 * 3 + b];
+      float t1 = V.Rc[a * 3 + 1] * R[1 * 3 + b];
+      float t2 = V.Rc[a * 3 + 2] * R[2 * 3 + b];
+      float acc = t0 + t1;
+      acc = acc + t2;
+      o.A[a * 3 + b] = acc;
+      M[a * 3 + b] = acc * s[b];
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float t0 = V.Rc[a * 3 + 0] * mu[0];
+    float t1 = V.Rc[a * 3 + 1] * mu[1];
+    float t2 = V.Rc[a * 3 + 2] * mu[2];
+    float acc = t0 + t1;
+    acc = acc + t2;
+    o.mc[a] = acc + V.tc[a];
+  }
+  const float* mc = o.mc;
+  {
+    float d0 = mc[0] * mc[0], d1 = mc[1] * mc[1], d2 = mc[2] * mc[2];
+    float dd = d0 + d1;
+    dd = dd + d2;
+    o.key = __float_as_uint(dd);
+  }
+  float ou2 = 0.0f;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    float t0 = o.A[0 * 3 + b] * mc[0];
+    float t1 = o.A[1 * 3 + b] * mc[1];
+    float t2 = o.A[2 * 3 + b] * mc[2];
+    float acc = t0 + t1;
+    acc = acc + t2;
+    float v = acc / s[b];
+    o.vou[b] = v;
+    float v2 = v * v;
+    ou2 = b == 0 ? v2 : ou2 + v2;
+  }
+  if (ou2 < 9.0f) return;  // camera inside 3 sigma: culled
+  if (!(qq > 0.0f)) return;
+  if (!(sigma > op.alpha_min)) return;
+
+  float L;
+  if (op.lambda_mode == 1) {
+    L = op.lam2_fixed;
+  } else {
+    int bkt = (int)(__float_as_uint(sigma) >> kLamShift) - op.lam_lo;
+    bkt = bkt < 0 ? 0 : (bkt >= op.lam_n ? op.lam_n - 1 : bkt);
+    L = lam_tab[bkt];
+  }
+
+#define DOT3(a, b) ((M[(a)*3 + 0] * M[(b)*3 + 0] + M[(a)*3 + 1] * M[(b)*3 + 1]) + M[(a)*3 + 2] * M[(b)*3 + 2])
+  float S00 = DOT3(0, 0), S02 = DOT3(0, 2), S22 = DOT3(2, 2), S11 = DOT3(1, 1), S12 = DOT3(1, 2);
+#undef DOT3
+  float T00 = L * S00 - mc[0] * mc[0];
+  float T02 = L * S02 - mc[0] * mc[2];
+  float T22 = L * S22 - mc[2] * mc[2];
+  float T11 = L * S11 - mc[1] * mc[1];
+  float T12 = L * S12 - mc[1] * mc[2];
+
+  const float* ex = edges + V.ex_off;
+  const float* ey = edges + V.ey_off;
+
+  int hx0, hx1;
+  {
+    float e0 = mc[0] * M[6] - mc[2] * M[0];
+    float e1 = mc[0] * M[7] - mc[2] * M[1];
+    float e2 = mc[0] * M[8] - mc[2] * M[2];
+    float P = (e0 * e0 + e1 * e1) + e2 * e2;
+    float c0 = M[1] * M[8] - M[2] * M[7];
+    float c1 = M[2] * M[6] - M[0] * M[8];
+    float c2 = M[0] * M[7] - M[1] * M[6];
+    float Qd = (c0 * c0 + c1 * c1) + c2 * c2;
+    float D = P - L * Qd;
+    bool full = !(D > P * 0x1p-12f);
+    if (full) {
+      hx0 = 0;
+      hx1 = V.nhx - 1;
+    } else {
+      float sd = __builtin_sqrtf(L * D);
+      float qv = T02 >= 0.0f ? T02 + sd : T02 - sd;
+      float rs[2] = {qv, T00}, rk[2] = {T22, qv};
+      float cand[4];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        float ss = rs[t], kk = rk[t];
+        if (kk < 0.0f) { ss = -ss; kk = -kk; }
+        float rr = __builtin_sqrtf(ss * ss + kk * kk);
+        float kr = kk + rr;
+        cand[2 * t + 0] = ss / kr;
+        cand[2 * t + 1] = -(kr / ss);
+      }
+      float rho = __builtin_sqrtf(mc[0] * mc[0] + mc[2] * mc[2]);
+      float tmu = mc[2] >= 0.0f ? mc[0] / (mc[2] + rho) : (rho - mc[2]) / mc[0];
+      bool has_lo = false, has_hi = false;
+      float lo = 0.0f, hi = 0.0f, cmin = cand[0], cmax = cand[0];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float c = cand[t];
+        cmin = f_min(cmin, c);
+        cmax = f_max(cmax, c);
+        if (c < tmu) { lo = has_lo ? f_max(lo, c) : c; has_lo = true; }
+        if (c > tmu) { hi = has_hi ? f_min(hi, c) : c; has_hi = true; }
+      }
+      float a[2], b[2];
+      int np;
+      if (has_lo && has_hi) {
+        a[0] = lo - pad_of(lo); b[0] = hi + pad_of(hi); np = 1;
+      } else {
+        a[0] = -INFINITY; b[0] = cmin + pad_of(cmin);
+        a[1] = cmax - pad_of(cmax); b[1] = INFINITY; np = 2;
+      }
+      if (!pieces_range(ex, V.nhx, np, a, b, hx0, hx1)) return;
+    }
+  }
+  int hy0, hy1;
+  {
+    float e0 = mc[1] * M[6] - mc[2] * M[3];
+    float e1 = mc[1] * M[7] - mc[2] * M[4];
+    float e2 = mc[1] * M[8] - mc[2] * M[5];
+    float P = (e0 * e0 + e1 * e1) + e2 * e2;
+    float c0 = M[4] * M[8] - M[5] * M[7];
+    float c1 = M[5] * M[6] - M[3] * M[8];
+    float c2 = M[3] * M[7] - M[4] * M[6];
+    float Qd = (c0 * c0 + c1 * c1) + c2 * c2;
+    float D = P - L * Qd;
+    float tz = (mc[2] * mc[2]) * 0x1p-12f;
+    bool full = !(D > P * 0x1p-12f) || !(T22 < -tz || T22 > tz);
+    if (full) {
+      hy0 = 0;
+      hy1 = V.nhy - 1;
+    } else {
+      float sd = __builtin_sqrtf(L * D);
+      float qv = T12 >= 0.0f ? T12 + sd : T12 - sd;
+      float r1 = qv / T22, r2 = T11 / qv;
+      float cmin = f_min(r1, r2), cmax = f_max(r1, r2);
+      float a[2], b[2];
+      int np;
+      if (T22 < 0.0f) {
+        a[0] = cmin - pad_of(cmin); b[0] = cmax + pad_of(cmax); np = 1;
+      } else {
+        a[0] = -INFINITY; b[0] = cmin + pad_of(cmin);
+        a[1] = cmax - pad_of(cmax); b[1] = INFINITY; np = 2;
+      }
+      if (!pieces_range(ey, V.nhy, np, a, b, hy0, hy1)) return;
+    }
+  }
+  o.hx0 = hx0; o.hx1 = hx1; o.hy0 = hy0; o.hy1 = hy1;
+  o.visible = true;
+}
+
+// SH basis (degree <= 3) at the unit direction v with the 3DGS sign
+// convention; optionally its gradient with respect to (x, y, z).  Returns K.
+__device__ __forceinline__ int sh_basis(int deg, const float v[3], float B[16], float (*dB)[3]) {
+  const float C0 = 0.28209479177387814f, C1 = 0.4886025119029199f;
+  const float C2[5] = {1.0925484305920792f, -1.0925484305920792f, 0.31539156525252005f,
+                       -1.0925484305920792f, 0.5462742152960396f};
+  const float C3[7] = {-0.5900435899266435f, 2.890611442640554f, -0.4570457994644658f, 0.3731763325901154f,
+                       -0.4570457994644658f, 1.445305721320277f, -0.5900435899266435f};
+  const float x = v[0], y = v[1], z = v[2];
+  B[0] = C0;
+  if (dB) { dB[0][0] = 0; dB[0][1] = 0; dB[0][2] = 0; }
+  if (deg < 1) return 1;
+  B[1] = -C1 * y; B[2] = C1 * z; B[3] = -C1 * x;
+  if (dB) {
+    dB[1][0] = 0; dB[1][1] = -C1; dB[1][2] = 0;
+    dB[2][0] = 0; dB[2][1] = 0; dB[2][2] = C1;
+    dB[3][0] = -C1; dB[3][1] = 0; dB[3][2] = 0;
+  }
+  if (deg < 2) return 4;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  B[4] = C2[0] * x * y;
+  B[5] = C2[1] * y * z;
+  B[6] = C2[2] * (2.0f * zz - xx - yy);
+  B[7] = C2[3] * x * z;
+  B[8] = C2[4] * (xx - yy);
+  if (dB) {
+    dB[4][0] = C2[0] * y; dB[4][1] = C2[0] * x; dB[4][2] = 0;
+    dB[5][0] = 0; dB[5][1] = C2[1] * z; dB[5][2] = C2[1] * y;
+    dB[6][0] = -2.0f * C2[2] * x; dB[6][1] = -2.0f * C2[2] * y; dB[6][2] = 4.0f * C2[2] * z;
+    dB[7][0] = C2[3] * z; dB[7][1] = 0; dB[7][2] = C2[3] * x;
+    dB[8][0] = 2.0f * C2[4] * x; dB[8][1] = -2.0f * C2[4] * y; dB[8][2] = 0;
+  }
+  if (deg < 3) return 9;
+  B[9] = C3[0] * y * (3.0f * xx - yy);
+  B[10] = C3[1] * x * y * z;
+  B[11] = C3[2] * y * (4.0f * zz - xx - yy);
+  B[12] = C3[3] * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  B[13] = C3[4] * x * (4.0f * zz - xx - yy);
+  B[14] = C3[5] * z * (xx - yy);
+  B[15] = C3[6] * x * (xx - 3.0f * yy);
+  if (dB) {
+    dB[9][0] = C3[0] * 6.0f * x * y; dB[9][1] = C3[0] * (3.0f * xx - 3.0f * yy); dB[9][2] = 0;
+    dB[10][0] = C3[1] * y * z; dB[10][1] = C3[1] * x * z; dB[10][2] = C3[1] * x * y;
+    dB[11][0] = -2.0f * C3[2] * x * y; dB[11][1] = C3[2] * (4.0f * zz - xx - 3.0f * yy);
+    dB[11][2] = 8.0f * C3[2] * y * z;
+    dB[12][0] = -6.0f * C3[3] * x * z; dB[12][1] = -6.0f * C3[3] * y * z;
+    dB[12][2] = C3[3] * (6.0f * zz - 3.0f * xx - 3.0f * yy);
+    dB[13][0] = C3[4] * (4.0f * zz - 3.0f * xx - yy); dB[13][1] = -2.0f * C3[4] * x * y;
+    dB[13][2] = 8.0f * C3[4] * x * z;
+    dB[14][0] = 2.0f * C3[5] * x * z; dB[14][1] = -2.0f * C3[5] * y * z; dB[14][2] = C3[5] * (xx - yy);
+    dB[15][0] = C3[6] * (3.0f * xx - 3.0f * yy); dB[15][1] = -6.0f * C3[6] * x * y; dB[15][2] = 0;
+  }
+  return 16;
+}
+
+// Orthonormal pair (e1, e2) completing n, built in the frame where n's
+// largest component plays the role of z (Duff et al. 2017 branchless basis),
+// so that every entry is accurate relative to n's small components.
+__device__ __forceinline__ void ortho_basis(const float n[3], float e1[3], float e2[3]) {
+  float ax = fabsf(n[0]), ay = fabsf(n[1]), az = fabsf(n[2]);
+  int k = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  int a = k == 0 ? 1 : 0;
+  int b = k == 2 ? 1 : 2;
+  float x = n[a], y = n[b], z = n[k];
+  float sg = copysignf(1.0f, z);
+  float p = -1.0f / (sg + z);
+  float q = x * y * p;
+  float u[3] = {1.0f + sg * x * x * p, sg * q, -sg * x};
+  float w[3] = {q, sg + y * y * p, -y};
+  e1[a] = u[0]; e1[b] = u[1]; e1[k] = u[2];
+  e2[a] = w[0]; e2[b] = w[1]; e2[k] = w[2];
+}
+
+// Rotated canonical frame of one (Gaussian, view) item: Wc = S^-1 A^T maps a
+// camera-space direction to canonical coordinates, o_u is the canonical
+// camera centre, and Q = (e1; e2; n) rotates o_u onto the third axis.
+struct Frame3 {
+  float Wc[9];
+  float ou[3];
+  float r2, r;
+  float e1[3], e2[3], nn[3];
+};
+
+__device__ __forceinline__ void canonical_frame(const AssocOut& A, const float s[3], Frame3& F) {
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) F.Wc[kk * 3 + ii] = A.A[ii * 3 + kk] / s[kk];
+  F.ou[0] = -A.vou[0]; F.ou[1] = -A.vou[1]; F.ou[2] = -A.vou[2];
+  F.r2 = F.ou[0] * F.ou[0] + F.ou[1] * F.ou[1] + F.ou[2] * F.ou[2];
+  const float rinv = rsqrtf(F.r2);
+  F.r = F.r2 * rinv;
+  F.nn[0] = F.ou[0] * rinv; F.nn[1] = F.ou[1] * rinv; F.nn[2] = F.ou[2] * rinv;
+  ortho_basis(F.nn, F.e1, F.e2);
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// band of tiles so that neighbouring tiles share its L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  int q = nblocks >> 3, r = nblocks & 7, x = bid & 7;
+  return x * q + min(x, r) + (bid >> 3);
+}
+
+// Unit camera-space direction of BEAP pixel (px, py) from the per-view
+// (sin, cos) tables.
+__device__ __forceinline__ void pixel_direction(const ViewDev& V, const float2* __restrict__ dtab, int px, int py,
+                                                float& dx, float& dy, float& dz) {
+  const float2 cth = dtab[V.dx_off + min(px, V.width - 1)];   // (sin, cos) theta
+  const float2 cph = dtab[V.dy_off + min(py, V.height - 1)];  // (sin, cos) phi
+  dx = cth.x * cph.y;
+  dy = cth.y * cph.x;
+  dz = cth.y * cph.y;
+  const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
+  dx *= dn;
+  dy *= dn;
+  dz *= dn;
+}
+
+// One (ray, Gaussian) pair in the rotated canonical frame: g = G d,
+// kappa = r^2 (gx^2 + gy^2) / |g|^2 = r^2 q, alpha_raw = sigma exp(-kappa/2).
+struct PairEval {
+  float gx, gy, gz, mm, ss, inv, q, a_raw;
+};
+
+__device__ __forceinline__ PairEval eval_pair(const Record& R, float dx, float dy, float dz) {
+  PairEval E;
+  E.gx = fmaf(R.g[2], dz, fmaf(R.g[1], dy, R.g[0] * dx));
+  E.gy = fmaf(R.g[5], dz, fmaf(R.g[4], dy, R.g[3] * dx));
+  E.gz = fmaf(R.g[8], dz, fmaf(R.g[7], dy, R.g[6] * dx));
+  E.mm = fmaf(E.gy, E.gy, E.gx * E.gx);
+  E.ss = fmaf(E.gz, E.gz, E.mm);
+  E.inv = __builtin_amdgcn_rcpf(E.ss);
+  E.q = E.mm * E.inv;
+  E.a_raw = __builtin_amdgcn_exp2f(fmaf(R.c0, E.q, R.lsig));
+  return E;
+}
+
+// The contribution rule: closest approach in front of the camera, alpha above
+// alpha_min, and (fixed-lambda mode) kappa <= lambda^2.
+template <bool kFixed>
+__device__ __forceinline__ bool pair_contributes(const Record& R, const PairEval& E, const Opts& op) {
+  bool ok = (E.gz > 0.0f) & (E.a_raw >= op.alpha_min);
+  if (kFixed) ok = ok & (E.q <= R.qmax);
+  return ok;
+}
+
+__device__ __forceinline__ float clamp_alpha(float a, const Opts& op) { return a < op.alpha_max ? a : op.alpha_max; }
+
+}  // namespace geer

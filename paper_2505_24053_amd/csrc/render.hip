@@ -20,34 +20,20 @@
 #include <hip/hip_runtime.h>
 
 #include "geer_common.h"
+#include "geer_device.h"
 
 namespace geer {
 
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-  // contiguous band of tiles so neighbouring tiles share its L2.
-  int q = nblocks >> 3, r = nblocks & 7, x = bid & 7;
-  return x * q + min(x, r) + (bid >> 3);
-}
-
 // One (ray, Gaussian) evaluation and blend, branch-free: lanes that already
-// terminated (or a disabled second slot) compute too -- their SIMD lane is
-// occupied either way -- but their blend weight is zero.
+// terminated compute too -- their SIMD lane is occupied either way -- but
+// their blend weight is zero.
 template <bool kFixed>
-__device__ __forceinline__ void blend_one(const Record& R, bool enable, float dx, float dy, float dz,
-                                          const Opts& op, uint32_t e, bool& done, float& T, float& cr,
-                                          float& cg, float& cb, float& D, uint32_t& last) {
-  const float gx = fmaf(R.g[2], dz, fmaf(R.g[1], dy, R.g[0] * dx));
-  const float gy = fmaf(R.g[5], dz, fmaf(R.g[4], dy, R.g[3] * dx));
-  const float gz = fmaf(R.g[8], dz, fmaf(R.g[7], dy, R.g[6] * dx));
-  const float mm = fmaf(gy, gy, gx * gx);
-  const float ss = fmaf(gz, gz, mm);
-  const float inv = __builtin_amdgcn_rcpf(ss);
-  const float q = mm * inv;
-  float a = __builtin_amdgcn_exp2f(fmaf(R.c0, q, R.lsig));
-  bool ok = enable & !done & (gz > 0.0f) & (a >= op.alpha_min);
-  if (kFixed) ok = ok & (q <= R.qmax);
-  a = a < op.alpha_max ? a : op.alpha_max;
+__device__ __forceinline__ void blend_one(const Record& R, float dx, float dy, float dz, const Opts& op, uint32_t e,
+                                          bool& done, float& T, float& cr, float& cg, float& cb, float& D,
+                                          uint32_t& last) {
+  const PairEval E = eval_pair(R, dx, dy, dz);
+  const bool ok = !done & pair_contributes<kFixed>(R, E, op);
+  const float a = clamp_alpha(E.a_raw, op);
   const float Tn = T * (1.0f - a);
   const bool term = ok & (Tn < op.t_min);
   const bool blend = ok & !term;
@@ -56,7 +42,7 @@ __device__ __forceinline__ void blend_one(const Record& R, bool enable, float dx
   cr = fmaf(w, R.rgb[0], cr);
   cg = fmaf(w, R.rgb[1], cg);
   cb = fmaf(w, R.rgb[2], cb);
-  D = fmaf(w * R.c1, gz * inv, D);
+  D = fmaf(w * R.c1, E.gz * E.inv, D);
   T = blend ? Tn : T;
   last = blend ? e + 1 : last;
 }
@@ -87,11 +73,8 @@ __global__ __launch_bounds__(256) void render_kernel(
   const int px = hx * kHalf + (lane & 7), py = hy * kHalf + (lane >> 3);
   const bool valid = wave_live && px < V.width && py < V.height;
 
-  const float2 cth = dtab[V.dx_off + min(px, V.width - 1)];  // (sin, cos) theta
-  const float2 cph = dtab[V.dy_off + min(py, V.height - 1)]; // (sin, cos) phi
-  float dx = cth.x * cph.y, dy = cth.y * cph.x, dz = cth.y * cph.y;
-  const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
-  dx *= dn; dy *= dn; dz *= dn;
+  float dx, dy, dz;
+  pixel_direction(V, dtab, px, py, dx, dy, dz);
 
   const uint32_t start = ranges[tile], end = ranges[tile + 1];
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, D = 0.0f;
@@ -147,7 +130,7 @@ __global__ __launch_bounds__(256) void render_kernel(
           float4* rr = reinterpret_cast<float4*>(&R);
           rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
           evals += (uint64_t)__popcll(__ballot(!done));
-          blend_one<kFixed>(R, true, dx, dy, dz, op, base + k, done, T, cr, cg, cb, D, last);
+          blend_one<kFixed>(R, dx, dy, dz, op, base + k, done, T, cr, cg, cb, D, last);
         }
       }
     }

@@ -163,34 +163,52 @@ __global__ __launch_bounds__(kBlock) void gather_counts_kernel(const uint32_t* _
 
 constexpr int kExpandPer = 8;
 
+// Each lane expands kExpandPer consecutive entries (one binary search for the
+// owner of its first entry), the block stages its 2048 entries in LDS and
+// writes them back lane-striped so every store is coalesced.
 __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restrict__ items,
                                                         const uint32_t* __restrict__ offs, int64_t m,
                                                         int64_t total, const uint2* __restrict__ rects,
                                                         const ViewDev* __restrict__ views, int64_t n,
                                                         uint32_t* __restrict__ tiles_out,
                                                         uint32_t* __restrict__ items_out) {
-  int64_t e0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kExpandPer;
-  if (e0 >= total) return;
-  // owner of e0: last j with offs[j] <= e0
-  int64_t lo = 0, hi = m;
-  while (hi - lo > 1) {
-    int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)offs[mid] <= e0) lo = mid; else hi = mid;
+  __shared__ uint32_t s_tile[kBlock * kExpandPer];
+  __shared__ uint32_t s_item[kBlock * kExpandPer];
+  const int64_t block0 = (int64_t)blockIdx.x * kBlock * kExpandPer;
+  const int64_t e0 = block0 + (int64_t)threadIdx.x * kExpandPer;
+  if (e0 < total) {
+    // owner of e0: last j with offs[j] <= e0
+    int64_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)offs[mid] <= e0) lo = mid; else hi = mid;
+    }
+    int64_t j = lo;
+    const int64_t e1 = min(e0 + kExpandPer, total);
+    for (int64_t e = e0; e < e1; ++e) {
+      while (j + 1 < m && (int64_t)offs[j + 1] <= e) ++j;
+      const uint32_t item = items[j];
+      const uint32_t local = (uint32_t)(e - (int64_t)offs[j]);
+      const uint2 r = rects[item];
+      const int tx0 = (int)(r.x & 0xffffu) >> 1, tx1 = (int)(r.x >> 16) >> 1;
+      const int ty0 = (int)(r.y & 0xffffu) >> 1;
+      const uint32_t wt = (uint32_t)(tx1 - tx0 + 1);
+      const ViewDev& V = views[item / (uint32_t)n];
+      const uint32_t ty = ty0 + local / wt, tx = tx0 + local % wt;
+      const int s = (int)(e - block0);
+      s_tile[s] = (uint32_t)V.tile_base + ty * (uint32_t)V.tiles_x + tx;
+      s_item[s] = item;
+    }
   }
-  int64_t j = lo;
-  int64_t e1 = min(e0 + kExpandPer, total);
-  for (int64_t e = e0; e < e1; ++e) {
-    while (j + 1 < m && (int64_t)offs[j + 1] <= e) ++j;
-    uint32_t item = items[j];
-    uint32_t local = (uint32_t)(e - (int64_t)offs[j]);
-    uint2 r = rects[item];
-    int tx0 = (int)(r.x & 0xffffu) >> 1, tx1 = (int)(r.x >> 16) >> 1;
-    int ty0 = (int)(r.y & 0xffffu) >> 1;
-    uint32_t wt = (uint32_t)(tx1 - tx0 + 1);
-    const ViewDev& V = views[item / (uint32_t)n];
-    uint32_t ty = ty0 + local / wt, tx = tx0 + local % wt;
-    tiles_out[e] = (uint32_t)V.tile_base + ty * (uint32_t)V.tiles_x + tx;
-    items_out[e] = item;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kExpandPer; ++k) {
+    const int s = k * kBlock + threadIdx.x;
+    const int64_t e = block0 + s;
+    if (e < total) {
+      tiles_out[e] = s_tile[s];
+      items_out[e] = s_item[s];
+    }
   }
 }
 

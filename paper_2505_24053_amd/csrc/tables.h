@@ -43,4 +43,18 @@ void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const View
                    const Record* recs, const Opts& op, float* rgb, float* depth, float* trans, uint32_t* nlast,
                    float* tfinal, unsigned long long* stats);
 
+// backward.hip
+void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t n, int32_t n_views,
+                     int32_t sh_degree, const float* mean, const float* scale, const float* quat,
+                     const float* opacity, const float* sh, const ViewDev* views, const float2* dtab,
+                     const float* edges, const float* lam_tab, const Opts& op, const uint32_t* ranges,
+                     const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
+                     const float* tfinal, const float* dl_drgb, float* acc, int accumulate, float* g_mean,
+                     float* g_scale, float* g_quat, float* g_opacity, float* g_sh);
+
+// loss.hip
+int64_t l1_partial_count(int64_t P);
+void launch_l1(hipStream_t st, int64_t P, const float* rgb, const float* target, const uint8_t* mask, float* dl,
+               float* loss, float2* partial, float* scale);
+
 }  // namespace geer

@@ -139,3 +139,67 @@ def views_of(flat: torch.Tensor, cams, channels: int):
         outs.append(flat[off: off + channels * hw].view(channels, int(c["height"]), int(c["width"])))
         off += channels * hw
     return outs
+
+
+def backward(frame: Frame, scene: dict, dl_drgb: torch.Tensor, accumulate: bool = False, grads=None):
+    """Gradients of the loss with respect to the scene given dL/dRGB (same
+    layout as the forward's rgb).  Returns a dict of tensors in the scene
+    layout (App. C chain, computed by the library)."""
+    n, deg = _check_scene(scene)
+    dev = scene["mean"].device
+    if grads is None:
+        grads = {k: torch.zeros_like(scene[k]) if accumulate else torch.empty_like(scene[k])
+                 for k in ("mean", "scale", "quat", "opacity", "sh")}
+    g = dl_drgb.contiguous()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    _lib.check(_lib.load().geer_render_backward(frame.ctx, frame.handle, _ptr(g), _ptr(grads["mean"]),
+                                                _ptr(grads["scale"]), _ptr(grads["quat"]), _ptr(grads["opacity"]),
+                                                _ptr(grads["sh"]), 1 if accumulate else 0, C.c_void_p(stream)),
+               frame.ctx)
+    return grads
+
+
+def l1_loss(rgb: torch.Tensor, target: torch.Tensor, mask: torch.Tensor):
+    """L1 over valid rays of one view: returns (loss [1], dL/drgb) computed on
+    the device; rgb, target: [3*P] planar, mask: uint8 [P]."""
+    dev = rgb.device
+    P = mask.numel()
+    dl = torch.empty_like(rgb)
+    loss = torch.empty(1, device=dev, dtype=torch.float32)
+    ctx = context(dev.index or 0)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    _lib.check(_lib.load().geer_l1_loss(ctx, P, _ptr(rgb.contiguous()), _ptr(target.contiguous()),
+                                        _ptr(mask.contiguous()), _ptr(dl), _ptr(loss), C.c_void_p(stream)), ctx)
+    return loss, dl
+
+
+class _Render(torch.autograd.Function):
+    """Differentiable render: RGB depends on (mean, scale, quat, opacity, sh);
+    depth and transmittance are returned without gradient."""
+
+    @staticmethod
+    def forward(ctx, mean, scale, quat, opacity, sh, sh_degree, cams, opts):
+        scene = dict(mean=mean, scale=scale, quat=quat, opacity=opacity, sh=sh, sh_degree=sh_degree)
+        rgb, depth, trans, frame = render(scene, cams, opts=opts, keep_frame=True)
+        ctx.frame = frame
+        ctx.sh_degree = sh_degree
+        ctx.save_for_backward(mean, scale, quat, opacity, sh)
+        ctx.mark_non_differentiable(depth, trans)
+        return rgb, depth, trans
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_trans):
+        mean, scale, quat, opacity, sh = ctx.saved_tensors
+        scene = dict(mean=mean, scale=scale, quat=quat, opacity=opacity, sh=sh, sh_degree=ctx.sh_degree)
+        if g_rgb is None:
+            g_rgb = torch.zeros(3 * sum(view_pixels(ctx.frame.cams)), device=mean.device)
+        grads = backward(ctx.frame, scene, g_rgb)
+        ctx.frame.release()
+        return grads["mean"], grads["scale"], grads["quat"], grads["opacity"], grads["sh"], None, None, None
+
+
+def render_differentiable(scene: dict, cams, opts: dict | None = None):
+    """torch.autograd entry point: returns (rgb, depth, trans) flat tensors;
+    backward() on a function of rgb fills .grad of the scene tensors."""
+    return _Render.apply(scene["mean"], scene["scale"], scene["quat"], scene["opacity"], scene["sh"],
+                         int(scene["sh_degree"]), cams, opts)

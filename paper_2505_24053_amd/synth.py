@@ -166,17 +166,26 @@ def kb_coeffs(seed: int, fov_deg: float, lim: float = 0.05) -> list:
             return [float(x) for x in k]
 
 
-def camera_kb(width: int, height: int, fov_deg: float, seed: int = 0, R=None, position=None) -> dict:
+def camera_kb(width: int, height: int, fov_deg: float, seed: int = 0, R=None, position=None,
+              fov_y_deg: float | None = None) -> dict:
     """Kannala-Brandt fisheye with random k1..k4; the focal length maps the
-    half-FoV to the sensor's horizontal edge; BEAP grid with equal pitch."""
+    half-FoV to the sensor's horizontal edge; BEAP grid with equal pitch
+    unless a vertical FoV is given."""
     k = kb_coeffs(seed, fov_deg)
     th = math.radians(fov_deg) / 2
     td = th * (1 + k[0] * th**2 + k[1] * th**4 + k[2] * th**6 + k[3] * th**8)
     f = (width / 2) / td
     fov = math.radians(fov_deg)
     Rw, t = _pose(R, position)
+    fov_y = math.radians(fov_y_deg) if fov_y_deg is not None else fov * height / width
     return dict(model="kb", width=width, height=height, fx=f, fy=f, cx=width / 2, cy=height / 2,
-                k=k, fov_x=fov, fov_y=fov * height / width, R=Rw, t=t)
+                k=k, fov_x=fov, fov_y=fov_y, R=Rw, t=t)
+
+
+def camera_slice(seed: int = 0, res: int = 32) -> dict:
+    """Finite-difference slice camera: Kannala-Brandt 190 deg on a res x res
+    BEAP grid spanning 190 x 142.5 degrees (the 1280 x 960 frame's extents)."""
+    return camera_kb(res, res, 190.0, seed=seed, fov_y_deg=142.5)
 
 
 def random_pose(rng: np.random.Generator, half: float = 8.0):

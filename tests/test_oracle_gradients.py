@@ -25,7 +25,7 @@ OPTS = dict(oracle.DEFAULT_OPTS)
 def slice_problem(seed=0, n=200, res=32, model="kb"):
     scene = synth.scene_slice(n, seed)
     if model == "kb":
-        cam = synth.camera_kb(res, res, 190.0, seed=seed)
+        cam = synth.camera_slice(seed=seed, res=res)
     else:
         cam = synth.camera_pinhole(res, res, 70.0)
     rng = np.random.default_rng(seed + 99)
