@@ -544,6 +544,9 @@ typedef struct {
   double u[3], m[3], uu;
   double band; /* FP32 error bound of kappa for this pair */
   int clamped;
+  int in64;    /* contributes in FP64 */
+  int flag;    /* within the FP32 error band of a contribution decision */
+  double ptol; /* how far flipping that decision can move the colour */
 } contrib;
 
 static int contrib_cmp(const void* a, const void* b) {
@@ -584,15 +587,13 @@ static double cmax_of(const gprep* p) {
   return c > p->col[2] ? c : p->col[2];
 }
 
-/* *amb is set when some pair lies within the FP32 error band of a decision;
- * *tol accumulates how much flipping those decisions can change the colour
- * (2 alpha_raw max(c) per pair: the pair's own term and the occlusion it
- * adds to what lies behind). */
+/* Collects, in (key, index) order, every pair that contributes in FP64 and
+ * every pair whose contribution decision lies within the FP32 error band of
+ * its threshold (flag = 1, with ptol = 2 alpha_raw max(c): the pair's own
+ * term and the occlusion it adds to what lies behind). */
 static int64_t gather(const gprep* P, int64_t n, const orc_opts* op, const double o[3], const double d[3],
-                      contrib** buf, int64_t* cap, int* amb, double* tol) {
+                      contrib** buf, int64_t* cap) {
   int64_t cnt = 0;
-  *amb = 0;
-  *tol = 0;
   for (int64_t g = 0; g < n; ++g) {
     const gprep* p = &P[g];
     if (!p->active) continue;
@@ -612,13 +613,8 @@ static int64_t gather(const gprep* P, int64_t n, const orc_opts* op, const doubl
       flag = 1;
     double araw = p->sigma * exp(-0.5 * kappa);
     if (op->lambda_mode == 1 && fabs(araw - op->alpha_min) <= 1e-3 * op->alpha_min) flag = 1;
-    if (flag) {
-      *amb = 1;
-      *tol += 2.0 * p->sigma * exp(-0.5 * (kappa - band > 0 ? kappa - band : 0)) * (cmax_of(p) + 1e-3);
-    }
-    if (!(tstar > 0)) continue;
-    if (!(kappa <= p->lam2)) continue;
-    if (op->lambda_mode == 1 && !(araw >= op->alpha_min)) continue;
+    const int in64 = tstar > 0 && kappa <= p->lam2 && !(op->lambda_mode == 1 && !(araw >= op->alpha_min));
+    if (!in64 && !flag) continue;
     if (cnt == *cap) {
       *cap = *cap ? *cap * 2 : 256;
       *buf = (contrib*)realloc(*buf, sizeof(contrib) * (size_t)*cap);
@@ -634,9 +630,20 @@ static int64_t gather(const gprep* P, int64_t n, const orc_opts* op, const doubl
     c->band = band;
     for (int a = 0; a < 3; ++a) { c->u[a] = u[a]; c->m[a] = m[a]; }
     c->uu = uu;
+    c->in64 = in64;
+    c->flag = flag;
+    c->ptol = flag ? 2.0 * p->sigma * exp(-0.5 * (kappa - band > 0 ? kappa - band : 0)) * (cmax_of(p) + 1e-3) : 0.0;
   }
   qsort(*buf, (size_t)cnt, sizeof(contrib), contrib_cmp);
   return cnt;
+}
+
+/* Keeps only the pairs that contribute in FP64 (order preserved). */
+static int64_t keep_contributors(contrib* buf, int64_t cnt) {
+  int64_t k = 0;
+  for (int64_t i = 0; i < cnt; ++i)
+    if (buf[i].in64) buf[k++] = buf[i];
+  return k;
 }
 
 static void camera_centre(const orc_view* v, double o[3]) {
@@ -672,19 +679,44 @@ int orc_render(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64
       int px = (int)(pix[t] % v->width), py = (int)(pix[t] / v->width);
       double d[3];
       pixel_dir(v, px, py, d);
-      int a_flag;
-      double tol;
-      int64_t cnt = gather(P, n, op, o, d, &buf, &cap, &a_flag, &tol);
+      int64_t cnt = gather(P, n, op, o, d, &buf, &cap);
       double cmax_all = 0;
       for (int64_t i = 0; i < cnt; ++i) {
         double cm = cmax_of(&P[buf[i].g]);
         cmax_all = cm > cmax_all ? cm : cmax_all;
       }
+      /* Latest possible termination: every flagged pair left out, and a step
+         whose transmittance is within the error band of T_min still taken.
+         Whatever FP32 decides, compositing stops at or before it, so flagged
+         pairs sorted after it cannot change the result. */
+      int64_t late = cnt;
+      if (op->t_min > 0) {
+        double T = 1, trel = 0;
+        for (int64_t i = 0; i < cnt; ++i) {
+          const contrib* c = &buf[i];
+          if (c->flag || !c->in64) continue;
+          double Tn = T * (1 - c->alpha);
+          trel += (c->clamped ? 0.0 : c->alpha * 0.5 * c->band) / (1 - c->alpha) + 0x1p-22;
+          if (Tn < op->t_min * (1 - trel - 0x1p-20)) {
+            late = i;
+            break;
+          }
+          T = Tn;
+        }
+      }
+      int a_flag = 0;
+      double tol = 0;
+      for (int64_t i = 0; i < cnt && i <= late; ++i)
+        if (buf[i].flag) {
+          a_flag = 1;
+          tol += buf[i].ptol;
+        }
       double T = 1, C[3] = {0, 0, 0}, D = 0;
       double trel = 0; /* first-order relative FP32 error of the transmittance */
       int32_t nc = 0;
       for (int64_t i = 0; i < cnt; ++i) {
         const contrib* c = &buf[i];
+        if (!c->in64) continue;
         double Tn = T * (1 - c->alpha);
         trel += (c->clamped ? 0.0 : c->alpha * 0.5 * c->band) / (1 - c->alpha) + 0x1p-22;
         if (op->t_min > 0) {
@@ -761,9 +793,7 @@ int orc_render_backward(const orc_scene* sc, const orc_view* v, const orc_opts* 
       int px = (int)(pix[t] % v->width), py = (int)(pix[t] / v->width);
       double d[3];
       pixel_dir(v, px, py, d);
-      int a_flag;
-      double tol_unused;
-      int64_t cnt = gather(P, n, op, o, d, &buf, &cap, &a_flag, &tol_unused);
+      int64_t cnt = keep_contributors(buf, gather(P, n, op, o, d, &buf, &cap));
       if (cnt > tcap) { tcap = cnt; Tb = (double*)realloc(Tb, sizeof(double) * (size_t)tcap); }
       /* forward pass storing T before each composited Gaussian */
       double T = 1;
@@ -931,9 +961,7 @@ int orc_contrib_mask(const orc_scene* sc, const orc_view* v, const orc_opts* op,
       int px = (int)(pix[t] % v->width), py = (int)(pix[t] / v->width);
       double d[3];
       pixel_dir(v, px, py, d);
-      int a_flag;
-      double tol_unused;
-      int64_t cnt = gather(P, n, op, o, d, &buf, &cap, &a_flag, &tol_unused);
+      int64_t cnt = keep_contributors(buf, gather(P, n, op, o, d, &buf, &cap));
       memset(mask + (size_t)t * (size_t)n, 0, (size_t)n);
       for (int64_t i = 0; i < cnt; ++i) mask[(size_t)t * (size_t)n + (size_t)buf[i].g] = 1;
     }

@@ -243,3 +243,40 @@ def test_valid_mask_shapes():
     m = oracle.valid_mask(wide)
     assert m[48, 64] and not m[48, 0] and not m[48, -1]
     assert 0.5 < m.mean() < 1.0
+
+
+def _concat(*scenes):
+    return synth.Scene(*(np.concatenate([getattr(s, k) for s in scenes], axis=-1)
+                         for k in ("mean", "scale", "quat", "opacity", "sh")), 0)
+
+
+def test_threshold_flags_only_before_latest_termination(oracle_lib):
+    """A Gaussian whose kappa sits exactly on lambda^2 for the centre ray is a
+    threshold-ambiguous pair.  Behind four opaque Gaussians that end the ray
+    (T falls 0.05^4 < T_min) it cannot change the result and is not flagged;
+    in front of them it is flagged, with a bound of 2 sigma max(c).  The
+    colours are the closed-form composites of the opaque ones."""
+    cam = synth.camera_pinhole(1, 1, 10.0)  # one ray along +z
+    q = [1.0, 0.0, 0.0, 0.0]
+    wall = [one_gaussian([0, 0, z], [0.1] * 3, q, 0.95, rgb=(0.2, 0.4, 0.6)) for z in (2.0, 3.0, 4.0, 5.0)]
+    sig, s = 0.5, 0.3
+    lam2 = 2 * math.log(float(np.float32(sig)) / (1 / 255))
+    b = float(np.float32(s)) * math.sqrt(lam2)
+
+    def edge(z):
+        return one_gaussian([b, 0, z], [s] * 3, q, sig, rgb=(0.9, 0.1, 0.1))
+
+    kappa, tstar, _, lam2_o = oracle.pair(edge(10.0), cam, 0, [0.0, 0.0, 1.0])
+    assert kappa == pytest.approx(lam2, rel=1e-6) and lam2_o == pytest.approx(lam2, rel=1e-12) and tstar > 0
+    a = 0.95
+    c_wall = 0.2 * (a + a * (1 - a) + a * (1 - a) ** 2)  # three composited, the fourth ends the ray
+    behind = oracle.render(_concat(*wall, edge(10.0)), cam)
+    assert not behind["amb"][0]
+    assert behind["ncomp"][0] == 3
+    assert behind["rgb"][0, 0] == pytest.approx(c_wall, abs=1e-6)
+    front = oracle.render(_concat(edge(1.0), *wall), cam)
+    assert front["amb"][0]
+    assert front["amb_tol"][0] >= 2 * sig * 0.9 * math.exp(-0.5 * lam2) * 0.99
+    # with no termination the pair behind is reachable again, hence flagged
+    no_stop = oracle.render(_concat(*wall, edge(10.0)), cam, t_min=0.0)
+    assert no_stop["amb"][0]
