@@ -208,6 +208,48 @@ geer_status geer_set_profiling(geer_ctx* ctx, int32_t enable);
  * the recorded work to finish.  Clears the records. */
 int32_t geer_profile_read(geer_ctx* ctx, geer_profile_record* out, int32_t max);
 
+/*
+ * Render plans (batched serving).  A plan fixes a batch shape -- the number
+ * of views and each view's BEAP grid size -- the scene, the options, the
+ * output buffers and a capacity for the association list.  Its forward is
+ * enqueued with capacity-sized launches that read the live counts on the
+ * device (no host read-back), captured once into a hipGraph, and replayed by
+ * geer_plan_launch with new cameras (model, intrinsics, FoV, pose; the grid
+ * sizes must match the plan's).  Results are identical to geer_render of the
+ * same views.  A launch waits for the plan's previous launch; concurrent
+ * batches use separate plans on separate streams.  The scene arrays and the
+ * outputs must stay valid, and the scene unchanged, while the plan lives.
+ * When a batch's association list exceeds the capacity, that launch renders
+ * background and geer_plan_entries reports the overflow.
+ */
+typedef struct geer_plan geer_plan;
+
+/* Device workspace a plan of this shape needs, in bytes (same checks as
+ * geer_plan_create). */
+geer_status geer_plan_workspace_bytes(geer_ctx* ctx, const geer_scene* scene, int32_t n_views,
+                                      const geer_view* views, const geer_opts* opts, int64_t entry_capacity,
+                                      int64_t* bytes);
+/* Captures the plan's graph.  `views` give the shapes (the cameras are taken
+ * from each launch); rgb / depth / trans are device outputs as for
+ * geer_render, written by every launch (depth, trans may be NULL).
+ * entry_capacity bounds the association list.  workspace: caller-owned device
+ * memory of at least geer_plan_workspace_bytes, 256-byte aligned, or NULL for
+ * a plan-owned allocation.  Plans may share one workspace only if all their
+ * launches go to one stream.  Nothing runs on the device until a launch. */
+geer_status geer_plan_create(geer_ctx* ctx, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                             const geer_opts* opts, int64_t entry_capacity, void* workspace, int64_t workspace_bytes,
+                             float* rgb, float* depth, float* trans, geer_plan** out);
+/* Uploads the cameras of the next batch and replays the graph on `stream`. */
+geer_status geer_plan_launch(geer_plan* plan, const geer_view* views, void* stream);
+/* Waits for the last launch; reports its association-list length and the
+ * capacity, and returns GEER_ERR_CAPACITY if the list did not fit (the
+ * outputs of that launch are then incomplete and must be re-rendered). */
+geer_status geer_plan_entries(geer_plan* plan, int64_t* entries, int64_t* capacity);
+/* Device memory the plan allocated itself (0 with a caller workspace). */
+int64_t geer_plan_device_bytes(const geer_plan* plan);
+/* Waits for the plan's last launch and releases it (before geer_destroy). */
+void geer_plan_destroy(geer_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

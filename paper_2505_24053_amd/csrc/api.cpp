@@ -34,6 +34,13 @@ struct ProfSlot {
   uint64_t* host_stats = nullptr;  // pinned copy of the frame's device counters
 };
 
+// Conservative lambda^2 table for one alpha_min (device copy).
+struct LamTab {
+  float amin = 0.0f;
+  float* dev = nullptr;
+  int lo = 0, n = 0;
+};
+
 struct geer_ctx {
   int device = 0;
   bool profiling = false;
@@ -42,12 +49,33 @@ struct geer_ctx {
   std::mutex mu;
   std::vector<Block> cache;  // released device blocks, reusable on the same stream
   std::string err;
-  float lam_amin = -1.0f;
-  float* lam_dev = nullptr;
-  int lam_lo = 0, lam_n = 0;
+  std::vector<LamTab> lams;  // lambda^2 tables by alpha_min, kept until destroy
   void* pinned = nullptr;  // host staging for table uploads and read-backs
   size_t pinned_bytes = 0;
   int64_t live_frames = 0;
+};
+
+struct geer_plan {
+  geer_ctx* ctx = nullptr;
+  geer_scene scene{};
+  Opts op{};
+  int32_t nviews = 0;
+  std::vector<geer_view> shapes;
+  int64_t n = 0, items = 0, ntiles = 0, npix = 0, ecap = 0, bytes = 0;
+  size_t meta_bytes = 0;
+  void* ws = nullptr;     // workspace (device)
+  bool owns_ws = false;   // allocated by the plan
+  void* meta = nullptr;   // view tables inside the workspace
+  uint64_t* stats = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* staging[2] = {nullptr, nullptr};
+  hipEvent_t staged[2] = {nullptr, nullptr};
+  bool staged_used[2] = {false, false};
+  int next = 0;
+  hipEvent_t done = nullptr;
+  bool launched = false;
+  uint64_t* host_stats = nullptr;
 };
 
 struct geer_frame {
@@ -55,6 +83,7 @@ struct geer_frame {
   hipStream_t stream = nullptr;
   geer_scene scene{};
   Opts op{};
+  const float* lam = nullptr;  // lambda^2 table of the forward's alpha_min
   int32_t nviews = 0;
   int64_t n = 0, items = 0, ntiles = 0, npix = 0, entries = 0, visible = 0;
   size_t edges_off = 0, dtab_off = 0;  // sub-buffers of meta
@@ -177,21 +206,28 @@ geer_status check_opts(geer_ctx* c, const geer_opts& o) {
   return GEER_OK;
 }
 
-geer_status lambda_dev(geer_ctx* c, float amin, hipStream_t st) {
-  if (c->lam_dev && c->lam_amin == amin) return GEER_OK;
+// The device table for alpha_min, built on first use.  Tables are never freed
+// before the context, so frames and plans keep plain pointers to them.
+geer_status lambda_dev(geer_ctx* c, float amin, LamTab* out) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (const LamTab& t : c->lams)
+    if (t.amin == amin) {
+      *out = t;
+      return GEER_OK;
+    }
+  if (c->lams.size() >= 256) return fail(c, GEER_ERR_CAPACITY, "more than 256 distinct alpha_min values");
   std::vector<float> tab;
-  int lo, n;
-  lambda_table(amin, tab, lo, n);
-  if (c->lam_dev) {
-    HIP_TRY(c, hipStreamSynchronize(st));
-    (void)hipFree(c->lam_dev);
-    c->lam_dev = nullptr;
+  LamTab t;
+  t.amin = amin;
+  lambda_table(amin, tab, t.lo, t.n);
+  HIP_TRY(c, hipMalloc(&t.dev, tab.size() * sizeof(float)));
+  hipError_t e = hipMemcpy(t.dev, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(t.dev);
+    return fail(c, GEER_ERR_HIP, "lambda table upload: %s", hipGetErrorString(e));
   }
-  HIP_TRY(c, hipMalloc(&c->lam_dev, tab.size() * sizeof(float)));
-  HIP_TRY(c, hipMemcpy(c->lam_dev, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice));
-  c->lam_amin = amin;
-  c->lam_lo = lo;
-  c->lam_n = n;
+  c->lams.push_back(t);
+  *out = t;
   return GEER_OK;
 }
 
@@ -221,6 +257,146 @@ int bytes_for_tiles(int64_t max_tile) {
     max_tile >>= 8;
   }
   return passes;
+}
+
+
+// Device pointers of one forward.
+struct FwdBufs {
+  const ViewDev* views = nullptr;
+  const float* edges = nullptr;
+  const float2* dtab = nullptr;
+  Record* recs = nullptr;
+  uint2* rects = nullptr;
+  uint32_t *keys = nullptr, *counts = nullptr;
+  uint64_t* stats = nullptr;  // [0] entries, [1] visible, [2] evaluated pairs, [3] entries before the guard
+  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr, *hist = nullptr, *scratch = nullptr;
+  uint32_t *cnt_sorted = nullptr, *tiles_a = nullptr, *tiles_b = nullptr, *items_b = nullptr;
+  uint32_t *list = nullptr, *ranges = nullptr, *nlast = nullptr;
+  float* tfinal = nullptr;
+};
+
+// Stage (a): zero the counters, then preprocess + PBF of every item.
+void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, const Opts& op, const float* lam,
+                        const FwdBufs& b) {
+  launch_fill_u32(st, (uint32_t*)b.stats, 8, 0u);
+  launch_preprocess(st, sc.n, nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh, b.views, op, lam,
+                    b.edges, b.recs, b.rects, b.keys, b.counts, (unsigned long long*)b.stats);
+}
+
+// Stage (b): association list.  With exact sizes (dyn == false) nvis_cap and
+// ecap are the counts read back from the device; otherwise they are
+// capacities and every kernel reads the live counts from b.stats.
+// Returns the buffer holding the final (tile-sorted) list in b.list.
+void enqueue_association(hipStream_t st, int64_t n, int64_t items, int64_t nvis_cap, int64_t ecap, int64_t ntiles,
+                         bool dyn, const FwdBufs& b) {
+  const unsigned long long* dE = dyn ? (const unsigned long long*)b.stats : nullptr;
+  const unsigned long long* dV = dyn ? (const unsigned long long*)(b.stats + 1) : nullptr;
+  if (dyn) launch_capacity_guard(st, (unsigned long long*)b.stats, ecap);
+  if (nvis_cap > 0) {
+    radix_pass(st, b.keys, nullptr, b.counts, items, nullptr, 0, b.ka, b.va, b.hist, b.scratch);
+    radix_pass(st, b.ka, b.va, nullptr, nvis_cap, dV, 8, b.kb, b.vb, b.hist, b.scratch);
+    radix_pass(st, b.kb, b.vb, nullptr, nvis_cap, dV, 16, b.ka, b.va, b.hist, b.scratch);
+    radix_pass(st, b.ka, b.va, nullptr, nvis_cap, dV, 24, b.kb, b.vb, b.hist, b.scratch);
+    launch_gather_counts(st, b.vb, nvis_cap, dV, b.counts, b.cnt_sorted);
+    scan_exclusive(st, b.cnt_sorted, b.cnt_sorted, nvis_cap, b.scratch);
+    // Expansion in depth order into pair A or B, chosen so that after the
+    // tile passes (alternating A <-> B) the items end in b.list (pair B).
+    uint32_t *tA = b.tiles_a, *iA = b.items_b, *tB = b.tiles_b, *iB = b.list;
+    const int passes = bytes_for_tiles(ntiles - 1);
+    uint32_t* tc = (passes % 2 == 1) ? tA : tB;
+    uint32_t* ic = (passes % 2 == 1) ? iA : iB;
+    launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, tc, ic);
+    for (int p = 0; p < passes; ++p) {
+      uint32_t* to = (tc == tA) ? tB : tA;
+      uint32_t* io = (ic == iA) ? iB : iA;
+      radix_pass(st, tc, ic, nullptr, ecap, dE, 8 * p, to, io, b.hist, b.scratch);
+      tc = to;
+      ic = io;
+    }
+    if (dyn) launch_pad_list(st, b.list, ecap, dE);
+    else launch_fill_u32(st, b.list + ecap, 8, 0u);
+    launch_ranges(st, tc, ecap, dE, ntiles, b.ranges);
+  } else {
+    launch_fill_u32(st, b.list, 8, 0u);
+    launch_ranges(st, nullptr, 0, nullptr, ntiles, b.ranges);
+  }
+}
+
+// Stage (c): the render kernel.
+void enqueue_render(hipStream_t st, const Opts& op, int64_t ntiles, int32_t nviews, const FwdBufs& b, float* rgb,
+                    float* depth, float* trans) {
+  launch_render(st, op.lambda_mode == 1, ntiles, b.views, nviews, b.dtab, b.ranges, b.list, b.rects, b.recs, op, rgb,
+                depth, trans, b.nlast, b.tfinal, (unsigned long long*)(b.stats + 2));
+}
+
+// Host-side per-view tables of a batch, packed as [ViewDev...][edges][dtab].
+struct ViewTables {
+  std::vector<ViewDev> hv;
+  std::vector<float> edges, dtab;
+  int64_t ntiles = 0, npix = 0;
+  size_t views_bytes = 0, edges_off = 0, dtab_off = 0, bytes = 0;
+};
+
+geer_status build_tables(geer_ctx* c, int32_t n_views, const geer_view* views, ViewTables& t) {
+  t.hv.assign(n_views, ViewDev{});
+  t.edges.clear();
+  t.dtab.clear();
+  t.ntiles = t.npix = 0;
+  for (int i = 0; i < n_views; ++i) {
+    view_constants(views[i], t.hv[i]);
+    std::vector<float> ex, ey, dx, dy;
+    edge_tables(views[i], ex, ey);
+    direction_tables(views[i], dx, dy);
+    t.hv[i].tile_base = (int32_t)t.ntiles;
+    t.hv[i].pix_base = (int32_t)t.npix;
+    t.hv[i].ex_off = (int32_t)t.edges.size();
+    t.edges.insert(t.edges.end(), ex.begin(), ex.end());
+    t.hv[i].ey_off = (int32_t)t.edges.size();
+    t.edges.insert(t.edges.end(), ey.begin(), ey.end());
+    t.hv[i].dx_off = (int32_t)(t.dtab.size() / 2);
+    t.dtab.insert(t.dtab.end(), dx.begin(), dx.end());
+    t.hv[i].dy_off = (int32_t)(t.dtab.size() / 2);
+    t.dtab.insert(t.dtab.end(), dy.begin(), dy.end());
+    t.ntiles += (int64_t)t.hv[i].tiles_x * t.hv[i].tiles_y;
+    t.npix += (int64_t)views[i].width * views[i].height;
+    if (t.ntiles >= ((int64_t)1 << 31) || t.npix >= ((int64_t)1 << 31))
+      return fail(c, GEER_ERR_CAPACITY, "batch exceeds 2^31 tiles or pixels");
+  }
+  t.views_bytes = sizeof(ViewDev) * t.hv.size();
+  t.edges_off = round_up(t.views_bytes, 256);
+  t.dtab_off = round_up(t.edges_off + t.edges.size() * sizeof(float), 256);
+  t.bytes = t.dtab_off + t.dtab.size() * sizeof(float);
+  return GEER_OK;
+}
+
+void pack_tables(const ViewTables& t, void* dst) {
+  std::memcpy(dst, t.hv.data(), t.views_bytes);
+  std::memcpy((char*)dst + t.edges_off, t.edges.data(), t.edges.size() * sizeof(float));
+  std::memcpy((char*)dst + t.dtab_off, t.dtab.data(), t.dtab.size() * sizeof(float));
+}
+
+Opts make_opts(const LamTab& lt, const geer_opts& o) {
+  Opts op{};
+  op.alpha_min = o.alpha_min;
+  op.alpha_max = o.alpha_max;
+  op.t_min = o.t_min;
+  op.lambda_fixed = o.lambda_fixed;
+  op.lambda_mode = o.lambda_mode;
+  op.lam2_fixed = lambda_fixed_hat(o.lambda_fixed);
+  op.kmax_fixed = o.lambda_fixed * o.lambda_fixed;
+  op.lam_lo = lt.lo;
+  op.lam_n = lt.n;
+  return op;
+}
+
+geer_status check_scene(geer_ctx* c, const geer_scene* scene) {
+  const int64_t n = scene->n;
+  if (n < 0 || n > ((int64_t)1 << 28)) return fail(c, GEER_ERR_INVALID_ARG, "scene size %lld", (long long)n);
+  if (scene->sh_degree < 0 || scene->sh_degree > 3) return fail(c, GEER_ERR_INVALID_ARG, "sh_degree must be 0..3");
+  if (scene->reserved != 0) return fail(c, GEER_ERR_INVALID_ARG, "scene.reserved must be 0");
+  if (n > 0 && (!scene->mean || !scene->scale || !scene->quat || !scene->opacity || !scene->sh))
+    return fail(c, GEER_ERR_INVALID_ARG, "null scene array");
+  return GEER_OK;
 }
 
 }  // namespace
@@ -263,7 +439,7 @@ void geer_destroy(geer_ctx* c) {
       if (e) (void)hipEventDestroy(e);
     if (ps.host_stats) (void)hipHostFree(ps.host_stats);
   }
-  if (c->lam_dev) (void)hipFree(c->lam_dev);
+  for (LamTab& t : c->lams) (void)hipFree(t.dev);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
 }
@@ -277,56 +453,22 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   if (frame_out) *frame_out = nullptr;
   if (!scene || !views || !opts || !rgb) return fail(c, GEER_ERR_INVALID_ARG, "null argument");
   if (n_views < 1 || n_views > 4096) return fail(c, GEER_ERR_INVALID_ARG, "n_views %d out of range", n_views);
-  const int64_t n = scene->n;
-  if (n < 0 || n > ((int64_t)1 << 28)) return fail(c, GEER_ERR_INVALID_ARG, "scene size %lld", (long long)n);
-  if (scene->sh_degree < 0 || scene->sh_degree > 3) return fail(c, GEER_ERR_INVALID_ARG, "sh_degree must be 0..3");
-  if (scene->reserved != 0) return fail(c, GEER_ERR_INVALID_ARG, "scene.reserved must be 0");
-  if (n > 0 && (!scene->mean || !scene->scale || !scene->quat || !scene->opacity || !scene->sh))
-    return fail(c, GEER_ERR_INVALID_ARG, "null scene array");
   geer_status s;
+  if ((s = check_scene(c, scene)) != GEER_OK) return s;
   if ((s = check_opts(c, *opts)) != GEER_OK) return s;
+  const int64_t n = scene->n;
   const int64_t items = n * n_views;
   if (items >= ((int64_t)1 << 32) - 16) return fail(c, GEER_ERR_CAPACITY, "Gaussians x views exceeds 2^32");
   for (int i = 0; i < n_views; ++i)
     if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(c, hipSetDevice(c->device));
-
-  // ---- per-view constants and tables, one upload ----
-  std::vector<ViewDev> hv(n_views);
-  std::vector<float> edges, dtab;
-  int64_t ntiles = 0, npix = 0;
-  for (int i = 0; i < n_views; ++i) {
-    view_constants(views[i], hv[i]);
-    std::vector<float> ex, ey, dx, dy;
-    edge_tables(views[i], ex, ey);
-    direction_tables(views[i], dx, dy);
-    hv[i].tile_base = (int32_t)ntiles;
-    hv[i].pix_base = (int32_t)npix;
-    hv[i].ex_off = (int32_t)edges.size();
-    edges.insert(edges.end(), ex.begin(), ex.end());
-    hv[i].ey_off = (int32_t)edges.size();
-    edges.insert(edges.end(), ey.begin(), ey.end());
-    hv[i].dx_off = (int32_t)(dtab.size() / 2);
-    dtab.insert(dtab.end(), dx.begin(), dx.end());
-    hv[i].dy_off = (int32_t)(dtab.size() / 2);
-    dtab.insert(dtab.end(), dy.begin(), dy.end());
-    ntiles += (int64_t)hv[i].tiles_x * hv[i].tiles_y;
-    npix += (int64_t)views[i].width * views[i].height;
-    if (ntiles >= ((int64_t)1 << 31) || npix >= ((int64_t)1 << 31))
-      return fail(c, GEER_ERR_CAPACITY, "batch exceeds 2^31 tiles or pixels");
-  }
-  Opts op{};
-  op.alpha_min = opts->alpha_min;
-  op.alpha_max = opts->alpha_max;
-  op.t_min = opts->t_min;
-  op.lambda_fixed = opts->lambda_fixed;
-  op.lambda_mode = opts->lambda_mode;
-  op.lam2_fixed = lambda_fixed_hat(opts->lambda_fixed);
-  op.kmax_fixed = opts->lambda_fixed * opts->lambda_fixed;
-  if ((s = lambda_dev(c, opts->alpha_min, st)) != GEER_OK) return s;
-  op.lam_lo = c->lam_lo;
-  op.lam_n = c->lam_n;
+  ViewTables tab;
+  if ((s = build_tables(c, n_views, views, tab)) != GEER_OK) return s;
+  LamTab lt;
+  if ((s = lambda_dev(c, opts->alpha_min, &lt)) != GEER_OK) return s;
+  const Opts op = make_opts(lt, *opts);
+  const int64_t ntiles = tab.ntiles, npix = tab.npix;
 
   geer_frame* f = new (std::nothrow) geer_frame();
   if (!f) return fail(c, GEER_ERR_OOM, "frame allocation");
@@ -334,13 +476,16 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   f->stream = st;
   f->scene = *scene;
   f->op = op;
+  f->lam = lt.dev;
   f->nviews = n_views;
   f->n = n;
   f->items = items;
   f->ntiles = ntiles;
   f->npix = npix;
   f->views.assign(views, views + n_views);
-  f->hviews = hv;
+  f->hviews = tab.hv;
+  f->edges_off = tab.edges_off;
+  f->dtab_off = tab.dtab_off;
 
   // Temporaries of the sort; released at the end of the call.
   Block ka, va, kb, vb, hist, scratch, tiles_a, tiles_b, items_b, cnt_sorted;
@@ -363,23 +508,16 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
     if (e_ != hipSuccess) return cleanup(fail(c, GEER_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)));   \
   } while (0)
 
-  const size_t views_bytes = sizeof(ViewDev) * hv.size();
-  const size_t edges_off = round_up(views_bytes, 256);
-  const size_t dtab_off = round_up(edges_off + edges.size() * sizeof(float), 256);
-  const size_t meta_bytes = dtab_off + dtab.size() * sizeof(float);
-  TRY(acquire(c, meta_bytes, st, f->meta));
-  TRY(ensure_pinned(c, std::max<size_t>(meta_bytes, 64)));
+  TRY(acquire(c, tab.bytes, st, f->meta));
+  TRY(ensure_pinned(c, std::max<size_t>(tab.bytes, 64)));
   // The previous call's read-back synchronised the stream, so the staging
   // buffer is free again.
-  std::memcpy(c->pinned, hv.data(), views_bytes);
-  std::memcpy((char*)c->pinned + edges_off, edges.data(), edges.size() * sizeof(float));
-  std::memcpy((char*)c->pinned + dtab_off, dtab.data(), dtab.size() * sizeof(float));
-  HTRY(hipMemcpyAsync(f->meta.p, c->pinned, meta_bytes, hipMemcpyHostToDevice, st));
-  f->edges_off = edges_off;
-  f->dtab_off = dtab_off;
-  const ViewDev* d_views = (const ViewDev*)f->meta.p;
-  const float* d_edges = (const float*)((char*)f->meta.p + edges_off);
-  const float2* d_dtab = (const float2*)((char*)f->meta.p + dtab_off);
+  pack_tables(tab, c->pinned);
+  HTRY(hipMemcpyAsync(f->meta.p, c->pinned, tab.bytes, hipMemcpyHostToDevice, st));
+  FwdBufs b;
+  b.views = (const ViewDev*)f->meta.p;
+  b.edges = (const float*)((char*)f->meta.p + tab.edges_off);
+  b.dtab = (const float2*)((char*)f->meta.p + tab.dtab_off);
 
   // ---- stage (a): preprocess + PBF ----
   const int64_t it1 = std::max<int64_t>(items, 1);
@@ -387,17 +525,18 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   TRY(acquire(c, sizeof(uint2) * it1, st, f->rects));
   TRY(acquire(c, 4 * it1, st, f->keys));
   TRY(acquire(c, 4 * it1, st, f->counts));
-  TRY(acquire(c, 64, st, f->stats));  // [0] entries, [1] visible, [2] evaluated, [3] spare
-  uint64_t* d_stats = (uint64_t*)f->stats.p;
-  launch_fill_u32(st, (uint32_t*)d_stats, 8, 0u);
+  TRY(acquire(c, 64, st, f->stats));
+  b.recs = (Record*)f->recs.p;
+  b.rects = (uint2*)f->rects.p;
+  b.keys = (uint32_t*)f->keys.p;
+  b.counts = (uint32_t*)f->counts.p;
+  b.stats = (uint64_t*)f->stats.p;
   ProfSlot* ps = prof_slot(c);
   prof_mark(ps, 0, st);
-  launch_preprocess(st, n, n_views, scene->sh_degree, scene->mean, scene->scale, scene->quat, scene->opacity,
-                    scene->sh, d_views, op, c->lam_dev, d_edges, (Record*)f->recs.p, (uint2*)f->rects.p,
-                    (uint32_t*)f->keys.p, (uint32_t*)f->counts.p, (unsigned long long*)d_stats);
+  enqueue_preprocess(st, *scene, n_views, op, lt.dev, b);
   HTRY(hipGetLastError());
   prof_mark(ps, 1, st);
-  HTRY(hipMemcpyAsync(c->pinned, d_stats, 16, hipMemcpyDeviceToHost, st));
+  HTRY(hipMemcpyAsync(c->pinned, b.stats, 16, hipMemcpyDeviceToHost, st));
   HTRY(hipStreamSynchronize(st));
   uint64_t totals[2];
   std::memcpy(totals, c->pinned, 16);
@@ -423,45 +562,12 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   TRY(acquire(c, 4 * (e1 + 8), st, f->list));
   TRY(acquire(c, 4 * (e1 + 8), st, items_b));
   TRY(acquire(c, 4 * (ntiles + 1), st, f->ranges));
+  b.ka = (uint32_t*)ka.p; b.va = (uint32_t*)va.p; b.kb = (uint32_t*)kb.p; b.vb = (uint32_t*)vb.p;
+  b.hist = (uint32_t*)hist.p; b.scratch = (uint32_t*)scratch.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
+  b.tiles_a = (uint32_t*)tiles_a.p; b.tiles_b = (uint32_t*)tiles_b.p; b.items_b = (uint32_t*)items_b.p;
+  b.list = (uint32_t*)f->list.p; b.ranges = (uint32_t*)f->ranges.p;
   prof_mark(ps, 2, st);
-  uint32_t* H = (uint32_t*)hist.p;
-  uint32_t* SC = (uint32_t*)scratch.p;
-  if (nvis > 0) {
-    radix_pass(st, (const uint32_t*)f->keys.p, nullptr, (const uint32_t*)f->counts.p, items, 0, (uint32_t*)ka.p,
-               (uint32_t*)va.p, H, SC);
-    radix_pass(st, (uint32_t*)ka.p, (uint32_t*)va.p, nullptr, nvis, 8, (uint32_t*)kb.p, (uint32_t*)vb.p, H, SC);
-    radix_pass(st, (uint32_t*)kb.p, (uint32_t*)vb.p, nullptr, nvis, 16, (uint32_t*)ka.p, (uint32_t*)va.p, H, SC);
-    radix_pass(st, (uint32_t*)ka.p, (uint32_t*)va.p, nullptr, nvis, 24, (uint32_t*)kb.p, (uint32_t*)vb.p, H, SC);
-    const uint32_t* sorted_items = (const uint32_t*)vb.p;
-    launch_gather_counts(st, sorted_items, nvis, (const uint32_t*)f->counts.p, (uint32_t*)cnt_sorted.p);
-    scan_exclusive(st, (uint32_t*)cnt_sorted.p, (uint32_t*)cnt_sorted.p, nvis, SC);
-    // Expansion writes (tile, item) entries in depth order into buffer pair A
-    // or B, chosen so that after the tile passes (alternating A <-> B) the
-    // items end in f->list (pair B).
-    uint32_t* tA = (uint32_t*)tiles_a.p;
-    uint32_t* iA = (uint32_t*)items_b.p;
-    uint32_t* tB = (uint32_t*)tiles_b.p;
-    uint32_t* iB = (uint32_t*)f->list.p;
-    const int passes = bytes_for_tiles(ntiles - 1);
-    uint32_t* tc = (passes % 2 == 1) ? tA : tB;
-    uint32_t* ic = (passes % 2 == 1) ? iA : iB;
-    launch_expand(st, sorted_items, (const uint32_t*)cnt_sorted.p, nvis, E, (const uint2*)f->rects.p, d_views, n,
-                  tc, ic);
-    for (int p = 0; p < passes; ++p) {
-      uint32_t* to = (tc == tA) ? tB : tA;
-      uint32_t* io = (ic == iA) ? iB : iA;
-      radix_pass(st, tc, ic, nullptr, E, 8 * p, to, io, H, SC);
-      tc = to;
-      ic = io;
-    }
-    const uint32_t* final_tiles = tc;
-    uint32_t* i_out = iB;
-    launch_fill_u32(st, i_out + E, 8, 0u);  // padding read by the 8-wide batches
-    launch_ranges(st, final_tiles, E, ntiles, (uint32_t*)f->ranges.p);
-  } else {
-    launch_fill_u32(st, (uint32_t*)f->list.p, 8, 0u);
-    launch_ranges(st, nullptr, 0, ntiles, (uint32_t*)f->ranges.p);
-  }
+  enqueue_association(st, n, items, nvis, E, ntiles, false, b);
   HTRY(hipGetLastError());
 
   // ---- stage (c): render ----
@@ -469,15 +575,14 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   if (keep) {
     TRY(acquire(c, 4 * npix, st, f->nlast));
     TRY(acquire(c, 4 * npix, st, f->tfinal));
+    b.nlast = (uint32_t*)f->nlast.p;
+    b.tfinal = (float*)f->tfinal.p;
   }
   prof_mark(ps, 3, st);
-  launch_render(st, op.lambda_mode == 1, ntiles, d_views, n_views, d_dtab, (const uint32_t*)f->ranges.p,
-                (const uint32_t*)f->list.p, (const uint2*)f->rects.p, (const Record*)f->recs.p, op, rgb, depth,
-                trans, keep ? (uint32_t*)f->nlast.p : nullptr, keep ? (float*)f->tfinal.p : nullptr,
-                (unsigned long long*)(d_stats + 2));
+  enqueue_render(st, op, ntiles, n_views, b, rgb, depth, trans);
   HTRY(hipGetLastError());
   prof_mark(ps, 4, st);
-  if (ps) HTRY(hipMemcpyAsync(ps->host_stats, d_stats, 32, hipMemcpyDeviceToHost, st));
+  if (ps) HTRY(hipMemcpyAsync(ps->host_stats, b.stats, 32, hipMemcpyDeviceToHost, st));
   cleanup(GEER_OK);
   if (keep) {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -503,10 +608,6 @@ geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* 
   if (!f->nlast.p || !f->tfinal.p) return fail(c, GEER_ERR_INVALID_ARG, "frame holds no forward state");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(c, hipSetDevice(c->device));
-  if ((f->op.lambda_mode == 0) && (!c->lam_dev || c->lam_amin != f->op.alpha_min)) {
-    geer_status s = lambda_dev(c, f->op.alpha_min, st);
-    if (s != GEER_OK) return s;
-  }
   Block acc;
   geer_status s = acquire(c, sizeof(float) * 16 * (size_t)std::max<int64_t>(f->items, 1), st, acc);
   if (s != GEER_OK) return s;
@@ -516,7 +617,7 @@ geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* 
   const float2* d_dtab = (const float2*)(meta + f->dtab_off);
   const geer_scene& sc = f->scene;
   launch_backward(st, f->op.lambda_mode == 1, f->ntiles, f->n, f->nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat,
-                  sc.opacity, sc.sh, d_views, d_dtab, d_edges, c->lam_dev, f->op, (const uint32_t*)f->ranges.p,
+                  sc.opacity, sc.sh, d_views, d_dtab, d_edges, f->lam, f->op, (const uint32_t*)f->ranges.p,
                   (const uint32_t*)f->list.p, (const uint2*)f->rects.p, (const Record*)f->recs.p,
                   (const uint32_t*)f->nlast.p, (const float*)f->tfinal.p, dl_drgb, (float*)acc.p, accumulate != 0,
                   g_mean, g_scale, g_quat, g_opacity, g_sh);
@@ -659,6 +760,244 @@ geer_status geer_l1_loss(geer_ctx* c, int64_t pixels, const float* rgb, const fl
   release(c, scratch);
   if (e != hipSuccess) return fail(c, GEER_ERR_HIP, "loss launch: %s", hipGetErrorString(e));
   return GEER_OK;
+}
+
+
+// Workspace layout of a plan: every buffer of the capacity-sized forward,
+// 256-byte aligned, carved from one block.
+struct PlanLayout {
+  size_t meta = 0, recs = 0, rects = 0, keys = 0, counts = 0, stats = 0, ka = 0, va = 0, kb = 0, vb = 0, hist = 0,
+         scratch = 0, cnt_sorted = 0, tiles_a = 0, tiles_b = 0, items_b = 0, list = 0, ranges = 0, total = 0;
+};
+
+PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t ntiles) {
+  PlanLayout L;
+  size_t off = 0;
+  auto put = [&](size_t bytes) {
+    const size_t at = off;
+    off += round_up(std::max<size_t>(bytes, 256), 256);
+    return at;
+  };
+  const int64_t it1 = std::max<int64_t>(items, 1);
+  const int64_t hist_words = radix_hist_words(std::max(it1, ecap));
+  L.meta = put(meta_bytes);
+  L.recs = put(sizeof(Record) * it1);
+  L.rects = put(sizeof(uint2) * it1);
+  L.keys = put(4 * it1);
+  L.counts = put(4 * it1);
+  L.stats = put(64);
+  L.ka = put(4 * it1);
+  L.va = put(4 * it1);
+  L.kb = put(4 * it1);
+  L.vb = put(4 * it1);
+  L.hist = put(4 * (size_t)hist_words);
+  L.scratch = put(4 * (size_t)scan_scratch_words(std::max<int64_t>(hist_words, it1)));
+  L.cnt_sorted = put(4 * it1);
+  L.tiles_a = put(4 * (ecap + 8));
+  L.tiles_b = put(4 * (ecap + 8));
+  L.items_b = put(4 * (ecap + 8));
+  L.list = put(4 * (ecap + 8));
+  L.ranges = put(4 * (ntiles + 1));
+  L.total = off;
+  return L;
+}
+
+// Shared argument checks of geer_plan_workspace_bytes and geer_plan_create.
+geer_status plan_check(geer_ctx* c, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                       const geer_opts* opts, int64_t entry_capacity, ViewTables& tab) {
+  if (!scene || !views || !opts) return fail(c, GEER_ERR_INVALID_ARG, "null argument");
+  if (n_views < 1 || n_views > 4096) return fail(c, GEER_ERR_INVALID_ARG, "n_views %d out of range", n_views);
+  if (entry_capacity < 1 || entry_capacity >= ((int64_t)1 << 32) - 16)
+    return fail(c, GEER_ERR_INVALID_ARG, "entry capacity %lld out of range", (long long)entry_capacity);
+  geer_status s;
+  if ((s = check_scene(c, scene)) != GEER_OK) return s;
+  if ((s = check_opts(c, *opts)) != GEER_OK) return s;
+  for (int i = 0; i < n_views; ++i)
+    if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
+  if (scene->n < 1) return fail(c, GEER_ERR_INVALID_ARG, "a plan needs a non-empty scene");
+  if (scene->n * n_views >= ((int64_t)1 << 32) - 16)
+    return fail(c, GEER_ERR_CAPACITY, "Gaussians x views exceeds 2^32");
+  return build_tables(c, n_views, views, tab);
+}
+
+geer_status geer_plan_workspace_bytes(geer_ctx* c, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                                      const geer_opts* opts, int64_t entry_capacity, int64_t* bytes) {
+  if (!c || !bytes) return GEER_ERR_INVALID_ARG;
+  ViewTables tab;
+  geer_status s = plan_check(c, scene, n_views, views, opts, entry_capacity, tab);
+  if (s != GEER_OK) return s;
+  *bytes = (int64_t)plan_layout(tab.bytes, scene->n * n_views, entry_capacity, tab.ntiles).total;
+  return GEER_OK;
+}
+
+geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                             const geer_opts* opts, int64_t entry_capacity, void* workspace,
+                             int64_t workspace_bytes, float* rgb, float* depth, float* trans, geer_plan** out) {
+  if (!c || !out) return GEER_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!rgb) return fail(c, GEER_ERR_INVALID_ARG, "null rgb");
+  ViewTables tab;
+  geer_status s = plan_check(c, scene, n_views, views, opts, entry_capacity, tab);
+  if (s != GEER_OK) return s;
+  const int64_t items = scene->n * n_views;
+  const PlanLayout lay = plan_layout(tab.bytes, items, entry_capacity, tab.ntiles);
+  if (workspace && ((uintptr_t)workspace % 256 != 0 || workspace_bytes < (int64_t)lay.total))
+    return fail(c, GEER_ERR_INVALID_ARG, "workspace must be 256-byte aligned and hold %zu bytes", lay.total);
+  HIP_TRY(c, hipSetDevice(c->device));
+  LamTab lt;
+  if ((s = lambda_dev(c, opts->alpha_min, &lt)) != GEER_OK) return s;
+
+  geer_plan* P = new (std::nothrow) geer_plan();
+  if (!P) return fail(c, GEER_ERR_OOM, "plan allocation");
+  P->ctx = c;
+  P->scene = *scene;
+  P->op = make_opts(lt, *opts);
+  P->nviews = n_views;
+  P->shapes.assign(views, views + n_views);
+  P->n = scene->n;
+  P->items = items;
+  P->ntiles = tab.ntiles;
+  P->npix = tab.npix;
+  P->ecap = entry_capacity;
+  P->meta_bytes = tab.bytes;
+  auto bail = [&](geer_status st_) {
+    geer_plan_destroy(P);
+    return st_;
+  };
+#define PHIP(call)                                                                                       \
+  do {                                                                                                   \
+    hipError_t e_ = (call);                                                                              \
+    if (e_ != hipSuccess) return bail(fail(c, GEER_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)));    \
+  } while (0)
+  if (workspace) {
+    P->ws = workspace;
+  } else {
+    if (hipMalloc(&P->ws, lay.total) != hipSuccess) {
+      (void)hipGetLastError();
+      P->ws = nullptr;
+      return bail(fail(c, GEER_ERR_OOM, "plan workspace of %zu bytes", lay.total));
+    }
+    P->owns_ws = true;
+    P->bytes = (int64_t)lay.total;
+  }
+  char* w = (char*)P->ws;
+  FwdBufs b;
+  P->meta = w + lay.meta;
+  b.views = (const ViewDev*)P->meta;
+  b.edges = (const float*)((char*)P->meta + tab.edges_off);
+  b.dtab = (const float2*)((char*)P->meta + tab.dtab_off);
+  b.recs = (Record*)(w + lay.recs);
+  b.rects = (uint2*)(w + lay.rects);
+  b.keys = (uint32_t*)(w + lay.keys);
+  b.counts = (uint32_t*)(w + lay.counts);
+  b.stats = (uint64_t*)(w + lay.stats);
+  P->stats = b.stats;
+  b.ka = (uint32_t*)(w + lay.ka);
+  b.va = (uint32_t*)(w + lay.va);
+  b.kb = (uint32_t*)(w + lay.kb);
+  b.vb = (uint32_t*)(w + lay.vb);
+  b.hist = (uint32_t*)(w + lay.hist);
+  b.scratch = (uint32_t*)(w + lay.scratch);
+  b.cnt_sorted = (uint32_t*)(w + lay.cnt_sorted);
+  b.tiles_a = (uint32_t*)(w + lay.tiles_a);
+  b.tiles_b = (uint32_t*)(w + lay.tiles_b);
+  b.items_b = (uint32_t*)(w + lay.items_b);
+  b.list = (uint32_t*)(w + lay.list);
+  b.ranges = (uint32_t*)(w + lay.ranges);
+  for (int k = 0; k < 2; ++k) {
+    PHIP(hipHostMalloc(&P->staging[k], std::max<size_t>(tab.bytes, 64), hipHostMallocDefault));
+    PHIP(hipEventCreateWithFlags(&P->staged[k], hipEventDisableTiming));
+  }
+  PHIP(hipEventCreateWithFlags(&P->done, hipEventDisableTiming));
+  PHIP(hipHostMalloc((void**)&P->host_stats, 64, hipHostMallocDefault));
+
+  // Capture the forward once.  Nothing runs at capture time; the tables are
+  // uploaded by every launch before the graph.
+  hipStream_t cs = nullptr;
+  PHIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    enqueue_preprocess(cs, P->scene, n_views, P->op, lt.dev, b);
+    enqueue_association(cs, P->n, items, std::max<int64_t>(items, 1), entry_capacity, P->ntiles, true, b);
+    enqueue_render(cs, P->op, P->ntiles, n_views, b, rgb, depth, trans);
+    hipError_t e2 = hipStreamEndCapture(cs, &P->graph);
+    e = e2 != hipSuccess ? e2 : hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return bail(fail(c, GEER_ERR_HIP, "graph capture: %s", hipGetErrorString(e)));
+  *out = P;
+  return GEER_OK;
+#undef PHIP
+}
+
+geer_status geer_plan_launch(geer_plan* P, const geer_view* views, void* stream) {
+  if (!P || !views) return GEER_ERR_INVALID_ARG;
+  geer_ctx* c = P->ctx;
+  geer_status s;
+  for (int i = 0; i < P->nviews; ++i) {
+    if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
+    if (views[i].width != P->shapes[i].width || views[i].height != P->shapes[i].height)
+      return fail(c, GEER_ERR_INVALID_ARG, "view %d: grid %dx%d differs from the plan's %dx%d", i, views[i].width,
+                  views[i].height, P->shapes[i].width, P->shapes[i].height);
+  }
+  HIP_TRY(c, hipSetDevice(c->device));
+  ViewTables tab;
+  if ((s = build_tables(c, P->nviews, views, tab)) != GEER_OK) return s;
+  if (tab.bytes != P->meta_bytes) return fail(c, GEER_ERR_INVALID_ARG, "view tables changed size");
+  hipStream_t st = (hipStream_t)stream;
+  // the previous launch (possibly on another stream) still reads the tables
+  if (P->launched) HIP_TRY(c, hipStreamWaitEvent(st, P->done, 0));
+  const int k = P->next;
+  if (P->staged_used[k]) HIP_TRY(c, hipEventSynchronize(P->staged[k]));  // its previous upload has left the buffer
+  pack_tables(tab, P->staging[k]);
+  HIP_TRY(c, hipMemcpyAsync(P->meta, P->staging[k], tab.bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(c, hipEventRecord(P->staged[k], st));
+  P->staged_used[k] = true;
+  P->next = 1 - k;
+  HIP_TRY(c, hipGraphLaunch(P->exec, st));
+  HIP_TRY(c, hipMemcpyAsync(P->host_stats, P->stats, 32, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipEventRecord(P->done, st));
+  P->launched = true;
+  return GEER_OK;
+}
+
+geer_status geer_plan_entries(geer_plan* P, int64_t* entries, int64_t* capacity) {
+  if (!P) return GEER_ERR_INVALID_ARG;
+  geer_ctx* c = P->ctx;
+  if (capacity) *capacity = P->ecap;
+  if (!P->launched) {
+    if (entries) *entries = 0;
+    return GEER_OK;
+  }
+  HIP_TRY(c, hipEventSynchronize(P->done));
+  const int64_t E = (int64_t)P->host_stats[3];
+  if (entries) *entries = E;
+  if (E > P->ecap)
+    return fail(c, GEER_ERR_CAPACITY, "association list of %lld entries exceeds the plan's %lld", (long long)E,
+                (long long)P->ecap);
+  return GEER_OK;
+}
+
+int64_t geer_plan_device_bytes(const geer_plan* P) { return P ? P->bytes : -1; }
+
+void geer_plan_destroy(geer_plan* P) {
+  if (!P) return;
+  (void)hipSetDevice(P->ctx->device);
+  if (P->launched) (void)hipEventSynchronize(P->done);
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  for (int k = 0; k < 2; ++k) {
+    if (P->staged[k]) {
+      if (P->staged_used[k]) (void)hipEventSynchronize(P->staged[k]);
+      (void)hipEventDestroy(P->staged[k]);
+    }
+    if (P->staging[k]) (void)hipHostFree(P->staging[k]);
+  }
+  if (P->done) (void)hipEventDestroy(P->done);
+  if (P->host_stats) (void)hipHostFree(P->host_stats);
+  if (P->owns_ws && P->ws) (void)hipFree(P->ws);
+  delete P;
 }
 
 }  // extern "C"

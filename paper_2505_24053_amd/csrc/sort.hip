@@ -12,6 +12,8 @@
 // histograms and a wave-ballot match to rank equal digits stably.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "geer_common.h"
 
 namespace geer {
@@ -88,10 +90,17 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t* __re
 
 // Per-block digit histogram, written digit-major: hist[d * nblocks + b].
 // With `filter`, items whose filter value is 0 are skipped (compaction pass).
+// The element count is n_cap, or min(*dyn, n_cap) when a device-side count
+// is given (capacity-sized launches that need no host read-back).
+__device__ __forceinline__ int64_t dyn_count(int64_t n_cap, const unsigned long long* dyn) {
+  return dyn ? min((int64_t)*dyn, n_cap) : n_cap;
+}
+
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                            const uint32_t* __restrict__ filter, int64_t n,
-                                                            int shift, uint32_t* __restrict__ hist,
-                                                            int64_t nblocks) {
+                                                            const uint32_t* __restrict__ filter, int64_t n_cap,
+                                                            const unsigned long long* __restrict__ dyn, int shift,
+                                                            uint32_t* __restrict__ hist, int64_t nblocks) {
+  const int64_t n = dyn_count(n_cap, dyn);
   __shared__ uint32_t cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -110,8 +119,10 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
 // its wave (ballot match) plus the counts of the earlier waves.
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    const uint32_t* __restrict__ filter, int64_t n, int shift, const uint32_t* __restrict__ hist_off,
-    int64_t nblocks, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    const uint32_t* __restrict__ filter, int64_t n_cap, const unsigned long long* __restrict__ dyn, int shift,
+    const uint32_t* __restrict__ hist_off, int64_t nblocks, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out) {
+  const int64_t n = dyn_count(n_cap, dyn);
   __shared__ uint32_t running[256];
   __shared__ uint32_t wcnt[2][4][256];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -154,11 +165,14 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
 
 // ------------------------------------------------------------ expansion --
 
-__global__ __launch_bounds__(kBlock) void gather_counts_kernel(const uint32_t* __restrict__ items, int64_t m,
+__global__ __launch_bounds__(kBlock) void gather_counts_kernel(const uint32_t* __restrict__ items, int64_t m_cap,
+                                                               const unsigned long long* __restrict__ dyn,
                                                                const uint32_t* __restrict__ counts,
                                                                uint32_t* __restrict__ out) {
+  const int64_t m = dyn_count(m_cap, dyn);
   int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j < m) out[j] = counts[items[j]];
+  else if (j < m_cap) out[j] = 0u;
 }
 
 constexpr int kExpandPer = 8;
@@ -167,11 +181,16 @@ constexpr int kExpandPer = 8;
 // owner of its first entry), the block stages its 2048 entries in LDS and
 // writes them back lane-striped so every store is coalesced.
 __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restrict__ items,
-                                                        const uint32_t* __restrict__ offs, int64_t m,
-                                                        int64_t total, const uint2* __restrict__ rects,
+                                                        const uint32_t* __restrict__ offs, int64_t m_cap,
+                                                        const unsigned long long* __restrict__ dyn_m,
+                                                        int64_t total_cap,
+                                                        const unsigned long long* __restrict__ dyn_total,
+                                                        const uint2* __restrict__ rects,
                                                         const ViewDev* __restrict__ views, int64_t n,
                                                         uint32_t* __restrict__ tiles_out,
                                                         uint32_t* __restrict__ items_out) {
+  const int64_t m = dyn_count(m_cap, dyn_m);
+  const int64_t total = dyn_count(total_cap, dyn_total);
   __shared__ uint32_t s_tile[kBlock * kExpandPer];
   __shared__ uint32_t s_item[kBlock * kExpandPer];
   const int64_t block0 = (int64_t)blockIdx.x * kBlock * kExpandPer;
@@ -212,9 +231,15 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   }
 }
 
-__global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t* __restrict__ tiles, int64_t total,
+__global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t* __restrict__ tiles, int64_t total_cap,
+                                                        const unsigned long long* __restrict__ dyn,
                                                         int64_t ntiles, uint32_t* __restrict__ ranges) {
+  const int64_t total = dyn_count(total_cap, dyn);
   int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (total == 0) {
+    for (int64_t t = e; t <= ntiles; t += (int64_t)gridDim.x * kBlock) ranges[t] = 0u;
+    return;
+  }
   if (e >= total) return;
   int64_t cur = tiles[e];
   int64_t prev = e > 0 ? (int64_t)tiles[e - 1] : -1;
@@ -226,6 +251,29 @@ __global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t* __restri
 __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// list[total .. total + 8) = 0 with total read on the device (padding read by
+// the render's 8-aligned batches); total is clamped to the capacity.
+__global__ void pad_list_kernel(uint32_t* __restrict__ list, int64_t total_cap,
+                                const unsigned long long* __restrict__ dyn) {
+  const int64_t total = dyn_count(total_cap, dyn);
+  if (threadIdx.x < 8) list[total + threadIdx.x] = 0u;
+}
+
+// Capacity guard of capacity-sized launches: stats[3] keeps the entry count;
+// when it exceeds the capacity, the entry and visible counts are cleared so
+// every later kernel sees an empty list (the frame renders as background and
+// the host reports the overflow from stats[3]).
+__global__ void capacity_guard_kernel(unsigned long long* __restrict__ stats, int64_t cap) {
+  if (threadIdx.x == 0) {
+    const unsigned long long e = stats[0];
+    stats[3] = e;
+    if (e > (unsigned long long)cap) {
+      stats[0] = 0ull;
+      stats[1] = 0ull;
+    }
+  }
 }
 
 // --------------------------------------------------------------- host side --
@@ -258,40 +306,53 @@ void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n
 
 int64_t radix_hist_words(int64_t n) { return 256 * ((n + kTileItems - 1) / kTileItems) + 1; }
 
-// One stable 8-bit pass.  hist: radix_hist_words(n); scratch for its scan.
+// One stable 8-bit pass over n_cap keys (or the device count *dyn).
+// hist: radix_hist_words(n_cap); scratch for its scan.
 void radix_pass(hipStream_t st, const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* filter,
-                int64_t n, int shift, uint32_t* keys_out, uint32_t* vals_out, uint32_t* hist,
-                uint32_t* scan_scratch) {
-  if (n <= 0) return;
-  int64_t nb = (n + kTileItems - 1) / kTileItems;
-  hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, keys_in, filter, n, shift, hist,
-                     nb);
+                int64_t n_cap, const unsigned long long* dyn, int shift, uint32_t* keys_out, uint32_t* vals_out,
+                uint32_t* hist, uint32_t* scan_scratch) {
+  if (n_cap <= 0) return;
+  int64_t nb = (n_cap + kTileItems - 1) / kTileItems;
+  hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, keys_in, filter, n_cap, dyn, shift,
+                     hist, nb);
   scan_exclusive(st, hist, hist, 256 * nb, scan_scratch);
-  hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, keys_in, vals_in, filter, n,
-                     shift, (const uint32_t*)hist, nb, keys_out, vals_out);
+  hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, keys_in, vals_in, filter, n_cap,
+                     dyn, shift, (const uint32_t*)hist, nb, keys_out, vals_out);
 }
 
-void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m, const uint32_t* counts,
-                          uint32_t* out) {
-  if (m <= 0) return;
-  hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(m, kBlock)), dim3(kBlock), 0, st, items, m, counts, out);
+void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
+                          const uint32_t* counts, uint32_t* out) {
+  if (m_cap <= 0) return;
+  hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(m_cap, kBlock)), dim3(kBlock), 0, st, items, m_cap, dyn,
+                     counts, out);
 }
 
-void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m, int64_t total,
+void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
+                   const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, uint32_t* tiles_out, uint32_t* items_out) {
-  if (total <= 0) return;
-  hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total, (int64_t)kBlock * kExpandPer)), dim3(kBlock), 0, st, items,
-                     offs, m, total, rects, views, n, tiles_out, items_out);
+  if (total_cap <= 0) return;
+  hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total_cap, (int64_t)kBlock * kExpandPer)), dim3(kBlock), 0, st,
+                     items, offs, m_cap, dyn_m, total_cap, dyn_total, rects, views, n, tiles_out, items_out);
 }
 
-void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total, int64_t ntiles, uint32_t* ranges) {
-  if (total <= 0) {
+void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
+                   int64_t ntiles, uint32_t* ranges) {
+  if (total_cap <= 0 && !dyn) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(ntiles + 1, kBlock)), dim3(kBlock), 0, st, ranges, ntiles + 1,
                        0u);
     return;
   }
-  hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(total, kBlock)), dim3(kBlock), 0, st, tiles, total, ntiles,
+  const int64_t g = std::max<int64_t>(total_cap, ntiles + 1);
+  hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(g, kBlock)), dim3(kBlock), 0, st, tiles, total_cap, dyn, ntiles,
                      ranges);
+}
+
+void launch_capacity_guard(hipStream_t st, unsigned long long* stats, int64_t cap) {
+  hipLaunchKernelGGL(capacity_guard_kernel, dim3(1), dim3(64), 0, st, stats, cap);
+}
+
+void launch_pad_list(hipStream_t st, uint32_t* list, int64_t total_cap, const unsigned long long* dyn) {
+  hipLaunchKernelGGL(pad_list_kernel, dim3(1), dim3(64), 0, st, list, total_cap, dyn);
 }
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v) {

@@ -29,12 +29,17 @@ int64_t scan_scratch_words(int64_t n);
 void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch);
 int64_t radix_hist_words(int64_t n);
 void radix_pass(hipStream_t st, const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* filter,
-                int64_t n, int shift, uint32_t* keys_out, uint32_t* vals_out, uint32_t* hist,
-                uint32_t* scan_scratch);
-void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m, const uint32_t* counts, uint32_t* out);
-void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m, int64_t total,
+                int64_t n_cap, const unsigned long long* dyn, int shift, uint32_t* keys_out, uint32_t* vals_out,
+                uint32_t* hist, uint32_t* scan_scratch);
+void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
+                          const uint32_t* counts, uint32_t* out);
+void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
+                   const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, uint32_t* tiles_out, uint32_t* items_out);
-void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total, int64_t ntiles, uint32_t* ranges);
+void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
+                   int64_t ntiles, uint32_t* ranges);
+void launch_pad_list(hipStream_t st, uint32_t* list, int64_t total_cap, const unsigned long long* dyn);
+void launch_capacity_guard(hipStream_t st, unsigned long long* stats, int64_t cap);
 void launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v);
 
 // render.hip

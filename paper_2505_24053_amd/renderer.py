@@ -203,3 +203,80 @@ def render_differentiable(scene: dict, cams, opts: dict | None = None):
     backward() on a function of rgb fills .grad of the scene tensors."""
     return _Render.apply(scene["mean"], scene["scale"], scene["quat"], scene["opacity"], scene["sh"],
                          int(scene["sh_degree"]), cams, opts)
+
+
+def _scene_struct(scene: dict):
+    n, deg = _check_scene(scene)
+    sc = _lib.GeerScene()
+    sc.n, sc.sh_degree, sc.reserved = n, deg, 0
+    sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh = (scene[k].data_ptr() for k in
+                                                    ("mean", "scale", "quat", "opacity", "sh"))
+    return sc
+
+
+def _views(cams):
+    return (_lib.GeerView * len(cams))(*[_lib.make_view(c) for c in cams])
+
+
+def plan_workspace_bytes(scene: dict, cams, entry_capacity: int, opts: dict | None = None) -> int:
+    """Device workspace (bytes) of a plan for this batch shape."""
+    ctx = context(scene["mean"].device.index or 0)
+    out = C.c_int64()
+    _lib.check(_lib.load().geer_plan_workspace_bytes(ctx, C.byref(_scene_struct(scene)), len(cams), _views(cams),
+                                                     C.byref(_lib.make_opts(**(opts or {}))), int(entry_capacity),
+                                                     C.byref(out)), ctx)
+    return int(out.value)
+
+
+class Plan:
+    """A captured forward for a fixed batch shape (geer_plan): every launch
+    renders new cameras of the same grid sizes into the plan's outputs with
+    one graph replay.  `workspace` is an optional uint8 device tensor (shared
+    only by plans launched on one stream); `out` = (rgb, depth, trans)."""
+
+    def __init__(self, scene: dict, cams, entry_capacity: int, opts: dict | None = None, workspace=None,
+                 out=None):
+        dev = scene["mean"].device
+        self.ctx = context(dev.index or 0)
+        self.scene = scene  # keeps the scene tensors alive
+        self.shapes = [(int(c["width"]), int(c["height"])) for c in cams]
+        npix = sum(view_pixels(cams))
+        if out is None:
+            out = (torch.empty(3 * npix, device=dev), torch.empty(npix, device=dev), torch.empty(npix, device=dev))
+        self.rgb, self.depth, self.trans = out
+        self.workspace = workspace
+        ws_ptr = C.c_void_p(workspace.data_ptr()) if workspace is not None else None
+        ws_bytes = workspace.numel() if workspace is not None else 0
+        h = C.c_void_p()
+        _lib.check(_lib.load().geer_plan_create(self.ctx, C.byref(_scene_struct(scene)), len(cams), _views(cams),
+                                                C.byref(_lib.make_opts(**(opts or {}))), int(entry_capacity), ws_ptr,
+                                                ws_bytes, _ptr(self.rgb), _ptr(self.depth), _ptr(self.trans),
+                                                C.byref(h)), self.ctx)
+        self.handle = h
+
+    def launch(self, cams, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _lib.check(_lib.load().geer_plan_launch(self.handle, _views(cams), C.c_void_p(stream.cuda_stream)), self.ctx)
+
+    def entries(self):
+        """(entries, capacity, overflowed) of the last launch (waits for it)."""
+        e, cap = C.c_int64(), C.c_int64()
+        st = _lib.load().geer_plan_entries(self.handle, C.byref(e), C.byref(cap))
+        if st not in (0, _lib.ERR_CAPACITY):
+            _lib.check(st, self.ctx)
+        return int(e.value), int(cap.value), st == _lib.ERR_CAPACITY
+
+    def device_bytes(self) -> int:
+        return int(_lib.load().geer_plan_device_bytes(self.handle))
+
+    def destroy(self):
+        if self.handle:
+            _lib.load().geer_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -16,13 +16,11 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import adversarial_scene
+from helpers import RGB_TOL, adversarial_scene, compare_render
 from paper_2505_24053_amd import _lib, synth
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-RGB_TOL = 2e-4
 
 
 @pytest.fixture(scope="module")
@@ -81,27 +79,6 @@ def check_association(frame, scene, cams, **opts):
     st = frame.stats()
     assert st["n_entries"] == e_base
     return e_base
-
-
-def compare_render(got, ref, pix=None, rgb_tol=RGB_TOL):
-    """RGB within rgb_tol on unflagged rays; a flagged ray may also differ by
-    the oracle's bound on the decisions that fall within FP32 error."""
-    sel = slice(None) if pix is None else pix
-    g_rgb, g_d, g_t = got["rgb"][sel], got["depth"][sel], got["trans"][sel]
-    amb = ref["amb"]
-    ok = ~amb
-    err = np.abs(g_rgb - ref["rgb"]).max(axis=1)
-    assert err[ok].max(initial=0) <= rgb_tol, "max |rgb| err %g at %s" % (err[ok].max(), np.argmax(np.where(ok, err, 0)))
-    over = err[amb] - (rgb_tol + ref["amb_tol"][amb])
-    assert over.max(initial=-1) <= 0, "flagged ray beyond its bound by %g" % over.max()
-    terr = np.abs(g_t - ref["trans"])
-    assert terr[ok].max(initial=0) <= rgb_tol
-    derr = np.abs(g_d - ref["depth"]) / (1.0 + np.abs(ref["depth"]))
-    assert derr[ok].max(initial=0) <= 1e-3
-    assert amb.mean() < 0.10
-    print("rays %d, flagged %d (%.2f%%), flagged beyond %.0e: %d, max err unflagged %.3g"
-          % (amb.size, amb.sum(), 100 * amb.mean(), rgb_tol, int((err[amb] > rgb_tol).sum()), err[ok].max(initial=0)))
-    return float(err[ok].max(initial=0)), int(amb.sum())
 
 
 def test_small_workload_bit_exact_association_and_render(R):
