@@ -13,6 +13,12 @@ Printed (one JSON line on stdout):
                  timed with HIP events on its own stream inside the library
   cpu_baseline   the FP64 oracle on a bounded sample of the same rays,
                  on the host cores, with the GPU's RGB error on that sample
+  fwd_bwd        forward + L1 loss + backward of 500,000 Gaussians (SH 3)
+                 through a Kannala-Brandt 190-degree fisheye at 1280 x 960
+                 against a target rendered from perturbed parameters
+  serving        Poisson stream of render requests (pinhole 640 x 480,
+                 equidistant 1024 x 1024, KB 200-degree 1920 x 1080) over a
+                 resident 1M-Gaussian scene: p50/p99 latency, req/s, Mrays/s
 """
 from __future__ import annotations
 
@@ -58,6 +64,112 @@ def traffic_record(kernel_src):
     return rec.get("hbm_bytes_per_launch")
 
 
+def bench_fwd_bwd(args, dev):
+    """Forward + L1 + backward steps of the 500k-Gaussian KB 190-degree frame."""
+    import numpy as np
+    import torch
+
+    from paper_2505_24053_amd import _lib, renderer, synth
+
+    scene_np, cams, target_np = synth.workload_kb_train(seed=args.seed)
+    cam = cams[0]
+    rays = cam["width"] * cam["height"]
+    sc = renderer.scene_from_numpy(scene_np, device=dev)
+    tgt_sc = renderer.scene_from_numpy(target_np, device=dev)
+    target, _, _, _ = renderer.render(tgt_sc, cams)
+    mask = torch.as_tensor(_lib.valid_mask(cam).reshape(-1).astype(np.uint8), device=dev)
+    grads = {k: torch.empty_like(sc[k]) for k in ("mean", "scale", "quat", "opacity", "sh")}
+    out = (torch.empty(3 * rays, device=dev), torch.empty(rays, device=dev), torch.empty(rays, device=dev))
+    del tgt_sc
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    times = []
+
+    def step(timed):
+        if timed:
+            ev[0].record()
+        _, _, _, frame = renderer.render(sc, cams, out=out, keep_frame=True)
+        if timed:
+            ev[1].record()
+        loss, dl = renderer.l1_loss(out[0], target, mask)
+        if timed:
+            ev[2].record()
+        renderer.backward(frame, sc, dl, grads=grads)
+        if timed:
+            ev[3].record()
+        frame.release()
+        return loss
+
+    for _ in range(args.train_warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.train_steps):
+        loss = step(True)
+        torch.cuda.synchronize()
+        times.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.train_steps
+    med = np.median(np.array(times), axis=0)
+    return {"workload": "fwd_bwd_kb190_500k_sh3_1280x960_l1", "gaussians": scene_np.n, "rays": rays,
+            "steps": args.train_steps, "ms_per_step": round(ms_step, 4),
+            "mrays_per_s": round(rays / (ms_step * 1e-3) / 1e6, 3),
+            "stages_ms": {"forward": round(float(med[0]), 4), "l1_loss": round(float(med[1]), 4),
+                          "backward": round(float(med[2]), 4)},
+            "loss": round(float(loss.item()), 6)}
+
+
+def bench_serving(args, dev):
+    """Continuous batching over the resident 1M-Gaussian scene at a fixed rate."""
+    import numpy as np
+    import torch
+
+    from paper_2505_24053_amd import renderer, serve, synth
+
+    scene_np = synth.scene_box(1_000_000, seed=args.seed)
+    sc = renderer.scene_from_numpy(scene_np, device=dev)
+    del scene_np
+    # association capacity: the densest of a few sample requests, with margin
+    probe = synth.workload_serving_requests(9, seed=args.seed + 100)
+    per_tile, alone_ms = 0.0, {}
+    for c in probe:
+        renderer.render(sc, [c])  # warm the allocator
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, _, fr = renderer.render(sc, [c], keep_frame=True)
+        torch.cuda.synchronize()
+        alone_ms.setdefault(c["model"], []).append((time.perf_counter() - t) * 1e3)
+        per_tile = max(per_tile, fr.stats()["n_entries"] / serve.tiles_of((c["width"], c["height"])))
+        fr.release()
+    shapes = {(c["width"], c["height"]) for c in probe}
+    srv = serve.Server(sc, shapes, entries_per_tile=1.5 * per_tile, slots=args.serve_slots, slot_views=2,
+                       max_views=4)
+    graphs = srv.prepare(shapes)
+    warm = synth.workload_serving_requests(args.serve_warmup, seed=args.seed + 200)
+    srv.run([serve.Request(i, c) for i, c in enumerate(warm)],
+            serve.poisson_arrivals(len(warm), args.serve_rate, seed=args.seed + 201))
+    srv.stats = dict(batches=0, overflows=0, views=0, overlapped=0)
+    srv.intervals = []
+    cams = synth.workload_serving_requests(args.serve_requests, seed=args.seed + 300)
+    arrivals = serve.poisson_arrivals(len(cams), args.serve_rate, seed=args.seed + 301)
+    done = srv.run([serve.Request(i, c) for i, c in enumerate(cams)], arrivals)
+    summ = serve.latency_summary(done)
+    overlap = srv.device_overlap()
+    stats = dict(srv.stats)
+    ws_gb = srv.slot_bytes * len(srv.slots) / 2**30
+    srv.close()
+    return {"workload": "serving_1m_sh3_mixed_pinhole640x480_fisheye1024_kb200_1920x1080",
+            "rate_req_per_s": args.serve_rate, "requests": summ["requests"],
+            "p50_ms": round(summ["p50_ms"], 3), "p99_ms": round(summ["p99_ms"], 3),
+            "mean_ms": round(summ["mean_ms"], 3), "max_ms": round(summ["max_ms"], 3),
+            "req_per_s": round(summ["req_per_s"], 2), "mrays_per_s": round(summ["mrays_per_s"], 2),
+            "batches": stats["batches"], "mean_batch": round(stats["views"] / max(stats["batches"], 1), 2),
+            "admitted_while_busy": stats["overlapped"], "device_overlap_frac": round(overlap, 3),
+            "overflow_batches": stats["overflows"], "slots": len(srv.slots), "workspace_gib": round(ws_gb, 2),
+            "graphs_per_slot": graphs, "entries_per_tile_capacity": round(1.5 * per_tile, 1),
+            "alone_ms": {k: round(float(np.median(v)), 3) for k, v in alone_ms.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +180,12 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after timing, copy this many MiB device-to-device once (a plain copy kernel of known "
                          "size that calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE in the same run)")
+    ap.add_argument("--train-steps", type=int, default=10, help="fwd+bwd steps (0: skip)")
+    ap.add_argument("--train-warmup", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=600, help="served requests (0: skip)")
+    ap.add_argument("--serve-warmup", type=int, default=60)
+    ap.add_argument("--serve-rate", type=float, default=150.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-slots", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -159,6 +277,17 @@ def main():
                    "flagged_frac": round(float(ref["amb"].mean()), 5),
                    "flagged_within_bound": bool(np.all(err[~okm] <= 2e-4 + ref["amb_tol"][~okm]))}
 
+    fwd_bwd = None
+    if args.train_steps > 0:
+        log("fwd+bwd: 500k Gaussians, KB 190 deg 1280x960")
+        fwd_bwd = bench_fwd_bwd(args, dev)
+        log("fwd+bwd:", fwd_bwd)
+    serving = None
+    if args.serve_requests > 0:
+        log("serving: 1M Gaussians, %d requests at %.0f req/s" % (args.serve_requests, args.serve_rate))
+        serving = bench_serving(args, dev)
+        log("serving:", serving)
+
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -173,6 +302,8 @@ def main():
         "rgb_err_vs_fp64": rgb_err,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fwd_bwd": fwd_bwd,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

@@ -26,30 +26,40 @@ namespace geer {
 
 // One (ray, Gaussian) evaluation and blend, branch-free: lanes that already
 // terminated compute too -- their SIMD lane is occupied either way -- but
-// their blend weight is zero.
-template <bool kFixed>
+// their blend weight is zero.  `done` is the wave's mask of terminated rays
+// (wave-uniform, kept in scalar registers); a lane reads its own bit with an
+// inverse ballot, so the bookkeeping costs no vector instructions.  The blend
+// weight is the drop in transmittance, w = T - T(1 - alpha) (zero when the
+// pair does not blend).  With kKeep the index one past the last blended
+// entry is tracked for the backward replay.
+template <bool kFixed, bool kKeep>
 __device__ __forceinline__ void blend_one(const Record& R, float dx, float dy, float dz, const Opts& op, uint32_t e,
-                                          bool& done, float& T, float& cr, float& cg, float& cb, float& D,
+                                          uint64_t& done, float& T, float& cr, float& cg, float& cb, float& D,
                                           uint32_t& last) {
   const PairEval E = eval_pair(R, dx, dy, dz);
-  const bool ok = !done & pair_contributes<kFixed>(R, E, op);
-  const float a = clamp_alpha(E.a_raw, op);
-  const float Tn = T * (1.0f - a);
-  const bool term = ok & (Tn < op.t_min);
-  const bool blend = ok & !term;
-  done = done | term;
-  const float w = blend ? a * T : 0.0f;
+  // the contribution rule and the termination test as wave masks: each ballot
+  // of a plain comparison is that comparison's lane mask
+  uint64_t ok = ~done & __builtin_amdgcn_ballot_w64(E.gz > 0.0f) &
+                __builtin_amdgcn_ballot_w64(E.a_raw >= op.alpha_min);
+  if (kFixed) ok &= __builtin_amdgcn_ballot_w64(E.q <= R.qmax);
+  const float a = fminf(E.a_raw, op.alpha_max);
+  const float Tn = fmaf(-a, T, T);
+  const uint64_t term = ok & __builtin_amdgcn_ballot_w64(Tn < op.t_min);
+  const bool blend = __builtin_amdgcn_inverse_ballot_w64(ok & ~term);
+  done |= term;
+  const float Tnew = blend ? Tn : T;
+  const float w = T - Tnew;
+  T = Tnew;
   cr = fmaf(w, R.rgb[0], cr);
   cg = fmaf(w, R.rgb[1], cg);
   cb = fmaf(w, R.rgb[2], cb);
   D = fmaf(w * R.c1, E.gz * E.inv, D);
-  T = blend ? Tn : T;
-  last = blend ? e + 1 : last;
+  if (kKeep) last = blend ? e + 1 : last;
 }
 
 constexpr int kBatch = 256;  // list entries staged per workgroup pass (one per lane)
 
-template <bool kFixed>
+template <bool kFixed, bool kKeep>
 __global__ __launch_bounds__(256) void render_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
@@ -80,7 +90,7 @@ __global__ __launch_bounds__(256) void render_kernel(
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, D = 0.0f;
   uint32_t last = start;
   uint64_t evals = 0;
-  bool done = !valid;
+  uint64_t done = __ballot(!valid);  // wave mask of terminated (or absent) rays
   // the four half-tiles of this tile, for the per-entry hit bits
   const uint32_t hx0 = 2u * tx, hy0 = 2u * ty;
 
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(256) void render_kernel(
     }
     if (base + kBatch < end) fetch(base + kBatch);  // in flight while this batch blends
     __syncthreads();
-    if (__ballot(!done) != 0) {
+    if (~done != 0) {
       const uint32_t nb = min((uint32_t)kBatch, end - base);
 #pragma unroll
       for (int g = 0; g < kBatch / 64; ++g) {
@@ -129,13 +139,13 @@ __global__ __launch_bounds__(256) void render_kernel(
           Record R;
           float4* rr = reinterpret_cast<float4*>(&R);
           rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
-          evals += (uint64_t)__popcll(__ballot(!done));
-          blend_one<kFixed>(R, dx, dy, dz, op, base + k, done, T, cr, cg, cb, D, last);
+          evals += (uint64_t)__popcll(~done);
+          blend_one<kFixed, kKeep>(R, dx, dy, dz, op, base + k, done, T, cr, cg, cb, D, last);
         }
       }
     }
     // every wave done -> the whole tile is done; the barrier also frees the LDS
-    if (__syncthreads_and(done ? 1 : 0)) break;
+    if (__syncthreads_and(~done == 0 ? 1 : 0)) break;
   }
 
   if (valid) {
@@ -148,8 +158,10 @@ __global__ __launch_bounds__(256) void render_kernel(
     const int64_t gp = (int64_t)V.pix_base + p;
     if (depth) depth[gp] = D;
     if (trans) trans[gp] = T;
-    if (nlast) nlast[gp] = last;
-    if (tfinal) tfinal[gp] = T;
+    if (kKeep) {
+      nlast[gp] = last;
+      tfinal[gp] = T;
+    }
   }
   if (stats && lane == 0 && evals) atomicAdd(&stats[0], (unsigned long long)evals);
 }
@@ -159,12 +171,18 @@ void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const View
                    const Record* recs, const Opts& op, float* rgb, float* depth, float* trans, uint32_t* nlast,
                    float* tfinal, unsigned long long* stats) {
   if (ntiles <= 0) return;
-  if (fixed_lambda)
-    hipLaunchKernelGGL(render_kernel<true>, dim3((unsigned)ntiles), dim3(256), 0, st, views, nviews, dtab, ranges,
-                       list, rects, recs, op, rgb, depth, trans, nlast, tfinal, stats);
-  else
-    hipLaunchKernelGGL(render_kernel<false>, dim3((unsigned)ntiles), dim3(256), 0, st, views, nviews, dtab, ranges,
-                       list, rects, recs, op, rgb, depth, trans, nlast, tfinal, stats);
+  const bool keep = nlast != nullptr && tfinal != nullptr;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(256), 0, st, views, nviews, dtab, ranges, list, rects, recs,
+                       op, rgb, depth, trans, nlast, tfinal, stats);
+  };
+  if (fixed_lambda) {
+    if (keep) go(render_kernel<true, true>);
+    else go(render_kernel<true, false>);
+  } else {
+    if (keep) go(render_kernel<false, true>);
+    else go(render_kernel<false, false>);
+  }
 }
 
 }  // namespace geer

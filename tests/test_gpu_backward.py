@@ -157,9 +157,12 @@ def test_autograd_function_matches_direct_backward(R):
     torch.cuda.synchronize()
     frame.release()
     assert torch.equal(rgb.detach(), rgb2)
+    # same kernels on the same frame state; only the order of the float
+    # atomics differs between the two runs
     for k in GROUPS:
-        a, b = params[k].grad, direct[k]
-        assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * float(b.abs().max()) + 1e-12), k
+        a, b = params[k].grad.double(), direct[k].double()
+        assert float((a - b).norm()) <= 1e-5 * float(b.norm()) + 1e-12, k
+        assert float((a - b).abs().max()) <= 1e-4 * float(b.abs().max()) + 1e-12, k
 
 
 def test_degenerate_gaussians_are_finite(R):
