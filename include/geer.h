@@ -47,7 +47,7 @@ typedef enum {
   GEER_OK = 0,
   GEER_ERR_INVALID_ARG = 1, /* bad pointer, size, camera or option */
   GEER_ERR_OOM = 2,         /* device or host allocation failed */
-  GEER_ERR_CAPACITY = 3,    /* association list larger than 2^32 - 1 entries */
+  GEER_ERR_CAPACITY = 3,    /* more than 2^30 - 16 items (Gaussians x views) or list entries */
   GEER_ERR_HIP = 4,         /* a HIP runtime call failed; see geer_last_error */
   GEER_ERR_UNSUPPORTED = 5  /* feature not available in this build */
 } geer_status;
@@ -88,14 +88,20 @@ typedef struct {
  *   lambda_mode 1: kappa <= lambda_fixed^2 and alpha_raw >= alpha_min; the
  *     PBF uses lambda_fixed (the paper's "typically 3").
  * alpha = min(alpha_raw, alpha_max); compositing stops before the first
- * Gaussian that would take the transmittance below t_min (t_min = 0: never). */
+ * Gaussian that would take the transmittance below t_min (t_min = 0: never).
+ * flags: GEER_OPT_NO_CONE_CULL makes the render and its backward evaluate
+ * every (ray, entry) pair whose half-tile rectangle test passes, instead of
+ * first skipping entries whose contribution cone misses all rays of the
+ * half-tile; the outputs are the same bits either way (for verification and
+ * measurement of the cull). */
+#define GEER_OPT_NO_CONE_CULL 1
 typedef struct {
   float alpha_min;    /* default 1/255, in (0, 1) */
   float alpha_max;    /* default 0.99, in [alpha_min, 1) */
   float t_min;        /* default 1e-4, in [0, 1) */
   float lambda_fixed; /* default 3, > 0 */
   int32_t lambda_mode;
-  int32_t reserved; /* must be 0 */
+  int32_t flags; /* GEER_OPT_* bits, default 0 */
 } geer_opts;
 
 typedef struct geer_ctx geer_ctx;     /* per-device library state */

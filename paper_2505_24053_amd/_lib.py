@@ -42,7 +42,7 @@ class GeerScene(C.Structure):
 
 class GeerOpts(C.Structure):
     _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
-                ("lambda_fixed", C.c_float), ("lambda_mode", C.c_int32), ("reserved", C.c_int32)]
+                ("lambda_fixed", C.c_float), ("lambda_mode", C.c_int32), ("flags", C.c_int32)]
 
 
 class GeerFrameStats(C.Structure):
@@ -127,10 +127,15 @@ def make_view(cam: dict) -> GeerView:
     return v
 
 
-def make_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, lambda_mode=0, lambda_fixed=3.0) -> GeerOpts:
+OPT_NO_CONE_CULL = 1
+
+
+def make_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, lambda_mode=0, lambda_fixed=3.0,
+              cone_cull=True) -> GeerOpts:
     o = GeerOpts()
     o.alpha_min, o.alpha_max, o.t_min = float(alpha_min), float(alpha_max), float(t_min)
-    o.lambda_fixed, o.lambda_mode, o.reserved = float(lambda_fixed), int(lambda_mode), 0
+    o.lambda_fixed, o.lambda_mode = float(lambda_fixed), int(lambda_mode)
+    o.flags = 0 if cone_cull else OPT_NO_CONE_CULL
     return o
 
 

@@ -55,6 +55,9 @@ struct geer_ctx {
   int64_t live_frames = 0;
 };
 
+// Largest key count of one sort (status words hold 30-bit counts).
+constexpr int64_t kMaxKeys = ((int64_t)1 << 30) - 16;
+
 struct geer_plan {
   geer_ctx* ctx = nullptr;
   geer_scene scene{};
@@ -202,7 +205,7 @@ geer_status check_opts(geer_ctx* c, const geer_opts& o) {
   if (o.lambda_mode != 0 && o.lambda_mode != 1) return fail(c, GEER_ERR_INVALID_ARG, "lambda_mode must be 0 or 1");
   if (o.lambda_mode == 1 && !(o.lambda_fixed > 0 && o.lambda_fixed < 100))
     return fail(c, GEER_ERR_INVALID_ARG, "lambda_fixed must be in (0, 100)");
-  if (o.reserved != 0) return fail(c, GEER_ERR_INVALID_ARG, "opts.reserved must be 0");
+  if ((o.flags & ~GEER_OPT_NO_CONE_CULL) != 0) return fail(c, GEER_ERR_INVALID_ARG, "unknown opts.flags bits");
   return GEER_OK;
 }
 
@@ -268,7 +271,8 @@ struct FwdBufs {
   Record* recs = nullptr;
   uint2* rects = nullptr;
   uint32_t *keys = nullptr, *counts = nullptr;
-  uint64_t* stats = nullptr;  // [0] entries, [1] visible, [2] evaluated pairs, [3] entries before the guard
+  uint64_t* stats = nullptr;  // [0] entries, [1] visible, [2] evaluated pairs, [3] entries before the guard,
+                              // [4] sort stall flag
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr, *hist = nullptr, *scratch = nullptr;
   uint32_t *cnt_sorted = nullptr, *tiles_a = nullptr, *tiles_b = nullptr, *items_b = nullptr;
   uint32_t *list = nullptr, *ranges = nullptr, *nlast = nullptr;
@@ -278,7 +282,7 @@ struct FwdBufs {
 // Stage (a): zero the counters, then preprocess + PBF of every item.
 void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, const Opts& op, const float* lam,
                         const FwdBufs& b) {
-  launch_fill_u32(st, (uint32_t*)b.stats, 8, 0u);
+  launch_fill_u32(st, (uint32_t*)b.stats, 16, 0u);
   launch_preprocess(st, sc.n, nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh, b.views, op, lam,
                     b.edges, b.recs, b.rects, b.keys, b.counts, (unsigned long long*)b.stats);
 }
@@ -292,30 +296,29 @@ void enqueue_association(hipStream_t st, int64_t n, int64_t items, int64_t nvis_
   const unsigned long long* dE = dyn ? (const unsigned long long*)b.stats : nullptr;
   const unsigned long long* dV = dyn ? (const unsigned long long*)(b.stats + 1) : nullptr;
   if (dyn) launch_capacity_guard(st, (unsigned long long*)b.stats, ecap);
+  unsigned long long* err = (unsigned long long*)(b.stats + 4);
   if (nvis_cap > 0) {
-    radix_pass(st, b.keys, nullptr, b.counts, items, nullptr, 0, b.ka, b.va, b.hist, b.scratch);
-    radix_pass(st, b.ka, b.va, nullptr, nvis_cap, dV, 8, b.kb, b.vb, b.hist, b.scratch);
-    radix_pass(st, b.kb, b.vb, nullptr, nvis_cap, dV, 16, b.ka, b.va, b.hist, b.scratch);
-    radix_pass(st, b.ka, b.va, nullptr, nvis_cap, dV, 24, b.kb, b.vb, b.hist, b.scratch);
+    // depth order of the visible items (pass 0 compacts them out of all items)
+    radix_sort(st, b.keys, nullptr, b.counts, items, nullptr, nvis_cap, dV, 0, 4, b.ka, b.va, b.kb, b.vb, b.hist,
+               err);
     launch_gather_counts(st, b.vb, nvis_cap, dV, b.counts, b.cnt_sorted);
     scan_exclusive(st, b.cnt_sorted, b.cnt_sorted, nvis_cap, b.scratch);
-    // Expansion in depth order into pair A or B, chosen so that after the
-    // tile passes (alternating A <-> B) the items end in b.list (pair B).
-    uint32_t *tA = b.tiles_a, *iA = b.items_b, *tB = b.tiles_b, *iB = b.list;
+    // Expansion in depth order, then the stable tile-id passes, arranged so
+    // that the sorted items end in b.list: pair P = (tiles_b, list),
+    // Q = (tiles_a, items_b); odd pass counts run Q -> P -> Q ..., even ones
+    // P -> Q -> P ...
     const int passes = bytes_for_tiles(ntiles - 1);
-    uint32_t* tc = (passes % 2 == 1) ? tA : tB;
-    uint32_t* ic = (passes % 2 == 1) ? iA : iB;
-    launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, tc, ic);
-    for (int p = 0; p < passes; ++p) {
-      uint32_t* to = (tc == tA) ? tB : tA;
-      uint32_t* io = (ic == iA) ? iB : iA;
-      radix_pass(st, tc, ic, nullptr, ecap, dE, 8 * p, to, io, b.hist, b.scratch);
-      tc = to;
-      ic = io;
-    }
+    uint32_t *pt = b.tiles_b, *pi = b.list, *qt = b.tiles_a, *qi = b.items_b;
+    uint32_t* tin = (passes % 2 == 1) ? qt : pt;
+    uint32_t* iin = (passes % 2 == 1) ? qi : pi;
+    uint32_t* at = (passes % 2 == 1) ? pt : qt;
+    uint32_t* ai = (passes % 2 == 1) ? pi : qi;
+    launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, tin, iin);
+    radix_sort(st, tin, iin, nullptr, ecap, dE, ecap, dE, 0, passes, at, ai, tin, iin, b.hist, err);
+    uint32_t* tfinal = (passes % 2 == 1) ? at : tin;
     if (dyn) launch_pad_list(st, b.list, ecap, dE);
     else launch_fill_u32(st, b.list + ecap, 8, 0u);
-    launch_ranges(st, tc, ecap, dE, ntiles, b.ranges);
+    launch_ranges(st, tfinal, ecap, dE, ntiles, b.ranges);
   } else {
     launch_fill_u32(st, b.list, 8, 0u);
     launch_ranges(st, nullptr, 0, nullptr, ntiles, b.ranges);
@@ -386,6 +389,8 @@ Opts make_opts(const LamTab& lt, const geer_opts& o) {
   op.kmax_fixed = o.lambda_fixed * o.lambda_fixed;
   op.lam_lo = lt.lo;
   op.lam_n = lt.n;
+  op.log2_amin = (float)std::log2((double)o.alpha_min);
+  op.cone_cull = (o.flags & GEER_OPT_NO_CONE_CULL) ? 0 : 1;
   return op;
 }
 
@@ -458,7 +463,7 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   if ((s = check_opts(c, *opts)) != GEER_OK) return s;
   const int64_t n = scene->n;
   const int64_t items = n * n_views;
-  if (items >= ((int64_t)1 << 32) - 16) return fail(c, GEER_ERR_CAPACITY, "Gaussians x views exceeds 2^32");
+  if (items >= kMaxKeys) return fail(c, GEER_ERR_CAPACITY, "Gaussians x views exceeds 2^30");
   for (int i = 0; i < n_views; ++i)
     if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
   hipStream_t st = (hipStream_t)stream;
@@ -541,21 +546,21 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   uint64_t totals[2];
   std::memcpy(totals, c->pinned, 16);
   const int64_t E = (int64_t)totals[0], nvis = (int64_t)totals[1];
-  if (totals[0] >= ((uint64_t)1 << 32) - 16)
-    return cleanup(fail(c, GEER_ERR_CAPACITY, "association list of %llu entries exceeds 2^32",
+  if (totals[0] >= (uint64_t)kMaxKeys)
+    return cleanup(fail(c, GEER_ERR_CAPACITY, "association list of %llu entries exceeds 2^30",
                         (unsigned long long)totals[0]));
   f->entries = E;
   f->visible = nvis;
 
   // ---- stage (b): depth sort, expansion, tile sort, ranges ----
   const int64_t nv1 = std::max<int64_t>(nvis, 1), e1 = std::max<int64_t>(E, 1);
-  const int64_t hist_words = radix_hist_words(std::max(items, E));
+  const int64_t hist_words = radix_work_words(std::max(items, E));
   TRY(acquire(c, 4 * nv1, st, ka));
   TRY(acquire(c, 4 * nv1, st, va));
   TRY(acquire(c, 4 * nv1, st, kb));
   TRY(acquire(c, 4 * nv1, st, vb));
   TRY(acquire(c, 4 * (size_t)hist_words, st, hist));
-  TRY(acquire(c, 4 * (size_t)scan_scratch_words(std::max<int64_t>(hist_words, nv1)), st, scratch));
+  TRY(acquire(c, 4 * (size_t)scan_scratch_words(nv1), st, scratch));
   TRY(acquire(c, 4 * nv1, st, cnt_sorted));
   TRY(acquire(c, 4 * (e1 + 8), st, tiles_a));
   TRY(acquire(c, 4 * (e1 + 8), st, tiles_b));
@@ -641,10 +646,11 @@ void geer_frame_release(geer_frame* f) {
 geer_status geer_frame_get_stats(const geer_frame* f, geer_frame_stats* out) {
   if (!f || !out) return GEER_ERR_INVALID_ARG;
   geer_ctx* c = f->ctx;
-  uint64_t st[4];
+  uint64_t st[5];
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipMemcpyAsync(st, f->stats.p, sizeof st, hipMemcpyDeviceToHost, f->stream));
   HIP_TRY(c, hipStreamSynchronize(f->stream));
+  if (st[4] != 0) return fail(c, GEER_ERR_HIP, "association sort stalled (look-back spin limit)");
   out->n_items = f->items;
   out->n_visible = (int64_t)st[1];
   out->n_entries = (int64_t)st[0];
@@ -779,7 +785,7 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
     return at;
   };
   const int64_t it1 = std::max<int64_t>(items, 1);
-  const int64_t hist_words = radix_hist_words(std::max(it1, ecap));
+  const int64_t hist_words = radix_work_words(std::max(it1, ecap));
   L.meta = put(meta_bytes);
   L.recs = put(sizeof(Record) * it1);
   L.rects = put(sizeof(uint2) * it1);
@@ -791,7 +797,7 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
   L.kb = put(4 * it1);
   L.vb = put(4 * it1);
   L.hist = put(4 * (size_t)hist_words);
-  L.scratch = put(4 * (size_t)scan_scratch_words(std::max<int64_t>(hist_words, it1)));
+  L.scratch = put(4 * (size_t)scan_scratch_words(it1));
   L.cnt_sorted = put(4 * it1);
   L.tiles_a = put(4 * (ecap + 8));
   L.tiles_b = put(4 * (ecap + 8));
@@ -807,7 +813,7 @@ geer_status plan_check(geer_ctx* c, const geer_scene* scene, int32_t n_views, co
                        const geer_opts* opts, int64_t entry_capacity, ViewTables& tab) {
   if (!scene || !views || !opts) return fail(c, GEER_ERR_INVALID_ARG, "null argument");
   if (n_views < 1 || n_views > 4096) return fail(c, GEER_ERR_INVALID_ARG, "n_views %d out of range", n_views);
-  if (entry_capacity < 1 || entry_capacity >= ((int64_t)1 << 32) - 16)
+  if (entry_capacity < 1 || entry_capacity >= kMaxKeys)
     return fail(c, GEER_ERR_INVALID_ARG, "entry capacity %lld out of range", (long long)entry_capacity);
   geer_status s;
   if ((s = check_scene(c, scene)) != GEER_OK) return s;
@@ -815,8 +821,7 @@ geer_status plan_check(geer_ctx* c, const geer_scene* scene, int32_t n_views, co
   for (int i = 0; i < n_views; ++i)
     if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
   if (scene->n < 1) return fail(c, GEER_ERR_INVALID_ARG, "a plan needs a non-empty scene");
-  if (scene->n * n_views >= ((int64_t)1 << 32) - 16)
-    return fail(c, GEER_ERR_CAPACITY, "Gaussians x views exceeds 2^32");
+  if (scene->n * n_views >= kMaxKeys) return fail(c, GEER_ERR_CAPACITY, "Gaussians x views exceeds 2^30");
   return build_tables(c, n_views, views, tab);
 }
 
@@ -956,7 +961,7 @@ geer_status geer_plan_launch(geer_plan* P, const geer_view* views, void* stream)
   P->staged_used[k] = true;
   P->next = 1 - k;
   HIP_TRY(c, hipGraphLaunch(P->exec, st));
-  HIP_TRY(c, hipMemcpyAsync(P->host_stats, P->stats, 32, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipMemcpyAsync(P->host_stats, P->stats, 40, hipMemcpyDeviceToHost, st));
   HIP_TRY(c, hipEventRecord(P->done, st));
   P->launched = true;
   return GEER_OK;
@@ -973,6 +978,7 @@ geer_status geer_plan_entries(geer_plan* P, int64_t* entries, int64_t* capacity)
   HIP_TRY(c, hipEventSynchronize(P->done));
   const int64_t E = (int64_t)P->host_stats[3];
   if (entries) *entries = E;
+  if (P->host_stats[4] != 0) return fail(c, GEER_ERR_HIP, "association sort stalled (look-back spin limit)");
   if (E > P->ecap)
     return fail(c, GEER_ERR_CAPACITY, "association list of %lld entries exceeds the plan's %lld", (long long)E,
                 (long long)P->ecap);

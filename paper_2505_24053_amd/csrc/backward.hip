@@ -1,11 +1,12 @@
 // Gradient of the render (App. C, two-stage propagation).
 //
-// Render backward (ray-wise, "RenderCUDA" stage): one workgroup per tile, the
-// same 256-entry LDS batches as the forward but walked back to front from
-// each ray's saved final transmittance and last blended entry.  A pair is
-// replayed only if the forward blended it (same rectangle skip, same
-// evaluation functions, bit-identical decisions); the transmittance before it
-// is recovered as T / (1 - alpha) (no per-sample state is stored).  Per pair:
+// Render backward (ray-wise, "RenderCUDA" stage): one wave per 8x8 half-tile
+// as in the forward, walking the tile's list back to front in windows of 64
+// entries from the largest saved last-blended index of its rays, with the
+// forward's rectangle and contribution-cone skips.  A pair is replayed only
+// if the forward blended it (same evaluation functions, bit-identical
+// decisions); the transmittance before it is recovered as T / (1 - alpha)
+// (no per-sample state is stored).  Per pair:
 //   dL/dc     = alpha T G,           dL/dalpha = T (c - C_behind) . G,
 //   dL/dkappa = -alpha / 2 dL/dalpha,
 // and, in the canonical frame rotated so that o_u = (0, 0, r) (u' = Q Wc d,
@@ -30,7 +31,7 @@
 
 namespace geer {
 
-constexpr int kBatchB = 256;
+constexpr int kWinB = 64;  // list entries staged per wave pass
 constexpr int kAcc = 16;  // accumulator floats per (Gaussian, view) item
 
 // Sum v[0..15] over the wave; lanes with (lane & 3) == 0 end up holding the
@@ -67,31 +68,29 @@ __device__ __forceinline__ void wave_reduce16_add(const float v[16], float* __re
 }
 
 template <bool kFixed>
-__global__ __launch_bounds__(256) void render_backward_kernel(
+__global__ __launch_bounds__(64) void render_backward_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
     const Record* __restrict__ recs, Opts op, const uint32_t* __restrict__ nlast, const float* __restrict__ tfinal,
     const float* __restrict__ dl_drgb, float* __restrict__ acc) {
-  __shared__ float4 s_rec[kBatchB][4];
-  __shared__ uint32_t s_item[kBatchB];
-  __shared__ uint64_t s_hit[4][kBatchB / 64];
-  __shared__ uint32_t s_last[4];
+  __shared__ float4 s_rec[kWinB][4];
+  __shared__ uint32_t s_item[kWinB];
 
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int hidx = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = hidx >> 2, quad = hidx & 3;
   int v = 0;
   while (v + 1 < nviews && tile >= views[v + 1].tile_base) ++v;
   const ViewDev& V = views[v];
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
-  const int tid = threadIdx.x;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63;
-  const int hx = 2 * tx + (wv & 1), hy = 2 * ty + (wv >> 1);
-  const bool wave_live = hx < V.nhx && hy < V.nhy;
+  const uint32_t hx = 2u * tx + (quad & 1), hy = 2u * ty + (quad >> 1);
+  if (hx >= (uint32_t)V.nhx || hy >= (uint32_t)V.nhy) return;
+  const int lane = threadIdx.x;
   const int px = hx * kHalf + (lane & 7), py = hy * kHalf + (lane >> 3);
-  const bool valid = wave_live && px < V.width && py < V.height;
+  const bool valid = px < V.width && py < V.height;
   float dx, dy, dz;
   pixel_direction(V, dtab, px, py, dx, dy, dz);
+  const QuadCone Q = half_tile_cone(V, dtab, hx, hy);
 
   const uint32_t start = ranges[tile];
   const int64_t hw = (int64_t)V.width * V.height;
@@ -109,99 +108,87 @@ __global__ __launch_bounds__(256) void render_backward_kernel(
   }
   float cb0 = 0.0f, cb1 = 0.0f, cb2 = 0.0f;  // colour of everything behind, as seen just in front of it
 
-  // the tile's replay range is [start, max over its rays of last)
-  uint32_t wmax = last;
+  // this wave replays [start, max over its rays of last)
+  uint32_t top = last;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, off));
-  if (lane == 0) s_last[wv] = wmax;
-  __syncthreads();
-  const uint32_t top = max(max(s_last[0], s_last[1]), max(s_last[2], s_last[3]));
+  for (int off = 32; off > 0; off >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, off));
 
   float4 p0, p1, p2, p3;
-  uint2 prc;
   uint32_t pitem = 0;
+  bool phit = false;
   auto fetch = [&](uint32_t b, uint32_t e_end) {
-    const uint32_t e = b + tid;
+    const uint32_t e = b + lane;
+    phit = false;
     if (e < e_end) {
       pitem = list[e];
-      prc = rects[pitem];
-      const float4* r = reinterpret_cast<const float4*>(recs + pitem);
-      p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
-    } else {
-      prc = make_uint2(1u, 0u);
+      const uint2 rc = rects[pitem];
+      phit = (rc.x & 0xffffu) <= hx && hx <= (rc.x >> 16) && (rc.y & 0xffffu) <= hy && hy <= (rc.y >> 16);
+      if (phit) {
+        const float4* r = reinterpret_cast<const float4*>(recs + pitem);
+        p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
+      }
     }
   };
-  const uint32_t hx0 = 2u * tx, hy0 = 2u * ty;
   uint32_t bend = top;
-  uint32_t bbase = bend > start + kBatchB ? bend - kBatchB : start;
+  uint32_t bbase = bend > start + kWinB ? bend - kWinB : start;
   if (start < top) fetch(bbase, bend);
 
   while (bend > start) {
-    s_rec[tid][0] = p0; s_rec[tid][1] = p1; s_rec[tid][2] = p2; s_rec[tid][3] = p3;
-    s_item[tid] = pitem;
-    const uint32_t rx0 = prc.x & 0xffffu, rx1 = prc.x >> 16, ry0 = prc.y & 0xffffu, ry1 = prc.y >> 16;
-    const bool cx0 = rx0 <= hx0 && hx0 <= rx1, cx1 = rx0 <= hx0 + 1 && hx0 + 1 <= rx1;
-    const bool cy0 = ry0 <= hy0 && hy0 <= ry1, cy1 = ry0 <= hy0 + 1 && hy0 + 1 <= ry1;
-    const uint64_t b00 = __ballot(cx0 && cy0), b10 = __ballot(cx1 && cy0);
-    const uint64_t b01 = __ballot(cx0 && cy1), b11 = __ballot(cx1 && cy1);
-    if (lane == 0) {
-      s_hit[0][wv] = b00; s_hit[1][wv] = b10; s_hit[2][wv] = b01; s_hit[3][wv] = b11;
+    if (phit && op.cone_cull) phit = cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, kFixed);
+    uint64_t m = __builtin_amdgcn_ballot_w64(phit);
+    if (phit) {
+      s_rec[lane][0] = p0; s_rec[lane][1] = p1; s_rec[lane][2] = p2; s_rec[lane][3] = p3;
+      s_item[lane] = pitem;
     }
     const uint32_t base = bbase;
-    const uint32_t nb = bend - bbase;
-    // prefetch the batch in front of this one
+    // prefetch the window in front of this one
     bend = bbase;
-    bbase = bend > start + kBatchB ? bend - kBatchB : start;
+    bbase = bend > start + kWinB ? bend - kWinB : start;
     if (bend > start) fetch(bbase, bend);
-    __syncthreads();
-    if (__ballot(valid && last > base) != 0) {
-      for (int g = (int)((nb + 63) / 64) - 1; g >= 0; --g) {
-        const uint64_t mv = s_hit[wv][g];
-        uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32)) << 32) |
-                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mv);
-        if (g == (int)((nb - 1) / 64)) m &= (nb % 64 == 0) ? ~0ull : ((1ull << (nb % 64)) - 1);
-        while (m) {
-          const int bit = 63 - __builtin_clzll(m);
-          m &= ~(1ull << bit);
-          const int k = g * 64 + bit;
-          const uint32_t e = base + (uint32_t)k;
-          Record R;
-          float4* rr = reinterpret_cast<float4*>(&R);
-          rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
-          const PairEval E = eval_pair(R, dx, dy, dz);
-          const bool on = valid & (e < last) & pair_contributes<kFixed>(R, E, op);
-          if (__ballot(on) == 0) continue;
-          const float a = clamp_alpha(E.a_raw, op);
-          const bool clamped = !(E.a_raw < op.alpha_max);
-          const float Tb = on ? T / (1.0f - a) : T;  // transmittance in front of this Gaussian
-          const float w = on ? a * Tb : 0.0f;
-          float part[kAcc];
-          part[1] = w * G0;
-          part[2] = w * G1;
-          part[3] = w * G2;
-          const float dla = on ? Tb * ((R.rgb[0] - cb0) * G0 + (R.rgb[1] - cb1) * G1 + (R.rgb[2] - cb2) * G2) : 0.0f;
-          cb0 = on ? fmaf(a, R.rgb[0] - cb0, cb0) : cb0;
-          cb1 = on ? fmaf(a, R.rgb[1] - cb1, cb1) : cb1;
-          cb2 = on ? fmaf(a, R.rgb[2] - cb2, cb2) : cb2;
-          T = Tb;
-          const float dlk = clamped ? 0.0f : -0.5f * a * dla;  // dL/dkappa
-          part[0] = clamped ? 0.0f : dla * a;                  // dL/dlog(sigma)
-          const float r = sqrtf(R.c1);
-          const float f = 2.0f * r * E.inv * dlk;               // dL/dkappa * 2 r / ss
-          part[4] = f * E.gx * E.gz;
-          part[5] = f * E.gy * E.gz;
-          part[6] = f * E.mm;
-          const float h = f * (R.c1 * E.inv);
-          const float gz2 = E.gz * E.gz;
-          const float du0 = h * gz2 * E.gx, du1 = h * gz2 * E.gy, du2 = h * E.mm * E.gz;
-          part[7] = du0 * dx; part[8] = du0 * dy; part[9] = du0 * dz;
-          part[10] = du1 * dx; part[11] = du1 * dy; part[12] = du1 * dz;
-          part[13] = du2 * dx; part[14] = du2 * dy; part[15] = du2 * dz;
-          wave_reduce16_add(part, acc + (int64_t)s_item[k] * kAcc);
-        }
-      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    while (m != 0) {
+      const int k = 63 - __builtin_clzll(m);  // back to front
+      m &= ~(1ull << k);
+      const uint32_t e = base + (uint32_t)k;
+      Record R;
+      float4* rr = reinterpret_cast<float4*>(&R);
+      rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
+      const PairEval E = eval_pair(R, dx, dy, dz);
+      const bool on = valid & (e < last) & pair_contributes<kFixed>(R, E, op);
+      if (__ballot(on) == 0) continue;
+      const float a = clamp_alpha(E.a_raw, op);
+      const bool clamped = !(E.a_raw < op.alpha_max);
+      const float Tb = on ? T / (1.0f - a) : T;  // transmittance in front of this Gaussian
+      const float w = on ? a * Tb : 0.0f;
+      float part[kAcc];
+      part[1] = w * G0;
+      part[2] = w * G1;
+      part[3] = w * G2;
+      const float dla = on ? Tb * ((R.rgb[0] - cb0) * G0 + (R.rgb[1] - cb1) * G1 + (R.rgb[2] - cb2) * G2) : 0.0f;
+      cb0 = on ? fmaf(a, R.rgb[0] - cb0, cb0) : cb0;
+      cb1 = on ? fmaf(a, R.rgb[1] - cb1, cb1) : cb1;
+      cb2 = on ? fmaf(a, R.rgb[2] - cb2, cb2) : cb2;
+      T = Tb;
+      const float dlk = clamped ? 0.0f : -0.5f * a * dla;  // dL/dkappa
+      part[0] = clamped ? 0.0f : dla * a;                  // dL/dlog(sigma)
+      const float r = sqrtf(R.c1);
+      const float f = 2.0f * r * E.inv * dlk;               // dL/dkappa * 2 r / ss
+      part[4] = f * E.gx * E.gz;
+      part[5] = f * E.gy * E.gz;
+      part[6] = f * E.mm;
+      const float h = f * (R.c1 * E.inv);
+      const float gz2 = E.gz * E.gz;
+      const float du0 = h * gz2 * E.gx, du1 = h * gz2 * E.gy, du2 = h * E.mm * E.gz;
+      part[7] = du0 * dx; part[8] = du0 * dy; part[9] = du0 * dz;
+      part[10] = du1 * dx; part[11] = du1 * dy; part[12] = du1 * dz;
+      part[13] = du2 * dx; part[14] = du2 * dy; part[15] = du2 * dz;
+      wave_reduce16_add(part, acc + (int64_t)s_item[k] * kAcc);
     }
-    __syncthreads();  // the next pass overwrites the staged batch
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -354,11 +341,11 @@ void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t 
     hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nacc + 255) / 256)), dim3(256), 0, st, acc, nacc);
   if (ntiles > 0) {
     if (fixed_lambda)
-      hipLaunchKernelGGL(render_backward_kernel<true>, dim3((unsigned)ntiles), dim3(256), 0, st, views, n_views,
-                         dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc);
+      hipLaunchKernelGGL(render_backward_kernel<true>, dim3((unsigned)(4 * ntiles)), dim3(kWinB), 0, st, views,
+                         n_views, dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc);
     else
-      hipLaunchKernelGGL(render_backward_kernel<false>, dim3((unsigned)ntiles), dim3(256), 0, st, views, n_views,
-                         dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc);
+      hipLaunchKernelGGL(render_backward_kernel<false>, dim3((unsigned)(4 * ntiles)), dim3(kWinB), 0, st, views,
+                         n_views, dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc);
   }
   if (n > 0) {
     const dim3 grid((unsigned)((n + 255) / 256));

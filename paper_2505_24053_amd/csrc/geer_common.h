@@ -44,7 +44,9 @@ struct Opts {
   float kmax_fixed;   // lambda_fixed^2 for the contribution test
   int32_t lam_lo;     // first bucket index of the lambda^2 table
   int32_t lam_n;      // number of buckets
-  int32_t pad_[3];
+  float log2_amin;    // log2(alpha_min), for the half-tile cone test
+  int32_t cone_cull;  // 1: skip entries whose contribution cone misses the half-tile
+  int32_t pad_[1];
 };
 
 __host__ __device__ inline uint32_t pack16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }

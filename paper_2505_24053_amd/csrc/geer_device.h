@@ -365,6 +365,90 @@ __device__ __forceinline__ void pixel_direction(const ViewDev& V, const float2* 
   dz *= dn;
 }
 
+// Rays of one half-tile.  Lines of constant theta and of constant phi on the
+// BEAP grid are great circles (x cos(theta) = z sin(theta), y = z tan(phi)),
+// so every ray of a block of pixel centres lies in the convex cone spanned by
+// the block's four corner rays, listed here in cyclic order.
+struct QuadCone {
+  float d[4][3];
+};
+
+__device__ __forceinline__ QuadCone half_tile_cone(const ViewDev& V, const float2* __restrict__ dtab, int hx, int hy) {
+  const int x0 = hx * kHalf, y0 = hy * kHalf;
+  const int x1 = min(x0 + kHalf - 1, V.width - 1), y1 = min(y0 + kHalf - 1, V.height - 1);
+  QuadCone C;
+  pixel_direction(V, dtab, x0, y0, C.d[0][0], C.d[0][1], C.d[0][2]);
+  pixel_direction(V, dtab, x1, y0, C.d[1][0], C.d[1][1], C.d[1][2]);
+  pixel_direction(V, dtab, x1, y1, C.d[2][0], C.d[2][1], C.d[2][2]);
+  pixel_direction(V, dtab, x0, y1, C.d[3][0], C.d[3][1], C.d[3][2]);
+  return C;
+}
+
+// Conservative test of whether any ray of a half-tile can contribute through
+// a record (false only when none can).  In the record's frame g = G d a ray
+// contributes only if q = |g_xy|^2 / |g|^2 <= Qc, the largest q that keeps
+// sigma exp(-kappa/2) >= alpha_min (and, with a fixed lambda, q <= qmax), and
+// g_z > 0: a circular cone |g_xy| <= tau g_z, tau^2 = Qc / (1 - Qc).  The
+// half-tile's cone maps to the cone over the four corners g_k = G d_k; on the
+// plane g_z = 1 this is a convex quadrilateral and the contribution cone a
+// disc of radius tau about the origin, so the test is disc against polygon.
+// FP32 margins: Qc is inflated by 2^-8 (the blend's own q and exp2 are
+// accurate to a few ulp), the disc radius by 2^-16 of the polygon's extent,
+// and grazing corners (|p| > 2^10) accept outright.
+__device__ __forceinline__ bool cone_meets_quad(const float4& p0, const float4& p1, const float4& p2, const float4& p3,
+                                                const QuadCone& C, float log2_amin, bool fixed) {
+  const float G[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x};
+  const float c0 = p2.y, lsig = p2.z, qmax = p3.w;
+  float Qc = (lsig - log2_amin) / (-c0);
+  if (fixed) Qc = fminf(Qc, qmax);
+  Qc = fmaf(Qc, 0x1p-8f, Qc) + 0x1p-20f;
+  if (!(Qc > 0.0f)) return false;
+  if (Qc >= 1.0f) return true;
+  const float tau2 = Qc / (1.0f - Qc);
+  float px[4], py[4];
+  bool any_front = false, grazing = false;
+  float ext = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float* d = C.d[k];
+    const float gx = fmaf(G[2], d[2], fmaf(G[1], d[1], G[0] * d[0]));
+    const float gy = fmaf(G[5], d[2], fmaf(G[4], d[1], G[3] * d[0]));
+    const float gz = fmaf(G[8], d[2], fmaf(G[7], d[1], G[6] * d[0]));
+    any_front |= gz > 0.0f;
+    grazing |= !(gz * 0x1p10f > fabsf(gx) + fabsf(gy));
+    const float iz = 1.0f / gz;
+    px[k] = gx * iz;
+    py[k] = gy * iz;
+    ext = fmaxf(ext, fmaxf(fabsf(px[k]), fabsf(py[k])));
+  }
+  if (!any_front) return false;  // every ray of the block has g_z <= 0
+  if (grazing) return true;
+  const float r = sqrtf(tau2) + ext * 0x1p-16f;
+  const float r2 = r * r;
+  // origin inside the polygon: the four edge cross products share a sign
+  bool pos = true, neg = true;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int j = (k + 1) & 3;
+    const float cr = px[k] * py[j] - py[k] * px[j];
+    pos &= cr >= 0.0f;
+    neg &= cr <= 0.0f;
+  }
+  if (pos | neg) return true;
+  // otherwise the disc must reach an edge
+  bool meet = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int j = (k + 1) & 3;
+    const float ex = px[j] - px[k], ey = py[j] - py[k];
+    const float ee = fmaf(ex, ex, ey * ey);
+    const float t = fminf(fmaxf(-fmaf(px[k], ex, py[k] * ey) / ee, 0.0f), 1.0f);
+    const float cx = fmaf(t, ex, px[k]), cy = fmaf(t, ey, py[k]);
+    meet |= fmaf(cx, cx, cy * cy) <= r2;
+  }
+  return meet;
+}
+
 // One (ray, Gaussian) pair in the rotated canonical frame: g = G d,
 // kappa = r^2 (gx^2 + gy^2) / |g|^2 = r^2 q, alpha_raw = sigma exp(-kappa/2).
 struct PairEval {

@@ -1,15 +1,19 @@
 // Stage (c): per-ray front-to-back compositing (Alg. 1 render loop, Eq. color)
 // with the closed-form ray opacity alpha = sigma exp(-kappa/2).
 //
-// Mapping: one 256-lane workgroup per 16x16 tile (camera sub-frustum), one
-// wave64 per 8x8 half-tile, one lane per ray.  The workgroup walks its tile's
-// depth-ordered list in batches of 256 entries: each lane fetches one entry's
-// 64-byte record (vector loads, the next batch prefetched into registers
-// while the current one blends) and stages it in LDS; wave ballots publish,
-// per half-tile, which staged entries its rectangle meets.  Each wave then
-// visits only its own hits, reading records from LDS as broadcasts, and skips
-// the batch entirely once all of its rays have terminated; the tile stops
-// when all four waves have.
+// Mapping: one wave64 per 8x8 half-tile (a quarter of a 16x16 camera
+// sub-frustum), one lane per ray, each wave its own 64-lane workgroup so that
+// nothing ties it to the other quarters of its tile.  The wave walks its
+// tile's depth-ordered list in windows of 64 entries: lane k reads entry
+// base + k's list slot and half-tile rectangle, and, when the rectangle meets
+// this half-tile, its 64-byte record (the next window is prefetched into
+// registers while the current one blends).  Lane k then tests whether the
+// Gaussian's contribution cone reaches any ray of the half-tile at all (most
+// rectangle hits of thin or small Gaussians do not); a ballot of the two
+// tests gives the window's hits, staged in the wave's own 4 KB of LDS and
+// visited in order, each record read as an LDS broadcast.  Skipped entries
+// are exactly ones that would blend nothing, so the image is unchanged.  The
+// wave stops as soon as all of its rays have terminated.
 //
 // Per pair, kappa = |o_u x d_u|^2 / |d_u|^2 is evaluated in a canonical frame
 // rotated so that o_u lies on its third axis (the canonical Gaussian is
@@ -33,16 +37,18 @@ namespace geer {
 // pair does not blend).  With kKeep the index one past the last blended
 // entry is tracked for the backward replay.
 template <bool kFixed, bool kKeep>
-__device__ __forceinline__ void blend_one(const Record& R, float dx, float dy, float dz, const Opts& op, uint32_t e,
-                                          uint64_t& done, float& T, float& cr, float& cg, float& cb, float& D,
-                                          uint32_t& last) {
+__device__ __forceinline__ void blend_one(const Record& R, float dx, float dy, float dz, const Opts& op, int amax_bits,
+                                          uint32_t e, uint64_t& done, float& T, float& cr, float& cg, float& cb,
+                                          float& D, uint32_t& last) {
   const PairEval E = eval_pair(R, dx, dy, dz);
   // the contribution rule and the termination test as wave masks: each ballot
   // of a plain comparison is that comparison's lane mask
   uint64_t ok = ~done & __builtin_amdgcn_ballot_w64(E.gz > 0.0f) &
                 __builtin_amdgcn_ballot_w64(E.a_raw >= op.alpha_min);
   if (kFixed) ok &= __builtin_amdgcn_ballot_w64(E.q <= R.qmax);
-  const float a = fminf(E.a_raw, op.alpha_max);
+  // min(alpha_raw, alpha_max): both are >= +0, where the order of the bit
+  // patterns is the order of the values (a NaN pattern also maps to alpha_max)
+  const float a = __int_as_float(min(__float_as_int(E.a_raw), amax_bits));
   const float Tn = fmaf(-a, T, T);
   const uint64_t term = ok & __builtin_amdgcn_ballot_w64(Tn < op.t_min);
   const bool blend = __builtin_amdgcn_inverse_ballot_w64(ok & ~term);
@@ -57,95 +63,87 @@ __device__ __forceinline__ void blend_one(const Record& R, float dx, float dy, f
   if (kKeep) last = blend ? e + 1 : last;
 }
 
-constexpr int kBatch = 256;  // list entries staged per workgroup pass (one per lane)
+constexpr int kWin = 64;  // list entries staged per wave pass (one per lane)
 
 template <bool kFixed, bool kKeep>
-__global__ __launch_bounds__(256) void render_kernel(
+__global__ __launch_bounds__(64) void render_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
     const Record* __restrict__ recs, Opts op, float* __restrict__ rgb, float* __restrict__ depth,
     float* __restrict__ trans, uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
     unsigned long long* __restrict__ stats) {
-  __shared__ float4 s_rec[kBatch][4];     // 16 KB of records, one batch
-  __shared__ uint64_t s_hit[4][kBatch / 64];  // per half-tile: which staged entries meet it
+  __shared__ float4 s_rec[kWin][4];  // this wave's window of records
 
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  // four consecutive indices are the quarters of one tile (same XCD)
+  const int hidx = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = hidx >> 2, quad = hidx & 3;
   int v = 0;
   while (v + 1 < nviews && tile >= views[v + 1].tile_base) ++v;
   const ViewDev& V = views[v];
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
-  const int tid = threadIdx.x;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63;
-  const int hx = 2 * tx + (wv & 1), hy = 2 * ty + (wv >> 1);
-  const bool wave_live = hx < V.nhx && hy < V.nhy;  // half-tile inside a ragged image
+  const uint32_t hx = 2u * tx + (quad & 1), hy = 2u * ty + (quad >> 1);
+  if (hx >= (uint32_t)V.nhx || hy >= (uint32_t)V.nhy) return;  // quarter outside a ragged image
+  const int lane = threadIdx.x;
   const int px = hx * kHalf + (lane & 7), py = hy * kHalf + (lane >> 3);
-  const bool valid = wave_live && px < V.width && py < V.height;
+  const bool valid = px < V.width && py < V.height;
 
   float dx, dy, dz;
   pixel_direction(V, dtab, px, py, dx, dy, dz);
 
   const uint32_t start = ranges[tile], end = ranges[tile + 1];
+  const QuadCone Q = half_tile_cone(V, dtab, hx, hy);
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, D = 0.0f;
   uint32_t last = start;
   uint64_t evals = 0;
-  uint64_t done = __ballot(!valid);  // wave mask of terminated (or absent) rays
-  // the four half-tiles of this tile, for the per-entry hit bits
-  const uint32_t hx0 = 2u * tx, hy0 = 2u * ty;
+  uint64_t done = __builtin_amdgcn_ballot_w64(!valid);  // wave mask of terminated (or absent) rays
+  const int amax_bits = __float_as_int(op.alpha_max);
 
-  // Prefetch of one batch into registers: entry start + k goes to lane k.
+  // Prefetch of one window into registers: entry base + k goes to lane k.
   float4 p0, p1, p2, p3;
-  uint2 prc;
+  bool phit = false;
   auto fetch = [&](uint32_t b) {
-    const uint32_t e = b + tid;
+    const uint32_t e = b + lane;
+    phit = false;
     if (e < end) {
       const uint32_t item = list[e];
-      prc = rects[item];
-      const float4* r = reinterpret_cast<const float4*>(recs + item);
-      p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
-    } else {
-      prc = make_uint2(1u, 0u);  // empty rectangle: meets no half-tile
+      const uint2 rc = rects[item];
+      phit = (rc.x & 0xffffu) <= hx && hx <= (rc.x >> 16) && (rc.y & 0xffffu) <= hy && hy <= (rc.y >> 16);
+      if (phit) {
+        const float4* r = reinterpret_cast<const float4*>(recs + item);
+        p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
+      }
     }
   };
   if (start < end) fetch(start);
 
-  for (uint32_t base = start; base < end; base += kBatch) {
-    // stage the prefetched batch (the barrier closing the previous pass made
-    // the LDS free) and publish each half-tile's hit mask
-    s_rec[tid][0] = p0; s_rec[tid][1] = p1; s_rec[tid][2] = p2; s_rec[tid][3] = p3;
-    const uint32_t rx0 = prc.x & 0xffffu, rx1 = prc.x >> 16, ry0 = prc.y & 0xffffu, ry1 = prc.y >> 16;
-    const bool cx0 = rx0 <= hx0 && hx0 <= rx1, cx1 = rx0 <= hx0 + 1 && hx0 + 1 <= rx1;
-    const bool cy0 = ry0 <= hy0 && hy0 <= ry1, cy1 = ry0 <= hy0 + 1 && hy0 + 1 <= ry1;
-    const uint64_t b00 = __ballot(cx0 && cy0), b10 = __ballot(cx1 && cy0);
-    const uint64_t b01 = __ballot(cx0 && cy1), b11 = __ballot(cx1 && cy1);
-    if (lane == 0) {
-      s_hit[0][wv] = b00; s_hit[1][wv] = b10; s_hit[2][wv] = b01; s_hit[3][wv] = b11;
+  for (uint32_t base = start; base < end && ~done != 0; base += kWin) {
+    // entries whose rectangle meets the half-tile and whose contribution cone
+    // reaches one of its rays
+    if (phit && op.cone_cull) phit = cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, kFixed);
+    uint64_t m = __builtin_amdgcn_ballot_w64(phit);
+    if (phit) {
+      s_rec[lane][0] = p0; s_rec[lane][1] = p1; s_rec[lane][2] = p2; s_rec[lane][3] = p3;
     }
-    if (base + kBatch < end) fetch(base + kBatch);  // in flight while this batch blends
-    __syncthreads();
-    if (~done != 0) {
-      const uint32_t nb = min((uint32_t)kBatch, end - base);
-#pragma unroll
-      for (int g = 0; g < kBatch / 64; ++g) {
-        if ((uint32_t)(g * 64) >= nb) break;
-        const uint64_t mv = s_hit[wv][g];  // same value in every lane: move it to SGPRs
-        // (readfirstlane returns int: go through uint32_t so nothing sign-extends)
-        uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32)) << 32) |
-                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mv);
-        while (m) {
-          const int k = g * 64 + __builtin_ctzll(m);
-          m &= m - 1;
-          Record R;
-          float4* rr = reinterpret_cast<float4*>(&R);
-          rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
-          evals += (uint64_t)__popcll(~done);
-          blend_one<kFixed, kKeep>(R, dx, dy, dz, op, base + k, done, T, cr, cg, cb, D, last);
-        }
-      }
+    if (base + kWin < end) fetch(base + kWin);  // in flight while this window blends
+    // LDS traffic of one wave completes in order; the fences keep the
+    // compiler from moving the window's reads above its writes (and the next
+    // window's writes above these reads)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    while (m != 0 && ~done != 0) {
+      const int k = __builtin_ctzll(m);
+      m &= m - 1;
+      Record R;
+      float4* rr = reinterpret_cast<float4*>(&R);
+      rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
+      evals += (uint64_t)__popcll(~done);
+      blend_one<kFixed, kKeep>(R, dx, dy, dz, op, amax_bits, base + k, done, T, cr, cg, cb, D, last);
     }
-    // every wave done -> the whole tile is done; the barrier also frees the LDS
-    if (__syncthreads_and(~done == 0 ? 1 : 0)) break;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 
   if (valid) {
@@ -173,8 +171,8 @@ void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const View
   if (ntiles <= 0) return;
   const bool keep = nlast != nullptr && tfinal != nullptr;
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(256), 0, st, views, nviews, dtab, ranges, list, rects, recs,
-                       op, rgb, depth, trans, nlast, tfinal, stats);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(4 * ntiles)), dim3(kWin), 0, st, views, nviews, dtab, ranges, list,
+                       rects, recs, op, rgb, depth, trans, nlast, tfinal, stats);
   };
   if (fixed_lambda) {
     if (keep) go(render_kernel<true, true>);

@@ -8,8 +8,8 @@
 //   4. stable LSD radix sort of the entries by global tile id, so each tile's
 //      run stays in (depth key, item) order;
 //   5. run boundaries -> ranges[tile].
-// Radix passes use 8-bit digits, 4096 keys per 256-lane block, LDS
-// histograms and a wave-ballot match to rank equal digits stably.
+// Radix passes use 8-bit digits, one kernel per pass with decoupled
+// look-back (below).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -86,80 +86,174 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t* __re
   }
 }
 
-// ----------------------------------------------------------------- radix --
-
-// Per-block digit histogram, written digit-major: hist[d * nblocks + b].
-// With `filter`, items whose filter value is 0 are skipped (compaction pass).
 // The element count is n_cap, or min(*dyn, n_cap) when a device-side count
 // is given (capacity-sized launches that need no host read-back).
 __device__ __forceinline__ int64_t dyn_count(int64_t n_cap, const unsigned long long* dyn) {
   return dyn ? min((int64_t)*dyn, n_cap) : n_cap;
 }
 
-__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                            const uint32_t* __restrict__ filter, int64_t n_cap,
-                                                            const unsigned long long* __restrict__ dyn, int shift,
-                                                            uint32_t* __restrict__ hist, int64_t nblocks) {
-  const int64_t n = dyn_count(n_cap, dyn);
-  __shared__ uint32_t cnt[256];
-  cnt[threadIdx.x] = 0;
+// ----------------------------------------------------------------- radix --
+//
+// Stable LSD radix sort with 8-bit digits, one kernel per pass ("onesweep"
+// with decoupled look-back).  An upsweep kernel first counts the digits of
+// every pass over the (filtered) input.  In a pass, each block takes the next
+// 2048-key chunk in the order blocks start (an atomic ticket, so every block
+// it waits on is already running), ranks its keys stably (per wave: ballot
+// match on the digit; across waves and slices: running counts in LDS),
+// publishes its per-digit counts, and walks back over earlier blocks'
+// published counts -- stopping at the first that already holds its inclusive
+// prefix -- to find where its run of each digit starts.  Keys are then
+// reordered by digit in LDS and written out as contiguous runs.  A status
+// word is [flag:2 | count:30]; the look-back spin is bounded and reports a
+// stall through an error word instead of hanging.
+
+constexpr int kOSPer = 8;                       // keys per thread
+constexpr int kOSItems = kBlock * kOSPer;       // 2048 keys per block
+constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kWorkHead = 1024 + 64;            // histograms of 4 passes + 4 tickets (padded)
+
+__device__ __forceinline__ int64_t os_blocks(int64_t n) { return (n + kOSItems - 1) / kOSItems; }
+
+// Exclusive scan of one value per thread over a 256-lane block; also returns
+// the block total.  Uses s_w[4].
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s_w, uint32_t& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan(x);
+  if (lane == 63) s_w[w] = incl;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kTileItems;
-#pragma unroll 4
-  for (int it = 0; it < kPerThread; ++it) {
-    int64_t i = base + it * kBlock + threadIdx.x;
-    if (i < n && (!filter || filter[i] != 0)) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
-  }
+  uint32_t pre = 0;
+  for (int q = 0; q < w; ++q) pre += s_w[q];
+  total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+  return pre + incl - x;
 }
 
-// Stable scatter.  Items of a block are processed in 16 consecutive slices of
-// 256; within a slice the rank of an item among equal digits is its rank in
-// its wave (ballot match) plus the counts of the earlier waves.
-__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    const uint32_t* __restrict__ filter, int64_t n_cap, const unsigned long long* __restrict__ dyn, int shift,
-    const uint32_t* __restrict__ hist_off, int64_t nblocks, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out) {
+__global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* __restrict__ keys,
+                                                               const uint32_t* __restrict__ filter, int64_t n_cap,
+                                                               const unsigned long long* __restrict__ dyn,
+                                                               int shift0, int npass, uint32_t* __restrict__ ghist) {
   const int64_t n = dyn_count(n_cap, dyn);
-  __shared__ uint32_t running[256];
-  __shared__ uint32_t wcnt[2][4][256];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  running[tid] = hist_off[(int64_t)tid * nblocks + blockIdx.x];
+  __shared__ uint32_t h[4][256];
 #pragma unroll
-  for (int w = 0; w < 4; ++w) { wcnt[0][w][tid] = 0; wcnt[1][w][tid] = 0; }
+  for (int p = 0; p < 4; ++p) h[p][threadIdx.x] = 0u;
   __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    if (filter && filter[i] == 0u) continue;
+    const uint32_t k = keys[i];
+    for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (shift0 + 8 * p)) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int p = 0; p < npass; ++p) {
+    const uint32_t c = h[p][threadIdx.x];
+    if (c) atomicAdd(&ghist[p * 256 + threadIdx.x], c);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, const uint32_t* __restrict__ filter,
+    int64_t n_cap, const unsigned long long* __restrict__ dyn, int shift, const uint32_t* __restrict__ ghist_p,
+    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next, uint32_t* __restrict__ ticket,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, unsigned long long* __restrict__ err) {
+  __shared__ uint32_t s_cnt[4][256];  // per-wave running digit counts, then per-wave offsets
+  __shared__ uint32_t s_loc[256];     // block-local start of each digit
+  __shared__ uint32_t s_glob[256];    // global start of this block's run of each digit
+  __shared__ uint32_t s_key[kOSItems], s_val[kOSItems];
+  __shared__ uint32_t s_w[4];
+  __shared__ uint32_t s_blk;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) s_blk = atomicAdd(ticket, 1u);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s_cnt[q][tid] = 0u;
+  __syncthreads();
+  const int64_t blk = s_blk;
+  const int64_t n = dyn_count(n_cap, dyn);
+  if (blk >= os_blocks(n)) return;
+  if (status_next) status_next[blk * 256 + tid] = 0u;  // this row is clear for the next pass
+
+  // stable ranks within the wave: wave w owns keys [base, base + 64 kOSPer)
+  const int64_t base = blk * kOSItems + (int64_t)w * 64 * kOSPer;
   const uint64_t lt = lanemask_lt();
-  int64_t base = (int64_t)blockIdx.x * kTileItems;
-  for (int it = 0; it < kPerThread; ++it) {
-    const int buf = it & 1;
-    int64_t i = base + it * kBlock + tid;
-    bool active = i < n && (!filter || filter[i] != 0);
-    uint32_t key = active ? keys_in[i] : 0u;
-    uint32_t val = active ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
-    uint32_t d = (key >> shift) & 255u;
-    uint64_t m = __ballot(active);
+  uint32_t key[kOSPer], val[kOSPer], rank[kOSPer];
+  uint32_t act = 0u;
+#pragma unroll
+  for (int sl = 0; sl < kOSPer; ++sl) {
+    const int64_t i = base + sl * 64 + lane;
+    const bool a = i < n && (!filter || filter[i] != 0u);
+    key[sl] = a ? keys_in[i] : 0u;
+    val[sl] = a ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+    const uint32_t d = (key[sl] >> shift) & 255u;
+    uint64_t m = __builtin_amdgcn_ballot_w64(a);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      uint64_t bb = __ballot(active && ((d >> b) & 1u));
+      const uint64_t bb = __builtin_amdgcn_ballot_w64(((d >> b) & 1u) != 0u);
       m &= ((d >> b) & 1u) ? bb : ~bb;
     }
-    uint32_t rank = (uint32_t)__popcll(m & lt);
-    if (active && rank == 0) wcnt[buf][wv][d] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (active) {
-      uint32_t pre = 0;
-      for (int w = 0; w < wv; ++w) pre += wcnt[buf][w][d];
-      uint32_t pos = running[d] + pre + rank;
-      keys_out[pos] = key;
-      vals_out[pos] = val;
+    const uint32_t r = (uint32_t)__popcll(m & lt);
+    const uint32_t pre = a ? s_cnt[w][d] : 0u;  // every lane of a digit reads before its leader writes
+    rank[sl] = pre + r;
+    if (a && r == 0u) s_cnt[w][d] = pre + (uint32_t)__popcll(m);
+    act |= (a ? 1u : 0u) << sl;
+    // the wave's next slice reads these counts (LDS order within a wave)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+
+  // per digit (thread tid): wave offsets and the block's count
+  const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
+  const uint32_t tot = c0 + c1 + c2 + c3;
+  s_cnt[0][tid] = 0u;
+  s_cnt[1][tid] = c0;
+  s_cnt[2][tid] = c0 + c1;
+  s_cnt[3][tid] = c0 + c1 + c2;
+  __hip_atomic_store(&status[blk * 256 + tid], kFlagAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+  // decoupled look-back over the earlier blocks
+  uint32_t excl = 0u, spins = 0u;
+  for (int64_t j = blk - 1; j >= 0;) {
+    const uint32_t v = __hip_atomic_load(&status[j * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t f = v & ~kValMask;
+    if (f == 0u) {
+      if (++spins > kSpinLimit) {
+        atomicOr(err, 1ull);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
     }
-    uint32_t tot = wcnt[buf][0][tid] + wcnt[buf][1][tid] + wcnt[buf][2][tid] + wcnt[buf][3][tid];
-    __syncthreads();
-    running[tid] += tot;
+    excl += v & kValMask;
+    if (f == kFlagInc) break;
+    --j;
+  }
+  __hip_atomic_store(&status[blk * 256 + tid], kFlagInc | (excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+  uint32_t gtotal, ltotal;
+  const uint32_t gstart = block_excl_scan256(ghist_p[tid], s_w, gtotal);
+  const uint32_t lstart = block_excl_scan256(tot, s_w, ltotal);
+  s_glob[tid] = gstart + excl;
+  s_loc[tid] = lstart;
+  __syncthreads();
+
+  // reorder by digit in LDS, then write contiguous runs
 #pragma unroll
-    for (int w = 0; w < 4; ++w) wcnt[buf][w][tid] = 0;
+  for (int sl = 0; sl < kOSPer; ++sl) {
+    if ((act >> sl) & 1u) {
+      const uint32_t d = (key[sl] >> shift) & 255u;
+      const uint32_t lp = s_loc[d] + s_cnt[w][d] + rank[sl];
+      s_key[lp] = key[sl];
+      s_val[lp] = val[sl];
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < ltotal; i += kBlock) {
+    const uint32_t k = s_key[i];
+    const uint32_t d = (k >> shift) & 255u;
+    const uint32_t g = s_glob[d] + (i - s_loc[d]);
+    keys_out[g] = k;
+    vals_out[g] = s_val[i];
   }
 }
 
@@ -304,20 +398,43 @@ void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n
                      out);
 }
 
-int64_t radix_hist_words(int64_t n) { return 256 * ((n + kTileItems - 1) / kTileItems) + 1; }
+// Workspace of radix_sort, in u32 words: histograms and tickets, then two
+// status tables of 256 words per 2048-key block.
+int64_t radix_work_words(int64_t n_cap) { return kWorkHead + 2 * 256 * ((n_cap + kOSItems - 1) / kOSItems); }
 
-// One stable 8-bit pass over n_cap keys (or the device count *dyn).
-// hist: radix_hist_words(n_cap); scratch for its scan.
-void radix_pass(hipStream_t st, const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* filter,
-                int64_t n_cap, const unsigned long long* dyn, int shift, uint32_t* keys_out, uint32_t* vals_out,
-                uint32_t* hist, uint32_t* scan_scratch) {
-  if (n_cap <= 0) return;
-  int64_t nb = (n_cap + kTileItems - 1) / kTileItems;
-  hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, keys_in, filter, n_cap, dyn, shift,
-                     hist, nb);
-  scan_exclusive(st, hist, hist, 256 * nb, scan_scratch);
-  hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, keys_in, vals_in, filter, n_cap,
-                     dyn, shift, (const uint32_t*)hist, nb, keys_out, vals_out);
+// Stable sort of n0 keys (filtered; values = in_v, or the key index when
+// in_v is null) by npass 8-bit digits from bit shift0.  Pass 0 reads (in_k,
+// in_v) with the n0 count and the filter; later passes read n1 keys (the
+// filtered count, read on the device when dyn1 is given).  Passes write A, B,
+// A, ...: the result is in A for odd npass, in B for even.
+void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, int64_t n0_cap,
+                const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1, int shift0, int npass,
+                uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work, unsigned long long* err) {
+  if (n0_cap <= 0 || npass <= 0) return;
+  const int64_t nmax = std::max(n0_cap, n1_cap);
+  const int64_t rows = 256 * ((nmax + kOSItems - 1) / kOSItems);
+  uint32_t* ghist = work;
+  uint32_t* tickets = work + 1024;
+  uint32_t* stat[2] = {work + kWorkHead, work + kWorkHead + rows};
+  // histograms, tickets and the first status table start at zero
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
+                     (int64_t)kWorkHead + rows, 0u);
+  const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(n0_cap, kBlock), 1), 2048);
+  hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, in_k, filter, n0_cap, dyn0, shift0, npass,
+                     ghist);
+  const uint32_t *sk = in_k, *sv = in_v;
+  for (int p = 0; p < npass; ++p) {
+    uint32_t* ok = (p % 2 == 0) ? ak : bk;
+    uint32_t* ov = (p % 2 == 0) ? av : bv;
+    const int64_t ncap = p == 0 ? n0_cap : n1_cap;
+    const unsigned long long* dy = p == 0 ? dyn0 : dyn1;
+    const unsigned nb = (unsigned)std::max<int64_t>((ncap + kOSItems - 1) / kOSItems, 1);
+    hipLaunchKernelGGL(radix_onesweep_kernel, dim3(nb), dim3(kBlock), 0, st, sk, sv, p == 0 ? filter : nullptr, ncap,
+                       dy, shift0 + 8 * p, (const uint32_t*)(ghist + 256 * p), stat[p % 2],
+                       p + 1 < npass ? stat[(p + 1) % 2] : nullptr, tickets + p, ok, ov, err);
+    sk = ok;
+    sv = ov;
+  }
 }
 
 void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,

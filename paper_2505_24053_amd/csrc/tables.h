@@ -27,10 +27,10 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
 // sort.hip
 int64_t scan_scratch_words(int64_t n);
 void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch);
-int64_t radix_hist_words(int64_t n);
-void radix_pass(hipStream_t st, const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* filter,
-                int64_t n_cap, const unsigned long long* dyn, int shift, uint32_t* keys_out, uint32_t* vals_out,
-                uint32_t* hist, uint32_t* scan_scratch);
+int64_t radix_work_words(int64_t n_cap);
+void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, int64_t n0_cap,
+                const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1, int shift0, int npass,
+                uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work, unsigned long long* err);
 void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
                           const uint32_t* counts, uint32_t* out);
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
