@@ -147,27 +147,33 @@ def bench_serving(args, dev):
     graphs = srv.prepare(shapes)
     warm = synth.workload_serving_requests(args.serve_warmup, seed=args.seed + 200)
     srv.run([serve.Request(i, c) for i, c in enumerate(warm)],
-            serve.poisson_arrivals(len(warm), args.serve_rate, seed=args.seed + 201))
-    srv.stats = dict(batches=0, overflows=0, views=0, overlapped=0)
-    srv.intervals = []
-    cams = synth.workload_serving_requests(args.serve_requests, seed=args.seed + 300)
-    arrivals = serve.poisson_arrivals(len(cams), args.serve_rate, seed=args.seed + 301)
-    done = srv.run([serve.Request(i, c) for i, c in enumerate(cams)], arrivals)
-    summ = serve.latency_summary(done)
-    overlap = srv.device_overlap()
-    stats = dict(srv.stats)
+            serve.poisson_arrivals(len(warm), args.serve_rates[0], seed=args.seed + 201))
+    points = []
+    for j, rate in enumerate(args.serve_rates):
+        srv.stats = dict(batches=0, overflows=0, views=0, overlapped=0)
+        srv.intervals = []
+        cams = synth.workload_serving_requests(args.serve_requests, seed=args.seed + 300 + 10 * j)
+        arrivals = serve.poisson_arrivals(len(cams), rate, seed=args.seed + 301 + 10 * j)
+        done = srv.run([serve.Request(i, c) for i, c in enumerate(cams)], arrivals)
+        summ = serve.latency_summary(done)
+        st = dict(srv.stats)
+        points.append({"rate_req_per_s": rate, "requests": summ["requests"], "p50_ms": round(summ["p50_ms"], 3),
+                       "p99_ms": round(summ["p99_ms"], 3), "mean_ms": round(summ["mean_ms"], 3),
+                       "max_ms": round(summ["max_ms"], 3), "req_per_s": round(float(summ["req_per_s"]), 2),
+                       "mrays_per_s": round(float(summ["mrays_per_s"]), 2), "batches": st["batches"],
+                       "mean_batch": round(st["views"] / max(st["batches"], 1), 2),
+                       "admitted_while_busy": st["overlapped"],
+                       "device_overlap_frac": round(srv.device_overlap(), 3), "overflow_batches": st["overflows"]})
+        log("serving at %.0f req/s:" % rate, points[-1])
     ws_gb = srv.slot_bytes * len(srv.slots) / 2**30
     srv.close()
-    return {"workload": "serving_1m_sh3_mixed_pinhole640x480_fisheye1024_kb200_1920x1080",
-            "rate_req_per_s": args.serve_rate, "requests": summ["requests"],
-            "p50_ms": round(summ["p50_ms"], 3), "p99_ms": round(summ["p99_ms"], 3),
-            "mean_ms": round(summ["mean_ms"], 3), "max_ms": round(summ["max_ms"], 3),
-            "req_per_s": round(summ["req_per_s"], 2), "mrays_per_s": round(summ["mrays_per_s"], 2),
-            "batches": stats["batches"], "mean_batch": round(stats["views"] / max(stats["batches"], 1), 2),
-            "admitted_while_busy": stats["overlapped"], "device_overlap_frac": round(overlap, 3),
-            "overflow_batches": stats["overflows"], "slots": len(srv.slots), "workspace_gib": round(ws_gb, 2),
-            "graphs_per_slot": graphs, "entries_per_tile_capacity": round(1.5 * per_tile, 1),
-            "alone_ms": {k: round(float(np.median(v)), 3) for k, v in alone_ms.items()}}
+    out = {"workload": "serving_1m_sh3_mixed_pinhole640x480_fisheye1024_kb200_1920x1080"}
+    out.update(points[0])
+    out.update({"slots": len(srv.slots), "workspace_gib": round(ws_gb, 2), "graphs_per_slot": graphs,
+                "entries_per_tile_capacity": round(1.5 * per_tile, 1),
+                "alone_ms": {k: round(float(np.median(v)), 3) for k, v in alone_ms.items()},
+                "rates": points})
+    return out
 
 
 def main():
@@ -184,7 +190,8 @@ def main():
     ap.add_argument("--train-warmup", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=600, help="served requests (0: skip)")
     ap.add_argument("--serve-warmup", type=int, default=60)
-    ap.add_argument("--serve-rate", type=float, default=150.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-rates", type=lambda t: [float(x) for x in t.split(",")], default=[200.0, 500.0],
+                    help="Poisson arrival rates (requests/s), comma-separated; the first is the headline point")
     ap.add_argument("--serve-slots", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -284,7 +291,7 @@ def main():
         log("fwd+bwd:", fwd_bwd)
     serving = None
     if args.serve_requests > 0:
-        log("serving: 1M Gaussians, %d requests at %.0f req/s" % (args.serve_requests, args.serve_rate))
+        log("serving: 1M Gaussians, %d requests at %s req/s" % (args.serve_requests, args.serve_rates))
         serving = bench_serving(args, dev)
         log("serving:", serving)
 
