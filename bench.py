@@ -139,7 +139,7 @@ def bench_serving(args, dev):
         _, _, _, fr = renderer.render(sc, [c], keep_frame=True)
         torch.cuda.synchronize()
         alone_ms.setdefault(c["model"], []).append((time.perf_counter() - t) * 1e3)
-        per_tile = max(per_tile, fr.stats()["n_entries"] / serve.tiles_of((c["width"], c["height"])))
+        per_tile = max(per_tile, fr.stats()["n_candidates"] / serve.tiles_of((c["width"], c["height"])))
         fr.release()
     shapes = {(c["width"], c["height"]) for c in probe}
     srv = serve.Server(sc, shapes, entries_per_tile=1.5 * per_tile, slots=args.serve_slots, slot_views=2,
@@ -303,7 +303,8 @@ def main():
                    "camera": "equidistant 180 deg", "beap_grid": [W, H], "tile": 16, "rays": rays},
         "stages_ms": {"preprocess": round(ms_prep, 4), "sort": round(ms_sort, 4), "render": round(ms_render, 4),
                       "device_total": round(ms_total, 4)},
-        "association": {"entries": int(n_entries), "visible": int(st["n_visible"]),
+        "association": {"entries": int(n_entries), "pbf_pairs": int(st["n_candidates"]),
+                        "visible": int(st["n_visible"]),
                         "entries_per_tile_mean": round(float(per_tile.mean()), 1),
                         "entries_per_tile_std": round(float(per_tile.std()), 1)},
         "rgb_err_vs_fp64": rgb_err,

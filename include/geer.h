@@ -89,11 +89,12 @@ typedef struct {
  *     PBF uses lambda_fixed (the paper's "typically 3").
  * alpha = min(alpha_raw, alpha_max); compositing stops before the first
  * Gaussian that would take the transmittance below t_min (t_min = 0: never).
- * flags: GEER_OPT_NO_CONE_CULL makes the render and its backward evaluate
- * every (ray, entry) pair whose half-tile rectangle test passes, instead of
- * first skipping entries whose contribution cone misses all rays of the
- * half-tile; the outputs are the same bits either way (for verification and
- * measurement of the cull). */
+ * flags: GEER_OPT_NO_CONE_CULL keeps every (tile, Gaussian) pair of the PBF
+ * rectangles in the association list and makes the render and its backward
+ * evaluate every (ray, entry) pair whose half-tile rectangle test passes.
+ * Without it, pairs whose contribution cone meets no ray of the tile (list)
+ * or of the half-tile (render) are skipped; the outputs are the same bits
+ * either way (the flag is for verification and measurement of the cull). */
 #define GEER_OPT_NO_CONE_CULL 1
 typedef struct {
   float alpha_min;    /* default 1/255, in (0, 1) */
@@ -115,7 +116,9 @@ typedef struct {
   int64_t n_tiles;     /* 16x16 tiles over all views */
   int64_t n_pixels;    /* rays over all views */
   int64_t n_evaluated; /* (ray, entry) pairs evaluated by the render kernel */
-  int64_t n_composited;/* (ray, Gaussian) pairs blended */
+  int64_t n_candidates;/* (tile, Gaussian) pairs of the PBF rectangles, before the
+                          contribution-cone cull removed those no ray of the tile
+                          can see (equal to n_entries with GEER_OPT_NO_CONE_CULL) */
 } geer_frame_stats;
 
 /* Association buffers a frame can export (for parity checks). */
@@ -247,9 +250,11 @@ geer_status geer_plan_create(geer_ctx* ctx, const geer_scene* scene, int32_t n_v
                              float* rgb, float* depth, float* trans, geer_plan** out);
 /* Uploads the cameras of the next batch and replays the graph on `stream`. */
 geer_status geer_plan_launch(geer_plan* plan, const geer_view* views, void* stream);
-/* Waits for the last launch; reports its association-list length and the
- * capacity, and returns GEER_ERR_CAPACITY if the list did not fit (the
- * outputs of that launch are then incomplete and must be re-rendered). */
+/* Waits for the last launch; reports its count of PBF (tile, Gaussian) pairs
+ * -- what entry_capacity bounds, before the contribution-cone cull shortens
+ * the list -- and the capacity, and returns GEER_ERR_CAPACITY if they did not
+ * fit (the outputs of that launch are then background and must be
+ * re-rendered). */
 geer_status geer_plan_entries(geer_plan* plan, int64_t* entries, int64_t* capacity);
 /* Device memory the plan allocated itself (0 with a caller workspace). */
 int64_t geer_plan_device_bytes(const geer_plan* plan);

@@ -90,6 +90,8 @@ def lib():
             L.orc_lambda2_hat.argtypes = [C.c_float, C.c_float, C.c_int, C.c_double]
             L.orc_lambda2_hat.restype = C.c_float
             L.orc_contrib_mask.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p]
+            L.orc_tile_pairs_contribute.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p,
+                                                    C.c_void_p, C.c_int]
             _lib = L
     return _lib
 
@@ -324,3 +326,17 @@ def opts_dict(**kw):
 
 __all__ = ["build", "assoc_fp32", "tile_list", "render", "render_backward", "sh_basis", "pair", "edges",
            "lambda2_hat", "contrib_mask", "valid_mask", "pixel_dirs_camera", "pixel_dirs_world", "DEFAULT_OPTS"]
+
+
+def tile_pairs_contribute(scene, cam, tiles, gids, nthreads: int = 0, **opts):
+    """FP64: for each (tile, Gaussian) pair of one view, whether some ray of
+    the 16x16 tile meets the contribution rule with the Gaussian."""
+    tiles = np.ascontiguousarray(tiles, dtype=np.int32)
+    gids = np.ascontiguousarray(gids, dtype=np.int64)
+    out = np.zeros(tiles.size, np.uint8)
+    ref = _SceneRef(scene)
+    r = lib().orc_tile_pairs_contribute(C.byref(ref.c), C.byref(make_view(cam)), C.byref(make_opts(**opts)),
+                                        tiles.size, _ptr(tiles), _ptr(gids), _ptr(out), int(nthreads))
+    if r != 0:
+        raise MemoryError("oracle allocation failed")
+    return out.astype(bool)

@@ -587,6 +587,24 @@ static double cmax_of(const gprep* p) {
   return c > p->col[2] ? c : p->col[2];
 }
 
+/* The contribution rule for one (ray, Gaussian) pair, FP64: not culled,
+ * closest approach in front of the camera, kappa <= lambda_i^2, and (fixed
+ * lambda) alpha_raw >= alpha_min. */
+static int pair_contributes64(const gprep* p, const orc_opts* op, const double d[3]) {
+  if (!p->active) return 0;
+  const double* W = p->W;
+  double u[3];
+  for (int a = 0; a < 3; ++a) u[a] = W[a * 3 + 0] * d[0] + W[a * 3 + 1] * d[1] + W[a * 3 + 2] * d[2];
+  const double* ou = p->ou;
+  double m[3] = {ou[1] * u[2] - ou[2] * u[1], ou[2] * u[0] - ou[0] * u[2], ou[0] * u[1] - ou[1] * u[0]};
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double kappa = (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / uu;
+  double od = ou[0] * u[0] + ou[1] * u[1] + ou[2] * u[2];
+  double tstar = -od / uu;
+  double araw = p->sigma * exp(-0.5 * kappa);
+  return tstar > 0 && kappa <= p->lam2 && !(op->lambda_mode == 1 && !(araw >= op->alpha_min));
+}
+
 /* Collects, in (key, index) order, every pair that contributes in FP64 and
  * every pair whose contribution decision lies within the FP32 error band of
  * its threshold (flag = 1, with ptol = 2 alpha_raw max(c): the pair's own
@@ -966,6 +984,41 @@ int orc_contrib_mask(const orc_scene* sc, const orc_view* v, const orc_opts* op,
       for (int64_t i = 0; i < cnt; ++i) mask[(size_t)t * (size_t)n + (size_t)buf[i].g] = 1;
     }
     free(buf);
+  }
+  free(as);
+  free(P);
+  return 0;
+}
+
+/* For (tile, Gaussian) pairs of one view: 1 when some ray of the 16x16 tile
+ * (clipped to the grid) meets the contribution rule with the Gaussian (FP64,
+ * no early termination), else 0.  The tests use it to prove that pairs left
+ * out of the GPU association list are ones no ray of their tile can see
+ * (the list is the PBF list of Sec. 3.2 minus such pairs). */
+int orc_tile_pairs_contribute(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64_t npairs,
+                              const int32_t* tiles, const int64_t* gids, uint8_t* out, int nthreads) {
+  int64_t n = sc->n;
+  orc_assoc* as = (orc_assoc*)malloc(sizeof(orc_assoc) * (size_t)(n > 0 ? n : 1));
+  gprep* P = (gprep*)malloc(sizeof(gprep) * (size_t)(n > 0 ? n : 1));
+  if (!as || !P) { free(as); free(P); return -1; }
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  orc_assoc_fp32(sc, v, op, as);
+  prep_gaussians(sc, v, op, P, as);
+  const int tw = (v->width + 15) / 16;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < npairs; ++i) {
+    const gprep* p = &P[gids[i]];
+    const int tx = tiles[i] % tw, ty = tiles[i] / tw;
+    int hit = 0;
+    for (int py = ty * 16; py < ty * 16 + 16 && py < v->height && !hit; ++py)
+      for (int px = tx * 16; px < tx * 16 + 16 && px < v->width && !hit; ++px) {
+        double d[3];
+        pixel_dir(v, px, py, d);
+        hit = pair_contributes64(p, op, d);
+      }
+    out[i] = (uint8_t)hit;
   }
   free(as);
   free(P);

@@ -48,7 +48,7 @@ class GeerOpts(C.Structure):
 class GeerFrameStats(C.Structure):
     _fields_ = [("n_items", C.c_int64), ("n_visible", C.c_int64), ("n_entries", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_pixels", C.c_int64), ("n_evaluated", C.c_int64),
-                ("n_composited", C.c_int64)]
+                ("n_candidates", C.c_int64)]
 
 
 class GeerProfileRecord(C.Structure):

@@ -89,10 +89,12 @@ struct geer_frame {
   const float* lam = nullptr;  // lambda^2 table of the forward's alpha_min
   int32_t nviews = 0;
   int64_t n = 0, items = 0, ntiles = 0, npix = 0, entries = 0, visible = 0;
+  mutable int64_t kept = -1;  // list length after the cone cull (read from the device on first use)
   size_t edges_off = 0, dtab_off = 0;  // sub-buffers of meta
   std::vector<geer_view> views;
   std::vector<ViewDev> hviews;
-  Block meta, recs, rects, keys, counts, list, ranges, nlast, tfinal, stats;
+  Block meta, recs, rects, keys, counts, list, ranges, nlast, tfinal, stats, heavy_list, heavy_flag;
+  int hmax = 0;
 };
 
 namespace {
@@ -237,7 +239,7 @@ geer_status lambda_dev(geer_ctx* c, float amin, LamTab* out) {
 void free_frame_buffers(geer_frame* f) {
   geer_ctx* c = f->ctx;
   for (Block* b : {&f->meta, &f->recs, &f->rects, &f->keys, &f->counts, &f->list, &f->ranges, &f->nlast,
-                   &f->tfinal, &f->stats})
+                   &f->tfinal, &f->stats, &f->heavy_list, &f->heavy_flag})
     release(c, *b);
 }
 
@@ -271,12 +273,16 @@ struct FwdBufs {
   Record* recs = nullptr;
   uint2* rects = nullptr;
   uint32_t *keys = nullptr, *counts = nullptr;
-  uint64_t* stats = nullptr;  // [0] entries, [1] visible, [2] evaluated pairs, [3] entries before the guard,
-                              // [4] sort stall flag
+  uint64_t* stats = nullptr;  // [0] rectangle entries, [1] visible, [2] evaluated pairs, [3] entries before
+                              // the guard, [4] sort stall flag, [5] list length after the cone cull,
+                              // [6] heavy tiles
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr, *hist = nullptr, *scratch = nullptr;
   uint32_t *cnt_sorted = nullptr, *tiles_a = nullptr, *tiles_b = nullptr, *items_b = nullptr;
   uint32_t *list = nullptr, *ranges = nullptr, *nlast = nullptr;
   float* tfinal = nullptr;
+  uint32_t *heavy_list = nullptr, *heavy_flag = nullptr;  // heavy-tile work list
+  int hmax = 0;
+  HeavyTiles heavy() const { return HeavyTiles{heavy_list, heavy_flag, (unsigned long long*)(stats + 6), hmax}; }
 };
 
 // Stage (a): zero the counters, then preprocess + PBF of every item.
@@ -291,34 +297,36 @@ void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, co
 // ecap are the counts read back from the device; otherwise they are
 // capacities and every kernel reads the live counts from b.stats.
 // Returns the buffer holding the final (tile-sorted) list in b.list.
-void enqueue_association(hipStream_t st, int64_t n, int64_t items, int64_t nvis_cap, int64_t ecap, int64_t ntiles,
-                         bool dyn, const FwdBufs& b) {
+void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t items, int64_t nvis_cap, int64_t ecap,
+                         int64_t ntiles, bool dyn, const FwdBufs& b) {
   const unsigned long long* dE = dyn ? (const unsigned long long*)b.stats : nullptr;
   const unsigned long long* dV = dyn ? (const unsigned long long*)(b.stats + 1) : nullptr;
-  if (dyn) launch_capacity_guard(st, (unsigned long long*)b.stats, ecap);
+  unsigned long long* kept = (unsigned long long*)(b.stats + 5);  // list length after the cone cull
   unsigned long long* err = (unsigned long long*)(b.stats + 4);
+  if (dyn) launch_capacity_guard(st, (unsigned long long*)b.stats, ecap);
   if (nvis_cap > 0) {
     // depth order of the visible items (pass 0 compacts them out of all items)
-    radix_sort(st, b.keys, nullptr, b.counts, items, nullptr, nvis_cap, dV, 0, 4, b.ka, b.va, b.kb, b.vb, b.hist,
-               err);
+    radix_sort(st, b.keys, nullptr, b.counts, false, items, nullptr, nvis_cap, dV, 0, 4, b.ka, b.va, b.kb, b.vb,
+               b.hist, nullptr, err);
     launch_gather_counts(st, b.vb, nvis_cap, dV, b.counts, b.cnt_sorted);
     scan_exclusive(st, b.cnt_sorted, b.cnt_sorted, nvis_cap, b.scratch);
-    // Expansion in depth order, then the stable tile-id passes, arranged so
-    // that the sorted items end in b.list: pair P = (tiles_b, list),
-    // Q = (tiles_a, items_b); odd pass counts run Q -> P -> Q ..., even ones
-    // P -> Q -> P ...
-    const int passes = bytes_for_tiles(ntiles - 1);
+    // Expansion in depth order (entries no ray of their tile can see marked
+    // for dropping), then the stable tile-id passes -- the first compacts --
+    // arranged so that the sorted items end in b.list: pair P = (tiles_b,
+    // list), Q = (tiles_a, items_b); odd pass counts run Q -> P -> Q ...,
+    // even ones P -> Q -> P ...
+    const int passes = std::max(1, bytes_for_tiles(ntiles - 1));
     uint32_t *pt = b.tiles_b, *pi = b.list, *qt = b.tiles_a, *qi = b.items_b;
     uint32_t* tin = (passes % 2 == 1) ? qt : pt;
     uint32_t* iin = (passes % 2 == 1) ? qi : pi;
     uint32_t* at = (passes % 2 == 1) ? pt : qt;
     uint32_t* ai = (passes % 2 == 1) ? pi : qi;
-    launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, tin, iin);
-    radix_sort(st, tin, iin, nullptr, ecap, dE, ecap, dE, 0, passes, at, ai, tin, iin, b.hist, err);
+    launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, b.dtab, b.recs, op, tin, iin);
+    radix_sort(st, tin, iin, nullptr, op.cone_cull != 0, ecap, dE, ecap, kept, 0, passes, at, ai, tin, iin, b.hist,
+               kept, err);
     uint32_t* tfinal = (passes % 2 == 1) ? at : tin;
-    if (dyn) launch_pad_list(st, b.list, ecap, dE);
-    else launch_fill_u32(st, b.list + ecap, 8, 0u);
-    launch_ranges(st, tfinal, ecap, dE, ntiles, b.ranges);
+    launch_pad_list(st, b.list, ecap, kept);
+    launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges);
   } else {
     launch_fill_u32(st, b.list, 8, 0u);
     launch_ranges(st, nullptr, 0, nullptr, ntiles, b.ranges);
@@ -328,8 +336,9 @@ void enqueue_association(hipStream_t st, int64_t n, int64_t items, int64_t nvis_
 // Stage (c): the render kernel.
 void enqueue_render(hipStream_t st, const Opts& op, int64_t ntiles, int32_t nviews, const FwdBufs& b, float* rgb,
                     float* depth, float* trans) {
-  launch_render(st, op.lambda_mode == 1, ntiles, b.views, nviews, b.dtab, b.ranges, b.list, b.rects, b.recs, op, rgb,
-                depth, trans, b.nlast, b.tfinal, (unsigned long long*)(b.stats + 2));
+  launch_mark_heavy(st, b.ranges, ntiles, b.heavy());
+  launch_render(st, op.lambda_mode == 1, ntiles, b.views, nviews, b.dtab, b.ranges, b.list, b.rects, b.recs, op,
+                b.heavy(), rgb, depth, trans, b.nlast, b.tfinal, (unsigned long long*)(b.stats + 2));
 }
 
 // Host-side per-view tables of a batch, packed as [ViewDev...][edges][dtab].
@@ -572,10 +581,16 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   b.tiles_a = (uint32_t*)tiles_a.p; b.tiles_b = (uint32_t*)tiles_b.p; b.items_b = (uint32_t*)items_b.p;
   b.list = (uint32_t*)f->list.p; b.ranges = (uint32_t*)f->ranges.p;
   prof_mark(ps, 2, st);
-  enqueue_association(st, n, items, nvis, E, ntiles, false, b);
+  enqueue_association(st, op, n, items, nvis, E, ntiles, false, b);
   HTRY(hipGetLastError());
 
   // ---- stage (c): render ----
+  f->hmax = heavy_capacity(ntiles);
+  TRY(acquire(c, 4 * (size_t)f->hmax, st, f->heavy_list));
+  TRY(acquire(c, 4 * (size_t)ntiles, st, f->heavy_flag));
+  b.heavy_list = (uint32_t*)f->heavy_list.p;
+  b.heavy_flag = (uint32_t*)f->heavy_flag.p;
+  b.hmax = f->hmax;
   const bool keep = frame_out != nullptr;
   if (keep) {
     TRY(acquire(c, 4 * npix, st, f->nlast));
@@ -587,7 +602,7 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   enqueue_render(st, op, ntiles, n_views, b, rgb, depth, trans);
   HTRY(hipGetLastError());
   prof_mark(ps, 4, st);
-  if (ps) HTRY(hipMemcpyAsync(ps->host_stats, b.stats, 32, hipMemcpyDeviceToHost, st));
+  if (ps) HTRY(hipMemcpyAsync(ps->host_stats, b.stats, 48, hipMemcpyDeviceToHost, st));
   cleanup(GEER_OK);
   if (keep) {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -621,8 +636,10 @@ geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* 
   const float* d_edges = (const float*)(meta + f->edges_off);
   const float2* d_dtab = (const float2*)(meta + f->dtab_off);
   const geer_scene& sc = f->scene;
+  const HeavyTiles heavy{(uint32_t*)f->heavy_list.p, (uint32_t*)f->heavy_flag.p,
+                         (unsigned long long*)((uint64_t*)f->stats.p + 6), f->hmax};
   launch_backward(st, f->op.lambda_mode == 1, f->ntiles, f->n, f->nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat,
-                  sc.opacity, sc.sh, d_views, d_dtab, d_edges, f->lam, f->op, (const uint32_t*)f->ranges.p,
+                  sc.opacity, sc.sh, d_views, d_dtab, d_edges, f->lam, f->op, heavy, (const uint32_t*)f->ranges.p,
                   (const uint32_t*)f->list.p, (const uint2*)f->rects.p, (const Record*)f->recs.p,
                   (const uint32_t*)f->nlast.p, (const float*)f->tfinal.p, dl_drgb, (float*)acc.p, accumulate != 0,
                   g_mean, g_scale, g_quat, g_opacity, g_sh);
@@ -643,21 +660,28 @@ void geer_frame_release(geer_frame* f) {
   delete f;
 }
 
-geer_status geer_frame_get_stats(const geer_frame* f, geer_frame_stats* out) {
-  if (!f || !out) return GEER_ERR_INVALID_ARG;
+geer_status read_frame_stats(const geer_frame* f, uint64_t st[6]) {
   geer_ctx* c = f->ctx;
-  uint64_t st[5];
   HIP_TRY(c, hipSetDevice(c->device));
-  HIP_TRY(c, hipMemcpyAsync(st, f->stats.p, sizeof st, hipMemcpyDeviceToHost, f->stream));
+  HIP_TRY(c, hipMemcpyAsync(st, f->stats.p, 6 * sizeof(uint64_t), hipMemcpyDeviceToHost, f->stream));
   HIP_TRY(c, hipStreamSynchronize(f->stream));
   if (st[4] != 0) return fail(c, GEER_ERR_HIP, "association sort stalled (look-back spin limit)");
+  f->kept = f->entries > 0 ? (int64_t)st[5] : 0;
+  return GEER_OK;
+}
+
+geer_status geer_frame_get_stats(const geer_frame* f, geer_frame_stats* out) {
+  if (!f || !out) return GEER_ERR_INVALID_ARG;
+  uint64_t st[6];
+  geer_status s = read_frame_stats(f, st);
+  if (s != GEER_OK) return s;
   out->n_items = f->items;
   out->n_visible = (int64_t)st[1];
-  out->n_entries = (int64_t)st[0];
+  out->n_entries = f->kept;
   out->n_tiles = f->ntiles;
   out->n_pixels = f->npix;
   out->n_evaluated = (int64_t)st[2];
-  out->n_composited = -1;
+  out->n_candidates = (int64_t)st[0];
   return GEER_OK;
 }
 
@@ -667,7 +691,13 @@ int64_t geer_frame_buffer_bytes(const geer_frame* f, int32_t which) {
     case GEER_BUF_RECT: return 8 * f->items;
     case GEER_BUF_COUNT: return 4 * f->items;
     case GEER_BUF_KEY: return 4 * f->items;
-    case GEER_BUF_LIST: return 4 * f->entries;
+    case GEER_BUF_LIST: {
+      if (f->kept < 0) {
+        uint64_t st[6];
+        if (read_frame_stats(f, st) != GEER_OK) return -1;
+      }
+      return 4 * f->kept;
+    }
     case GEER_BUF_RANGES: return 4 * (f->ntiles + 1);
     case GEER_BUF_NLAST: return 4 * f->npix;
     default: return -1;
@@ -705,7 +735,7 @@ geer_status geer_set_profiling(geer_ctx* c, int32_t enable) {
     c->prof.resize(64);
     for (auto& ps : c->prof) {
       for (auto& e : ps.ev) HIP_TRY(c, hipEventCreate(&e));
-      HIP_TRY(c, hipHostMalloc((void**)&ps.host_stats, 32, hipHostMallocDefault));
+      HIP_TRY(c, hipHostMalloc((void**)&ps.host_stats, 64, hipHostMallocDefault));
     }
   }
   c->profiling = enable != 0;
@@ -733,7 +763,7 @@ int32_t geer_profile_read(geer_ctx* c, geer_profile_record* out, int32_t max) {
     out[i].ms_sort = t23;
     out[i].ms_render = t34;
     out[i].ms_total = t04;
-    out[i].n_entries = (int64_t)ps.host_stats[0];
+    out[i].n_entries = (int64_t)ps.host_stats[5];
     out[i].n_evaluated = (int64_t)ps.host_stats[2];
   }
   c->prof_count = 0;
@@ -773,7 +803,8 @@ geer_status geer_l1_loss(geer_ctx* c, int64_t pixels, const float* rgb, const fl
 // 256-byte aligned, carved from one block.
 struct PlanLayout {
   size_t meta = 0, recs = 0, rects = 0, keys = 0, counts = 0, stats = 0, ka = 0, va = 0, kb = 0, vb = 0, hist = 0,
-         scratch = 0, cnt_sorted = 0, tiles_a = 0, tiles_b = 0, items_b = 0, list = 0, ranges = 0, total = 0;
+         scratch = 0, cnt_sorted = 0, tiles_a = 0, tiles_b = 0, items_b = 0, list = 0, ranges = 0, heavy_list = 0,
+         heavy_flag = 0, total = 0;
 };
 
 PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t ntiles) {
@@ -804,6 +835,8 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
   L.items_b = put(4 * (ecap + 8));
   L.list = put(4 * (ecap + 8));
   L.ranges = put(4 * (ntiles + 1));
+  L.heavy_list = put(4 * (size_t)heavy_capacity(ntiles));
+  L.heavy_flag = put(4 * (size_t)ntiles);
   L.total = off;
   return L;
 }
@@ -909,6 +942,9 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
   b.items_b = (uint32_t*)(w + lay.items_b);
   b.list = (uint32_t*)(w + lay.list);
   b.ranges = (uint32_t*)(w + lay.ranges);
+  b.heavy_list = (uint32_t*)(w + lay.heavy_list);
+  b.heavy_flag = (uint32_t*)(w + lay.heavy_flag);
+  b.hmax = heavy_capacity(P->ntiles);
   for (int k = 0; k < 2; ++k) {
     PHIP(hipHostMalloc(&P->staging[k], std::max<size_t>(tab.bytes, 64), hipHostMallocDefault));
     PHIP(hipEventCreateWithFlags(&P->staged[k], hipEventDisableTiming));
@@ -923,7 +959,7 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     enqueue_preprocess(cs, P->scene, n_views, P->op, lt.dev, b);
-    enqueue_association(cs, P->n, items, std::max<int64_t>(items, 1), entry_capacity, P->ntiles, true, b);
+    enqueue_association(cs, P->op, P->n, items, std::max<int64_t>(items, 1), entry_capacity, P->ntiles, true, b);
     enqueue_render(cs, P->op, P->ntiles, n_views, b, rgb, depth, trans);
     hipError_t e2 = hipStreamEndCapture(cs, &P->graph);
     e = e2 != hipSuccess ? e2 : hipGetLastError();
@@ -961,7 +997,7 @@ geer_status geer_plan_launch(geer_plan* P, const geer_view* views, void* stream)
   P->staged_used[k] = true;
   P->next = 1 - k;
   HIP_TRY(c, hipGraphLaunch(P->exec, st));
-  HIP_TRY(c, hipMemcpyAsync(P->host_stats, P->stats, 40, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipMemcpyAsync(P->host_stats, P->stats, 48, hipMemcpyDeviceToHost, st));
   HIP_TRY(c, hipEventRecord(P->done, st));
   P->launched = true;
   return GEER_OK;

@@ -71,26 +71,24 @@ template <bool kFixed>
 __global__ __launch_bounds__(64) void render_backward_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
-    const Record* __restrict__ recs, Opts op, const uint32_t* __restrict__ nlast, const float* __restrict__ tfinal,
-    const float* __restrict__ dl_drgb, float* __restrict__ acc) {
+    const Record* __restrict__ recs, Opts op, HeavyTiles heavy, const uint32_t* __restrict__ nlast,
+    const float* __restrict__ tfinal, const float* __restrict__ dl_drgb, float* __restrict__ acc) {
   __shared__ float4 s_rec[kWinB][4];
   __shared__ uint32_t s_item[kWinB];
 
-  const int hidx = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = hidx >> 2, quad = hidx & 3;
-  int v = 0;
-  while (v + 1 < nviews && tile >= views[v + 1].tile_base) ++v;
-  const ViewDev& V = views[v];
-  const int lt = tile - V.tile_base;
-  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
-  const uint32_t hx = 2u * tx + (quad & 1), hy = 2u * ty + (quad >> 1);
-  if (hx >= (uint32_t)V.nhx || hy >= (uint32_t)V.nhy) return;
+  const WaveBlock W = wave_block(blockIdx.x, gridDim.x, views, nviews, heavy.list, heavy.flag, heavy.count,
+                                 heavy.hmax);
+  if (!W.live) return;
+  const ViewDev& V = views[W.v];
+  const int tile = W.tile;
+  const uint32_t hx = (uint32_t)W.bx0 >> 3, hy = (uint32_t)W.by0 >> 3;  // half-tile of the block
   const int lane = threadIdx.x;
-  const int px = hx * kHalf + (lane & 7), py = hy * kHalf + (lane >> 3);
-  const bool valid = px < V.width && py < V.height;
+  const int lb = W.bs == 8 ? 3 : 2;
+  const int px = W.bx0 + (lane & (W.bs - 1)), py = W.by0 + (lane >> lb);
+  const bool valid = lane < W.bs * W.bs && px < V.width && py < V.height;
   float dx, dy, dz;
   pixel_direction(V, dtab, px, py, dx, dy, dz);
-  const QuadCone Q = half_tile_cone(V, dtab, hx, hy);
+  const QuadCone Q = block_cone(V, dtab, W.bx0, W.by0, W.bs);
 
   const uint32_t start = ranges[tile];
   const int64_t hw = (int64_t)V.width * V.height;
@@ -332,20 +330,22 @@ __global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ p, in
 void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t n, int32_t n_views,
                      int32_t sh_degree, const float* mean, const float* scale, const float* quat,
                      const float* opacity, const float* sh, const ViewDev* views, const float2* dtab,
-                     const float* edges, const float* lam_tab, const Opts& op, const uint32_t* ranges,
-                     const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
+                     const float* edges, const float* lam_tab, const Opts& op, const HeavyTiles& heavy,
+                     const uint32_t* ranges, const uint32_t* list, const uint2* rects, const Record* recs,
+                     const uint32_t* nlast,
                      const float* tfinal, const float* dl_drgb, float* acc, int accumulate, float* g_mean,
                      float* g_scale, float* g_quat, float* g_opacity, float* g_sh) {
   const int64_t nacc = n * n_views * kAcc;
   if (nacc > 0)
     hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nacc + 255) / 256)), dim3(256), 0, st, acc, nacc);
   if (ntiles > 0) {
+    const unsigned grid = (unsigned)(kHeavySplit * heavy.hmax + 4 * ntiles);
     if (fixed_lambda)
-      hipLaunchKernelGGL(render_backward_kernel<true>, dim3((unsigned)(4 * ntiles)), dim3(kWinB), 0, st, views,
-                         n_views, dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc);
+      hipLaunchKernelGGL(render_backward_kernel<true>, dim3(grid), dim3(kWinB), 0, st, views, n_views, dtab, ranges,
+                         list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
     else
-      hipLaunchKernelGGL(render_backward_kernel<false>, dim3((unsigned)(4 * ntiles)), dim3(kWinB), 0, st, views,
-                         n_views, dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc);
+      hipLaunchKernelGGL(render_backward_kernel<false>, dim3(grid), dim3(kWinB), 0, st, views, n_views, dtab, ranges,
+                         list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
   }
   if (n > 0) {
     const dim3 grid((unsigned)((n + 255) / 256));

@@ -365,18 +365,78 @@ __device__ __forceinline__ void pixel_direction(const ViewDev& V, const float2* 
   dz *= dn;
 }
 
-// Rays of one half-tile.  Lines of constant theta and of constant phi on the
-// BEAP grid are great circles (x cos(theta) = z sin(theta), y = z tan(phi)),
-// so every ray of a block of pixel centres lies in the convex cone spanned by
-// the block's four corner rays, listed here in cyclic order.
-struct QuadCone {
-  float d[4][3];
+// Work of one render wave: a block of rays of one tile.  Ordinary tiles are
+// split into four 8x8 half-tiles (one lane per ray).  Tiles flagged heavy --
+// many more list entries than the mean, which on wide BEAP grids happens
+// where a tile fans over a wide range of directions and its rays see mostly
+// different Gaussians -- are split into sixteen 4x4 blocks (16 lanes active),
+// so that each wave walks only the entries of its own rays; their waves come
+// first in the grid.  Block indices below kHeavySplit * hmax address heavy
+// tiles, the rest ordinary ones (XCD-banded).
+constexpr int kHeavySplit = 16;
+
+struct WaveBlock {
+  int tile, v;     // global tile, view
+  int bx0, by0;    // first pixel of the block (view coordinates)
+  int bs;          // block edge: 8, or 4 in heavy tiles
+  bool live;       // false: nothing to do for this wave
 };
 
-__device__ __forceinline__ QuadCone half_tile_cone(const ViewDev& V, const float2* __restrict__ dtab, int hx, int hy) {
-  const int x0 = hx * kHalf, y0 = hy * kHalf;
-  const int x1 = min(x0 + kHalf - 1, V.width - 1), y1 = min(y0 + kHalf - 1, V.height - 1);
+__device__ __forceinline__ WaveBlock wave_block(int bid, int nblocks, const ViewDev* __restrict__ views,
+                                                int nviews, const uint32_t* __restrict__ heavy_list,
+                                                const uint32_t* __restrict__ heavy_flag,
+                                                const unsigned long long* __restrict__ heavy_count, int hmax) {
+  WaveBlock w;
+  w.live = false;
+  int sub;
+  const int nheavy_blocks = kHeavySplit * hmax;
+  if (bid < nheavy_blocks) {
+    const int h = bid / kHeavySplit;
+    if (h >= (int)min(*heavy_count, (unsigned long long)hmax)) return w;
+    w.tile = (int)heavy_list[h];
+    sub = bid % kHeavySplit;
+    w.bs = 4;
+  } else {
+    const int hidx = xcd_remap(bid - nheavy_blocks, nblocks - nheavy_blocks);
+    w.tile = hidx >> 2;
+    if (heavy_flag && heavy_flag[w.tile]) return w;
+    sub = hidx & 3;
+    w.bs = 8;
+  }
+  int v = 0;
+  while (v + 1 < nviews && w.tile >= views[v + 1].tile_base) ++v;
+  const ViewDev& V = views[v];
+  w.v = v;
+  const int lt = w.tile - V.tile_base;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int per = kTile / w.bs;  // blocks per tile edge
+  w.bx0 = tx * kTile + (sub % per) * w.bs;
+  w.by0 = ty * kTile + (sub / per) * w.bs;
+  w.live = w.bx0 < V.width && w.by0 < V.height;
+  return w;
+}
+
+// Rays of a block of pixels.  Lines of constant theta and of constant phi
+// on the BEAP grid are great circles (x cos(theta) = z sin(theta),
+// y cos(phi) = z sin(phi)).  While cos(theta) keeps one sign over the block,
+// theta = atan2(x, z) and sign(cos theta) (y cos(phi0) - z sin(phi0)) >= 0
+// for phi >= phi0, so the block's directions are the intersection of four
+// half-spaces: the convex cone spanned by its four corner rays, listed here
+// in cyclic order.  A block whose theta range reaches +-90 degrees contains
+// the pole where every phi line meets and is not that cone (valid = false).
+struct QuadCone {
+  float d[4][3];
+  bool valid;
+};
+
+// Corner rays of the block of pixels [x0, x0 + size) x [y0, y0 + size) (clipped
+// to the image).
+__device__ __forceinline__ QuadCone block_cone(const ViewDev& V, const float2* __restrict__ dtab, int x0, int y0,
+                                               int size) {
+  const int x1 = min(x0 + size - 1, V.width - 1), y1 = min(y0 + size - 1, V.height - 1);
   QuadCone C;
+  const float c0 = dtab[V.dx_off + x0].y, c1 = dtab[V.dx_off + x1].y;  // cos(theta) of the end columns
+  C.valid = (c0 > 0.0f && c1 > 0.0f) || (c0 < 0.0f && c1 < 0.0f);
   pixel_direction(V, dtab, x0, y0, C.d[0][0], C.d[0][1], C.d[0][2]);
   pixel_direction(V, dtab, x1, y0, C.d[1][0], C.d[1][1], C.d[1][2]);
   pixel_direction(V, dtab, x1, y1, C.d[2][0], C.d[2][1], C.d[2][2]);
@@ -384,19 +444,29 @@ __device__ __forceinline__ QuadCone half_tile_cone(const ViewDev& V, const float
   return C;
 }
 
-// Conservative test of whether any ray of a half-tile can contribute through
-// a record (false only when none can).  In the record's frame g = G d a ray
-// contributes only if q = |g_xy|^2 / |g|^2 <= Qc, the largest q that keeps
-// sigma exp(-kappa/2) >= alpha_min (and, with a fixed lambda, q <= qmax), and
-// g_z > 0: a circular cone |g_xy| <= tau g_z, tau^2 = Qc / (1 - Qc).  The
-// half-tile's cone maps to the cone over the four corners g_k = G d_k; on the
-// plane g_z = 1 this is a convex quadrilateral and the contribution cone a
-// disc of radius tau about the origin, so the test is disc against polygon.
-// FP32 margins: Qc is inflated by 2^-8 (the blend's own q and exp2 are
-// accurate to a few ulp), the disc radius by 2^-16 of the polygon's extent,
-// and grazing corners (|p| > 2^10) accept outright.
+__device__ __forceinline__ QuadCone half_tile_cone(const ViewDev& V, const float2* __restrict__ dtab, int hx, int hy) {
+  return block_cone(V, dtab, hx * kHalf, hy * kHalf, kHalf);
+}
+
+// Conservative test of whether any ray of a block of pixels (a half-tile or
+// a tile) can contribute through a record (false only when none can).  In
+// the record's frame g = G d a ray contributes only if q = |g_xy|^2 / |g|^2
+// <= Qc, the largest q that keeps sigma exp(-kappa/2) >= alpha_min (and,
+// with a fixed lambda, q <= qmax), and g_z > 0: a circular cone
+// |g_xy| <= tau g_z, tau^2 = Qc / (1 - Qc).  On the plane g_z = 1 that cone is
+// the disc |p| <= tau, and the part of the block's cone (spanned by the
+// corners g_k) in front, g_z > 0, is the intersection of the four half-planes
+// n_k . (p, 1) >= 0 with n_k = g_k x g_(k+1) oriented inward (bounded or
+// not, whatever the signs of the corners' g_z).  The test is whether the
+// distance from the disc's centre to that region is at most tau: zero if
+// every n_k,z >= 0, else the smallest of the distances to the face lines
+// whose foot point lies in the region and to the corners in front.  The
+// corner vectors are rescaled to unit max-norm first (the cone is unchanged);
+// FP32 margins: Qc + 2^-8 Qc + 2^-20, tau^2 + 2^-8 tau^2 + 2^-18 (1 + d^2),
+// and 2^-12 relative slack in the foot-point test.
 __device__ __forceinline__ bool cone_meets_quad(const float4& p0, const float4& p1, const float4& p2, const float4& p3,
                                                 const QuadCone& C, float log2_amin, bool fixed) {
+  if (!C.valid) return true;
   const float G[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x};
   const float c0 = p2.y, lsig = p2.z, qmax = p3.w;
   float Qc = (lsig - log2_amin) / (-c0);
@@ -405,48 +475,69 @@ __device__ __forceinline__ bool cone_meets_quad(const float4& p0, const float4& 
   if (!(Qc > 0.0f)) return false;
   if (Qc >= 1.0f) return true;
   const float tau2 = Qc / (1.0f - Qc);
-  float px[4], py[4];
-  bool any_front = false, grazing = false;
-  float ext = 0.0f;
+  float g[4][3];
+  bool any_front = false;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const float* d = C.d[k];
-    const float gx = fmaf(G[2], d[2], fmaf(G[1], d[1], G[0] * d[0]));
-    const float gy = fmaf(G[5], d[2], fmaf(G[4], d[1], G[3] * d[0]));
-    const float gz = fmaf(G[8], d[2], fmaf(G[7], d[1], G[6] * d[0]));
+    float gx = fmaf(G[2], d[2], fmaf(G[1], d[1], G[0] * d[0]));
+    float gy = fmaf(G[5], d[2], fmaf(G[4], d[1], G[3] * d[0]));
+    float gz = fmaf(G[8], d[2], fmaf(G[7], d[1], G[6] * d[0]));
+    const float m = fmaxf(fmaxf(fabsf(gx), fabsf(gy)), fabsf(gz));
+    const float im = m > 0.0f ? 1.0f / m : 0.0f;
+    g[k][0] = gx * im;
+    g[k][1] = gy * im;
+    g[k][2] = gz * im;
     any_front |= gz > 0.0f;
-    grazing |= !(gz * 0x1p10f > fabsf(gx) + fabsf(gy));
-    const float iz = 1.0f / gz;
-    px[k] = gx * iz;
-    py[k] = gy * iz;
-    ext = fmaxf(ext, fmaxf(fabsf(px[k]), fabsf(py[k])));
   }
   if (!any_front) return false;  // every ray of the block has g_z <= 0
-  if (grazing) return true;
-  const float r = sqrtf(tau2) + ext * 0x1p-16f;
-  const float r2 = r * r;
-  // origin inside the polygon: the four edge cross products share a sign
-  bool pos = true, neg = true;
+  float n[4][3];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int j = (k + 1) & 3;
-    const float cr = px[k] * py[j] - py[k] * px[j];
-    pos &= cr >= 0.0f;
-    neg &= cr <= 0.0f;
+    const float* a = g[k];
+    const float* b = g[(k + 1) & 3];
+    n[k][0] = a[1] * b[2] - a[2] * b[1];
+    n[k][1] = a[2] * b[0] - a[0] * b[2];
+    n[k][2] = a[0] * b[1] - a[1] * b[0];
   }
-  if (pos | neg) return true;
-  // otherwise the disc must reach an edge
-  bool meet = false;
+  // inward orientation: the corners' sum lies inside the cone
+  const float ox = g[0][0] + g[1][0] + g[2][0] + g[3][0];
+  const float oy = g[0][1] + g[1][1] + g[2][1] + g[3][1];
+  const float oz = g[0][2] + g[1][2] + g[2][2] + g[3][2];
+  const float orient = n[0][0] * ox + n[0][1] * oy + n[0][2] * oz;
+  if (!(fabsf(orient) > 1e-12f)) return true;  // degenerate block cone
+  const float sg = orient > 0.0f ? 1.0f : -1.0f;
+  bool inside = true;
+  float nxy[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int j = (k + 1) & 3;
-    const float ex = px[j] - px[k], ey = py[j] - py[k];
-    const float ee = fmaf(ex, ex, ey * ey);
-    const float t = fminf(fmaxf(-fmaf(px[k], ex, py[k] * ey) / ee, 0.0f), 1.0f);
-    const float cx = fmaf(t, ex, px[k]), cy = fmaf(t, ey, py[k]);
-    meet |= fmaf(cx, cx, cy * cy) <= r2;
+    n[k][0] *= sg;
+    n[k][1] *= sg;
+    n[k][2] *= sg;
+    inside &= n[k][2] >= 0.0f;
+    nxy[k] = sqrtf(fmaf(n[k][0], n[k][0], n[k][1] * n[k][1]));
   }
-  return meet;
+  if (inside) return true;
+  float best = INFINITY;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!(nxy[k] > 0.0f)) continue;
+    const float t = n[k][2] / (nxy[k] * nxy[k]);
+    const float px = -t * n[k][0], py = -t * n[k][1];
+    const float pn = sqrtf(fmaf(px, px, py * py));
+    bool on = true;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j == k) continue;
+      const float val = fmaf(n[j][0], px, fmaf(n[j][1], py, n[j][2]));
+      on &= val >= -0x1p-12f * (fabsf(n[j][2]) + nxy[j] * pn);
+    }
+    if (on) best = fminf(best, (n[k][2] * n[k][2]) / (nxy[k] * nxy[k]));
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (g[k][2] > 0.0f) best = fminf(best, fmaf(g[k][0], g[k][0], g[k][1] * g[k][1]) / (g[k][2] * g[k][2]));
+  return best <= fmaf(tau2, 0x1p-8f, tau2) + 0x1p-18f * (1.0f + best);
 }
 
 // One (ray, Gaussian) pair in the rotated canonical frame: g = G d,

@@ -23,6 +23,8 @@
 // first-order (not the squared) cancellation of the cross product.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "geer_common.h"
 #include "geer_device.h"
 
@@ -69,30 +71,27 @@ template <bool kFixed, bool kKeep>
 __global__ __launch_bounds__(64) void render_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
-    const Record* __restrict__ recs, Opts op, float* __restrict__ rgb, float* __restrict__ depth,
+    const Record* __restrict__ recs, Opts op, HeavyTiles heavy, float* __restrict__ rgb, float* __restrict__ depth,
     float* __restrict__ trans, uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
     unsigned long long* __restrict__ stats) {
   __shared__ float4 s_rec[kWin][4];  // this wave's window of records
 
-  // four consecutive indices are the quarters of one tile (same XCD)
-  const int hidx = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = hidx >> 2, quad = hidx & 3;
-  int v = 0;
-  while (v + 1 < nviews && tile >= views[v + 1].tile_base) ++v;
-  const ViewDev& V = views[v];
-  const int lt = tile - V.tile_base;
-  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
-  const uint32_t hx = 2u * tx + (quad & 1), hy = 2u * ty + (quad >> 1);
-  if (hx >= (uint32_t)V.nhx || hy >= (uint32_t)V.nhy) return;  // quarter outside a ragged image
+  const WaveBlock W = wave_block(blockIdx.x, gridDim.x, views, nviews, heavy.list, heavy.flag, heavy.count,
+                                 heavy.hmax);
+  if (!W.live) return;
+  const ViewDev& V = views[W.v];
+  const int tile = W.tile;
+  const uint32_t hx = (uint32_t)W.bx0 >> 3, hy = (uint32_t)W.by0 >> 3;  // half-tile of the block
   const int lane = threadIdx.x;
-  const int px = hx * kHalf + (lane & 7), py = hy * kHalf + (lane >> 3);
-  const bool valid = px < V.width && py < V.height;
+  const int lb = W.bs == 8 ? 3 : 2;
+  const int px = W.bx0 + (lane & (W.bs - 1)), py = W.by0 + (lane >> lb);
+  const bool valid = lane < W.bs * W.bs && px < V.width && py < V.height;
 
   float dx, dy, dz;
   pixel_direction(V, dtab, px, py, dx, dy, dz);
 
   const uint32_t start = ranges[tile], end = ranges[tile + 1];
-  const QuadCone Q = half_tile_cone(V, dtab, hx, hy);
+  const QuadCone Q = block_cone(V, dtab, W.bx0, W.by0, W.bs);
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, D = 0.0f;
   uint32_t last = start;
   uint64_t evals = 0;
@@ -164,15 +163,46 @@ __global__ __launch_bounds__(64) void render_kernel(
   if (stats && lane == 0 && evals) atomicAdd(&stats[0], (unsigned long long)evals);
 }
 
+// Flags tiles with more than 3x the mean list length (+64) as heavy and lists
+// up to hmax of them; the others (and any beyond hmax) keep the flag 0.
+__global__ __launch_bounds__(256) void mark_heavy_kernel(const uint32_t* __restrict__ ranges, int64_t ntiles,
+                                                         uint32_t* __restrict__ heavy_list,
+                                                         uint32_t* __restrict__ heavy_flag,
+                                                         unsigned long long* __restrict__ heavy_count, int hmax) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= ntiles) return;
+  const uint32_t total = ranges[ntiles];
+  const uint32_t cnt = ranges[t + 1] - ranges[t];
+  const uint64_t thr = 3ull * total / (uint64_t)ntiles + 64ull;
+  uint32_t flag = 0u;
+  if (cnt > thr) {
+    const unsigned long long slot = atomicAdd(heavy_count, 1ull);
+    if (slot < (unsigned long long)hmax) {
+      heavy_list[slot] = (uint32_t)t;
+      flag = 1u;
+    }
+  }
+  heavy_flag[t] = flag;
+}
+
+int heavy_capacity(int64_t ntiles) { return (int)std::min<int64_t>(1024, std::max<int64_t>(16, ntiles / 16)); }
+
+void launch_mark_heavy(hipStream_t st, const uint32_t* ranges, int64_t ntiles, const HeavyTiles& h) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(mark_heavy_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st, ranges, ntiles,
+                     h.list, h.flag, h.count, h.hmax);
+}
+
 void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const ViewDev* views, int nviews,
                    const float2* dtab, const uint32_t* ranges, const uint32_t* list, const uint2* rects,
-                   const Record* recs, const Opts& op, float* rgb, float* depth, float* trans, uint32_t* nlast,
-                   float* tfinal, unsigned long long* stats) {
+                   const Record* recs, const Opts& op, const HeavyTiles& heavy, float* rgb, float* depth,
+                   float* trans, uint32_t* nlast, float* tfinal, unsigned long long* stats) {
   if (ntiles <= 0) return;
   const bool keep = nlast != nullptr && tfinal != nullptr;
+  const unsigned grid = (unsigned)(kHeavySplit * heavy.hmax + 4 * ntiles);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)(4 * ntiles)), dim3(kWin), 0, st, views, nviews, dtab, ranges, list,
-                       rects, recs, op, rgb, depth, trans, nlast, tfinal, stats);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWin), 0, st, views, nviews, dtab, ranges, list, rects, recs, op, heavy,
+                       rgb, depth, trans, nlast, tfinal, stats);
   };
   if (fixed_lambda) {
     if (keep) go(render_kernel<true, true>);

@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "geer_common.h"
+#include "geer_device.h"
 
 namespace geer {
 
@@ -129,30 +130,44 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s_w
   return pre + incl - x;
 }
 
+// A key equal to kDropKey is not sorted when `drop` is set (entries the
+// expansion found unable to contribute); the pass-0 output count is then
+// added to *kept.
+constexpr uint32_t kDropKey = 0xffffffffu;
+
 __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* __restrict__ keys,
-                                                               const uint32_t* __restrict__ filter, int64_t n_cap,
+                                                               const uint32_t* __restrict__ filter, int drop,
+                                                               int64_t n_cap,
                                                                const unsigned long long* __restrict__ dyn,
-                                                               int shift0, int npass, uint32_t* __restrict__ ghist) {
+                                                               int shift0, int npass, uint32_t* __restrict__ ghist,
+                                                               unsigned long long* __restrict__ kept) {
   const int64_t n = dyn_count(n_cap, dyn);
   __shared__ uint32_t h[4][256];
+  __shared__ uint32_t s_kept;
 #pragma unroll
   for (int p = 0; p < 4; ++p) h[p][threadIdx.x] = 0u;
+  if (threadIdx.x == 0) s_kept = 0u;
   __syncthreads();
+  uint32_t mine = 0u;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
     if (filter && filter[i] == 0u) continue;
     const uint32_t k = keys[i];
+    if (drop && k == kDropKey) continue;
+    ++mine;
     for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (shift0 + 8 * p)) & 255u], 1u);
   }
+  if (kept && mine) atomicAdd(&s_kept, mine);
   __syncthreads();
   for (int p = 0; p < npass; ++p) {
     const uint32_t c = h[p][threadIdx.x];
     if (c) atomicAdd(&ghist[p * 256 + threadIdx.x], c);
   }
+  if (kept && threadIdx.x == 0 && s_kept) atomicAdd(kept, (unsigned long long)s_kept);
 }
 
 __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, const uint32_t* __restrict__ filter,
-    int64_t n_cap, const unsigned long long* __restrict__ dyn, int shift, const uint32_t* __restrict__ ghist_p,
+    int drop, int64_t n_cap, const unsigned long long* __restrict__ dyn, int shift, const uint32_t* __restrict__ ghist_p,
     uint32_t* __restrict__ status, uint32_t* __restrict__ status_next, uint32_t* __restrict__ ticket,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, unsigned long long* __restrict__ err) {
   __shared__ uint32_t s_cnt[4][256];  // per-wave running digit counts, then per-wave offsets
@@ -180,8 +195,9 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
 #pragma unroll
   for (int sl = 0; sl < kOSPer; ++sl) {
     const int64_t i = base + sl * 64 + lane;
-    const bool a = i < n && (!filter || filter[i] != 0u);
+    bool a = i < n && (!filter || filter[i] != 0u);
     key[sl] = a ? keys_in[i] : 0u;
+    if (drop) a = a && key[sl] != kDropKey;
     val[sl] = a ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
     const uint32_t d = (key[sl] >> shift) & 255u;
     uint64_t m = __builtin_amdgcn_ballot_w64(a);
@@ -273,7 +289,9 @@ constexpr int kExpandPer = 8;
 
 // Each lane expands kExpandPer consecutive entries (one binary search for the
 // owner of its first entry), the block stages its 2048 entries in LDS and
-// writes them back lane-striped so every store is coalesced.
+// writes them back lane-striped so every store is coalesced.  With `cull`,
+// an entry whose Gaussian's contribution cone meets no ray of its tile gets
+// the tile id kDropKey and is left out by the tile sort.
 __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restrict__ items,
                                                         const uint32_t* __restrict__ offs, int64_t m_cap,
                                                         const unsigned long long* __restrict__ dyn_m,
@@ -281,6 +299,8 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
                                                         const unsigned long long* __restrict__ dyn_total,
                                                         const uint2* __restrict__ rects,
                                                         const ViewDev* __restrict__ views, int64_t n,
+                                                        const float2* __restrict__ dtab,
+                                                        const Record* __restrict__ recs, Opts op, int cull,
                                                         uint32_t* __restrict__ tiles_out,
                                                         uint32_t* __restrict__ items_out) {
   const int64_t m = dyn_count(m_cap, dyn_m);
@@ -289,6 +309,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   __shared__ uint32_t s_item[kBlock * kExpandPer];
   const int64_t block0 = (int64_t)blockIdx.x * kBlock * kExpandPer;
   const int64_t e0 = block0 + (int64_t)threadIdx.x * kExpandPer;
+  const bool fixed = op.lambda_mode == 1;
   if (e0 < total) {
     // owner of e0: last j with offs[j] <= e0
     int64_t lo = 0, hi = m;
@@ -298,6 +319,8 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
     }
     int64_t j = lo;
     const int64_t e1 = min(e0 + kExpandPer, total);
+    uint32_t have = 0xffffffffu;  // item whose record is loaded
+    float4 p0, p1, p2, p3;
     for (int64_t e = e0; e < e1; ++e) {
       while (j + 1 < m && (int64_t)offs[j + 1] <= e) ++j;
       const uint32_t item = items[j];
@@ -308,8 +331,18 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
       const uint32_t wt = (uint32_t)(tx1 - tx0 + 1);
       const ViewDev& V = views[item / (uint32_t)n];
       const uint32_t ty = ty0 + local / wt, tx = tx0 + local % wt;
+      uint32_t tile = (uint32_t)V.tile_base + ty * (uint32_t)V.tiles_x + tx;
+      if (cull) {
+        if (item != have) {
+          const float4* rp = reinterpret_cast<const float4*>(recs + item);
+          p0 = rp[0]; p1 = rp[1]; p2 = rp[2]; p3 = rp[3];
+          have = item;
+        }
+        const QuadCone Q = block_cone(V, dtab, (int)tx * kTile, (int)ty * kTile, kTile);
+        if (!cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, fixed)) tile = kDropKey;
+      }
       const int s = (int)(e - block0);
-      s_tile[s] = (uint32_t)V.tile_base + ty * (uint32_t)V.tiles_x + tx;
+      s_tile[s] = tile;
       s_item[s] = item;
     }
   }
@@ -404,12 +437,14 @@ int64_t radix_work_words(int64_t n_cap) { return kWorkHead + 2 * 256 * ((n_cap +
 
 // Stable sort of n0 keys (filtered; values = in_v, or the key index when
 // in_v is null) by npass 8-bit digits from bit shift0.  Pass 0 reads (in_k,
-// in_v) with the n0 count and the filter; later passes read n1 keys (the
-// filtered count, read on the device when dyn1 is given).  Passes write A, B,
-// A, ...: the result is in A for odd npass, in B for even.
-void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, int64_t n0_cap,
-                const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1, int shift0, int npass,
-                uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work, unsigned long long* err) {
+// in_v) with the n0 count, the filter and (with drop) leaves out kDropKey
+// keys, counting the rest into *kept when given; later passes read n1 keys
+// (the filtered count, read on the device when dyn1 is given).  Passes write
+// A, B, A, ...: the result is in A for odd npass, in B for even.
+void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, bool drop,
+                int64_t n0_cap, const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1,
+                int shift0, int npass, uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work,
+                unsigned long long* kept, unsigned long long* err) {
   if (n0_cap <= 0 || npass <= 0) return;
   const int64_t nmax = std::max(n0_cap, n1_cap);
   const int64_t rows = 256 * ((nmax + kOSItems - 1) / kOSItems);
@@ -419,9 +454,10 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
   // histograms, tickets and the first status table start at zero
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
                      (int64_t)kWorkHead + rows, 0u);
-  const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(n0_cap, kBlock), 1), 2048);
-  hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, in_k, filter, n0_cap, dyn0, shift0, npass,
-                     ghist);
+  // few blocks: every block adds its counts to the same 256 words per pass
+  const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(n0_cap, kBlock), 1), 256);
+  hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, in_k, filter, drop ? 1 : 0, n0_cap, dyn0,
+                     shift0, npass, ghist, kept);
   const uint32_t *sk = in_k, *sv = in_v;
   for (int p = 0; p < npass; ++p) {
     uint32_t* ok = (p % 2 == 0) ? ak : bk;
@@ -429,8 +465,8 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
     const int64_t ncap = p == 0 ? n0_cap : n1_cap;
     const unsigned long long* dy = p == 0 ? dyn0 : dyn1;
     const unsigned nb = (unsigned)std::max<int64_t>((ncap + kOSItems - 1) / kOSItems, 1);
-    hipLaunchKernelGGL(radix_onesweep_kernel, dim3(nb), dim3(kBlock), 0, st, sk, sv, p == 0 ? filter : nullptr, ncap,
-                       dy, shift0 + 8 * p, (const uint32_t*)(ghist + 256 * p), stat[p % 2],
+    hipLaunchKernelGGL(radix_onesweep_kernel, dim3(nb), dim3(kBlock), 0, st, sk, sv, p == 0 ? filter : nullptr,
+                       (p == 0 && drop) ? 1 : 0, ncap, dy, shift0 + 8 * p, (const uint32_t*)(ghist + 256 * p), stat[p % 2],
                        p + 1 < npass ? stat[(p + 1) % 2] : nullptr, tickets + p, ok, ov, err);
     sk = ok;
     sv = ov;
@@ -446,10 +482,12 @@ void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, 
 
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
-                   const uint2* rects, const ViewDev* views, int64_t n, uint32_t* tiles_out, uint32_t* items_out) {
+                   const uint2* rects, const ViewDev* views, int64_t n, const float2* dtab, const Record* recs,
+                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out) {
   if (total_cap <= 0) return;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total_cap, (int64_t)kBlock * kExpandPer)), dim3(kBlock), 0, st,
-                     items, offs, m_cap, dyn_m, total_cap, dyn_total, rects, views, n, tiles_out, items_out);
+                     items, offs, m_cap, dyn_m, total_cap, dyn_total, rects, views, n, dtab, recs, op, op.cone_cull,
+                     tiles_out, items_out);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,

@@ -28,14 +28,16 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
 int64_t scan_scratch_words(int64_t n);
 void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch);
 int64_t radix_work_words(int64_t n_cap);
-void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, int64_t n0_cap,
-                const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1, int shift0, int npass,
-                uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work, unsigned long long* err);
+void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, bool drop,
+                int64_t n0_cap, const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1,
+                int shift0, int npass, uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work,
+                unsigned long long* kept, unsigned long long* err);
 void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
                           const uint32_t* counts, uint32_t* out);
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
-                   const uint2* rects, const ViewDev* views, int64_t n, uint32_t* tiles_out, uint32_t* items_out);
+                   const uint2* rects, const ViewDev* views, int64_t n, const float2* dtab, const Record* recs,
+                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out);
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
                    int64_t ntiles, uint32_t* ranges);
 void launch_pad_list(hipStream_t st, uint32_t* list, int64_t total_cap, const unsigned long long* dyn);
@@ -43,17 +45,20 @@ void launch_capacity_guard(hipStream_t st, unsigned long long* stats, int64_t ca
 void launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v);
 
 // render.hip
+int heavy_capacity(int64_t ntiles);
+void launch_mark_heavy(hipStream_t st, const uint32_t* ranges, int64_t ntiles, const HeavyTiles& h);
 void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const ViewDev* views, int nviews,
                    const float2* dtab, const uint32_t* ranges, const uint32_t* list, const uint2* rects,
-                   const Record* recs, const Opts& op, float* rgb, float* depth, float* trans, uint32_t* nlast,
-                   float* tfinal, unsigned long long* stats);
+                   const Record* recs, const Opts& op, const HeavyTiles& heavy, float* rgb, float* depth,
+                   float* trans, uint32_t* nlast, float* tfinal, unsigned long long* stats);
 
 // backward.hip
 void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t n, int32_t n_views,
                      int32_t sh_degree, const float* mean, const float* scale, const float* quat,
                      const float* opacity, const float* sh, const ViewDev* views, const float2* dtab,
-                     const float* edges, const float* lam_tab, const Opts& op, const uint32_t* ranges,
-                     const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
+                     const float* edges, const float* lam_tab, const Opts& op, const HeavyTiles& heavy,
+                     const uint32_t* ranges, const uint32_t* list, const uint2* rects, const Record* recs,
+                     const uint32_t* nlast,
                      const float* tfinal, const float* dl_drgb, float* acc, int accumulate, float* g_mean,
                      float* g_scale, float* g_quat, float* g_opacity, float* g_sh);
 

@@ -77,7 +77,8 @@ def tiles_of(shape) -> int:
 class Server:
     """slots: concurrent batches (streams); slot_views: the workspace arena of
     a slot holds that many views of the largest shape (or give slot_bytes);
-    entries_per_tile: association-list capacity per 16x16 tile of a view;
+    entries_per_tile: capacity of PBF (tile, Gaussian) pairs per 16x16 tile
+    of a view;
     max_views: largest batch."""
 
     def __init__(self, scene: dict, shapes, entries_per_tile: float, slots: int = 3, slot_views: int = 1,

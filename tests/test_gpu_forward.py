@@ -48,14 +48,22 @@ def gpu_render(R, scene, cams, **opts):
     return out, frame
 
 
-def check_association(frame, scene, cams, **opts):
+def check_association(frame, scene, cams, max_proof=300_000, **opts):
+    """Rectangles, tile counts and depth keys bit-exact against the oracle's
+    FP32 association reference.  The list: with the contribution-cone cull
+    off it is the oracle's PBF list, (tile, key, index) order, bit for bit;
+    with it on, it is that list with some pairs left out -- the same order --
+    and every left-out pair (all of them, or a seeded sample of max_proof) is
+    shown by the FP64 oracle to reach no ray of its tile."""
+    cull = opts.pop("cone_cull", True)
     n = scene.n
+    nv = n * len(cams)
     rect = frame.export(_lib.BUF_RECT).reshape(-1, 2)
     count = frame.export(_lib.BUF_COUNT)
     key = frame.export(_lib.BUF_KEY)
-    lst = frame.export(_lib.BUF_LIST)
-    ranges = frame.export(_lib.BUF_RANGES)
-    all_items, tile_base, e_base, all_ranges = [], 0, 0, []
+    lst = frame.export(_lib.BUF_LIST).astype(np.int64)
+    ranges = frame.export(_lib.BUF_RANGES).astype(np.int64)
+    o_tile, o_item, o_view, o_ranges, tile_base, e_base = [], [], [], [], 0, 0
     for v, cam in enumerate(cams):
         a = oracle.assoc_fp32(scene, cam, **opts)
         sl = slice(v * n, (v + 1) * n)
@@ -68,27 +76,49 @@ def check_association(frame, scene, cams, **opts):
         np.testing.assert_array_equal(gr[vis, 1] & 0xFFFF, a["hy0"][vis])
         np.testing.assert_array_equal(gr[vis, 1] >> 16, a["hy1"][vis])
         tiles, gids, rng = oracle.tile_list(a, cam)
-        all_items.append(gids + v * n)
-        all_ranges.append(rng[:-1] + e_base)
+        o_tile.append(tiles.astype(np.int64) + tile_base)
+        o_item.append(gids.astype(np.int64) + v * n)
+        o_view.append(np.full(tiles.size, v))
+        o_ranges.append(rng[:-1] + e_base)
         e_base += tiles.size
         tw, th = oracle.tile_grid(cam)
         tile_base += tw * th
-    all_ranges.append(np.array([e_base]))
-    np.testing.assert_array_equal(lst, np.concatenate(all_items))
-    np.testing.assert_array_equal(ranges, np.concatenate(all_ranges))
+    o_tile, o_item, o_view = np.concatenate(o_tile), np.concatenate(o_item), np.concatenate(o_view)
     st = frame.stats()
-    assert st["n_entries"] == e_base
+    assert st["n_candidates"] == o_tile.size
+    assert st["n_entries"] == lst.size and ranges[-1] == lst.size
+    g_tile = np.repeat(np.arange(ranges.size - 1), np.diff(ranges))
+    if not cull:
+        np.testing.assert_array_equal(lst, o_item)
+        np.testing.assert_array_equal(ranges, np.concatenate(o_ranges + [np.array([e_base])]))
+        return e_base
+    code_o = o_tile * nv + o_item
+    code_g = g_tile * nv + lst
+    kept = np.isin(code_o, code_g)
+    np.testing.assert_array_equal(code_o[kept], code_g)
+    drop = np.nonzero(~kept)[0]
+    if drop.size > max_proof:
+        drop = np.sort(np.random.default_rng(0).choice(drop, max_proof, replace=False))
+    for v, cam in enumerate(cams):
+        d = drop[o_view[drop] == v]
+        if d.size == 0:
+            continue
+        base = sum(int(np.prod(oracle.tile_grid(c))) for c in cams[:v])
+        seen = oracle.tile_pairs_contribute(scene, cam, o_tile[d] - base, o_item[d] - v * n, **opts)
+        assert not seen.any(), "a left-out pair reaches a ray of its tile: %s" % (d[seen][:5],)
+    print("association: %d PBF pairs, %d kept (%.1f%%)" % (o_tile.size, lst.size, 100.0 * lst.size / max(o_tile.size, 1)))
     return e_base
 
 
 def test_small_workload_bit_exact_association_and_render(R):
     scene, cams = synth.workload_small()
-    got, frame = gpu_render(R, scene, cams)
-    e = check_association(frame, scene, cams)
-    assert e > 1000
     ref = oracle.render(scene, cams[0])
-    compare_render(got[0], ref)
-    frame.release()
+    for cull in (True, False):
+        got, frame = gpu_render(R, scene, cams, cone_cull=cull)
+        e = check_association(frame, scene, cams, cone_cull=cull)
+        assert e > 1000
+        compare_render(got[0], ref)
+        frame.release()
 
 
 @pytest.mark.parametrize("seed", range(3))
@@ -102,11 +132,13 @@ def test_adversarial_multiview_batch(R, seed):
                               lambda R_, c: synth.camera_kb(40, 24, 200.0, seed=2, R=R_, position=c)]):
         Rm, c = synth.random_pose(rng, half=1.0) if k % 2 else (None, None)
         cams.append(make(Rm, c))
-    got, frame = gpu_render(R, scene, cams)
-    check_association(frame, scene, cams)
-    for v, cam in enumerate(cams):
-        compare_render(got[v], oracle.render(scene, cam))
-    frame.release()
+    refs = [oracle.render(scene, cam) for cam in cams]
+    for cull in ((True, False) if seed == 0 else (True,)):
+        got, frame = gpu_render(R, scene, cams, cone_cull=cull)
+        check_association(frame, scene, cams, cone_cull=cull)
+        for v in range(len(cams)):
+            compare_render(got[v], refs[v])
+        frame.release()
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -208,13 +240,14 @@ def test_invalid_arguments_rejected(R):
         R.render(dict(sc, mean=sc["mean"].double()), cams)
 
 
-@pytest.mark.parametrize("case", ["adversarial", "box_kb200", "box_fixed_lambda", "needles_pinhole"])
+@pytest.mark.parametrize("case", ["adversarial", "box_kb200", "box_fixed_lambda", "needles_pinhole", "slice_kb190"])
 def test_cone_cull_is_exact(R, case):
     """Skipping entries whose contribution cone misses every ray of a
     half-tile leaves every output bit unchanged (forward) and the gradients
     equal up to the order of float atomics (backward), while evaluating
     fewer pairs."""
-    rng = np.random.default_rng(["adversarial", "box_kb200", "box_fixed_lambda", "needles_pinhole"].index(case))
+    rng = np.random.default_rng(["adversarial", "box_kb200", "box_fixed_lambda", "needles_pinhole",
+                                 "slice_kb190"].index(case))
     opts = {}
     if case == "adversarial":
         scene = adversarial_scene(7, n=400)
@@ -226,6 +259,10 @@ def test_cone_cull_is_exact(R, case):
         scene = synth.scene_box(30000, seed=10, half=4.0)
         cams = [synth.camera_equidistant(128, 128, 180.0)]
         opts = dict(lambda_mode=1)
+    elif case == "slice_kb190":
+        # 6-degree pixels: tiles and half-tiles span +-90 degrees of theta
+        scene = synth.scene_slice(400, seed=3)
+        cams = [synth.camera_slice(seed=3), synth.camera_kb(48, 36, 200.0, seed=4)]
     else:
         scene = synth.scene_box(20000, seed=11, half=4.0)
         k = rng.integers(0, 3, scene.n)

@@ -51,9 +51,11 @@ def small_cams(rng, kinds, half=3.0):
 
 
 def eager(R, sc, cams):
+    """Eager render; also returns the PBF pair count, which a plan's
+    association capacity bounds."""
     rgb, depth, trans, frame = R.render(sc, cams, keep_frame=True)
     torch.cuda.synchronize()
-    e = frame.stats()["n_entries"]
+    e = frame.stats()["n_candidates"]
     frame.release()
     return rgb, depth, trans, e
 

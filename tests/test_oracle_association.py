@@ -254,3 +254,25 @@ def test_depth_key_orders_by_camera_distance(oracle_lib):
     order = np.argsort(a["key"], kind="stable")
     gaps = np.diff(d2[order])
     assert np.all(gaps > -1e-5 * d2[order][1:])
+
+
+def test_tile_pairs_contribute_matches_per_ray_mask(oracle_lib):
+    """The per-(tile, Gaussian) FP64 check used to prove culled list entries
+    unseen agrees with the per-ray contribution mask, OR-ed over each tile's
+    rays, on a ragged grid in both lambda modes."""
+    scene = synth.scene_box(300, seed=21, half=3.0, sh_degree=0)
+    cam = synth.camera_equidistant(40, 24, 180.0)
+    w, h = cam["width"], cam["height"]
+    tw, th = oracle.tile_grid(cam)
+    for mode in (0, 1):
+        mask = oracle.contrib_mask(scene, cam, lambda_mode=mode)  # [P, N]
+        tiles = np.repeat(np.arange(tw * th), scene.n)
+        gids = np.tile(np.arange(scene.n), tw * th)
+        got = oracle.tile_pairs_contribute(scene, cam, tiles, gids, lambda_mode=mode)
+        py, px = np.divmod(np.arange(w * h), w)
+        tile_of = (py // 16) * tw + px // 16
+        ref = np.zeros((tw * th, scene.n), bool)
+        for t in range(tw * th):
+            ref[t] = mask[tile_of == t].any(axis=0)
+        np.testing.assert_array_equal(got, ref.reshape(-1))
+        assert ref.any() and not ref.all()
