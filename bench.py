@@ -16,6 +16,9 @@ Printed (one JSON line on stdout):
   fwd_bwd        forward + L1 loss + backward of 500,000 Gaussians (SH 3)
                  through a Kannala-Brandt 190-degree fisheye at 1280 x 960
                  against a target rendered from perturbed parameters
+  train_batched  one captured training step (per view: forward, L1, backward)
+                 of 3M Gaussians (SH 3) over 8 views of 1920 x 1080, four
+                 pinhole 90-degree and four equidistant 180-degree
   serving        Poisson stream of render requests (pinhole 640 x 480,
                  equidistant 1024 x 1024, KB 200-degree 1920 x 1080) over a
                  resident 1M-Gaussian scene: p50/p99 latency, req/s, Mrays/s
@@ -119,6 +122,49 @@ def bench_fwd_bwd(args, dev):
             "loss": round(float(loss.item()), 6)}
 
 
+def bench_train_batched(args, dev):
+    """Captured batched training steps: 3M Gaussians SH3, 8 views of 1920x1080."""
+    import numpy as np
+    import torch
+
+    from paper_2505_24053_amd import _lib, renderer, synth
+
+    scene_np = synth.scene_box(3_000_000, seed=args.seed)
+    cams = synth.workload_batched_views(seed=args.seed)
+    sc = renderer.scene_from_numpy(scene_np, device=dev)
+    tsc = renderer.scene_from_numpy(synth.perturb(scene_np, args.seed + 1), device=dev)
+    del scene_np
+    target, _, _, _ = renderer.render(tsc, cams)
+    del tsc
+    mask = torch.as_tensor(np.concatenate([_lib.valid_mask(c).reshape(-1) for c in cams]).astype(np.uint8),
+                           device=dev)
+    pbf = 0
+    for c in cams:  # the PBF pairs of the densest view size the plan's capacity
+        _, _, _, fr = renderer.render(sc, [c], keep_frame=True)
+        pbf = max(pbf, fr.stats()["n_candidates"])
+        fr.release()
+    rays = sum(c["width"] * c["height"] for c in cams)
+    plan = renderer.TrainPlan(sc, cams, int(pbf * 1.25) + 1024, target, mask)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.train_warmup):
+        plan.launch(cams, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batched_steps):
+        plan.launch(cams, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    E, cap, over = plan.entries()
+    ms = (t1 - t0) * 1e3 / args.batched_steps
+    out = {"workload": "train_step_3m_sh3_8x1920x1080_pinhole90_fisheye180_l1", "gaussians": sc["mean"].shape[1],
+           "views": len(cams), "rays": rays, "steps": args.batched_steps, "ms_per_step": round(ms, 3),
+           "mrays_per_s": round(rays / (ms * 1e-3) / 1e6, 2), "loss": round(float(plan.loss.item()), 6),
+           "max_pbf_pairs_per_view": int(E), "capacity": int(cap), "overflow": bool(over),
+           "device_workspace_gib": round(plan.device_bytes() / 2**30, 2)}
+    plan.destroy()
+    return out
+
+
 def bench_serving(args, dev):
     """Continuous batching over the resident 1M-Gaussian scene at a fixed rate."""
     import numpy as np
@@ -188,6 +234,7 @@ def main():
                          "size that calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE in the same run)")
     ap.add_argument("--train-steps", type=int, default=10, help="fwd+bwd steps (0: skip)")
     ap.add_argument("--train-warmup", type=int, default=3)
+    ap.add_argument("--batched-steps", type=int, default=5, help="captured 8-view training steps (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=600, help="served requests (0: skip)")
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--serve-rates", type=lambda t: [float(x) for x in t.split(",")], default=[200.0, 500.0],
@@ -289,6 +336,11 @@ def main():
         log("fwd+bwd: 500k Gaussians, KB 190 deg 1280x960")
         fwd_bwd = bench_fwd_bwd(args, dev)
         log("fwd+bwd:", fwd_bwd)
+    train_batched = None
+    if args.batched_steps > 0:
+        log("batched training step: 3M Gaussians, 8 views of 1920x1080")
+        train_batched = bench_train_batched(args, dev)
+        log("batched:", train_batched)
     serving = None
     if args.serve_requests > 0:
         log("serving: 1M Gaussians, %d requests at %s req/s" % (args.serve_requests, args.serve_rates))
@@ -311,6 +363,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd,
+        "train_batched": train_batched,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

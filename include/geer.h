@@ -227,7 +227,8 @@ int32_t geer_profile_read(geer_ctx* ctx, geer_profile_record* out, int32_t max);
  * sizes must match the plan's).  Results are identical to geer_render of the
  * same views.  A launch waits for the plan's previous launch; concurrent
  * batches use separate plans on separate streams.  The scene arrays and the
- * outputs must stay valid, and the scene unchanged, while the plan lives.
+ * outputs must stay allocated while the plan lives (the scene's values are
+ * read by each launch).
  * When a batch's association list exceeds the capacity, that launch renders
  * background and geer_plan_entries reports the overflow.
  */
@@ -248,6 +249,27 @@ geer_status geer_plan_workspace_bytes(geer_ctx* ctx, const geer_scene* scene, in
 geer_status geer_plan_create(geer_ctx* ctx, const geer_scene* scene, int32_t n_views, const geer_view* views,
                              const geer_opts* opts, int64_t entry_capacity, void* workspace, int64_t workspace_bytes,
                              float* rgb, float* depth, float* trans, geer_plan** out);
+/* Training plans (batched training step).  One graph runs, for each view in
+ * turn, the forward (keeping only each ray's final transmittance and last
+ * blended entry), the L1 loss of that view against its target over the valid
+ * rays (mask, or every ray when NULL), and the backward (App. C), so that the
+ * gradient arrays receive the gradient of
+ *   loss = (1 / n_views) sum_v L1_v,   L1_v = sum |rgb - target| / (3 n_valid_v),
+ * and *loss its value.  target / mask / rgb use the concatenated per-view
+ * layout of geer_render; the gradient arrays use the scene layout and are
+ * overwritten by every launch.  entry_capacity bounds the PBF pairs of each
+ * view.  Launched, checked and destroyed with geer_plan_launch,
+ * geer_plan_entries (largest view) and geer_plan_destroy.  The scene arrays
+ * must stay allocated while the plan lives; their values are read by each
+ * launch, so an optimiser may update them in place between launches. */
+geer_status geer_train_plan_workspace_bytes(geer_ctx* ctx, const geer_scene* scene, int32_t n_views,
+                                            const geer_view* views, const geer_opts* opts, int64_t entry_capacity,
+                                            int64_t* bytes);
+geer_status geer_train_plan_create(geer_ctx* ctx, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                                   const geer_opts* opts, int64_t entry_capacity, void* workspace,
+                                   int64_t workspace_bytes, const float* target, const uint8_t* mask, float* rgb,
+                                   float* loss, float* g_mean, float* g_scale, float* g_quat, float* g_opacity,
+                                   float* g_sh, geer_plan** out);
 /* Uploads the cameras of the next batch and replays the graph on `stream`. */
 geer_status geer_plan_launch(geer_plan* plan, const geer_view* views, void* stream);
 /* Waits for the last launch; reports its count of PBF (tile, Gaussian) pairs

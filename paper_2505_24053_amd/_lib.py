@@ -24,7 +24,8 @@ BUF_RECT, BUF_COUNT, BUF_KEY, BUF_LIST, BUF_RANGES, BUF_NLAST = range(6)
 EXPORTS = ["geer_create", "geer_destroy", "geer_last_error", "geer_default_opts", "geer_render",
            "geer_render_backward", "geer_frame_release", "geer_frame_get_stats", "geer_frame_buffer_bytes",
            "geer_frame_export", "geer_valid_mask", "geer_l1_loss", "geer_set_profiling", "geer_profile_read",
-           "geer_plan_workspace_bytes", "geer_plan_create", "geer_plan_launch", "geer_plan_entries", "geer_plan_device_bytes", "geer_plan_destroy"]
+           "geer_plan_workspace_bytes", "geer_plan_create", "geer_train_plan_workspace_bytes",
+           "geer_train_plan_create", "geer_plan_launch", "geer_plan_entries", "geer_plan_device_bytes", "geer_plan_destroy"]
 
 
 class GeerView(C.Structure):
@@ -100,6 +101,10 @@ def load():
                                                 P(C.c_int64)]
         L.geer_plan_create.argtypes = [V, P(GeerScene), C.c_int32, P(GeerView), P(GeerOpts), C.c_int64, V,
                                        C.c_int64, V, V, V, P(V)]
+        L.geer_train_plan_workspace_bytes.argtypes = [V, P(GeerScene), C.c_int32, P(GeerView), P(GeerOpts),
+                                                      C.c_int64, P(C.c_int64)]
+        L.geer_train_plan_create.argtypes = [V, P(GeerScene), C.c_int32, P(GeerView), P(GeerOpts), C.c_int64, V,
+                                             C.c_int64, V, V, V, V, V, V, V, V, V, P(V)]
         L.geer_plan_launch.argtypes = [V, P(GeerView), V]
         L.geer_plan_entries.argtypes = [V, P(C.c_int64), P(C.c_int64)]
         L.geer_plan_device_bytes.argtypes = [V]

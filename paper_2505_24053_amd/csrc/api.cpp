@@ -79,6 +79,10 @@ struct geer_plan {
   hipEvent_t done = nullptr;
   bool launched = false;
   uint64_t* host_stats = nullptr;
+  // training plans: one segment (forward, loss, backward) per view
+  int nseg = 0;                 // 0 for a forward plan
+  std::vector<size_t> seg_off;  // offset of each view's tables in meta
+  int nstat = 1;                // statistics blocks (8 words each), one per segment
 };
 
 struct geer_frame {
@@ -791,7 +795,7 @@ geer_status geer_l1_loss(geer_ctx* c, int64_t pixels, const float* rgb, const fl
   if (s != GEER_OK) return s;
   float2* partial = (float2*)scratch.p;
   float* scale = (float*)(partial + nb + 1);
-  launch_l1(st, pixels, rgb, target, mask, dl_drgb, loss, partial, scale);
+  launch_l1(st, pixels, rgb, target, mask, dl_drgb, loss, partial, scale, 1.0);
   hipError_t e = hipGetLastError();
   release(c, scratch);
   if (e != hipSuccess) return fail(c, GEER_ERR_HIP, "loss launch: %s", hipGetErrorString(e));
@@ -950,7 +954,7 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
     PHIP(hipEventCreateWithFlags(&P->staged[k], hipEventDisableTiming));
   }
   PHIP(hipEventCreateWithFlags(&P->done, hipEventDisableTiming));
-  PHIP(hipHostMalloc((void**)&P->host_stats, 64, hipHostMallocDefault));
+  PHIP(hipHostMalloc((void**)&P->host_stats, 64 * (size_t)P->nstat, hipHostMallocDefault));
 
   // Capture the forward once.  Nothing runs at capture time; the tables are
   // uploaded by every launch before the graph.
@@ -961,6 +965,224 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
     enqueue_preprocess(cs, P->scene, n_views, P->op, lt.dev, b);
     enqueue_association(cs, P->op, P->n, items, std::max<int64_t>(items, 1), entry_capacity, P->ntiles, true, b);
     enqueue_render(cs, P->op, P->ntiles, n_views, b, rgb, depth, trans);
+    hipError_t e2 = hipStreamEndCapture(cs, &P->graph);
+    e = e2 != hipSuccess ? e2 : hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return bail(fail(c, GEER_ERR_HIP, "graph capture: %s", hipGetErrorString(e)));
+  *out = P;
+  return GEER_OK;
+#undef PHIP
+}
+
+// ---------------------------------------------------------- training plans
+
+// Workspace of a training plan: the forward plan's buffers sized for the
+// largest view (one view at a time), then the state kept between a view's
+// forward and backward, the loss and the per-view statistics.
+struct TrainLayout {
+  PlanLayout fwd;
+  size_t nlast = 0, tfinal = 0, dl = 0, acc = 0, partial = 0, loss_views = 0, stats = 0, mask = 0, total = 0;
+};
+
+struct TrainShape {
+  std::vector<ViewTables> tabs;
+  std::vector<size_t> seg_off;
+  std::vector<int64_t> pix_off;
+  size_t meta_bytes = 0;
+  int64_t ntiles_max = 0, npix_max = 0, npix_total = 0;
+};
+
+geer_status train_shape(geer_ctx* c, int32_t n_views, const geer_view* views, TrainShape& S) {
+  S.tabs.assign(n_views, ViewTables{});
+  S.seg_off.assign(n_views, 0);
+  S.pix_off.assign(n_views, 0);
+  size_t off = 0;
+  for (int v = 0; v < n_views; ++v) {
+    geer_status s = build_tables(c, 1, views + v, S.tabs[v]);
+    if (s != GEER_OK) return s;
+    S.seg_off[v] = off;
+    off += round_up(std::max<size_t>(S.tabs[v].bytes, 256), 256);
+    S.pix_off[v] = S.npix_total;
+    S.npix_total += S.tabs[v].npix;
+    S.ntiles_max = std::max(S.ntiles_max, S.tabs[v].ntiles);
+    S.npix_max = std::max(S.npix_max, S.tabs[v].npix);
+  }
+  S.meta_bytes = off;
+  return GEER_OK;
+}
+
+TrainLayout train_layout(const TrainShape& S, int64_t n, int64_t ecap, int32_t n_views) {
+  TrainLayout L;
+  L.fwd = plan_layout(S.meta_bytes, n, ecap, S.ntiles_max);
+  size_t off = L.fwd.total;
+  auto put = [&](size_t bytes) {
+    const size_t at = off;
+    off += round_up(std::max<size_t>(bytes, 256), 256);
+    return at;
+  };
+  L.nlast = put(4 * (size_t)S.npix_max);
+  L.tfinal = put(4 * (size_t)S.npix_max);
+  L.dl = put(12 * (size_t)S.npix_max);
+  L.acc = put(64 * (size_t)std::max<int64_t>(n, 1));
+  L.partial = put(sizeof(float2) * (size_t)(l1_partial_count(S.npix_max) + 1) + 16);
+  L.loss_views = put(4 * (size_t)n_views);
+  L.stats = put(64 * (size_t)n_views);
+  L.mask = put((size_t)S.npix_max);
+  L.total = off;
+  return L;
+}
+
+geer_status train_check(geer_ctx* c, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                        const geer_opts* opts, int64_t entry_capacity, TrainShape& S) {
+  if (!scene || !views || !opts) return fail(c, GEER_ERR_INVALID_ARG, "null argument");
+  if (n_views < 1 || n_views > 4096) return fail(c, GEER_ERR_INVALID_ARG, "n_views %d out of range", n_views);
+  if (entry_capacity < 1 || entry_capacity >= kMaxKeys)
+    return fail(c, GEER_ERR_INVALID_ARG, "entry capacity %lld out of range", (long long)entry_capacity);
+  geer_status s;
+  if ((s = check_scene(c, scene)) != GEER_OK) return s;
+  if ((s = check_opts(c, *opts)) != GEER_OK) return s;
+  for (int i = 0; i < n_views; ++i)
+    if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
+  if (scene->n < 1) return fail(c, GEER_ERR_INVALID_ARG, "a plan needs a non-empty scene");
+  return train_shape(c, n_views, views, S);
+}
+
+geer_status geer_train_plan_workspace_bytes(geer_ctx* c, const geer_scene* scene, int32_t n_views,
+                                            const geer_view* views, const geer_opts* opts, int64_t entry_capacity,
+                                            int64_t* bytes) {
+  if (!c || !bytes) return GEER_ERR_INVALID_ARG;
+  TrainShape S;
+  geer_status s = train_check(c, scene, n_views, views, opts, entry_capacity, S);
+  if (s != GEER_OK) return s;
+  *bytes = (int64_t)train_layout(S, scene->n, entry_capacity, n_views).total;
+  return GEER_OK;
+}
+
+geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                                   const geer_opts* opts, int64_t entry_capacity, void* workspace,
+                                   int64_t workspace_bytes, const float* target, const uint8_t* mask, float* rgb,
+                                   float* loss, float* g_mean, float* g_scale, float* g_quat, float* g_opacity,
+                                   float* g_sh, geer_plan** out) {
+  if (!c || !out) return GEER_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!target || !rgb || !loss || !g_mean || !g_scale || !g_quat || !g_opacity || !g_sh)
+    return fail(c, GEER_ERR_INVALID_ARG, "null output or target");
+  TrainShape S;
+  geer_status s = train_check(c, scene, n_views, views, opts, entry_capacity, S);
+  if (s != GEER_OK) return s;
+  const int64_t n = scene->n;
+  const TrainLayout lay = train_layout(S, n, entry_capacity, n_views);
+  if (workspace && ((uintptr_t)workspace % 256 != 0 || workspace_bytes < (int64_t)lay.total))
+    return fail(c, GEER_ERR_INVALID_ARG, "workspace must be 256-byte aligned and hold %zu bytes", lay.total);
+  HIP_TRY(c, hipSetDevice(c->device));
+  LamTab lt;
+  if ((s = lambda_dev(c, opts->alpha_min, &lt)) != GEER_OK) return s;
+
+  geer_plan* P = new (std::nothrow) geer_plan();
+  if (!P) return fail(c, GEER_ERR_OOM, "plan allocation");
+  P->ctx = c;
+  P->scene = *scene;
+  P->op = make_opts(lt, *opts);
+  P->nviews = n_views;
+  P->shapes.assign(views, views + n_views);
+  P->n = n;
+  P->items = n;
+  P->ntiles = S.ntiles_max;
+  P->npix = S.npix_total;
+  P->ecap = entry_capacity;
+  P->meta_bytes = S.meta_bytes;
+  P->nseg = n_views;
+  P->seg_off = S.seg_off;
+  P->nstat = n_views;
+  auto bail = [&](geer_status st_) {
+    geer_plan_destroy(P);
+    return st_;
+  };
+#define PHIP(call)                                                                                       \
+  do {                                                                                                   \
+    hipError_t e_ = (call);                                                                              \
+    if (e_ != hipSuccess) return bail(fail(c, GEER_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)));    \
+  } while (0)
+  if (workspace) {
+    P->ws = workspace;
+  } else {
+    if (hipMalloc(&P->ws, lay.total) != hipSuccess) {
+      (void)hipGetLastError();
+      P->ws = nullptr;
+      return bail(fail(c, GEER_ERR_OOM, "plan workspace of %zu bytes", lay.total));
+    }
+    P->owns_ws = true;
+    P->bytes = (int64_t)lay.total;
+  }
+  char* w = (char*)P->ws;
+  const PlanLayout& F = lay.fwd;
+  P->meta = w + F.meta;
+  P->stats = (uint64_t*)(w + lay.stats);
+  FwdBufs b;
+  b.recs = (Record*)(w + F.recs);
+  b.rects = (uint2*)(w + F.rects);
+  b.keys = (uint32_t*)(w + F.keys);
+  b.counts = (uint32_t*)(w + F.counts);
+  b.ka = (uint32_t*)(w + F.ka);
+  b.va = (uint32_t*)(w + F.va);
+  b.kb = (uint32_t*)(w + F.kb);
+  b.vb = (uint32_t*)(w + F.vb);
+  b.hist = (uint32_t*)(w + F.hist);
+  b.scratch = (uint32_t*)(w + F.scratch);
+  b.cnt_sorted = (uint32_t*)(w + F.cnt_sorted);
+  b.tiles_a = (uint32_t*)(w + F.tiles_a);
+  b.tiles_b = (uint32_t*)(w + F.tiles_b);
+  b.items_b = (uint32_t*)(w + F.items_b);
+  b.list = (uint32_t*)(w + F.list);
+  b.ranges = (uint32_t*)(w + F.ranges);
+  b.heavy_list = (uint32_t*)(w + F.heavy_list);
+  b.heavy_flag = (uint32_t*)(w + F.heavy_flag);
+  b.hmax = heavy_capacity(S.ntiles_max);
+  b.nlast = (uint32_t*)(w + lay.nlast);
+  b.tfinal = (float*)(w + lay.tfinal);
+  float* dl = (float*)(w + lay.dl);
+  float* acc = (float*)(w + lay.acc);
+  float2* partial = (float2*)(w + lay.partial);
+  float* scale = (float*)(partial + l1_partial_count(S.npix_max) + 1);
+  float* loss_views = (float*)(w + lay.loss_views);
+  uint8_t* ones = (uint8_t*)(w + lay.mask);
+  if (!mask) PHIP(hipMemset(ones, 1, (size_t)S.npix_max));  // every ray valid (set once, outside the graph)
+  for (int k = 0; k < 2; ++k) {
+    PHIP(hipHostMalloc(&P->staging[k], std::max<size_t>(S.meta_bytes, 64), hipHostMallocDefault));
+    PHIP(hipEventCreateWithFlags(&P->staged[k], hipEventDisableTiming));
+  }
+  PHIP(hipEventCreateWithFlags(&P->done, hipEventDisableTiming));
+  PHIP(hipHostMalloc((void**)&P->host_stats, 64 * (size_t)n_views, hipHostMallocDefault));
+
+  // Capture: per view, forward (keeping T_final and the last blended index),
+  // weighted L1, backward accumulated into the gradients; then the loss sum.
+  hipStream_t cs = nullptr;
+  PHIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const double weight = 1.0 / (double)n_views;
+    for (int v = 0; v < n_views; ++v) {
+      const ViewTables& T = S.tabs[v];
+      char* mv = (char*)P->meta + S.seg_off[v];
+      b.views = (const ViewDev*)mv;
+      b.edges = (const float*)(mv + T.edges_off);
+      b.dtab = (const float2*)(mv + T.dtab_off);
+      b.stats = P->stats + 8 * v;
+      const int64_t po = S.pix_off[v];
+      float* rgb_v = rgb + 3 * po;
+      enqueue_preprocess(cs, P->scene, 1, P->op, lt.dev, b);
+      enqueue_association(cs, P->op, n, n, n, entry_capacity, T.ntiles, true, b);
+      enqueue_render(cs, P->op, T.ntiles, 1, b, rgb_v, nullptr, nullptr);
+      launch_l1(cs, T.npix, rgb_v, target + 3 * po, mask ? mask + po : ones, dl, loss_views + v, partial, scale,
+                weight);
+      launch_backward(cs, P->op.lambda_mode == 1, T.ntiles, n, 1, scene->sh_degree, scene->mean, scene->scale,
+                      scene->quat, scene->opacity, scene->sh, b.views, b.dtab, b.edges, lt.dev, P->op, b.heavy(),
+                      b.ranges, b.list, b.rects, b.recs, b.nlast, b.tfinal, dl, acc, v > 0 ? 1 : 0, g_mean, g_scale,
+                      g_quat, g_opacity, g_sh);
+    }
+    launch_sum_f32(cs, n_views, loss_views, loss);
     hipError_t e2 = hipStreamEndCapture(cs, &P->graph);
     e = e2 != hipSuccess ? e2 : hipGetLastError();
   }
@@ -983,21 +1205,30 @@ geer_status geer_plan_launch(geer_plan* P, const geer_view* views, void* stream)
                   views[i].height, P->shapes[i].width, P->shapes[i].height);
   }
   HIP_TRY(c, hipSetDevice(c->device));
-  ViewTables tab;
-  if ((s = build_tables(c, P->nviews, views, tab)) != GEER_OK) return s;
-  if (tab.bytes != P->meta_bytes) return fail(c, GEER_ERR_INVALID_ARG, "view tables changed size");
+  std::vector<ViewTables> tabs(P->nseg ? P->nseg : 1);
+  if (P->nseg) {
+    for (int v = 0; v < P->nseg; ++v)
+      if ((s = build_tables(c, 1, views + v, tabs[v])) != GEER_OK) return s;
+  } else if ((s = build_tables(c, P->nviews, views, tabs[0])) != GEER_OK) {
+    return s;
+  }
+  if (!P->nseg && tabs[0].bytes != P->meta_bytes) return fail(c, GEER_ERR_INVALID_ARG, "view tables changed size");
   hipStream_t st = (hipStream_t)stream;
   // the previous launch (possibly on another stream) still reads the tables
   if (P->launched) HIP_TRY(c, hipStreamWaitEvent(st, P->done, 0));
   const int k = P->next;
   if (P->staged_used[k]) HIP_TRY(c, hipEventSynchronize(P->staged[k]));  // its previous upload has left the buffer
-  pack_tables(tab, P->staging[k]);
-  HIP_TRY(c, hipMemcpyAsync(P->meta, P->staging[k], tab.bytes, hipMemcpyHostToDevice, st));
+  if (P->nseg) {
+    for (int v = 0; v < P->nseg; ++v) pack_tables(tabs[v], (char*)P->staging[k] + P->seg_off[v]);
+  } else {
+    pack_tables(tabs[0], P->staging[k]);
+  }
+  HIP_TRY(c, hipMemcpyAsync(P->meta, P->staging[k], P->meta_bytes, hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipEventRecord(P->staged[k], st));
   P->staged_used[k] = true;
   P->next = 1 - k;
   HIP_TRY(c, hipGraphLaunch(P->exec, st));
-  HIP_TRY(c, hipMemcpyAsync(P->host_stats, P->stats, 48, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipMemcpyAsync(P->host_stats, P->stats, 64 * (size_t)P->nstat, hipMemcpyDeviceToHost, st));
   HIP_TRY(c, hipEventRecord(P->done, st));
   P->launched = true;
   return GEER_OK;
@@ -1012,9 +1243,14 @@ geer_status geer_plan_entries(geer_plan* P, int64_t* entries, int64_t* capacity)
     return GEER_OK;
   }
   HIP_TRY(c, hipEventSynchronize(P->done));
-  const int64_t E = (int64_t)P->host_stats[3];
+  int64_t E = 0;
+  bool stalled = false;
+  for (int i = 0; i < P->nstat; ++i) {
+    E = std::max<int64_t>(E, (int64_t)P->host_stats[8 * i + 3]);
+    stalled |= P->host_stats[8 * i + 4] != 0;
+  }
   if (entries) *entries = E;
-  if (P->host_stats[4] != 0) return fail(c, GEER_ERR_HIP, "association sort stalled (look-back spin limit)");
+  if (stalled) return fail(c, GEER_ERR_HIP, "association sort stalled (look-back spin limit)");
   if (E > P->ecap)
     return fail(c, GEER_ERR_CAPACITY, "association list of %lld entries exceeds the plan's %lld", (long long)E,
                 (long long)P->ecap);

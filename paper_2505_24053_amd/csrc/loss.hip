@@ -1,6 +1,8 @@
-// L1 photometric loss over the valid rays of one view and its gradient:
-//   L = sum_{valid rays, channels} |rgb - target| / (3 n_valid),
-//   dL/drgb = sign(rgb - target) / (3 n_valid) on valid rays, 0 elsewhere.
+// L1 photometric loss over the valid rays of one view and its gradient, with
+// a weight w (1 for a single view; 1/V for one view of a V-view batch whose
+// loss is the mean of the views' losses):
+//   L = w sum_{valid rays, channels} |rgb - target| / (3 n_valid),
+//   dL/drgb = w sign(rgb - target) / (3 n_valid) on valid rays, 0 elsewhere.
 // Block partial sums are reduced by one block in a fixed order, so the loss
 // is deterministic.
 #include <hip/hip_runtime.h>
@@ -42,7 +44,8 @@ __global__ __launch_bounds__(kLossBlock) void l1_partial_kernel(int64_t P, const
 }
 
 __global__ __launch_bounds__(kLossBlock) void l1_finalize_kernel(int64_t nblocks, const float2* __restrict__ partial,
-                                                                 float* __restrict__ loss, float* __restrict__ scale) {
+                                                                 double weight, float* __restrict__ loss,
+                                                                 float* __restrict__ scale) {
   __shared__ double rs[kLossBlock], rc[kLossBlock];
   double s = 0.0, c = 0.0;
   for (int64_t b = threadIdx.x; b < nblocks; b += kLossBlock) {
@@ -61,8 +64,8 @@ __global__ __launch_bounds__(kLossBlock) void l1_finalize_kernel(int64_t nblocks
   }
   if (threadIdx.x == 0) {
     const double n = rc[0];
-    *loss = n > 0 ? (float)(rs[0] / (3.0 * n)) : 0.0f;
-    *scale = n > 0 ? (float)(1.0 / (3.0 * n)) : 0.0f;
+    *loss = n > 0 ? (float)(weight * rs[0] / (3.0 * n)) : 0.0f;
+    *scale = n > 0 ? (float)(weight / (3.0 * n)) : 0.0f;
   }
 }
 
@@ -83,12 +86,26 @@ __global__ __launch_bounds__(kLossBlock) void l1_grad_kernel(int64_t P, const fl
 
 int64_t l1_partial_count(int64_t P) { return (P + kLossBlock * kLossPer - 1) / (kLossBlock * kLossPer); }
 
+// Sum of n floats in index order (one lane), e.g. the per-view losses of a batch.
+__global__ void sum_f32_kernel(int n, const float* __restrict__ in, float* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += in[i];
+    *out = (float)s;
+  }
+}
+
+void launch_sum_f32(hipStream_t st, int n, const float* in, float* out) {
+  hipLaunchKernelGGL(sum_f32_kernel, dim3(1), dim3(64), 0, st, n, in, out);
+}
+
 void launch_l1(hipStream_t st, int64_t P, const float* rgb, const float* target, const uint8_t* mask, float* dl,
-               float* loss, float2* partial, float* scale) {
+               float* loss, float2* partial, float* scale, double weight) {
   const int64_t nb = l1_partial_count(P);
   if (nb > 0)
     hipLaunchKernelGGL(l1_partial_kernel, dim3((unsigned)nb), dim3(kLossBlock), 0, st, P, rgb, target, mask, partial);
-  hipLaunchKernelGGL(l1_finalize_kernel, dim3(1), dim3(kLossBlock), 0, st, nb, (const float2*)partial, loss, scale);
+  hipLaunchKernelGGL(l1_finalize_kernel, dim3(1), dim3(kLossBlock), 0, st, nb, (const float2*)partial, weight, loss,
+                     scale);
   if (P > 0)
     hipLaunchKernelGGL(l1_grad_kernel, dim3((unsigned)((P + kLossBlock - 1) / kLossBlock)), dim3(kLossBlock), 0, st, P,
                        rgb, target, mask, (const float*)scale, dl);

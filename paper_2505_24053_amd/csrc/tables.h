@@ -65,6 +65,7 @@ void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t 
 // loss.hip
 int64_t l1_partial_count(int64_t P);
 void launch_l1(hipStream_t st, int64_t P, const float* rgb, const float* target, const uint8_t* mask, float* dl,
-               float* loss, float2* partial, float* scale);
+               float* loss, float2* partial, float* scale, double weight);
+void launch_sum_f32(hipStream_t st, int n, const float* in, float* out);
 
 }  // namespace geer

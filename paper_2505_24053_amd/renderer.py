@@ -280,3 +280,48 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+class TrainPlan(Plan):
+    """A captured batched training step (geer_train_plan): per view the
+    forward, the L1 loss against `target` over `mask` (every ray when None)
+    and the backward; every launch fills rgb, loss ([1]) and the scene-shaped
+    gradient tensors in `grads` with the gradient of the mean of the views'
+    L1 losses.  `target` / `mask` / rgb use the concatenated per-view layout
+    of render()."""
+
+    def __init__(self, scene: dict, cams, entry_capacity: int, target: torch.Tensor, mask=None,
+                 opts: dict | None = None, workspace=None):
+        dev = scene["mean"].device
+        self.ctx = context(dev.index or 0)
+        self.scene = scene
+        self.shapes = [(int(c["width"]), int(c["height"])) for c in cams]
+        npix = sum(view_pixels(cams))
+        self.target = target.contiguous()
+        self.mask = mask.contiguous() if mask is not None else None
+        if self.target.numel() != 3 * npix or (self.mask is not None and self.mask.numel() != npix):
+            raise ValueError("target must hold 3 x %d values and mask %d" % (npix, npix))
+        self.rgb = torch.empty(3 * npix, device=dev)
+        self.depth = self.trans = None
+        self.loss = torch.zeros(1, device=dev)
+        self.grads = {k: torch.empty_like(scene[k]) for k in ("mean", "scale", "quat", "opacity", "sh")}
+        self.workspace = workspace
+        ws_ptr = C.c_void_p(workspace.data_ptr()) if workspace is not None else None
+        ws_bytes = workspace.numel() if workspace is not None else 0
+        g = self.grads
+        h = C.c_void_p()
+        _lib.check(_lib.load().geer_train_plan_create(
+            self.ctx, C.byref(_scene_struct(scene)), len(cams), _views(cams), C.byref(_lib.make_opts(**(opts or {}))),
+            int(entry_capacity), ws_ptr, ws_bytes, _ptr(self.target), _ptr(self.mask), _ptr(self.rgb),
+            _ptr(self.loss), _ptr(g["mean"]), _ptr(g["scale"]), _ptr(g["quat"]), _ptr(g["opacity"]), _ptr(g["sh"]),
+            C.byref(h)), self.ctx)
+        self.handle = h
+
+
+def train_plan_workspace_bytes(scene: dict, cams, entry_capacity: int, opts: dict | None = None) -> int:
+    ctx = context(scene["mean"].device.index or 0)
+    out = C.c_int64()
+    _lib.check(_lib.load().geer_train_plan_workspace_bytes(ctx, C.byref(_scene_struct(scene)), len(cams),
+                                                           _views(cams), C.byref(_lib.make_opts(**(opts or {}))),
+                                                           int(entry_capacity), C.byref(out)), ctx)
+    return int(out.value)

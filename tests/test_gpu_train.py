@@ -1,0 +1,113 @@
+"""Training plans (batched training step, one captured graph): for each view
+the forward, the L1 loss against a target and the backward, giving the
+gradient of the mean of the views' losses.  Checked against the eager path
+(render + L1 + backward per view, accumulated), which the other suites check
+against the FP64 oracle: RGB bit for bit, loss to 1e-6, gradients to 1e-5
+relative L2 (float atomics sum in another order); over repeated launches
+with new cameras and after the parameters change in place."""
+import numpy as np
+import pytest
+
+from paper_2505_24053_amd import _lib, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GROUPS = ("mean", "scale", "quat", "opacity", "sh")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_24053_amd import renderer
+
+    if not __import__("os").path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    return renderer
+
+
+def cams_for(rng):
+    out = []
+    for k in range(3):
+        Rm, c = synth.random_pose(rng, 2.0)
+        if k == 0:
+            out.append(synth.camera_pinhole(64, 48, 70.0, Rm, c))
+        elif k == 1:
+            out.append(synth.camera_equidistant(80, 80, 180.0, Rm, c))
+        else:
+            out.append(synth.camera_kb(96, 54, 200.0, seed=int(rng.integers(1 << 20)), R=Rm, position=c))
+    return out
+
+
+def eager_step(R, sc, cams, target, mask):
+    """Mean over views of the per-view L1 losses, its gradient, and the RGB."""
+    V = len(cams)
+    grads = {k: torch.zeros_like(sc[k]) for k in GROUPS}
+    rgbs, losses, off = [], [], 0
+    for cam in cams:
+        hw = cam["width"] * cam["height"]
+        rgb, _, _, frame = R.render(sc, [cam], keep_frame=True)
+        loss, dl = R.l1_loss(rgb, target[3 * off: 3 * (off + hw)], mask[off: off + hw])
+        R.backward(frame, sc, dl / V, accumulate=True, grads=grads)
+        torch.cuda.synchronize()
+        frame.release()
+        rgbs.append(rgb)
+        losses.append(float(loss.item()))
+        off += hw
+    return torch.cat(rgbs), sum(losses) / V, grads
+
+
+def check_step(R, plan, sc, cams, target, mask):
+    plan.launch(cams)
+    E, cap, over = plan.entries()
+    assert not over
+    rgb, loss, grads = eager_step(R, sc, cams, target, mask)
+    assert torch.equal(plan.rgb, rgb)
+    assert float(plan.loss.item()) == pytest.approx(loss, rel=1e-6)
+    for k in GROUPS:
+        a, b = plan.grads[k].double(), grads[k].double()
+        assert float((a - b).norm()) <= 1e-5 * float(b.norm()) + 1e-12, k
+    return E
+
+
+def test_train_plan_matches_eager_step(R):
+    scene = synth.scene_box(20000, seed=31, half=4.0, sh_degree=2)
+    target_scene = synth.perturb(scene, seed=32)
+    sc, tsc = R.scene_from_numpy(scene), R.scene_from_numpy(target_scene)
+    rng = np.random.default_rng(33)
+    cams = cams_for(rng)
+    target, _, _, _ = R.render(tsc, cams)
+    mask = torch.as_tensor(np.concatenate([_lib.valid_mask(c).reshape(-1) for c in cams]).astype(np.uint8),
+                           device="cuda")
+    plan = R.TrainPlan(sc, cams, 2_000_000, target, mask)
+    check_step(R, plan, sc, cams, target, mask)
+    # new cameras of the same grid sizes
+    cams2 = cams_for(rng)
+    target2, _, _, _ = R.render(tsc, cams2)
+    plan.target.copy_(target2)
+    check_step(R, plan, sc, cams2, target2, mask)
+    # the parameters change in place between launches (an optimiser step)
+    with torch.no_grad():
+        for k in GROUPS:
+            sc[k].sub_(1e-3 * plan.grads[k].sign())
+    check_step(R, plan, sc, cams2, target2, mask)
+    plan.destroy()
+
+
+def test_train_plan_without_mask_and_capacity(R):
+    scene = synth.scene_box(5000, seed=34, half=3.0, sh_degree=0)
+    sc = R.scene_from_numpy(scene)
+    cams = cams_for(np.random.default_rng(35))
+    npix = sum(c["width"] * c["height"] for c in cams)
+    target = torch.rand(3 * npix, device="cuda")
+    plan = R.TrainPlan(sc, cams, 1_000_000, target)
+    E = check_step(R, plan, sc, cams, target, torch.ones(npix, dtype=torch.uint8, device="cuda"))
+    assert E > 0
+    tight = R.TrainPlan(sc, cams, max(E // 4, 1), target)
+    tight.launch(cams)
+    assert tight.entries()[2]
+    tight.destroy()
+    plan.destroy()
