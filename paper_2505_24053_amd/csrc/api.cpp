@@ -290,11 +290,12 @@ struct FwdBufs {
 };
 
 // Stage (a): zero the counters, then preprocess + PBF of every item.
+// With per_view_stats the counters of view v are the 8 words at b.stats + 8v.
 void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, const Opts& op, const float* lam,
-                        const FwdBufs& b) {
-  launch_fill_u32(st, (uint32_t*)b.stats, 16, 0u);
+                        const FwdBufs& b, bool per_view_stats = false) {
+  launch_fill_u32(st, (uint32_t*)b.stats, per_view_stats ? 16 * nviews : 16, 0u);
   launch_preprocess(st, sc.n, nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh, b.views, op, lam,
-                    b.edges, b.recs, b.rects, b.keys, b.counts, (unsigned long long*)b.stats);
+                    b.edges, b.recs, b.rects, b.keys, b.counts, (unsigned long long*)b.stats, per_view_stats ? 8 : 0);
 }
 
 // Stage (b): association list.  With exact sizes (dyn == false) nvis_cap and
@@ -811,7 +812,8 @@ struct PlanLayout {
          heavy_flag = 0, total = 0;
 };
 
-PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t ntiles) {
+// pre_items (default: items) sizes the per-item outputs of the preprocess.
+PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t ntiles, int64_t pre_items = -1) {
   PlanLayout L;
   size_t off = 0;
   auto put = [&](size_t bytes) {
@@ -822,10 +824,11 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
   const int64_t it1 = std::max<int64_t>(items, 1);
   const int64_t hist_words = radix_work_words(std::max(it1, ecap));
   L.meta = put(meta_bytes);
-  L.recs = put(sizeof(Record) * it1);
-  L.rects = put(sizeof(uint2) * it1);
-  L.keys = put(4 * it1);
-  L.counts = put(4 * it1);
+  const int64_t pre1 = pre_items < 0 ? it1 : std::max<int64_t>(pre_items, 1);
+  L.recs = put(sizeof(Record) * pre1);
+  L.rects = put(sizeof(uint2) * pre1);
+  L.keys = put(4 * pre1);
+  L.counts = put(4 * pre1);
   L.stats = put(64);
   L.ka = put(4 * it1);
   L.va = put(4 * it1);
@@ -991,6 +994,7 @@ struct TrainShape {
   std::vector<size_t> seg_off;
   std::vector<int64_t> pix_off;
   size_t meta_bytes = 0;
+  size_t all_off = 0;  // ViewDev of every view, edge offsets relative to the meta base (Gaussian-wise backward)
   int64_t ntiles_max = 0, npix_max = 0, npix_total = 0;
 };
 
@@ -1009,13 +1013,29 @@ geer_status train_shape(geer_ctx* c, int32_t n_views, const geer_view* views, Tr
     S.ntiles_max = std::max(S.ntiles_max, S.tabs[v].ntiles);
     S.npix_max = std::max(S.npix_max, S.tabs[v].npix);
   }
+  S.all_off = off;
+  off += round_up(sizeof(ViewDev) * (size_t)n_views, 256);
   S.meta_bytes = off;
   return GEER_OK;
 }
 
+// Packs the per-view table blocks and the all-views ViewDev array.
+void pack_train_tables(const TrainShape& S, void* dst) {
+  const int nv = (int)S.tabs.size();
+  std::vector<ViewDev> all(nv);
+  for (int v = 0; v < nv; ++v) {
+    pack_tables(S.tabs[v], (char*)dst + S.seg_off[v]);
+    all[v] = S.tabs[v].hv[0];
+    const int32_t base = (int32_t)((S.seg_off[v] + S.tabs[v].edges_off) / sizeof(float));
+    all[v].ex_off += base;
+    all[v].ey_off += base;
+  }
+  std::memcpy((char*)dst + S.all_off, all.data(), sizeof(ViewDev) * (size_t)nv);
+}
+
 TrainLayout train_layout(const TrainShape& S, int64_t n, int64_t ecap, int32_t n_views) {
   TrainLayout L;
-  L.fwd = plan_layout(S.meta_bytes, n, ecap, S.ntiles_max);
+  L.fwd = plan_layout(S.meta_bytes, n, ecap, S.ntiles_max, n * n_views);
   size_t off = L.fwd.total;
   auto put = [&](size_t bytes) {
     const size_t at = off;
@@ -1025,7 +1045,7 @@ TrainLayout train_layout(const TrainShape& S, int64_t n, int64_t ecap, int32_t n
   L.nlast = put(4 * (size_t)S.npix_max);
   L.tfinal = put(4 * (size_t)S.npix_max);
   L.dl = put(12 * (size_t)S.npix_max);
-  L.acc = put(64 * (size_t)std::max<int64_t>(n, 1));
+  L.acc = put(64 * (size_t)std::max<int64_t>(n, 1) * (size_t)n_views);
   L.partial = put(sizeof(float2) * (size_t)(l1_partial_count(S.npix_max) + 1) + 16);
   L.loss_views = put(4 * (size_t)n_views);
   L.stats = put(64 * (size_t)n_views);
@@ -1163,6 +1183,17 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     const double weight = 1.0 / (double)n_views;
+    const ViewDev* all_views = (const ViewDev*)((char*)P->meta + S.all_off);
+    launch_zero_acc(cs, acc, n * (int64_t)n_views * 16);
+    // one preprocess for every view: the scene is read once, item v n + g
+    // holds Gaussian g in view v, view v's counters are P->stats + 8 v
+    b.views = all_views;
+    b.edges = (const float*)P->meta;
+    b.stats = P->stats;
+    enqueue_preprocess(cs, P->scene, n_views, P->op, lt.dev, b, true);
+    Record* const recs0 = b.recs;
+    uint2* const rects0 = b.rects;
+    uint32_t *const keys0 = b.keys, *const counts0 = b.counts;
     for (int v = 0; v < n_views; ++v) {
       const ViewTables& T = S.tabs[v];
       char* mv = (char*)P->meta + S.seg_off[v];
@@ -1170,18 +1201,25 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
       b.edges = (const float*)(mv + T.edges_off);
       b.dtab = (const float2*)(mv + T.dtab_off);
       b.stats = P->stats + 8 * v;
+      const int64_t io = (int64_t)v * n;
+      b.recs = recs0 + io;
+      b.rects = rects0 + io;
+      b.keys = keys0 + io;
+      b.counts = counts0 + io;
       const int64_t po = S.pix_off[v];
       float* rgb_v = rgb + 3 * po;
-      enqueue_preprocess(cs, P->scene, 1, P->op, lt.dev, b);
       enqueue_association(cs, P->op, n, n, n, entry_capacity, T.ntiles, true, b);
       enqueue_render(cs, P->op, T.ntiles, 1, b, rgb_v, nullptr, nullptr);
       launch_l1(cs, T.npix, rgb_v, target + 3 * po, mask ? mask + po : ones, dl, loss_views + v, partial, scale,
                 weight);
-      launch_backward(cs, P->op.lambda_mode == 1, T.ntiles, n, 1, scene->sh_degree, scene->mean, scene->scale,
-                      scene->quat, scene->opacity, scene->sh, b.views, b.dtab, b.edges, lt.dev, P->op, b.heavy(),
-                      b.ranges, b.list, b.rects, b.recs, b.nlast, b.tfinal, dl, acc, v > 0 ? 1 : 0, g_mean, g_scale,
-                      g_quat, g_opacity, g_sh);
+      // ray-wise backward of this view into its own accumulator slice
+      launch_render_backward(cs, P->op.lambda_mode == 1, T.ntiles, 1, b.views, b.dtab, P->op, b.heavy(), b.ranges,
+                             b.list, b.rects, b.recs, b.nlast, b.tfinal, dl, acc + (size_t)v * (size_t)n * 16);
     }
+    // Gaussian-wise backward once, summing every view
+    launch_preprocess_backward(cs, n, n_views, scene->sh_degree, scene->mean, scene->scale, scene->quat,
+                               scene->opacity, scene->sh, all_views,
+                               (const float*)P->meta, lt.dev, P->op, acc, 0, g_mean, g_scale, g_quat, g_opacity, g_sh);
     launch_sum_f32(cs, n_views, loss_views, loss);
     hipError_t e2 = hipStreamEndCapture(cs, &P->graph);
     e = e2 != hipSuccess ? e2 : hipGetLastError();
@@ -1205,24 +1243,22 @@ geer_status geer_plan_launch(geer_plan* P, const geer_view* views, void* stream)
                   views[i].height, P->shapes[i].width, P->shapes[i].height);
   }
   HIP_TRY(c, hipSetDevice(c->device));
-  std::vector<ViewTables> tabs(P->nseg ? P->nseg : 1);
+  ViewTables tab;
+  TrainShape S;
   if (P->nseg) {
-    for (int v = 0; v < P->nseg; ++v)
-      if ((s = build_tables(c, 1, views + v, tabs[v])) != GEER_OK) return s;
-  } else if ((s = build_tables(c, P->nviews, views, tabs[0])) != GEER_OK) {
-    return s;
+    if ((s = train_shape(c, P->nseg, views, S)) != GEER_OK) return s;
+    if (S.meta_bytes != P->meta_bytes) return fail(c, GEER_ERR_INVALID_ARG, "view tables changed size");
+  } else {
+    if ((s = build_tables(c, P->nviews, views, tab)) != GEER_OK) return s;
+    if (tab.bytes != P->meta_bytes) return fail(c, GEER_ERR_INVALID_ARG, "view tables changed size");
   }
-  if (!P->nseg && tabs[0].bytes != P->meta_bytes) return fail(c, GEER_ERR_INVALID_ARG, "view tables changed size");
   hipStream_t st = (hipStream_t)stream;
   // the previous launch (possibly on another stream) still reads the tables
   if (P->launched) HIP_TRY(c, hipStreamWaitEvent(st, P->done, 0));
   const int k = P->next;
   if (P->staged_used[k]) HIP_TRY(c, hipEventSynchronize(P->staged[k]));  // its previous upload has left the buffer
-  if (P->nseg) {
-    for (int v = 0; v < P->nseg; ++v) pack_tables(tabs[v], (char*)P->staging[k] + P->seg_off[v]);
-  } else {
-    pack_tables(tabs[0], P->staging[k]);
-  }
+  if (P->nseg) pack_train_tables(S, P->staging[k]);
+  else pack_tables(tab, P->staging[k]);
   HIP_TRY(c, hipMemcpyAsync(P->meta, P->staging[k], P->meta_bytes, hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipEventRecord(P->staged[k], st));
   P->staged_used[k] = true;

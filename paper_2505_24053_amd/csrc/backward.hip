@@ -327,39 +327,56 @@ __global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ p, in
   if (i < n) p[i] = 0.0f;
 }
 
+void launch_zero_acc(hipStream_t st, float* acc, int64_t nacc) {
+  if (nacc > 0)
+    hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nacc + 255) / 256)), dim3(256), 0, st, acc, nacc);
+}
+
+void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int32_t n_views, const ViewDev* views,
+                            const float2* dtab, const Opts& op, const HeavyTiles& heavy, const uint32_t* ranges,
+                            const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
+                            const float* tfinal, const float* dl_drgb, float* acc) {
+  if (ntiles <= 0) return;
+  const unsigned grid = (unsigned)(kHeavySplit * heavy.hmax + 4 * ntiles);
+  if (fixed_lambda)
+    hipLaunchKernelGGL(render_backward_kernel<true>, dim3(grid), dim3(kWinB), 0, st, views, n_views, dtab, ranges, list,
+                       rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
+  else
+    hipLaunchKernelGGL(render_backward_kernel<false>, dim3(grid), dim3(kWinB), 0, st, views, n_views, dtab, ranges,
+                       list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
+}
+
+void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
+                                const float* scale, const float* quat, const float* opacity, const float* sh,
+                                const ViewDev* views, const float* edges, const float* lam_tab, const Opts& op,
+                                const float* acc, int accumulate, float* g_mean, float* g_scale, float* g_quat,
+                                float* g_opacity, float* g_sh) {
+  if (n <= 0) return;
+  const dim3 grid((unsigned)((n + 255) / 256));
+#define GEER_PB(D)                                                                                              \
+  hipLaunchKernelGGL(preprocess_backward_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, scale, quat, opacity, \
+                     sh, views, op, lam_tab, edges, acc, accumulate, g_mean, g_scale, g_quat, g_opacity, g_sh)
+  switch (sh_degree) {
+    case 0: GEER_PB(0); break;
+    case 1: GEER_PB(1); break;
+    case 2: GEER_PB(2); break;
+    default: GEER_PB(3); break;
+  }
+#undef GEER_PB
+}
+
 void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t n, int32_t n_views,
                      int32_t sh_degree, const float* mean, const float* scale, const float* quat,
                      const float* opacity, const float* sh, const ViewDev* views, const float2* dtab,
                      const float* edges, const float* lam_tab, const Opts& op, const HeavyTiles& heavy,
                      const uint32_t* ranges, const uint32_t* list, const uint2* rects, const Record* recs,
-                     const uint32_t* nlast,
-                     const float* tfinal, const float* dl_drgb, float* acc, int accumulate, float* g_mean,
-                     float* g_scale, float* g_quat, float* g_opacity, float* g_sh) {
-  const int64_t nacc = n * n_views * kAcc;
-  if (nacc > 0)
-    hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nacc + 255) / 256)), dim3(256), 0, st, acc, nacc);
-  if (ntiles > 0) {
-    const unsigned grid = (unsigned)(kHeavySplit * heavy.hmax + 4 * ntiles);
-    if (fixed_lambda)
-      hipLaunchKernelGGL(render_backward_kernel<true>, dim3(grid), dim3(kWinB), 0, st, views, n_views, dtab, ranges,
-                         list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
-    else
-      hipLaunchKernelGGL(render_backward_kernel<false>, dim3(grid), dim3(kWinB), 0, st, views, n_views, dtab, ranges,
-                         list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
-  }
-  if (n > 0) {
-    const dim3 grid((unsigned)((n + 255) / 256));
-#define GEER_PB(D)                                                                                              \
-  hipLaunchKernelGGL(preprocess_backward_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, scale, quat, opacity, \
-                     sh, views, op, lam_tab, edges, acc, accumulate, g_mean, g_scale, g_quat, g_opacity, g_sh)
-    switch (sh_degree) {
-      case 0: GEER_PB(0); break;
-      case 1: GEER_PB(1); break;
-      case 2: GEER_PB(2); break;
-      default: GEER_PB(3); break;
-    }
-#undef GEER_PB
-  }
+                     const uint32_t* nlast, const float* tfinal, const float* dl_drgb, float* acc, int accumulate,
+                     float* g_mean, float* g_scale, float* g_quat, float* g_opacity, float* g_sh) {
+  launch_zero_acc(st, acc, n * n_views * kAcc);
+  launch_render_backward(st, fixed_lambda, ntiles, n_views, views, dtab, op, heavy, ranges, list, rects, recs, nlast,
+                         tfinal, dl_drgb, acc);
+  launch_preprocess_backward(st, n, n_views, sh_degree, mean, scale, quat, opacity, sh, views, edges, lam_tab, op, acc,
+                             accumulate, g_mean, g_scale, g_quat, g_opacity, g_sh);
 }
 
 }  // namespace geer

@@ -26,20 +26,53 @@
 
 namespace geer {
 
+// Adds the block's sums of association entries and visible items to
+// totals[0] and totals[1] (every thread of the 256-thread block calls it).
+__device__ __forceinline__ void block_add_totals(unsigned long long e, unsigned long long vis,
+                                                 unsigned long long* totals) {
+  __shared__ unsigned long long red[2][4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    e += __shfl_xor(e, off);
+    vis += __shfl_xor(vis, off);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();  // the previous call's reads of red are done
+  if (lane == 0) { red[0][wv] = e; red[1][wv] = vis; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long te = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const unsigned long long tv = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    if (te) atomicAdd(&totals[0], te);
+    if (tv) atomicAdd(&totals[1], tv);
+  }
+}
+
 __global__ __launch_bounds__(256) void preprocess_kernel(
     int64_t n, int32_t n_views, int32_t sh_degree, const float* __restrict__ mean, const float* __restrict__ scale,
     const float* __restrict__ quat, const float* __restrict__ opacity, const float* __restrict__ sh,
     const ViewDev* __restrict__ views, Opts op, const float* __restrict__ lam_tab,
     const float* __restrict__ edges, Record* __restrict__ recs, uint2* __restrict__ rects,
-    uint32_t* __restrict__ keys, uint32_t* __restrict__ counts, unsigned long long* __restrict__ totals) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ counts, unsigned long long* __restrict__ totals,
+    int totals_stride) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = g < n;
   unsigned long long my_entries = 0, my_visible = 0;
-  if (g < n) {
-    float mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
-    float s[3] = {scale[g], scale[n + g], scale[2 * n + g]};
-    float q[4] = {quat[g], quat[n + g], quat[2 * n + g], quat[3 * n + g]};
-    float sigma = opacity[g];
-    for (int v = 0; v < n_views; ++v) {
+  float mu[3], s[3], q[4], sigma = 0.0f;
+  if (in) {
+    mu[0] = mean[g]; mu[1] = mean[n + g]; mu[2] = mean[2 * n + g];
+    s[0] = scale[g]; s[1] = scale[n + g]; s[2] = scale[2 * n + g];
+    q[0] = quat[g]; q[1] = quat[n + g]; q[2] = quat[2 * n + g]; q[3] = quat[3 * n + g];
+    sigma = opacity[g];
+  }
+  for (int v = 0; v < n_views; ++v) {
+    // with a totals stride every view has its own counters: flush the sums of the previous view
+    if (totals_stride && v > 0) {
+      block_add_totals(my_entries, my_visible, totals + (int64_t)(v - 1) * totals_stride);
+      my_entries = my_visible = 0;
+    }
+    if (!in) continue;
+    {
       const ViewDev& V = views[v];
       int64_t item = (int64_t)v * n + g;
       AssocOut A;
@@ -89,33 +122,20 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
       dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];
     }
   }
-  // block totals: association entries and visible items
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    my_entries += __shfl_xor(my_entries, off);
-    my_visible += __shfl_xor(my_visible, off);
-  }
-  __shared__ unsigned long long red[2][4];
-  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) { red[0][wv] = my_entries; red[1][wv] = my_visible; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long e = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    unsigned long long vv = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-    if (e) atomicAdd(&totals[0], e);
-    if (vv) atomicAdd(&totals[1], vv);
-  }
+  block_add_totals(my_entries, my_visible,
+                   totals + (totals_stride ? (int64_t)(n_views - 1) * totals_stride : 0));
 }
 
 void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
                        const float* scale, const float* quat, const float* opacity, const float* sh,
                        const ViewDev* views, const Opts& op, const float* lam_tab, const float* edges,
                        Record* recs, uint2* rects, uint32_t* keys, uint32_t* counts,
-                       unsigned long long* totals) {
+                       unsigned long long* totals, int totals_stride) {
   if (n == 0) return;
   int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n, n_views, sh_degree, mean,
-                     scale, quat, opacity, sh, views, op, lam_tab, edges, recs, rects, keys, counts, totals);
+                     scale, quat, opacity, sh, views, op, lam_tab, edges, recs, rects, keys, counts, totals,
+                     totals_stride);
 }
 
 }  // namespace geer

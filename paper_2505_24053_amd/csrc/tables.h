@@ -22,7 +22,8 @@ void valid_mask(const geer_view& v, uint8_t* mask);
 void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
                        const float* scale, const float* quat, const float* opacity, const float* sh,
                        const ViewDev* views, const Opts& op, const float* lam_tab, const float* edges,
-                       Record* recs, uint2* rects, uint32_t* keys, uint32_t* counts, unsigned long long* totals);
+                       Record* recs, uint2* rects, uint32_t* keys, uint32_t* counts, unsigned long long* totals,
+                       int totals_stride);
 
 // sort.hip
 int64_t scan_scratch_words(int64_t n);
@@ -61,6 +62,17 @@ void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t 
                      const uint32_t* nlast,
                      const float* tfinal, const float* dl_drgb, float* acc, int accumulate, float* g_mean,
                      float* g_scale, float* g_quat, float* g_opacity, float* g_sh);
+
+void launch_zero_acc(hipStream_t st, float* acc, int64_t nacc);
+void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int32_t n_views, const ViewDev* views,
+                            const float2* dtab, const Opts& op, const HeavyTiles& heavy, const uint32_t* ranges,
+                            const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
+                            const float* tfinal, const float* dl_drgb, float* acc);
+void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
+                                const float* scale, const float* quat, const float* opacity, const float* sh,
+                                const ViewDev* views, const float* edges, const float* lam_tab, const Opts& op,
+                                const float* acc, int accumulate, float* g_mean, float* g_scale, float* g_quat,
+                                float* g_opacity, float* g_sh);
 
 // loss.hip
 int64_t l1_partial_count(int64_t P);
