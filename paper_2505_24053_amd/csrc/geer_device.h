@@ -463,18 +463,21 @@ __device__ __forceinline__ QuadCone half_tile_cone(const ViewDev& V, const float
 // whose foot point lies in the region and to the corners in front.  The
 // corner vectors are rescaled to unit max-norm first (the cone is unchanged);
 // FP32 margins: Qc + 2^-8 Qc + 2^-20, tau^2 + 2^-8 tau^2 + 2^-18 (1 + d^2),
-// and 2^-12 relative slack in the foot-point test.
+// and 2^-12 relative slack in the foot-point test.  Quotients and square
+// roots use the hardware reciprocal and square root (about 1 ulp): the
+// margins are orders of magnitude wider, and the rescale only needs a
+// positive factor.
 __device__ __forceinline__ bool cone_meets_quad(const float4& p0, const float4& p1, const float4& p2, const float4& p3,
                                                 const QuadCone& C, float log2_amin, bool fixed) {
   if (!C.valid) return true;
   const float G[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x};
   const float c0 = p2.y, lsig = p2.z, qmax = p3.w;
-  float Qc = (lsig - log2_amin) / (-c0);
+  float Qc = (lsig - log2_amin) * __builtin_amdgcn_rcpf(-c0);
   if (fixed) Qc = fminf(Qc, qmax);
   Qc = fmaf(Qc, 0x1p-8f, Qc) + 0x1p-20f;
   if (!(Qc > 0.0f)) return false;
   if (Qc >= 1.0f) return true;
-  const float tau2 = Qc / (1.0f - Qc);
+  const float tau2 = Qc * __builtin_amdgcn_rcpf(1.0f - Qc);
   float g[4][3];
   bool any_front = false;
 #pragma unroll
@@ -484,7 +487,7 @@ __device__ __forceinline__ bool cone_meets_quad(const float4& p0, const float4& 
     float gy = fmaf(G[5], d[2], fmaf(G[4], d[1], G[3] * d[0]));
     float gz = fmaf(G[8], d[2], fmaf(G[7], d[1], G[6] * d[0]));
     const float m = fmaxf(fmaxf(fabsf(gx), fabsf(gy)), fabsf(gz));
-    const float im = m > 0.0f ? 1.0f / m : 0.0f;
+    const float im = m > 0.0f ? __builtin_amdgcn_rcpf(m) : 0.0f;
     g[k][0] = gx * im;
     g[k][1] = gy * im;
     g[k][2] = gz * im;
@@ -508,23 +511,25 @@ __device__ __forceinline__ bool cone_meets_quad(const float4& p0, const float4& 
   if (!(fabsf(orient) > 1e-12f)) return true;  // degenerate block cone
   const float sg = orient > 0.0f ? 1.0f : -1.0f;
   bool inside = true;
-  float nxy[4];
+  float nxy2[4], nxy[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     n[k][0] *= sg;
     n[k][1] *= sg;
     n[k][2] *= sg;
     inside &= n[k][2] >= 0.0f;
-    nxy[k] = sqrtf(fmaf(n[k][0], n[k][0], n[k][1] * n[k][1]));
+    nxy2[k] = fmaf(n[k][0], n[k][0], n[k][1] * n[k][1]);
+    nxy[k] = __builtin_amdgcn_sqrtf(nxy2[k]);
   }
   if (inside) return true;
   float best = INFINITY;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (!(nxy[k] > 0.0f)) continue;
-    const float t = n[k][2] / (nxy[k] * nxy[k]);
+    if (!(nxy2[k] > 0.0f)) continue;
+    const float inv = __builtin_amdgcn_rcpf(nxy2[k]);
+    const float t = n[k][2] * inv;
     const float px = -t * n[k][0], py = -t * n[k][1];
-    const float pn = sqrtf(fmaf(px, px, py * py));
+    const float pn = __builtin_amdgcn_sqrtf(fmaf(px, px, py * py));
     bool on = true;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -532,11 +537,12 @@ __device__ __forceinline__ bool cone_meets_quad(const float4& p0, const float4& 
       const float val = fmaf(n[j][0], px, fmaf(n[j][1], py, n[j][2]));
       on &= val >= -0x1p-12f * (fabsf(n[j][2]) + nxy[j] * pn);
     }
-    if (on) best = fminf(best, (n[k][2] * n[k][2]) / (nxy[k] * nxy[k]));
+    if (on) best = fminf(best, (n[k][2] * n[k][2]) * inv);
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    if (g[k][2] > 0.0f) best = fminf(best, fmaf(g[k][0], g[k][0], g[k][1] * g[k][1]) / (g[k][2] * g[k][2]));
+    if (g[k][2] > 0.0f)
+      best = fminf(best, fmaf(g[k][0], g[k][0], g[k][1] * g[k][1]) * __builtin_amdgcn_rcpf(g[k][2] * g[k][2]));
   return best <= fmaf(tau2, 0x1p-8f, tau2) + 0x1p-18f * (1.0f + best);
 }
 
