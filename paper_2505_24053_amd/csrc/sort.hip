@@ -108,6 +108,7 @@ __device__ __forceinline__ int64_t dyn_count(int64_t n_cap, const unsigned long 
 // word is [flag:2 | count:30]; the look-back spin is bounded and reports a
 // stall through an error word instead of hanging.
 
+constexpr int kLookBack = 16;  // statuses read per look-back round
 constexpr int kOSPer = 8;                       // keys per thread
 constexpr int kOSItems = kBlock * kOSPer;       // 2048 keys per block
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
@@ -227,22 +228,39 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
   s_cnt[3][tid] = c0 + c1 + c2;
   __hip_atomic_store(&status[blk * 256 + tid], kFlagAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-  // decoupled look-back over the earlier blocks
+  // decoupled look-back over the earlier blocks, kLookBack statuses per
+  // round (independent loads in flight together): add aggregates from the
+  // nearest block back until an inclusive prefix; stop at a block that has
+  // not published yet and poll again from it.  Block 0's aggregate is its
+  // inclusive prefix, so the walk also ends after it.
   uint32_t excl = 0u, spins = 0u;
   for (int64_t j = blk - 1; j >= 0;) {
-    const uint32_t v = __hip_atomic_load(&status[j * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t f = v & ~kValMask;
-    if (f == 0u) {
+    uint32_t v[kLookBack];
+#pragma unroll
+    for (int q = 0; q < kLookBack; ++q)
+      v[q] = j - q >= 0 ? __hip_atomic_load(&status[(j - q) * 256 + tid], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : kFlagInc;
+    int q = 0;
+    bool done = false;
+#pragma unroll
+    for (int r = 0; r < kLookBack; ++r) {
+      if (q != r) continue;
+      const uint32_t f = v[r] & ~kValMask;
+      if (f == 0u) continue;  // not published: poll from here again
+      excl += v[r] & kValMask;
+      if (f == kFlagInc) done = true;
+      else q = r + 1;
+    }
+    if (done) break;
+    j -= q;
+    if (q < kLookBack) {
       if (++spins > kSpinLimit) {
         atomicOr(err, 1ull);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      continue;
     }
-    excl += v & kValMask;
-    if (f == kFlagInc) break;
-    --j;
   }
   __hip_atomic_store(&status[blk * 256 + tid], kFlagInc | (excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
@@ -287,11 +305,31 @@ __global__ __launch_bounds__(kBlock) void gather_counts_kernel(const uint32_t* _
 
 constexpr int kExpandPer = 8;
 
+// Corner directions of every 16x16 tile of every view (the expansion's
+// culling cone), four float4 per tile: corner k in .xyz of entry k, the
+// cone's validity in .w of entry 0.
+__global__ __launch_bounds__(kBlock) void tile_cones_kernel(const ViewDev* __restrict__ views, int nviews,
+                                                            const float2* __restrict__ dtab, int64_t ntiles,
+                                                            float4* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= ntiles) return;
+  int v = 0;
+  while (v + 1 < nviews && t >= views[v + 1].tile_base) ++v;
+  const ViewDev& V = views[v];
+  const int lt = (int)(t - V.tile_base);
+  const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
+  const QuadCone Q = block_cone(V, dtab, tx * kTile, ty * kTile, kTile);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    out[4 * t + k] = make_float4(Q.d[k][0], Q.d[k][1], Q.d[k][2], k == 0 ? (Q.valid ? 1.0f : 0.0f) : 0.0f);
+}
+
 // Each lane expands kExpandPer consecutive entries (one binary search for the
-// owner of its first entry), the block stages its 2048 entries in LDS and
-// writes them back lane-striped so every store is coalesced.  With `cull`,
-// an entry whose Gaussian's contribution cone meets no ray of its tile gets
-// the tile id kDropKey and is left out by the tile sort.
+// owner of its first entry; the tile position is derived once per owner and
+// then stepped along the rectangle's rows), the block stages its 2048 entries
+// in LDS and writes them back lane-striped so every store is coalesced.  With
+// `cull`, an entry whose Gaussian's contribution cone meets no ray of its
+// tile gets the tile id kDropKey and is left out by the tile sort.
 __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restrict__ items,
                                                         const uint32_t* __restrict__ offs, int64_t m_cap,
                                                         const unsigned long long* __restrict__ dyn_m,
@@ -299,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
                                                         const unsigned long long* __restrict__ dyn_total,
                                                         const uint2* __restrict__ rects,
                                                         const ViewDev* __restrict__ views, int64_t n,
-                                                        const float2* __restrict__ dtab,
+                                                        const float4* __restrict__ tcones,
                                                         const Record* __restrict__ recs, Opts op, int cull,
                                                         uint32_t* __restrict__ tiles_out,
                                                         uint32_t* __restrict__ items_out) {
@@ -317,28 +355,44 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
       int64_t mid = (lo + hi) >> 1;
       if ((int64_t)offs[mid] <= e0) lo = mid; else hi = mid;
     }
-    int64_t j = lo;
+    int64_t j = lo, cur = -1;
     const int64_t e1 = min(e0 + kExpandPer, total);
-    uint32_t have = 0xffffffffu;  // item whose record is loaded
+    uint32_t item = 0, tx = 0, ty = 0, tx0 = 0, tx1 = 0, row = 0, base = 0;
     float4 p0, p1, p2, p3;
     for (int64_t e = e0; e < e1; ++e) {
       while (j + 1 < m && (int64_t)offs[j + 1] <= e) ++j;
-      const uint32_t item = items[j];
-      const uint32_t local = (uint32_t)(e - (int64_t)offs[j]);
-      const uint2 r = rects[item];
-      const int tx0 = (int)(r.x & 0xffffu) >> 1, tx1 = (int)(r.x >> 16) >> 1;
-      const int ty0 = (int)(r.y & 0xffffu) >> 1;
-      const uint32_t wt = (uint32_t)(tx1 - tx0 + 1);
-      const ViewDev& V = views[item / (uint32_t)n];
-      const uint32_t ty = ty0 + local / wt, tx = tx0 + local % wt;
-      uint32_t tile = (uint32_t)V.tile_base + ty * (uint32_t)V.tiles_x + tx;
-      if (cull) {
-        if (item != have) {
+      if (j != cur) {
+        cur = j;
+        item = items[j];
+        const uint32_t local = (uint32_t)(e - (int64_t)offs[j]);
+        const uint2 r = rects[item];
+        tx0 = (r.x & 0xffffu) >> 1;
+        tx1 = (r.x >> 16) >> 1;
+        const uint32_t ty0 = (r.y & 0xffffu) >> 1;
+        const uint32_t wt = tx1 - tx0 + 1u;
+        const ViewDev& V = views[item / (uint32_t)n];
+        ty = ty0 + local / wt;
+        tx = tx0 + (local - (ty - ty0) * wt);
+        row = (uint32_t)V.tiles_x;
+        base = (uint32_t)V.tile_base;
+        if (cull) {
           const float4* rp = reinterpret_cast<const float4*>(recs + item);
           p0 = rp[0]; p1 = rp[1]; p2 = rp[2]; p3 = rp[3];
-          have = item;
         }
-        const QuadCone Q = block_cone(V, dtab, (int)tx * kTile, (int)ty * kTile, kTile);
+      } else if (++tx > tx1) {
+        tx = tx0;
+        ++ty;
+      }
+      uint32_t tile = base + ty * row + tx;
+      if (cull) {
+        const float4* cp = tcones + 4 * (size_t)tile;
+        const float4 c0 = cp[0], c1 = cp[1], c2 = cp[2], c3 = cp[3];
+        QuadCone Q;
+        Q.d[0][0] = c0.x; Q.d[0][1] = c0.y; Q.d[0][2] = c0.z;
+        Q.d[1][0] = c1.x; Q.d[1][1] = c1.y; Q.d[1][2] = c1.z;
+        Q.d[2][0] = c2.x; Q.d[2][1] = c2.y; Q.d[2][2] = c2.z;
+        Q.d[3][0] = c3.x; Q.d[3][1] = c3.y; Q.d[3][2] = c3.z;
+        Q.valid = c0.w != 0.0f;
         if (!cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, fixed)) tile = kDropKey;
       }
       const int s = (int)(e - block0);
@@ -480,14 +534,21 @@ void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, 
                      counts, out);
 }
 
+void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,
+                       float4* out) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(tile_cones_kernel, dim3(grid_for(ntiles, kBlock)), dim3(kBlock), 0, st, views, nviews, dtab,
+                     ntiles, out);
+}
+
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
-                   const uint2* rects, const ViewDev* views, int64_t n, const float2* dtab, const Record* recs,
+                   const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
                    const Opts& op, uint32_t* tiles_out, uint32_t* items_out) {
   if (total_cap <= 0) return;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total_cap, (int64_t)kBlock * kExpandPer)), dim3(kBlock), 0, st,
-                     items, offs, m_cap, dyn_m, total_cap, dyn_total, rects, views, n, dtab, recs, op, op.cone_cull,
-                     tiles_out, items_out);
+                     items, offs, m_cap, dyn_m, total_cap, dyn_total, rects, views, n, tcones, recs, op,
+                     op.cone_cull, tiles_out, items_out);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,

@@ -35,9 +35,11 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
                 unsigned long long* kept, unsigned long long* err);
 void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
                           const uint32_t* counts, uint32_t* out);
+void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,
+                       float4* out);
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
-                   const uint2* rects, const ViewDev* views, int64_t n, const float2* dtab, const Record* recs,
+                   const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
                    const Opts& op, uint32_t* tiles_out, uint32_t* items_out);
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
                    int64_t ntiles, uint32_t* ranges);
