@@ -76,8 +76,8 @@ __global__ __launch_bounds__(64) void render_backward_kernel(
   __shared__ float4 s_rec[kWinB][4];
   __shared__ uint32_t s_item[kWinB];
 
-  const WaveBlock W = wave_block(blockIdx.x, gridDim.x, views, nviews, heavy.list, heavy.flag, heavy.count,
-                                 heavy.hmax);
+  const WaveBlock W = wave_block(wave_index(blockIdx.x, gridDim.x, 1, 0, kHeavySplit * heavy.hmax), views, nviews,
+                                 heavy.list, heavy.flag, heavy.count, heavy.hmax);
   if (!W.live) return;
   const ViewDev& V = views[W.v];
   const int tile = W.tile;

@@ -382,22 +382,33 @@ struct WaveBlock {
   bool live;       // false: nothing to do for this wave
 };
 
-__device__ __forceinline__ WaveBlock wave_block(int bid, int nblocks, const ViewDev* __restrict__ views,
-                                                int nviews, const uint32_t* __restrict__ heavy_list,
+// Wave index of wave w of workgroup j (K waves per workgroup, nwg
+// workgroups, the first heavy_waves waves -- a multiple of K -- for heavy
+// tiles).  Ordinary workgroups are banded by XCD as whole workgroups, so the
+// K waves of a workgroup take K consecutive slots of its XCD's band.
+__device__ __forceinline__ int wave_index(int j, int nwg, int K, int w, int heavy_waves) {
+  const int jh = heavy_waves / K;
+  if (j < jh) return j * K + w;
+  return heavy_waves + K * xcd_remap(j - jh, nwg - jh) + w;
+}
+
+// Block of wave index wi (from wave_index).
+__device__ __forceinline__ WaveBlock wave_block(int wi, const ViewDev* __restrict__ views, int nviews,
+                                                const uint32_t* __restrict__ heavy_list,
                                                 const uint32_t* __restrict__ heavy_flag,
                                                 const unsigned long long* __restrict__ heavy_count, int hmax) {
   WaveBlock w;
   w.live = false;
   int sub;
   const int nheavy_blocks = kHeavySplit * hmax;
-  if (bid < nheavy_blocks) {
-    const int h = bid / kHeavySplit;
+  if (wi < nheavy_blocks) {
+    const int h = wi / kHeavySplit;
     if (h >= (int)min(*heavy_count, (unsigned long long)hmax)) return w;
     w.tile = (int)heavy_list[h];
-    sub = bid % kHeavySplit;
+    sub = wi % kHeavySplit;
     w.bs = 4;
   } else {
-    const int hidx = xcd_remap(bid - nheavy_blocks, nblocks - nheavy_blocks);
+    const int hidx = wi - nheavy_blocks;
     w.tile = hidx >> 2;
     if (heavy_flag && heavy_flag[w.tile]) return w;
     sub = hidx & 3;

@@ -28,6 +28,10 @@
 #include "geer_common.h"
 #include "geer_device.h"
 
+#ifndef RENDER_WAVES
+#define RENDER_WAVES 2
+#endif
+
 namespace geer {
 
 // One (ray, Gaussian) evaluation and blend, branch-free: lanes that already
@@ -67,22 +71,26 @@ __device__ __forceinline__ void blend_one(const Record& R, float dx, float dy, f
 
 constexpr int kWin = 64;  // list entries staged per wave pass (one per lane)
 
+constexpr int kRenderWaves = RENDER_WAVES;  // independent waves per workgroup
+
 template <bool kFixed, bool kKeep>
-__global__ __launch_bounds__(64) void render_kernel(
+__global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
     const Record* __restrict__ recs, Opts op, HeavyTiles heavy, float* __restrict__ rgb, float* __restrict__ depth,
     float* __restrict__ trans, uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
     unsigned long long* __restrict__ stats) {
-  __shared__ float4 s_rec[kWin][4];  // this wave's window of records
+  __shared__ float4 s_all[kRenderWaves][kWin][4];  // each wave's own window of records
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  float4(*s_rec)[4] = s_all[wv];
 
-  const WaveBlock W = wave_block(blockIdx.x, gridDim.x, views, nviews, heavy.list, heavy.flag, heavy.count,
-                                 heavy.hmax);
+  const int wi = wave_index(blockIdx.x, gridDim.x, kRenderWaves, wv, kHeavySplit * heavy.hmax);
+  const WaveBlock W = wave_block(wi, views, nviews, heavy.list, heavy.flag, heavy.count, heavy.hmax);
   if (!W.live) return;
   const ViewDev& V = views[W.v];
   const int tile = W.tile;
   const uint32_t hx = (uint32_t)W.bx0 >> 3, hy = (uint32_t)W.by0 >> 3;  // half-tile of the block
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int lb = W.bs == 8 ? 3 : 2;
   const int px = W.bx0 + (lane & (W.bs - 1)), py = W.by0 + (lane >> lb);
   const bool valid = lane < W.bs * W.bs && px < V.width && py < V.height;
@@ -199,10 +207,11 @@ void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const View
                    float* trans, uint32_t* nlast, float* tfinal, unsigned long long* stats) {
   if (ntiles <= 0) return;
   const bool keep = nlast != nullptr && tfinal != nullptr;
-  const unsigned grid = (unsigned)(kHeavySplit * heavy.hmax + 4 * ntiles);
+  // waves: 16 per heavy-tile slot, 4 per tile (both multiples of kRenderWaves)
+  const unsigned grid = (unsigned)((kHeavySplit * heavy.hmax + 4 * ntiles) / kRenderWaves);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWin), 0, st, views, nviews, dtab, ranges, list, rects, recs, op, heavy,
-                       rgb, depth, trans, nlast, tfinal, stats);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kRenderWaves), 0, st, views, nviews, dtab, ranges, list, rects,
+                       recs, op, heavy, rgb, depth, trans, nlast, tfinal, stats);
   };
   if (fixed_lambda) {
     if (keep) go(render_kernel<true, true>);
