@@ -34,55 +34,79 @@ namespace geer {
 constexpr int kWinB = 64;  // list entries staged per wave pass
 constexpr int kAcc = 16;  // accumulator floats per (Gaussian, view) item
 
-// Sum v[0..15] over the wave; lanes with (lane & 3) == 0 end up holding the
-// total of value index idx and add it to dst[idx].
+// Lane exchanges for the reduction: DPP within rows of 16 lanes, and the
+// gfx950 row swaps across rows.
+template <int kCtrl>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xF, 0xF, true));
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowMirror = 0x140;   // lane i <-> 15 - i within each row of 16
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within each half row of 8
+
+// a + b after swapping lanes 32..63 of a with lanes 0..31 of b: lanes below
+// 32 get a summed over the lane pair (i, i + 32), the others b.
+__device__ __forceinline__ float swap32_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// The same with rows of 16: rows 0 and 2 get a summed over (i, i + 16), rows 1 and 3 b.
+__device__ __forceinline__ float swap16_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum v[0..15] over the wave (every lane active) by value splitting: at
+// each level a lane keeps half of its values and adds its partner's partial
+// sums of them (partners differ in the level's lane bit and agree in the
+// bits already split on; the mirrors pair lane i with 15 - i and 7 - i).
+// Lanes with (lane & 3) == 0 end up holding the total of value index idx
+// and add it to dst[idx].
 __device__ __forceinline__ void wave_reduce16_add(const float v[16], float* __restrict__ dst) {
   const int lane = threadIdx.x & 63;
   const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8, h4 = lane & 4;
   float a8[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const float send = h32 ? v[j] : v[8 + j];
-    const float keep = h32 ? v[8 + j] : v[j];
-    a8[j] = keep + __shfl_xor(send, 32);
-  }
+  for (int j = 0; j < 8; ++j) a8[j] = swap32_add(v[j], v[8 + j]);  // lanes >= 32 hold values 8..15
   float a4[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const float send = h16 ? a8[j] : a8[4 + j];
-    const float keep = h16 ? a8[4 + j] : a8[j];
-    a4[j] = keep + __shfl_xor(send, 16);
-  }
+  for (int j = 0; j < 4; ++j) a4[j] = swap16_add(a8[j], a8[4 + j]);  // odd rows hold the upper half
   float a2[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const float send = h8 ? a4[j] : a4[2 + j];
     const float keep = h8 ? a4[2 + j] : a4[j];
-    a2[j] = keep + __shfl_xor(send, 8);
+    a2[j] = keep + dpp<kDppRowMirror>(send);
   }
-  float a1 = (h4 ? a2[1] : a2[0]) + __shfl_xor(h4 ? a2[0] : a2[1], 4);
-  a1 += __shfl_xor(a1, 2);
-  a1 += __shfl_xor(a1, 1);
+  float a1 = (h4 ? a2[1] : a2[0]) + dpp<kDppHalfMirror>(h4 ? a2[0] : a2[1]);
+  a1 += dpp<kDppXor1>(a1);
+  a1 += dpp<kDppXor2>(a1);
   const int idx = (h32 ? 8 : 0) + (h16 ? 4 : 0) + (h8 ? 2 : 0) + (h4 ? 1 : 0);
   if ((lane & 3) == 0 && a1 != 0.0f) unsafeAtomicAdd(dst + idx, a1);
 }
 
+constexpr int kBackWaves = 2;  // independent waves per workgroup
+
 template <bool kFixed>
-__global__ __launch_bounds__(64) void render_backward_kernel(
+__global__ __launch_bounds__(64 * kBackWaves) void render_backward_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
     const Record* __restrict__ recs, Opts op, HeavyTiles heavy, const uint32_t* __restrict__ nlast,
     const float* __restrict__ tfinal, const float* __restrict__ dl_drgb, float* __restrict__ acc) {
-  __shared__ float4 s_rec[kWinB][4];
-  __shared__ uint32_t s_item[kWinB];
+  __shared__ float4 s_rec_all[kBackWaves][kWinB][4];  // each wave's own window
+  __shared__ uint32_t s_item_all[kBackWaves][kWinB];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  float4(*s_rec)[4] = s_rec_all[wv];
+  uint32_t* s_item = s_item_all[wv];
 
-  const WaveBlock W = wave_block(wave_index(blockIdx.x, gridDim.x, 1, 0, kHeavySplit * heavy.hmax), views, nviews,
-                                 heavy.list, heavy.flag, heavy.count, heavy.hmax);
+  const WaveBlock W = wave_block(wave_index(blockIdx.x, gridDim.x, kBackWaves, wv, kHeavySplit * heavy.hmax), views,
+                                 nviews, heavy.list, heavy.flag, heavy.count, heavy.hmax);
   if (!W.live) return;
   const ViewDev& V = views[W.v];
   const int tile = W.tile;
   const uint32_t hx = (uint32_t)W.bx0 >> 3, hy = (uint32_t)W.by0 >> 3;  // half-tile of the block
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int lb = W.bs == 8 ? 3 : 2;
   const int px = W.bx0 + (lane & (W.bs - 1)), py = W.by0 + (lane >> lb);
   const bool valid = lane < W.bs * W.bs && px < V.width && py < V.height;
@@ -158,7 +182,7 @@ __global__ __launch_bounds__(64) void render_backward_kernel(
       if (__ballot(on) == 0) continue;
       const float a = clamp_alpha(E.a_raw, op);
       const bool clamped = !(E.a_raw < op.alpha_max);
-      const float Tb = on ? T / (1.0f - a) : T;  // transmittance in front of this Gaussian
+      const float Tb = on ? T * __builtin_amdgcn_rcpf(1.0f - a) : T;  // transmittance in front of this Gaussian
       const float w = on ? a * Tb : 0.0f;
       float part[kAcc];
       part[1] = w * G0;
@@ -171,7 +195,7 @@ __global__ __launch_bounds__(64) void render_backward_kernel(
       T = Tb;
       const float dlk = clamped ? 0.0f : -0.5f * a * dla;  // dL/dkappa
       part[0] = clamped ? 0.0f : dla * a;                  // dL/dlog(sigma)
-      const float r = sqrtf(R.c1);
+      const float r = __builtin_amdgcn_sqrtf(R.c1);
       const float f = 2.0f * r * E.inv * dlk;               // dL/dkappa * 2 r / ss
       part[4] = f * E.gx * E.gz;
       part[5] = f * E.gy * E.gz;
@@ -337,13 +361,14 @@ void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, i
                             const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
                             const float* tfinal, const float* dl_drgb, float* acc) {
   if (ntiles <= 0) return;
-  const unsigned grid = (unsigned)(kHeavySplit * heavy.hmax + 4 * ntiles);
+  // waves: 16 per heavy-tile slot, 4 per tile (both multiples of kBackWaves)
+  const unsigned grid = (unsigned)((kHeavySplit * heavy.hmax + 4 * ntiles) / kBackWaves);
   if (fixed_lambda)
-    hipLaunchKernelGGL(render_backward_kernel<true>, dim3(grid), dim3(kWinB), 0, st, views, n_views, dtab, ranges, list,
-                       rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
+    hipLaunchKernelGGL(render_backward_kernel<true>, dim3(grid), dim3(64 * kBackWaves), 0, st, views, n_views, dtab,
+                       ranges, list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
   else
-    hipLaunchKernelGGL(render_backward_kernel<false>, dim3(grid), dim3(kWinB), 0, st, views, n_views, dtab, ranges,
-                       list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
+    hipLaunchKernelGGL(render_backward_kernel<false>, dim3(grid), dim3(64 * kBackWaves), 0, st, views, n_views, dtab,
+                       ranges, list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
 }
 
 void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
