@@ -287,6 +287,7 @@ struct FwdBufs {
   uint32_t *heavy_list = nullptr, *heavy_flag = nullptr;  // heavy-tile work list
   int hmax = 0;
   float4* tcones = nullptr;  // per-tile corner cones of the expansion's cull (4 float4 per tile)
+  uint32_t* hparts = nullptr;  // partial tile-digit histograms filled by the expansion
   HeavyTiles heavy() const { return HeavyTiles{heavy_list, heavy_flag, (unsigned long long*)(stats + 6), hmax}; }
 };
 
@@ -328,10 +329,14 @@ void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t item
     uint32_t* at = (passes % 2 == 1) ? pt : qt;
     uint32_t* ai = (passes % 2 == 1) ? pi : qi;
     if (op.cone_cull) launch_tile_cones(st, b.views, n > 0 ? (int)(items / n) : 1, b.dtab, ntiles, b.tcones);
+    // the expansion also counts the tile digits of the kept entries (one or
+    // two passes), which replaces the sort's histogram pass over the list
+    const int hpass = passes <= 2 ? passes : 0;
+    if (hpass) launch_fill_u32(st, b.hparts, hist_parts_words(), 0u);
     launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, b.tcones, b.recs, op, tin,
-                  iin);
+                  iin, b.hparts, hpass);
     radix_sort(st, tin, iin, nullptr, op.cone_cull != 0, ecap, dE, ecap, kept, 0, passes, at, ai, tin, iin, b.hist,
-               kept, err);
+               kept, err, hpass ? b.hparts : nullptr);
     uint32_t* tfinal = (passes % 2 == 1) ? at : tin;
     launch_pad_list(st, b.list, ecap, kept);
     launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges);
@@ -510,9 +515,10 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   f->dtab_off = tab.dtab_off;
 
   // Temporaries of the sort; released at the end of the call.
-  Block ka, va, kb, vb, hist, scratch, tiles_a, tiles_b, items_b, cnt_sorted, tcones;
+  Block ka, va, kb, vb, hist, scratch, tiles_a, tiles_b, items_b, cnt_sorted, tcones, hparts;
   auto cleanup = [&](geer_status st_) {
-    for (Block* b : {&ka, &va, &kb, &vb, &hist, &scratch, &tiles_a, &tiles_b, &items_b, &cnt_sorted, &tcones})
+    for (Block* b :
+         {&ka, &va, &kb, &vb, &hist, &scratch, &tiles_a, &tiles_b, &items_b, &cnt_sorted, &tcones, &hparts})
       release(c, *b);
     if (st_ != GEER_OK) {
       free_frame_buffers(f);
@@ -587,6 +593,8 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   TRY(acquire(c, 4 * (ntiles + 1), st, f->ranges));
   TRY(acquire(c, 64 * (size_t)std::max<int64_t>(ntiles, 1), st, tcones));
   b.tcones = (float4*)tcones.p;
+  TRY(acquire(c, 4 * (size_t)hist_parts_words(), st, hparts));
+  b.hparts = (uint32_t*)hparts.p;
   b.ka = (uint32_t*)ka.p; b.va = (uint32_t*)va.p; b.kb = (uint32_t*)kb.p; b.vb = (uint32_t*)vb.p;
   b.hist = (uint32_t*)hist.p; b.scratch = (uint32_t*)scratch.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
   b.tiles_a = (uint32_t*)tiles_a.p; b.tiles_b = (uint32_t*)tiles_b.p; b.items_b = (uint32_t*)items_b.p;
@@ -815,7 +823,7 @@ geer_status geer_l1_loss(geer_ctx* c, int64_t pixels, const float* rgb, const fl
 struct PlanLayout {
   size_t meta = 0, recs = 0, rects = 0, keys = 0, counts = 0, stats = 0, ka = 0, va = 0, kb = 0, vb = 0, hist = 0,
          scratch = 0, cnt_sorted = 0, tiles_a = 0, tiles_b = 0, items_b = 0, list = 0, ranges = 0, heavy_list = 0,
-         heavy_flag = 0, tcones = 0, total = 0;
+         heavy_flag = 0, tcones = 0, hparts = 0, total = 0;
 };
 
 // pre_items (default: items) sizes the per-item outputs of the preprocess.
@@ -851,6 +859,7 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
   L.heavy_list = put(4 * (size_t)heavy_capacity(ntiles));
   L.heavy_flag = put(4 * (size_t)ntiles);
   L.tcones = put(64 * (size_t)std::max<int64_t>(ntiles, 1));
+  L.hparts = put(4 * (size_t)hist_parts_words());
   L.total = off;
   return L;
 }
@@ -959,6 +968,7 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
   b.heavy_list = (uint32_t*)(w + lay.heavy_list);
   b.heavy_flag = (uint32_t*)(w + lay.heavy_flag);
   b.tcones = (float4*)(w + lay.tcones);
+  b.hparts = (uint32_t*)(w + lay.hparts);
   b.hmax = heavy_capacity(P->ntiles);
   for (int k = 0; k < 2; ++k) {
     PHIP(hipHostMalloc(&P->staging[k], std::max<size_t>(tab.bytes, 64), hipHostMallocDefault));
@@ -1168,6 +1178,7 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
   b.heavy_list = (uint32_t*)(w + F.heavy_list);
   b.heavy_flag = (uint32_t*)(w + F.heavy_flag);
   b.tcones = (float4*)(w + F.tcones);
+  b.hparts = (uint32_t*)(w + F.hparts);
   b.hmax = heavy_capacity(S.ntiles_max);
   b.nlast = (uint32_t*)(w + lay.nlast);
   b.tfinal = (float*)(w + lay.tfinal);

@@ -291,6 +291,35 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
   }
 }
 
+// Partial digit histograms filled by a producer kernel: kHistCopies copies
+// (block b adds to copy b % kHistCopies), each with 256 words per pass for
+// up to kHistPasses passes and the count of kept keys at kHistKept.
+constexpr int kHistCopies = 64;
+constexpr int kHistPasses = 2;
+constexpr int kHistKept = 256 * kHistPasses;
+constexpr int kHistStride = kHistKept + 8;
+
+int hist_parts_words() { return kHistCopies * kHistStride; }
+
+// Writes the sort's work head and first status table: the pass histograms
+// summed over the copies, zero elsewhere; *kept = the summed kept count.
+__global__ __launch_bounds__(kBlock) void hist_prepare_kernel(uint32_t* __restrict__ work, int64_t nwords,
+                                                              const uint32_t* __restrict__ hparts, int npass,
+                                                              unsigned long long* __restrict__ kept) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nwords) return;
+  uint32_t v = 0u;
+  if (i < 256 * npass) {
+    for (int c = 0; c < kHistCopies; ++c) v += hparts[c * kHistStride + i];
+  }
+  work[i] = v;
+  if (i == 0 && kept) {
+    unsigned long long k = 0;
+    for (int c = 0; c < kHistCopies; ++c) k += hparts[c * kHistStride + kHistKept];
+    *kept = k;
+  }
+}
+
 // ------------------------------------------------------------ expansion --
 
 __global__ __launch_bounds__(kBlock) void gather_counts_kernel(const uint32_t* __restrict__ items, int64_t m_cap,
@@ -340,11 +369,21 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
                                                         const float4* __restrict__ tcones,
                                                         const Record* __restrict__ recs, Opts op, int cull,
                                                         uint32_t* __restrict__ tiles_out,
-                                                        uint32_t* __restrict__ items_out) {
+                                                        uint32_t* __restrict__ items_out,
+                                                        uint32_t* __restrict__ hparts, int hpass) {
   const int64_t m = dyn_count(m_cap, dyn_m);
   const int64_t total = dyn_count(total_cap, dyn_total);
   __shared__ uint32_t s_tile[kBlock * kExpandPer];
   __shared__ uint32_t s_item[kBlock * kExpandPer];
+  __shared__ uint32_t s_h[kHistPasses][256];  // this block's digit counts of the kept tile ids
+  __shared__ uint32_t s_kept;
+  if (hpass) {
+#pragma unroll
+    for (int p = 0; p < kHistPasses; ++p) s_h[p][threadIdx.x] = 0u;
+    if (threadIdx.x == 0) s_kept = 0u;
+    __syncthreads();
+  }
+  uint32_t my_kept = 0u, run_d = 0u, run_n = 0u;  // run of equal upper digits along this lane's entries
   const int64_t block0 = (int64_t)blockIdx.x * kBlock * kExpandPer;
   const int64_t e0 = block0 + (int64_t)threadIdx.x * kExpandPer;
   const bool fixed = op.lambda_mode == 1;
@@ -395,12 +434,37 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
         Q.valid = c0.w != 0.0f;
         if (!cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, fixed)) tile = kDropKey;
       }
+      if (hpass && tile != kDropKey) {
+        ++my_kept;
+        atomicAdd(&s_h[0][tile & 255u], 1u);
+        if (hpass > 1) {
+          const uint32_t d1 = (tile >> 8) & 255u;
+          if (d1 != run_d) {
+            if (run_n) atomicAdd(&s_h[1][run_d], run_n);
+            run_d = d1;
+            run_n = 0u;
+          }
+          ++run_n;
+        }
+      }
       const int s = (int)(e - block0);
       s_tile[s] = tile;
       s_item[s] = item;
     }
   }
+  if (hpass) {
+    if (run_n) atomicAdd(&s_h[1][run_d], run_n);
+    if (my_kept) atomicAdd(&s_kept, my_kept);
+  }
   __syncthreads();
+  if (hpass) {
+    uint32_t* hp = hparts + (blockIdx.x % kHistCopies) * kHistStride;
+    for (int p = 0; p < hpass; ++p) {
+      const uint32_t c = s_h[p][threadIdx.x];
+      if (c) atomicAdd(&hp[p * 256 + threadIdx.x], c);
+    }
+    if (threadIdx.x == 0 && s_kept) atomicAdd(&hp[kHistKept], s_kept);
+  }
 #pragma unroll
   for (int k = 0; k < kExpandPer; ++k) {
     const int s = k * kBlock + threadIdx.x;
@@ -498,20 +562,27 @@ int64_t radix_work_words(int64_t n_cap) { return kWorkHead + 2 * 256 * ((n_cap +
 void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, bool drop,
                 int64_t n0_cap, const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1,
                 int shift0, int npass, uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work,
-                unsigned long long* kept, unsigned long long* err) {
+                unsigned long long* kept, unsigned long long* err, const uint32_t* hparts) {
   if (n0_cap <= 0 || npass <= 0) return;
   const int64_t nmax = std::max(n0_cap, n1_cap);
   const int64_t rows = 256 * ((nmax + kOSItems - 1) / kOSItems);
   uint32_t* ghist = work;
   uint32_t* tickets = work + 1024;
   uint32_t* stat[2] = {work + kWorkHead, work + kWorkHead + rows};
-  // histograms, tickets and the first status table start at zero
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
-                     (int64_t)kWorkHead + rows, 0u);
-  // few blocks: every block adds its counts to the same 256 words per pass
-  const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(n0_cap, kBlock), 1), 256);
-  hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, in_k, filter, drop ? 1 : 0, n0_cap, dyn0,
-                     shift0, npass, ghist, kept);
+  if (hparts) {
+    // the producer already counted the digits into partial histograms:
+    // sum them into the histograms, clear tickets and the first status table
+    hipLaunchKernelGGL(hist_prepare_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
+                       (int64_t)kWorkHead + rows, hparts, npass, kept);
+  } else {
+    // histograms, tickets and the first status table start at zero
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
+                       (int64_t)kWorkHead + rows, 0u);
+    // few blocks: every block adds its counts to the same 256 words per pass
+    const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(n0_cap, kBlock), 1), 256);
+    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, in_k, filter, drop ? 1 : 0, n0_cap,
+                       dyn0, shift0, npass, ghist, kept);
+  }
   const uint32_t *sk = in_k, *sv = in_v;
   for (int p = 0; p < npass; ++p) {
     uint32_t* ok = (p % 2 == 0) ? ak : bk;
@@ -544,11 +615,11 @@ void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const f
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
-                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out) {
+                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* hparts, int hpass) {
   if (total_cap <= 0) return;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total_cap, (int64_t)kBlock * kExpandPer)), dim3(kBlock), 0, st,
                      items, offs, m_cap, dyn_m, total_cap, dyn_total, rects, views, n, tcones, recs, op,
-                     op.cone_cull, tiles_out, items_out);
+                     op.cone_cull, tiles_out, items_out, hparts, hpass);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
