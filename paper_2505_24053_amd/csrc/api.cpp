@@ -259,13 +259,18 @@ void prof_mark(ProfSlot* s, int i, hipStream_t st) {
   if (s) (void)hipEventRecord(s->ev[i], st);
 }
 
-int bytes_for_tiles(int64_t max_tile) {
-  int passes = 0;
-  while (max_tile > 0) {
-    ++passes;
-    max_tile >>= 8;
-  }
-  return passes;
+// Digits of the tile sort: tile ids 0..ntiles-1 take `bits` significant
+// bits, sorted in ceil(bits / 8) passes of equal width (e.g. 13 bits as
+// 7 + 7 rather than 8 + 5), so no pass scatters over more buckets than
+// needed.
+struct TileDigits {
+  int passes, bits;
+};
+TileDigits tile_digits(int64_t ntiles) {
+  int tbits = 1;
+  while (tbits < 32 && ((int64_t)1 << tbits) < ntiles) ++tbits;
+  const int passes = (tbits + 7) / 8;
+  return TileDigits{passes, (tbits + passes - 1) / passes};
 }
 
 
@@ -322,7 +327,8 @@ void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t item
     // arranged so that the sorted items end in b.list: pair P = (tiles_b,
     // list), Q = (tiles_a, items_b); odd pass counts run Q -> P -> Q ...,
     // even ones P -> Q -> P ...
-    const int passes = std::max(1, bytes_for_tiles(ntiles - 1));
+    const TileDigits td = tile_digits(ntiles);
+    const int passes = td.passes;
     uint32_t *pt = b.tiles_b, *pi = b.list, *qt = b.tiles_a, *qi = b.items_b;
     uint32_t* tin = (passes % 2 == 1) ? qt : pt;
     uint32_t* iin = (passes % 2 == 1) ? qi : pi;
@@ -334,9 +340,9 @@ void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t item
     const int hpass = passes <= 2 ? passes : 0;
     if (hpass) launch_fill_u32(st, b.hparts, hist_parts_words(), 0u);
     launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, b.tcones, b.recs, op, tin,
-                  iin, b.hparts, hpass);
+                  iin, b.hparts, hpass, td.bits);
     radix_sort(st, tin, iin, nullptr, op.cone_cull != 0, ecap, dE, ecap, kept, 0, passes, at, ai, tin, iin, b.hist,
-               kept, err, hpass ? b.hparts : nullptr);
+               kept, err, hpass ? b.hparts : nullptr, td.bits);
     uint32_t* tfinal = (passes % 2 == 1) ? at : tin;
     launch_pad_list(st, b.list, ecap, kept);
     launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges);

@@ -109,13 +109,15 @@ __device__ __forceinline__ int64_t dyn_count(int64_t n_cap, const unsigned long 
 // stall through an error word instead of hanging.
 
 constexpr int kLookBack = 16;  // statuses read per look-back round
-constexpr int kOSPer = 8;                       // keys per thread
-constexpr int kOSItems = kBlock * kOSPer;       // 2048 keys per block
+constexpr int kOSPer = 8;                       // keys per thread (small sorts)
+constexpr int kOSItems = kBlock * kOSPer;       // 2048 keys per block: the smallest chunk
+constexpr int kOSPerBig = 16;                   // keys per thread from kOSBigKeys keys on
+constexpr int64_t kOSBigKeys = 1 << 20;
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr int kWorkHead = 1024 + 64;            // histograms of 4 passes + 4 tickets (padded)
 
-__device__ __forceinline__ int64_t os_blocks(int64_t n) { return (n + kOSItems - 1) / kOSItems; }
+__host__ __device__ __forceinline__ int64_t os_blocks(int64_t n, int items) { return (n + items - 1) / items; }
 
 // Exclusive scan of one value per thread over a 256-lane block; also returns
 // the block total.  Uses s_w[4].
@@ -140,8 +142,10 @@ __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* _
                                                                const uint32_t* __restrict__ filter, int drop,
                                                                int64_t n_cap,
                                                                const unsigned long long* __restrict__ dyn,
-                                                               int shift0, int npass, uint32_t* __restrict__ ghist,
+                                                               int shift0, int bits, int npass,
+                                                               uint32_t* __restrict__ ghist,
                                                                unsigned long long* __restrict__ kept) {
+  const uint32_t dmask = (1u << bits) - 1u;
   const int64_t n = dyn_count(n_cap, dyn);
   __shared__ uint32_t h[4][256];
   __shared__ uint32_t s_kept;
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* _
     const uint32_t k = keys[i];
     if (drop && k == kDropKey) continue;
     ++mine;
-    for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (shift0 + 8 * p)) & 255u], 1u);
+    for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (shift0 + bits * p)) & dmask], 1u);
   }
   if (kept && mine) atomicAdd(&s_kept, mine);
   __syncthreads();
@@ -166,15 +170,18 @@ __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* _
   if (kept && threadIdx.x == 0 && s_kept) atomicAdd(kept, (unsigned long long)s_kept);
 }
 
+template <int kPer>
 __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, const uint32_t* __restrict__ filter,
-    int drop, int64_t n_cap, const unsigned long long* __restrict__ dyn, int shift, const uint32_t* __restrict__ ghist_p,
+    int drop, int64_t n_cap, const unsigned long long* __restrict__ dyn, int shift, uint32_t dmask,
+    const uint32_t* __restrict__ ghist_p,
     uint32_t* __restrict__ status, uint32_t* __restrict__ status_next, uint32_t* __restrict__ ticket,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, unsigned long long* __restrict__ err) {
   __shared__ uint32_t s_cnt[4][256];  // per-wave running digit counts, then per-wave offsets
   __shared__ uint32_t s_loc[256];     // block-local start of each digit
   __shared__ uint32_t s_glob[256];    // global start of this block's run of each digit
-  __shared__ uint32_t s_key[kOSItems], s_val[kOSItems];
+  constexpr int kItems = kBlock * kPer;
+  __shared__ uint32_t s_key[kItems], s_val[kItems];
   __shared__ uint32_t s_w[4];
   __shared__ uint32_t s_blk;
 
@@ -185,22 +192,22 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
   __syncthreads();
   const int64_t blk = s_blk;
   const int64_t n = dyn_count(n_cap, dyn);
-  if (blk >= os_blocks(n)) return;
+  if (blk >= os_blocks(n, kItems)) return;
   if (status_next) status_next[blk * 256 + tid] = 0u;  // this row is clear for the next pass
 
-  // stable ranks within the wave: wave w owns keys [base, base + 64 kOSPer)
-  const int64_t base = blk * kOSItems + (int64_t)w * 64 * kOSPer;
+  // stable ranks within the wave: wave w owns keys [base, base + 64 kPer)
+  const int64_t base = blk * kItems + (int64_t)w * 64 * kPer;
   const uint64_t lt = lanemask_lt();
-  uint32_t key[kOSPer], val[kOSPer], rank[kOSPer];
+  uint32_t key[kPer], val[kPer], rank[kPer];
   uint32_t act = 0u;
 #pragma unroll
-  for (int sl = 0; sl < kOSPer; ++sl) {
+  for (int sl = 0; sl < kPer; ++sl) {
     const int64_t i = base + sl * 64 + lane;
     bool a = i < n && (!filter || filter[i] != 0u);
     key[sl] = a ? keys_in[i] : 0u;
     if (drop) a = a && key[sl] != kDropKey;
     val[sl] = a ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
-    const uint32_t d = (key[sl] >> shift) & 255u;
+    const uint32_t d = (key[sl] >> shift) & dmask;
     uint64_t m = __builtin_amdgcn_ballot_w64(a);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -273,9 +280,9 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
 
   // reorder by digit in LDS, then write contiguous runs
 #pragma unroll
-  for (int sl = 0; sl < kOSPer; ++sl) {
+  for (int sl = 0; sl < kPer; ++sl) {
     if ((act >> sl) & 1u) {
-      const uint32_t d = (key[sl] >> shift) & 255u;
+      const uint32_t d = (key[sl] >> shift) & dmask;
       const uint32_t lp = s_loc[d] + s_cnt[w][d] + rank[sl];
       s_key[lp] = key[sl];
       s_val[lp] = val[sl];
@@ -284,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
   __syncthreads();
   for (uint32_t i = tid; i < ltotal; i += kBlock) {
     const uint32_t k = s_key[i];
-    const uint32_t d = (k >> shift) & 255u;
+    const uint32_t d = (k >> shift) & dmask;
     const uint32_t g = s_glob[d] + (i - s_loc[d]);
     keys_out[g] = k;
     vals_out[g] = s_val[i];
@@ -370,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
                                                         const Record* __restrict__ recs, Opts op, int cull,
                                                         uint32_t* __restrict__ tiles_out,
                                                         uint32_t* __restrict__ items_out,
-                                                        uint32_t* __restrict__ hparts, int hpass) {
+                                                        uint32_t* __restrict__ hparts, int hpass, int hbits) {
   const int64_t m = dyn_count(m_cap, dyn_m);
   const int64_t total = dyn_count(total_cap, dyn_total);
   __shared__ uint32_t s_tile[kBlock * kExpandPer];
@@ -436,9 +443,9 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
       }
       if (hpass && tile != kDropKey) {
         ++my_kept;
-        atomicAdd(&s_h[0][tile & 255u], 1u);
+        atomicAdd(&s_h[0][tile & ((1u << hbits) - 1u)], 1u);
         if (hpass > 1) {
-          const uint32_t d1 = (tile >> 8) & 255u;
+          const uint32_t d1 = tile >> hbits;  // a kept tile id has at most 2 hbits bits
           if (d1 != run_d) {
             if (run_n) atomicAdd(&s_h[1][run_d], run_n);
             run_d = d1;
@@ -562,10 +569,15 @@ int64_t radix_work_words(int64_t n_cap) { return kWorkHead + 2 * 256 * ((n_cap +
 void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, bool drop,
                 int64_t n0_cap, const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1,
                 int shift0, int npass, uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work,
-                unsigned long long* kept, unsigned long long* err, const uint32_t* hparts) {
+                unsigned long long* kept, unsigned long long* err, const uint32_t* hparts, int bits) {
   if (n0_cap <= 0 || npass <= 0) return;
   const int64_t nmax = std::max(n0_cap, n1_cap);
-  const int64_t rows = 256 * ((nmax + kOSItems - 1) / kOSItems);
+  // chunks of 4096 keys for large sorts: runs of one digit per chunk are
+  // twice as long, so the scattered writes cover more of each cache line
+  const bool big = nmax >= kOSBigKeys;
+  const int items = kBlock * (big ? kOSPerBig : kOSPer);
+  const int64_t rows = 256 * os_blocks(nmax, items);
+  const uint32_t dmask = (1u << bits) - 1u;
   uint32_t* ghist = work;
   uint32_t* tickets = work + 1024;
   uint32_t* stat[2] = {work + kWorkHead, work + kWorkHead + rows};
@@ -581,7 +593,7 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
     // few blocks: every block adds its counts to the same 256 words per pass
     const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(n0_cap, kBlock), 1), 256);
     hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, in_k, filter, drop ? 1 : 0, n0_cap,
-                       dyn0, shift0, npass, ghist, kept);
+                       dyn0, shift0, bits, npass, ghist, kept);
   }
   const uint32_t *sk = in_k, *sv = in_v;
   for (int p = 0; p < npass; ++p) {
@@ -589,9 +601,10 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
     uint32_t* ov = (p % 2 == 0) ? av : bv;
     const int64_t ncap = p == 0 ? n0_cap : n1_cap;
     const unsigned long long* dy = p == 0 ? dyn0 : dyn1;
-    const unsigned nb = (unsigned)std::max<int64_t>((ncap + kOSItems - 1) / kOSItems, 1);
-    hipLaunchKernelGGL(radix_onesweep_kernel, dim3(nb), dim3(kBlock), 0, st, sk, sv, p == 0 ? filter : nullptr,
-                       (p == 0 && drop) ? 1 : 0, ncap, dy, shift0 + 8 * p, (const uint32_t*)(ghist + 256 * p), stat[p % 2],
+    const unsigned nb = (unsigned)std::max<int64_t>(os_blocks(ncap, items), 1);
+    auto kern = big ? radix_onesweep_kernel<kOSPerBig> : radix_onesweep_kernel<kOSPer>;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, sk, sv, p == 0 ? filter : nullptr, (p == 0 && drop) ? 1 : 0,
+                       ncap, dy, shift0 + bits * p, dmask, (const uint32_t*)(ghist + 256 * p), stat[p % 2],
                        p + 1 < npass ? stat[(p + 1) % 2] : nullptr, tickets + p, ok, ov, err);
     sk = ok;
     sv = ov;
@@ -615,11 +628,12 @@ void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const f
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
-                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* hparts, int hpass) {
+                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* hparts, int hpass,
+                   int hbits) {
   if (total_cap <= 0) return;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total_cap, (int64_t)kBlock * kExpandPer)), dim3(kBlock), 0, st,
                      items, offs, m_cap, dyn_m, total_cap, dyn_total, rects, views, n, tcones, recs, op,
-                     op.cone_cull, tiles_out, items_out, hparts, hpass);
+                     op.cone_cull, tiles_out, items_out, hparts, hpass, hbits);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,

@@ -33,7 +33,7 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
                 int64_t n0_cap, const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1,
                 int shift0, int npass, uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work,
                 unsigned long long* kept, unsigned long long* err,
-                const uint32_t* hparts = nullptr);
+                const uint32_t* hparts = nullptr, int bits = 8);
 void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
                           const uint32_t* counts, uint32_t* out);
 void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,
@@ -41,7 +41,8 @@ void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const f
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
-                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* hparts, int hpass);
+                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* hparts, int hpass,
+                   int hbits);
 int hist_parts_words();
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
                    int64_t ntiles, uint32_t* ranges);
