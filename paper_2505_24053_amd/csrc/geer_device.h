@@ -38,11 +38,15 @@ __device__ __forceinline__ float pad_of(float x) {
   return s * 0x1p-14f;
 }
 
+// Union of the cells met by np <= 2 intervals [a[p], b[p]] (the loop runs
+// over the fixed maximum so that a and b stay in registers).
 __device__ __forceinline__ bool pieces_range(const float* __restrict__ e, int n, int np, const float* a,
                                              const float* b, int& c0, int& c1) {
   int lo = n, hi = -1;
   bool any = false;
-  for (int p = 0; p < np; ++p) {
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (p >= np) break;
     int x0 = first_cell(e, n, a[p]);
     int x1 = last_cell(e, n, b[p]);
     if (x0 <= x1) {
@@ -303,21 +307,30 @@ __device__ __forceinline__ int sh_basis(int deg, const float v[3], float B[16], 
 }
 
 // Orthonormal pair (e1, e2) completing n, built in the frame where n's
-// largest component plays the role of z (Duff et al. 2017 branchless basis),
-// so that every entry is accurate relative to n's small components.
+// largest component k plays the role of z (Duff et al. 2017 branchless
+// basis), so that every entry is accurate relative to n's small components.
+// The other two components, in order, play x and y.  Components are moved
+// with selects rather than an index, which keeps them in registers.
 __device__ __forceinline__ void ortho_basis(const float n[3], float e1[3], float e2[3]) {
-  float ax = fabsf(n[0]), ay = fabsf(n[1]), az = fabsf(n[2]);
-  int k = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
-  int a = k == 0 ? 1 : 0;
-  int b = k == 2 ? 1 : 2;
-  float x = n[a], y = n[b], z = n[k];
-  float sg = copysignf(1.0f, z);
-  float p = -1.0f / (sg + z);
-  float q = x * y * p;
-  float u[3] = {1.0f + sg * x * x * p, sg * q, -sg * x};
-  float w[3] = {q, sg + y * y * p, -y};
-  e1[a] = u[0]; e1[b] = u[1]; e1[k] = u[2];
-  e2[a] = w[0]; e2[b] = w[1]; e2[k] = w[2];
+  const float ax = fabsf(n[0]), ay = fabsf(n[1]), az = fabsf(n[2]);
+  const bool k0 = ax > ay && ax > az;   // k = 0
+  const bool k2 = !k0 && !(ay > az);    // k = 2 (else k = 1)
+  const float x = k0 ? n[1] : n[0];
+  const float y = k2 ? n[1] : n[2];
+  const float z = k0 ? n[0] : (k2 ? n[2] : n[1]);
+  const float sg = copysignf(1.0f, z);
+  const float p = -__builtin_amdgcn_rcpf(sg + z);
+  const float q = x * y * p;
+  const float u0 = 1.0f + sg * x * x * p, u1 = sg * q, u2 = -sg * x;
+  const float w0 = q, w1 = sg + y * y * p, w2 = -y;
+  // component 0 is x unless k = 0; component 1 is x (k = 0), y (k = 2) or z;
+  // component 2 is y unless k = 2
+  e1[0] = k0 ? u2 : u0;
+  e1[1] = k0 ? u0 : (k2 ? u1 : u2);
+  e1[2] = k2 ? u2 : u1;
+  e2[0] = k0 ? w2 : w0;
+  e2[1] = k0 ? w0 : (k2 ? w1 : w2);
+  e2[2] = k2 ? w2 : w1;
 }
 
 // Rotated canonical frame of one (Gaussian, view) item: Wc = S^-1 A^T maps a
@@ -332,9 +345,11 @@ struct Frame3 {
 
 __device__ __forceinline__ void canonical_frame(const AssocOut& A, const float s[3], Frame3& F) {
 #pragma unroll
-  for (int kk = 0; kk < 3; ++kk)
+  for (int kk = 0; kk < 3; ++kk) {
+    const float is = __builtin_amdgcn_rcpf(s[kk]);
 #pragma unroll
-    for (int ii = 0; ii < 3; ++ii) F.Wc[kk * 3 + ii] = A.A[ii * 3 + kk] / s[kk];
+    for (int ii = 0; ii < 3; ++ii) F.Wc[kk * 3 + ii] = A.A[ii * 3 + kk] * is;
+  }
   F.ou[0] = -A.vou[0]; F.ou[1] = -A.vou[1]; F.ou[2] = -A.vou[2];
   F.r2 = F.ou[0] * F.ou[0] + F.ou[1] * F.ou[1] + F.ou[2] * F.ou[2];
   const float rinv = rsqrtf(F.r2);

@@ -48,8 +48,9 @@ __device__ __forceinline__ void block_add_totals(unsigned long long e, unsigned 
   }
 }
 
+template <int kDeg>
 __global__ __launch_bounds__(256) void preprocess_kernel(
-    int64_t n, int32_t n_views, int32_t sh_degree, const float* __restrict__ mean, const float* __restrict__ scale,
+    int64_t n, int32_t n_views, const float* __restrict__ mean, const float* __restrict__ scale,
     const float* __restrict__ quat, const float* __restrict__ opacity, const float* __restrict__ sh,
     const ViewDev* __restrict__ views, Opts op, const float* __restrict__ lam_tab,
     const float* __restrict__ edges, Record* __restrict__ recs, uint2* __restrict__ rects,
@@ -110,8 +111,10 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
       const float dinv = rsqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
       const float vdir[3] = {dv[0] * dinv, dv[1] * dinv, dv[2] * dinv};
       float B[16];
-      const int K = sh_basis(sh_degree, vdir, B, nullptr);
+      sh_basis(kDeg, vdir, B, nullptr);
+      constexpr int K = (kDeg + 1) * (kDeg + 1);
       float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
       for (int kk = 0; kk < K; ++kk)
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c] = fmaf(B[kk], sh[(int64_t)(kk * 3 + c) * n + g], acc[c]);
@@ -132,10 +135,17 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
                        Record* recs, uint2* rects, uint32_t* keys, uint32_t* counts,
                        unsigned long long* totals, int totals_stride) {
   if (n == 0) return;
-  int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n, n_views, sh_degree, mean,
-                     scale, quat, opacity, sh, views, op, lam_tab, edges, recs, rects, keys, counts, totals,
-                     totals_stride);
+  const dim3 grid((unsigned)((n + 255) / 256));
+#define GEER_PRE(D)                                                                                               \
+  hipLaunchKernelGGL(preprocess_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, scale, quat, opacity, sh,     \
+                     views, op, lam_tab, edges, recs, rects, keys, counts, totals, totals_stride)
+  switch (sh_degree) {
+    case 0: GEER_PRE(0); break;
+    case 1: GEER_PRE(1); break;
+    case 2: GEER_PRE(2); break;
+    default: GEER_PRE(3); break;
+  }
+#undef GEER_PRE
 }
 
 }  // namespace geer
