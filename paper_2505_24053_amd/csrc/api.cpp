@@ -293,7 +293,9 @@ struct FwdBufs {
   int hmax = 0;
   float4* tcones = nullptr;  // per-tile corner cones of the expansion's cull (4 float4 per tile)
   uint32_t* hparts = nullptr;  // partial tile-digit histograms filled by the expansion
-  HeavyTiles heavy() const { return HeavyTiles{heavy_list, heavy_flag, (unsigned long long*)(stats + 6), hmax}; }
+  HeavyTiles heavy() const {
+    return HeavyTiles{heavy_list, heavy_flag, (unsigned long long*)(stats + 6), hmax, heavy_slots(hmax)};
+  }
 };
 
 // Stage (a): zero the counters, then preprocess + PBF of every item.
@@ -355,7 +357,7 @@ void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t item
 // Stage (c): the render kernel.
 void enqueue_render(hipStream_t st, const Opts& op, int64_t ntiles, int32_t nviews, const FwdBufs& b, float* rgb,
                     float* depth, float* trans) {
-  launch_mark_heavy(st, b.ranges, ntiles, b.heavy());
+  launch_mark_heavy(st, b.ranges, ntiles, b.views, nviews, b.heavy());
   launch_render(st, op.lambda_mode == 1, ntiles, b.views, nviews, b.dtab, b.ranges, b.list, b.rects, b.recs, op,
                 b.heavy(), rgb, depth, trans, b.nlast, b.tfinal, (unsigned long long*)(b.stats + 2));
 }
@@ -662,7 +664,7 @@ geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* 
   const float2* d_dtab = (const float2*)(meta + f->dtab_off);
   const geer_scene& sc = f->scene;
   const HeavyTiles heavy{(uint32_t*)f->heavy_list.p, (uint32_t*)f->heavy_flag.p,
-                         (unsigned long long*)((uint64_t*)f->stats.p + 6), f->hmax};
+                         (unsigned long long*)((uint64_t*)f->stats.p + 6), f->hmax, heavy_slots(f->hmax)};
   launch_backward(st, f->op.lambda_mode == 1, f->ntiles, f->n, f->nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat,
                   sc.opacity, sc.sh, d_views, d_dtab, d_edges, f->lam, f->op, heavy, (const uint32_t*)f->ranges.p,
                   (const uint32_t*)f->list.p, (const uint2*)f->rects.p, (const Record*)f->recs.p,

@@ -88,21 +88,15 @@ __device__ __forceinline__ void wave_reduce16_add(const float v[16], float* __re
 
 constexpr int kBackWaves = 2;  // independent waves per workgroup
 
+// Back-to-front replay of one block of rays (8x8, or 4x4 in heavy tiles).
 template <bool kFixed>
-__global__ __launch_bounds__(64 * kBackWaves) void render_backward_kernel(
-    const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
-    const Record* __restrict__ recs, Opts op, HeavyTiles heavy, const uint32_t* __restrict__ nlast,
-    const float* __restrict__ tfinal, const float* __restrict__ dl_drgb, float* __restrict__ acc) {
-  __shared__ float4 s_rec_all[kBackWaves][kWinB][4];  // each wave's own window
-  __shared__ uint32_t s_item_all[kBackWaves][kWinB];
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  float4(*s_rec)[4] = s_rec_all[wv];
-  uint32_t* s_item = s_item_all[wv];
-
-  const WaveBlock W = wave_block(wave_index(blockIdx.x, gridDim.x, kBackWaves, wv, kHeavySplit * heavy.hmax), views,
-                                 nviews, heavy.list, heavy.flag, heavy.count, heavy.hmax);
-  if (!W.live) return;
+__device__ __forceinline__ void backward_block(const WaveBlock& W, const ViewDev* __restrict__ views,
+                                               const float2* __restrict__ dtab, const uint32_t* __restrict__ ranges,
+                                               const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
+                                               const Record* __restrict__ recs, const Opts& op,
+                                               const uint32_t* __restrict__ nlast, const float* __restrict__ tfinal,
+                                               const float* __restrict__ dl_drgb, float* __restrict__ acc,
+                                               float4 (*s_rec)[4], uint32_t* s_item) {
   const ViewDev& V = views[W.v];
   const int tile = W.tile;
   const uint32_t hx = (uint32_t)W.bx0 >> 3, hy = (uint32_t)W.by0 >> 3;  // half-tile of the block
@@ -211,6 +205,35 @@ __global__ __launch_bounds__(64 * kBackWaves) void render_backward_kernel(
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+
+template <bool kFixed>
+__global__ __launch_bounds__(64 * kBackWaves) void render_backward_kernel(
+    const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
+    const Record* __restrict__ recs, Opts op, HeavyTiles heavy, const uint32_t* __restrict__ nlast,
+    const float* __restrict__ tfinal, const float* __restrict__ dl_drgb, float* __restrict__ acc) {
+  __shared__ float4 s_rec_all[kBackWaves][kWinB][4];  // each wave's own window
+  __shared__ uint32_t s_item_all[kBackWaves][kWinB];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  float4(*s_rec)[4] = s_rec_all[wv];
+  uint32_t* s_item = s_item_all[wv];
+  const int heavy_waves = kHeavySplit * heavy.hslots;
+  const int wi = wave_index(blockIdx.x, gridDim.x, kBackWaves, wv, heavy_waves);
+  // one block for an ordinary wave; for a heavy wave, block wi % 16 of the
+  // listed heavy tiles wi / 16, wi / 16 + slots, ... (one call site, so the
+  // replay is inlined once)
+  const bool hw = wi < heavy_waves;
+  const int nh = hw ? (int)min(*heavy.count, (unsigned long long)heavy.hmax) : 0;
+  for (int h = wi / kHeavySplit;; h += heavy.hslots) {
+    if (hw && h >= nh) break;
+    const WaveBlock W = hw ? heavy_block((int)heavy.list[h], wi % kHeavySplit, views, nviews)
+                           : ordinary_block(wi, heavy_waves, views, nviews, heavy.flag);
+    if (W.live)
+      backward_block<kFixed>(W, views, dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc, s_rec, s_item);
+    if (!hw) break;
   }
 }
 
@@ -361,8 +384,8 @@ void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, i
                             const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
                             const float* tfinal, const float* dl_drgb, float* acc) {
   if (ntiles <= 0) return;
-  // waves: 16 per heavy-tile slot, 4 per tile (both multiples of kBackWaves)
-  const unsigned grid = (unsigned)((kHeavySplit * heavy.hmax + 4 * ntiles) / kBackWaves);
+  // waves: 16 per heavy slot, 4 per tile (both multiples of kBackWaves)
+  const unsigned grid = (unsigned)((kHeavySplit * heavy.hslots + 4 * ntiles) / kBackWaves);
   if (fixed_lambda)
     hipLaunchKernelGGL(render_backward_kernel<true>, dim3(grid), dim3(64 * kBackWaves), 0, st, views, n_views, dtab,
                        ranges, list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);

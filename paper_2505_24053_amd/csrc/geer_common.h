@@ -49,13 +49,15 @@ struct Opts {
   int32_t pad_[1];
 };
 
-// Heavy-tile work list of a frame (device buffers): up to hmax tile ids, a
-// flag per tile, and the device count of listed tiles.
+// Heavy-tile work list of a frame (device buffers): up to hmax tile ids (a
+// capacity no frame can exceed), a flag per tile, the device count of listed
+// tiles, and the number of heavy wave slots that walk the list.
 struct HeavyTiles {
   uint32_t* list;
   uint32_t* flag;
   unsigned long long* count;
   int hmax;
+  int hslots;
 };
 
 __host__ __device__ inline uint32_t pack16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }

@@ -382,12 +382,12 @@ __device__ __forceinline__ void pixel_direction(const ViewDev& V, const float2* 
 
 // Work of one render wave: a block of rays of one tile.  Ordinary tiles are
 // split into four 8x8 half-tiles (one lane per ray).  Tiles flagged heavy --
-// many more list entries than the mean, which on wide BEAP grids happens
-// where a tile fans over a wide range of directions and its rays see mostly
-// different Gaussians -- are split into sixteen 4x4 blocks (16 lanes active),
-// so that each wave walks only the entries of its own rays; their waves come
-// first in the grid.  Block indices below kHeavySplit * hmax address heavy
-// tiles, the rest ordinary ones (XCD-banded).
+// list longer than 3x their view's mean (+64), which on wide BEAP grids
+// happens where a tile fans over a wide range of directions and its rays see
+// mostly different Gaussians -- are split into sixteen 4x4 blocks.  Their
+// waves come first in the grid: kHeavySplit per heavy slot, and the waves of
+// slot s render the listed tiles s, s + slots, s + 2 slots, ...  The rest of
+// the grid addresses ordinary blocks (XCD-banded), skipping heavy tiles.
 constexpr int kHeavySplit = 16;
 
 struct WaveBlock {
@@ -407,38 +407,36 @@ __device__ __forceinline__ int wave_index(int j, int nwg, int K, int w, int heav
   return heavy_waves + K * xcd_remap(j - jh, nwg - jh) + w;
 }
 
-// Block of wave index wi (from wave_index).
-__device__ __forceinline__ WaveBlock wave_block(int wi, const ViewDev* __restrict__ views, int nviews,
-                                                const uint32_t* __restrict__ heavy_list,
-                                                const uint32_t* __restrict__ heavy_flag,
-                                                const unsigned long long* __restrict__ heavy_count, int hmax) {
+__device__ __forceinline__ WaveBlock block_of(int tile, int sub, int bs, const ViewDev* __restrict__ views,
+                                              int nviews) {
   WaveBlock w;
-  w.live = false;
-  int sub;
-  const int nheavy_blocks = kHeavySplit * hmax;
-  if (wi < nheavy_blocks) {
-    const int h = wi / kHeavySplit;
-    if (h >= (int)min(*heavy_count, (unsigned long long)hmax)) return w;
-    w.tile = (int)heavy_list[h];
-    sub = wi % kHeavySplit;
-    w.bs = 4;
-  } else {
-    const int hidx = wi - nheavy_blocks;
-    w.tile = hidx >> 2;
-    if (heavy_flag && heavy_flag[w.tile]) return w;
-    sub = hidx & 3;
-    w.bs = 8;
-  }
+  w.tile = tile;
+  w.bs = bs;
   int v = 0;
-  while (v + 1 < nviews && w.tile >= views[v + 1].tile_base) ++v;
+  while (v + 1 < nviews && tile >= views[v + 1].tile_base) ++v;
   const ViewDev& V = views[v];
   w.v = v;
-  const int lt = w.tile - V.tile_base;
+  const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
-  const int per = kTile / w.bs;  // blocks per tile edge
-  w.bx0 = tx * kTile + (sub % per) * w.bs;
-  w.by0 = ty * kTile + (sub / per) * w.bs;
+  const int per = kTile / bs;  // blocks per tile edge
+  w.bx0 = tx * kTile + (sub % per) * bs;
+  w.by0 = ty * kTile + (sub / per) * bs;
   w.live = w.bx0 < V.width && w.by0 < V.height;
+  return w;
+}
+
+// 4x4 block `sub` of a heavy tile.
+__device__ __forceinline__ WaveBlock heavy_block(int tile, int sub, const ViewDev* __restrict__ views, int nviews) {
+  return block_of(tile, sub, 4, views, nviews);
+}
+
+// Ordinary block of wave index wi (past the heavy waves); not live when its
+// tile is heavy.
+__device__ __forceinline__ WaveBlock ordinary_block(int wi, int heavy_waves, const ViewDev* __restrict__ views,
+                                                    int nviews, const uint32_t* __restrict__ heavy_flag) {
+  const int hidx = wi - heavy_waves;
+  WaveBlock w = block_of(hidx >> 2, hidx & 3, 8, views, nviews);
+  if (heavy_flag && heavy_flag[w.tile]) w.live = false;
   return w;
 }
 

@@ -52,7 +52,9 @@ void launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v);
 
 // render.hip
 int heavy_capacity(int64_t ntiles);
-void launch_mark_heavy(hipStream_t st, const uint32_t* ranges, int64_t ntiles, const HeavyTiles& h);
+int heavy_slots(int hmax);
+void launch_mark_heavy(hipStream_t st, const uint32_t* ranges, int64_t ntiles, const ViewDev* views, int nviews,
+                       const HeavyTiles& h);
 void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const ViewDev* views, int nviews,
                    const float2* dtab, const uint32_t* ranges, const uint32_t* list, const uint2* rects,
                    const Record* recs, const Opts& op, const HeavyTiles& heavy, float* rgb, float* depth,

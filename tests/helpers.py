@@ -66,3 +66,22 @@ def compare_render(got, ref, pix=None, rgb_tol=RGB_TOL):
     print("rays %d, flagged %d (%.2f%%), flagged beyond %.0e: %d, max err unflagged %.3g"
           % (amb.size, amb.sum(), 100 * amb.mean(), rgb_tol, int((err[amb] > rgb_tol).sum()), err[ok].max(initial=0)))
     return float(err[ok].max(initial=0)), int(amb.sum())
+
+
+def heavy_pixel_mask(ranges, cams):
+    """Per ray (views concatenated) whether its 16x16 tile is heavy under the
+    renderer's rule: list longer than 3x the mean over the tiles of its own
+    view, plus 64.  Heavy tiles composite four entries per step, which rounds
+    differently from the one-entry steps of ordinary tiles."""
+    import numpy as np
+    cnt = np.diff(np.asarray(ranges, dtype=np.int64))
+    masks, base = [], 0
+    for cam in cams:
+        w, h = cam["width"], cam["height"]
+        tx, ty = (w + 15) // 16, (h + 15) // 16
+        c = cnt[base:base + tx * ty]
+        heavy = (c > 3 * int(c.sum()) // c.size + 64).reshape(ty, tx)
+        ys, xs = np.mgrid[0:h, 0:w]
+        masks.append(heavy[ys // 16, xs // 16].ravel())
+        base += tx * ty
+    return np.concatenate(masks)
