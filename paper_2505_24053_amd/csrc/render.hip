@@ -31,6 +31,9 @@
 #ifndef RENDER_WAVES
 #define RENDER_WAVES 2
 #endif
+#ifndef RENDER_HEAVY_PRIO
+#define RENDER_HEAVY_PRIO 2
+#endif
 
 namespace geer {
 
@@ -120,25 +123,36 @@ __device__ __forceinline__ void render_heavy_block(const WaveBlock& W, const Vie
   const int qsh = lane & ~3;              // this quad's bit offset in a wave mask
 
   // windows of 64 entries: lane k tests entry base + k (rectangle, then
-  // contribution cone) and stages its record; no prefetch, which keeps the
-  // register count of this path at the ordinary path's
+  // contribution cone) and stages its record.  The next window is loaded
+  // into registers while this one composites; its loads are unconditional
+  // (a lane past the end reads the tile's first entry) so that they stay
+  // plain register values.
+  if (start >= end) return;
+  float4 p0, p1, p2, p3;
+  bool phit;
+  {
+    const uint32_t e = start + lane;
+    const uint32_t item = list[e < end ? e : start];
+    const uint2 rc = rects[item];
+    phit = e < end && (rc.x & 0xffffu) <= hx && hx <= (rc.x >> 16) && (rc.y & 0xffffu) <= hy && hy <= (rc.y >> 16);
+    const float4* rp = reinterpret_cast<const float4*>(recs + item);
+    p0 = rp[0]; p1 = rp[1]; p2 = rp[2]; p3 = rp[3];
+  }
   for (uint32_t base = start; base < end && ~done != 0; base += kWin) {
-    const uint32_t e = base + lane;
-    bool phit = false;
-    if (e < end) {
-      const uint32_t item = list[e];
-      const uint2 rc = rects[item];
-      phit = (rc.x & 0xffffu) <= hx && hx <= (rc.x >> 16) && (rc.y & 0xffffu) <= hy && hy <= (rc.y >> 16);
-      if (phit) {
-        const float4* rp = reinterpret_cast<const float4*>(recs + item);
-        const float4 p0 = rp[0], p1 = rp[1], p2 = rp[2], p3 = rp[3];
-        if (op.cone_cull) phit = cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, kFixed);
-        if (phit) {
-          s_rec[lane][0] = p0; s_rec[lane][1] = p1; s_rec[lane][2] = p2; s_rec[lane][3] = p3;
-        }
-      }
-    }
+    if (phit && op.cone_cull) phit = cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, kFixed);
     uint64_t m = __builtin_amdgcn_ballot_w64(phit);
+    if (phit) {
+      s_rec[lane][0] = p0; s_rec[lane][1] = p1; s_rec[lane][2] = p2; s_rec[lane][3] = p3;
+    }
+    {
+      const uint32_t e = base + kWin + lane;
+      const uint32_t item = list[e < end ? e : start];
+      const uint2 rc = rects[item];
+      phit = e < end && (rc.x & 0xffffu) <= hx && hx <= (rc.x >> 16) && (rc.y & 0xffffu) <= hy &&
+             hy <= (rc.y >> 16);
+      const float4* rp = reinterpret_cast<const float4*>(recs + item);
+      p0 = rp[0]; p1 = rp[1]; p2 = rp[2]; p3 = rp[3];
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -240,7 +254,10 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
   const int wi = wave_index(blockIdx.x, gridDim.x, kRenderWaves, wv, heavy_waves);
   if (wi < heavy_waves) {
     // block wi % 16 of the listed heavy tiles wi / 16, wi / 16 + slots, ...
+    // Heavy waves are the kernel's critical path (each walks a whole long
+    // list): they take issue priority over the ordinary waves on their SIMD.
     const int nh = (int)min(*heavy.count, (unsigned long long)heavy.hmax);
+    if (wi / kHeavySplit < nh) __builtin_amdgcn_s_setprio(RENDER_HEAVY_PRIO);
     for (int h = wi / kHeavySplit; h < nh; h += heavy.hslots) {
       const WaveBlock Wh = heavy_block((int)heavy.list[h], wi % kHeavySplit, views, nviews);
       if (!Wh.live) continue;
@@ -270,22 +287,38 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
   const int amax_bits = __float_as_int(op.alpha_max);
 
   // Prefetch of one window into registers: entry base + k goes to lane k.
-  float4 p0, p1, p2, p3;
-  bool phit = false;
-  auto fetch = [&](uint32_t b) {
-    const uint32_t e = b + lane;
-    phit = false;
-    if (e < end) {
-      const uint32_t item = list[e];
-      const uint2 rc = rects[item];
-      phit = (rc.x & 0xffffu) <= hx && hx <= (rc.x >> 16) && (rc.y & 0xffffu) <= hy && hy <= (rc.y >> 16);
-      if (phit) {
-        const float4* r = reinterpret_cast<const float4*>(recs + item);
-        p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
+  // The loads are unconditional (a lane past the end reads the tile's first
+  // entry), so the prefetched values stay plain register values.
+  if (start >= end) {
+    // empty tile: background
+    if (valid) {
+      const int64_t hw = (int64_t)V.width * V.height;
+      const int64_t p = (int64_t)py * V.width + px;
+      float* out = rgb + 3 * (int64_t)V.pix_base;
+      out[p] = 0.0f;
+      out[hw + p] = 0.0f;
+      out[2 * hw + p] = 0.0f;
+      const int64_t gp = (int64_t)V.pix_base + p;
+      if (depth) depth[gp] = 0.0f;
+      if (trans) trans[gp] = 1.0f;
+      if (kKeep) {
+        nlast[gp] = start;
+        tfinal[gp] = 1.0f;
       }
     }
+    return;
+  }
+  float4 p0, p1, p2, p3;
+  bool phit;
+  auto fetch = [&](uint32_t b) {
+    const uint32_t e = b + lane;
+    const uint32_t item = list[e < end ? e : start];
+    const uint2 rc = rects[item];
+    phit = e < end && (rc.x & 0xffffu) <= hx && hx <= (rc.x >> 16) && (rc.y & 0xffffu) <= hy && hy <= (rc.y >> 16);
+    const float4* r = reinterpret_cast<const float4*>(recs + item);
+    p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
   };
-  if (start < end) fetch(start);
+  fetch(start);
 
   for (uint32_t base = start; base < end && ~done != 0; base += kWin) {
     // entries whose rectangle meets the half-tile and whose contribution cone
