@@ -31,9 +31,6 @@
 #ifndef RENDER_WAVES
 #define RENDER_WAVES 2
 #endif
-#ifndef RENDER_HEAVY_PRIO
-#define RENDER_HEAVY_PRIO 2
-#endif
 
 namespace geer {
 
@@ -254,10 +251,7 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
   const int wi = wave_index(blockIdx.x, gridDim.x, kRenderWaves, wv, heavy_waves);
   if (wi < heavy_waves) {
     // block wi % 16 of the listed heavy tiles wi / 16, wi / 16 + slots, ...
-    // Heavy waves are the kernel's critical path (each walks a whole long
-    // list): they take issue priority over the ordinary waves on their SIMD.
     const int nh = (int)min(*heavy.count, (unsigned long long)heavy.hmax);
-    if (wi / kHeavySplit < nh) __builtin_amdgcn_s_setprio(RENDER_HEAVY_PRIO);
     for (int h = wi / kHeavySplit; h < nh; h += heavy.hslots) {
       const WaveBlock Wh = heavy_block((int)heavy.list[h], wi % kHeavySplit, views, nviews);
       if (!Wh.live) continue;
