@@ -668,7 +668,8 @@ geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* 
   launch_backward(st, f->op.lambda_mode == 1, f->ntiles, f->n, f->nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat,
                   sc.opacity, sc.sh, d_views, d_dtab, d_edges, f->lam, f->op, heavy, (const uint32_t*)f->ranges.p,
                   (const uint32_t*)f->list.p, (const uint2*)f->rects.p, (const Record*)f->recs.p,
-                  (const uint32_t*)f->nlast.p, (const float*)f->tfinal.p, dl_drgb, (float*)acc.p, accumulate != 0,
+                  (const uint32_t*)f->counts.p, (const uint32_t*)f->nlast.p, (const float*)f->tfinal.p, dl_drgb,
+                  (float*)acc.p, accumulate != 0,
                   g_mean, g_scale, g_quat, g_opacity, g_sh);
   hipError_t e = hipGetLastError();
   release(c, acc);
@@ -1212,13 +1213,13 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
   if (e == hipSuccess) {
     const double weight = 1.0 / (double)n_views;
     const ViewDev* all_views = (const ViewDev*)((char*)P->meta + S.all_off);
-    launch_zero_acc(cs, acc, n * (int64_t)n_views * 16);
     // one preprocess for every view: the scene is read once, item v n + g
     // holds Gaussian g in view v, view v's counters are P->stats + 8 v
     b.views = all_views;
     b.edges = (const float*)P->meta;
     b.stats = P->stats;
     enqueue_preprocess(cs, P->scene, n_views, P->op, lt.dev, b, true);
+    launch_zero_acc(cs, acc, b.counts, n * (int64_t)n_views);  // the visible items' accumulators
     Record* const recs0 = b.recs;
     uint2* const rects0 = b.rects;
     uint32_t *const keys0 = b.keys, *const counts0 = b.counts;
@@ -1247,7 +1248,8 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
     // Gaussian-wise backward once, summing every view
     launch_preprocess_backward(cs, n, n_views, scene->sh_degree, scene->mean, scene->scale, scene->quat,
                                scene->opacity, scene->sh, all_views,
-                               (const float*)P->meta, lt.dev, P->op, acc, 0, g_mean, g_scale, g_quat, g_opacity, g_sh);
+                               (const float*)P->meta, lt.dev, P->op, counts0, acc, 0, g_mean, g_scale, g_quat,
+                               g_opacity, g_sh);
     launch_sum_f32(cs, n_views, loss_views, loss);
     hipError_t e2 = hipStreamEndCapture(cs, &P->graph);
     e = e2 != hipSuccess ? e2 : hipGetLastError();

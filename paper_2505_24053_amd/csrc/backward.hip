@@ -245,8 +245,9 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
     int64_t n, int32_t n_views, const float* __restrict__ mean, const float* __restrict__ scale,
     const float* __restrict__ quat, const float* __restrict__ opacity, const float* __restrict__ sh,
     const ViewDev* __restrict__ views, Opts op, const float* __restrict__ lam_tab, const float* __restrict__ edges,
-    const float* __restrict__ acc, int accumulate, float* __restrict__ g_mean, float* __restrict__ g_scale,
-    float* __restrict__ g_quat, float* __restrict__ g_opacity, float* __restrict__ g_sh) {
+    const uint32_t* __restrict__ counts, const float* __restrict__ acc, int accumulate, float* __restrict__ g_mean,
+    float* __restrict__ g_scale, float* __restrict__ g_quat, float* __restrict__ g_opacity,
+    float* __restrict__ g_sh) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const float mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
@@ -260,7 +261,18 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
   for (int i = 0; i < K * 3; ++i) dsh[i] = 0.0f;
   float R[9], qh[4] = {1, 0, 0, 0}, qn = 1.0f;
   bool any = false;
+  // views in groups of 8: the group's tile counts are loaded together, and
+  // only the views where the Gaussian is visible (its accumulator written
+  // by the ray-wise backward) are read
+  uint32_t vis = 0u;
   for (int v = 0; v < n_views; ++v) {
+    if ((v & 7) == 0) {
+      vis = 0u;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (v + k < n_views && counts[(int64_t)(v + k) * n + g] != 0u) vis |= 1u << k;
+    }
+    if (!((vis >> (v & 7)) & 1u)) continue;
     const int64_t item = (int64_t)v * n + g;
     const float4* ap = reinterpret_cast<const float4*>(acc + item * kAcc);
     const float4 A0 = ap[0], A1 = ap[1], A2 = ap[2], A3 = ap[3];
@@ -369,14 +381,22 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
   for (int k = 0; k < K * 3; ++k) put(g_sh, (int64_t)k * n + g, dsh[k]);
 }
 
-__global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ p, int64_t n) {
+// Clears the accumulators of the items visible in their view (tile count
+// above zero); the others are never written by the ray-wise backward and
+// never read by the Gaussian-wise one.
+__global__ __launch_bounds__(256) void zero_acc_kernel(float* __restrict__ acc, const uint32_t* __restrict__ counts,
+                                                       int64_t nitems) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = 0.0f;
+  if (i >= nitems || counts[i] == 0u) return;
+  float4* a = reinterpret_cast<float4*>(acc + i * kAcc);
+  const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  a[0] = z; a[1] = z; a[2] = z; a[3] = z;
 }
 
-void launch_zero_acc(hipStream_t st, float* acc, int64_t nacc) {
-  if (nacc > 0)
-    hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nacc + 255) / 256)), dim3(256), 0, st, acc, nacc);
+void launch_zero_acc(hipStream_t st, float* acc, const uint32_t* counts, int64_t nitems) {
+  if (nitems > 0)
+    hipLaunchKernelGGL(zero_acc_kernel, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, st, acc, counts,
+                       nitems);
 }
 
 void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int32_t n_views, const ViewDev* views,
@@ -397,13 +417,13 @@ void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, i
 void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
                                 const float* scale, const float* quat, const float* opacity, const float* sh,
                                 const ViewDev* views, const float* edges, const float* lam_tab, const Opts& op,
-                                const float* acc, int accumulate, float* g_mean, float* g_scale, float* g_quat,
-                                float* g_opacity, float* g_sh) {
+                                const uint32_t* counts, const float* acc, int accumulate, float* g_mean,
+                                float* g_scale, float* g_quat, float* g_opacity, float* g_sh) {
   if (n <= 0) return;
   const dim3 grid((unsigned)((n + 255) / 256));
 #define GEER_PB(D)                                                                                              \
   hipLaunchKernelGGL(preprocess_backward_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, scale, quat, opacity, \
-                     sh, views, op, lam_tab, edges, acc, accumulate, g_mean, g_scale, g_quat, g_opacity, g_sh)
+                     sh, views, op, lam_tab, edges, counts, acc, accumulate, g_mean, g_scale, g_quat, g_opacity, g_sh)
   switch (sh_degree) {
     case 0: GEER_PB(0); break;
     case 1: GEER_PB(1); break;
@@ -418,13 +438,14 @@ void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t 
                      const float* opacity, const float* sh, const ViewDev* views, const float2* dtab,
                      const float* edges, const float* lam_tab, const Opts& op, const HeavyTiles& heavy,
                      const uint32_t* ranges, const uint32_t* list, const uint2* rects, const Record* recs,
-                     const uint32_t* nlast, const float* tfinal, const float* dl_drgb, float* acc, int accumulate,
-                     float* g_mean, float* g_scale, float* g_quat, float* g_opacity, float* g_sh) {
-  launch_zero_acc(st, acc, n * n_views * kAcc);
+                     const uint32_t* counts, const uint32_t* nlast, const float* tfinal, const float* dl_drgb,
+                     float* acc, int accumulate, float* g_mean, float* g_scale, float* g_quat, float* g_opacity,
+                     float* g_sh) {
+  launch_zero_acc(st, acc, counts, n * n_views);
   launch_render_backward(st, fixed_lambda, ntiles, n_views, views, dtab, op, heavy, ranges, list, rects, recs, nlast,
                          tfinal, dl_drgb, acc);
-  launch_preprocess_backward(st, n, n_views, sh_degree, mean, scale, quat, opacity, sh, views, edges, lam_tab, op, acc,
-                             accumulate, g_mean, g_scale, g_quat, g_opacity, g_sh);
+  launch_preprocess_backward(st, n, n_views, sh_degree, mean, scale, quat, opacity, sh, views, edges, lam_tab, op,
+                             counts, acc, accumulate, g_mean, g_scale, g_quat, g_opacity, g_sh);
 }
 
 }  // namespace geer

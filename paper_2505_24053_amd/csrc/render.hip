@@ -124,7 +124,25 @@ __device__ __forceinline__ void render_heavy_block(const WaveBlock& W, const Vie
   // into registers while this one composites; its loads are unconditional
   // (a lane past the end reads the tile's first entry) so that they stay
   // plain register values.
-  if (start >= end) return;
+  if (start >= end) {
+    // an empty list (a heavy tile never has one): background
+    if (valid && j == 0) {
+      const int64_t hw = (int64_t)V.width * V.height;
+      const int64_t p = (int64_t)py * V.width + px;
+      float* out = rgb + 3 * (int64_t)V.pix_base;
+      out[p] = 0.0f;
+      out[hw + p] = 0.0f;
+      out[2 * hw + p] = 0.0f;
+      const int64_t gp = (int64_t)V.pix_base + p;
+      if (depth) depth[gp] = 0.0f;
+      if (trans) trans[gp] = 1.0f;
+      if (kKeep) {
+        nlast[gp] = start;
+        tfinal[gp] = 1.0f;
+      }
+    }
+    return;
+  }
   float4 p0, p1, p2, p3;
   bool phit;
   {

@@ -487,17 +487,20 @@ __global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t* __restri
                                                         const unsigned long long* __restrict__ dyn,
                                                         int64_t ntiles, uint32_t* __restrict__ ranges) {
   const int64_t total = dyn_count(total_cap, dyn);
-  int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t e0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (total == 0) {
-    for (int64_t t = e; t <= ntiles; t += (int64_t)gridDim.x * kBlock) ranges[t] = 0u;
+    for (int64_t t = e0; t <= ntiles; t += stride) ranges[t] = 0u;
     return;
   }
-  if (e >= total) return;
-  int64_t cur = tiles[e];
-  int64_t prev = e > 0 ? (int64_t)tiles[e - 1] : -1;
-  for (int64_t t = prev + 1; t <= cur; ++t) ranges[t] = (uint32_t)e;
-  if (e == total - 1)
-    for (int64_t t = cur + 1; t <= ntiles; ++t) ranges[t] = (uint32_t)total;
+  // grid-stride: the grid is bounded, however large the capacity
+  for (int64_t e = e0; e < total; e += stride) {
+    const int64_t cur = tiles[e];
+    const int64_t prev = e > 0 ? (int64_t)tiles[e - 1] : -1;
+    for (int64_t t = prev + 1; t <= cur; ++t) ranges[t] = (uint32_t)e;
+    if (e == total - 1)
+      for (int64_t t = cur + 1; t <= ntiles; ++t) ranges[t] = (uint32_t)total;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
@@ -644,8 +647,8 @@ void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, con
     return;
   }
   const int64_t g = std::max<int64_t>(total_cap, ntiles + 1);
-  hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(g, kBlock)), dim3(kBlock), 0, st, tiles, total_cap, dyn, ntiles,
-                     ranges);
+  hipLaunchKernelGGL(ranges_kernel, dim3(std::min<unsigned>(grid_for(g, kBlock), 8192u)), dim3(kBlock), 0, st, tiles,
+                     total_cap, dyn, ntiles, ranges);
 }
 
 void launch_capacity_guard(hipStream_t st, unsigned long long* stats, int64_t cap) {

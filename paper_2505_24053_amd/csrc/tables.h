@@ -66,11 +66,11 @@ void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t 
                      const float* opacity, const float* sh, const ViewDev* views, const float2* dtab,
                      const float* edges, const float* lam_tab, const Opts& op, const HeavyTiles& heavy,
                      const uint32_t* ranges, const uint32_t* list, const uint2* rects, const Record* recs,
-                     const uint32_t* nlast,
+                     const uint32_t* counts, const uint32_t* nlast,
                      const float* tfinal, const float* dl_drgb, float* acc, int accumulate, float* g_mean,
                      float* g_scale, float* g_quat, float* g_opacity, float* g_sh);
 
-void launch_zero_acc(hipStream_t st, float* acc, int64_t nacc);
+void launch_zero_acc(hipStream_t st, float* acc, const uint32_t* counts, int64_t nitems);
 void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int32_t n_views, const ViewDev* views,
                             const float2* dtab, const Opts& op, const HeavyTiles& heavy, const uint32_t* ranges,
                             const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
@@ -78,7 +78,7 @@ void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, i
 void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
                                 const float* scale, const float* quat, const float* opacity, const float* sh,
                                 const ViewDev* views, const float* edges, const float* lam_tab, const Opts& op,
-                                const float* acc, int accumulate, float* g_mean, float* g_scale, float* g_quat,
+                                const uint32_t* counts, const float* acc, int accumulate, float* g_mean, float* g_scale, float* g_quat,
                                 float* g_opacity, float* g_sh);
 
 // loss.hip
