@@ -146,7 +146,9 @@ void geer_default_opts(geer_opts* opts);
  * once.  rgb, depth, trans: device outputs laid out as in the header; any of
  * depth / trans may be NULL.  If `frame` is not NULL a frame is created and
  * returned that holds what geer_render_backward needs; the caller releases it.
- * Synchronises `stream` once (to size the association list).
+ * The host waits once, mid-call, for the association's entry count, which
+ * sizes the list; the depth sort is already enqueued behind it by then, so
+ * the device keeps working.  Calls on one context must not overlap.
  */
 geer_status geer_render(geer_ctx* ctx, const geer_scene* scene, int32_t n_views, const geer_view* views,
                         const geer_opts* opts, float* rgb, float* depth, float* trans, geer_frame** frame,

@@ -52,6 +52,7 @@ struct geer_ctx {
   std::vector<LamTab> lams;  // lambda^2 tables by alpha_min, kept until destroy
   void* pinned = nullptr;  // host staging for table uploads and read-backs
   size_t pinned_bytes = 0;
+  hipEvent_t totals_ready = nullptr;  // an eager forward's count read-back has landed
   int64_t live_frames = 0;
 };
 
@@ -307,23 +308,29 @@ void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, co
                     b.edges, b.recs, b.rects, b.keys, b.counts, (unsigned long long*)b.stats, per_view_stats ? 8 : 0);
 }
 
-// Stage (b): association list.  With exact sizes (dyn == false) nvis_cap and
-// ecap are the counts read back from the device; otherwise they are
-// capacities and every kernel reads the live counts from b.stats.
-// Returns the buffer holding the final (tile-sorted) list in b.list.
-void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t items, int64_t nvis_cap, int64_t ecap,
-                         int64_t ntiles, bool dyn, const FwdBufs& b) {
-  const unsigned long long* dE = dyn ? (const unsigned long long*)b.stats : nullptr;
-  const unsigned long long* dV = dyn ? (const unsigned long long*)(b.stats + 1) : nullptr;
+// Stage (b): association list; the tile-sorted list ends in b.list.
+// First half: the depth order of the visible items, their entry offsets and
+// the per-tile cones; none of it depends on the entry count.  dV: the live
+// visible count on the device, or null when nvis_cap is exact.
+void enqueue_depth_order(hipStream_t st, const Opts& op, int64_t n, int64_t items, int64_t nvis_cap,
+                         const unsigned long long* dV, int64_t ntiles, const FwdBufs& b) {
+  if (nvis_cap <= 0) return;
+  unsigned long long* err = (unsigned long long*)(b.stats + 4);
+  // depth order of the visible items (pass 0 compacts them out of all items)
+  radix_sort(st, b.keys, nullptr, b.counts, false, items, nullptr, nvis_cap, dV, 0, 4, b.ka, b.va, b.kb, b.vb,
+             b.hist, nullptr, err);
+  launch_gather_counts(st, b.vb, nvis_cap, dV, b.counts, b.cnt_sorted);
+  scan_exclusive(st, b.cnt_sorted, b.cnt_sorted, nvis_cap, b.scratch);
+  if (op.cone_cull) launch_tile_cones(st, b.views, n > 0 ? (int)(items / n) : 1, b.dtab, ntiles, b.tcones);
+}
+
+// Second half: expansion, tile sort and ranges.  dV / dE: live counts on the
+// device, or null when nvis_cap / ecap are exact.
+void enqueue_tile_lists(hipStream_t st, const Opts& op, int64_t n, int64_t nvis_cap, const unsigned long long* dV,
+                        int64_t ecap, const unsigned long long* dE, int64_t ntiles, const FwdBufs& b) {
   unsigned long long* kept = (unsigned long long*)(b.stats + 5);  // list length after the cone cull
   unsigned long long* err = (unsigned long long*)(b.stats + 4);
-  if (dyn) launch_capacity_guard(st, (unsigned long long*)b.stats, ecap);
   if (nvis_cap > 0) {
-    // depth order of the visible items (pass 0 compacts them out of all items)
-    radix_sort(st, b.keys, nullptr, b.counts, false, items, nullptr, nvis_cap, dV, 0, 4, b.ka, b.va, b.kb, b.vb,
-               b.hist, nullptr, err);
-    launch_gather_counts(st, b.vb, nvis_cap, dV, b.counts, b.cnt_sorted);
-    scan_exclusive(st, b.cnt_sorted, b.cnt_sorted, nvis_cap, b.scratch);
     // Expansion in depth order (entries no ray of their tile can see marked
     // for dropping), then the stable tile-id passes -- the first compacts --
     // arranged so that the sorted items end in b.list: pair P = (tiles_b,
@@ -336,7 +343,6 @@ void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t item
     uint32_t* iin = (passes % 2 == 1) ? qi : pi;
     uint32_t* at = (passes % 2 == 1) ? pt : qt;
     uint32_t* ai = (passes % 2 == 1) ? pi : qi;
-    if (op.cone_cull) launch_tile_cones(st, b.views, n > 0 ? (int)(items / n) : 1, b.dtab, ntiles, b.tcones);
     // the expansion also counts the tile digits of the kept entries (one or
     // two passes), which replaces the sort's histogram pass over the list
     const int hpass = passes <= 2 ? passes : 0;
@@ -352,6 +358,18 @@ void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t item
     launch_fill_u32(st, b.list, 8, 0u);
     launch_ranges(st, nullptr, 0, nullptr, ntiles, b.ranges);
   }
+}
+
+// Stage (b) in one go.  With exact sizes (dyn == false) nvis_cap and ecap are
+// the counts read back from the device; otherwise they are capacities and
+// every kernel reads the live counts from b.stats.
+void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t items, int64_t nvis_cap, int64_t ecap,
+                         int64_t ntiles, bool dyn, const FwdBufs& b) {
+  const unsigned long long* dE = dyn ? (const unsigned long long*)b.stats : nullptr;
+  const unsigned long long* dV = dyn ? (const unsigned long long*)(b.stats + 1) : nullptr;
+  if (dyn) launch_capacity_guard(st, (unsigned long long*)b.stats, ecap);
+  enqueue_depth_order(st, op, n, items, nvis_cap, dV, ntiles, b);
+  enqueue_tile_lists(st, op, n, nvis_cap, dV, ecap, dE, ntiles, b);
 }
 
 // Stage (c): the render kernel.
@@ -476,6 +494,7 @@ void geer_destroy(geer_ctx* c) {
   }
   for (LamTab& t : c->lams) (void)hipFree(t.dev);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->totals_ready) (void)hipEventDestroy(c->totals_ready);
   delete c;
 }
 
@@ -523,10 +542,10 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   f->dtab_off = tab.dtab_off;
 
   // Temporaries of the sort; released at the end of the call.
-  Block ka, va, kb, vb, hist, scratch, tiles_a, tiles_b, items_b, cnt_sorted, tcones, hparts;
+  Block ka, va, kb, vb, hist, hist2, scratch, tiles_a, tiles_b, items_b, cnt_sorted, tcones, hparts;
   auto cleanup = [&](geer_status st_) {
-    for (Block* b :
-         {&ka, &va, &kb, &vb, &hist, &scratch, &tiles_a, &tiles_b, &items_b, &cnt_sorted, &tcones, &hparts})
+    for (Block* b : {&ka, &va, &kb, &vb, &hist, &hist2, &scratch, &tiles_a, &tiles_b, &items_b, &cnt_sorted,
+                     &tcones, &hparts})
       release(c, *b);
     if (st_ != GEER_OK) {
       free_frame_buffers(f);
@@ -547,8 +566,8 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
 
   TRY(acquire(c, tab.bytes, st, f->meta));
   TRY(ensure_pinned(c, std::max<size_t>(tab.bytes, 64)));
-  // The previous call's read-back synchronised the stream, so the staging
-  // buffer is free again.
+  // The previous call waited for its count read-back, which follows its
+  // table upload on the stream, so the staging buffer is free again.
   pack_tables(tab, c->pinned);
   HTRY(hipMemcpyAsync(f->meta.p, c->pinned, tab.bytes, hipMemcpyHostToDevice, st));
   FwdBufs b;
@@ -573,8 +592,32 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   enqueue_preprocess(st, *scene, n_views, op, lt.dev, b);
   HTRY(hipGetLastError());
   prof_mark(ps, 1, st);
+  // The entry count sizes the list, so it is read back; the depth order of
+  // the visible items does not need it and is enqueued first (sized for all
+  // items, with the live count read on the device), so the device has work
+  // while the host waits for the count.
+  if (!c->totals_ready) HTRY(hipEventCreateWithFlags(&c->totals_ready, hipEventDisableTiming));
   HTRY(hipMemcpyAsync(c->pinned, b.stats, 16, hipMemcpyDeviceToHost, st));
-  HTRY(hipStreamSynchronize(st));
+  HTRY(hipEventRecord(c->totals_ready, st));
+
+  // ---- stage (b): depth sort, expansion, tile sort, ranges ----
+  const int64_t hist_items = radix_work_words(it1);
+  TRY(acquire(c, 4 * it1, st, ka));
+  TRY(acquire(c, 4 * it1, st, va));
+  TRY(acquire(c, 4 * it1, st, kb));
+  TRY(acquire(c, 4 * it1, st, vb));
+  TRY(acquire(c, 4 * (size_t)hist_items, st, hist));
+  TRY(acquire(c, 4 * (size_t)scan_scratch_words(it1), st, scratch));
+  TRY(acquire(c, 4 * it1, st, cnt_sorted));
+  TRY(acquire(c, 64 * (size_t)std::max<int64_t>(ntiles, 1), st, tcones));
+  b.tcones = (float4*)tcones.p;
+  b.ka = (uint32_t*)ka.p; b.va = (uint32_t*)va.p; b.kb = (uint32_t*)kb.p; b.vb = (uint32_t*)vb.p;
+  b.hist = (uint32_t*)hist.p; b.scratch = (uint32_t*)scratch.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
+  prof_mark(ps, 2, st);
+  enqueue_depth_order(st, op, n, items, items, (const unsigned long long*)(b.stats + 1), ntiles, b);
+  HTRY(hipGetLastError());
+
+  HTRY(hipEventSynchronize(c->totals_ready));
   uint64_t totals[2];
   std::memcpy(totals, c->pinned, 16);
   const int64_t E = (int64_t)totals[0], nvis = (int64_t)totals[1];
@@ -584,31 +627,21 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   f->entries = E;
   f->visible = nvis;
 
-  // ---- stage (b): depth sort, expansion, tile sort, ranges ----
-  const int64_t nv1 = std::max<int64_t>(nvis, 1), e1 = std::max<int64_t>(E, 1);
-  const int64_t hist_words = radix_work_words(std::max(items, E));
-  TRY(acquire(c, 4 * nv1, st, ka));
-  TRY(acquire(c, 4 * nv1, st, va));
-  TRY(acquire(c, 4 * nv1, st, kb));
-  TRY(acquire(c, 4 * nv1, st, vb));
-  TRY(acquire(c, 4 * (size_t)hist_words, st, hist));
-  TRY(acquire(c, 4 * (size_t)scan_scratch_words(nv1), st, scratch));
-  TRY(acquire(c, 4 * nv1, st, cnt_sorted));
+  const int64_t e1 = std::max<int64_t>(E, 1);
+  if (radix_work_words(e1) > hist_items) {  // the tile sort's own (larger) work area
+    TRY(acquire(c, 4 * (size_t)radix_work_words(e1), st, hist2));
+    b.hist = (uint32_t*)hist2.p;
+  }
   TRY(acquire(c, 4 * (e1 + 8), st, tiles_a));
   TRY(acquire(c, 4 * (e1 + 8), st, tiles_b));
   TRY(acquire(c, 4 * (e1 + 8), st, f->list));
   TRY(acquire(c, 4 * (e1 + 8), st, items_b));
   TRY(acquire(c, 4 * (ntiles + 1), st, f->ranges));
-  TRY(acquire(c, 64 * (size_t)std::max<int64_t>(ntiles, 1), st, tcones));
-  b.tcones = (float4*)tcones.p;
   TRY(acquire(c, 4 * (size_t)hist_parts_words(), st, hparts));
   b.hparts = (uint32_t*)hparts.p;
-  b.ka = (uint32_t*)ka.p; b.va = (uint32_t*)va.p; b.kb = (uint32_t*)kb.p; b.vb = (uint32_t*)vb.p;
-  b.hist = (uint32_t*)hist.p; b.scratch = (uint32_t*)scratch.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
   b.tiles_a = (uint32_t*)tiles_a.p; b.tiles_b = (uint32_t*)tiles_b.p; b.items_b = (uint32_t*)items_b.p;
   b.list = (uint32_t*)f->list.p; b.ranges = (uint32_t*)f->ranges.p;
-  prof_mark(ps, 2, st);
-  enqueue_association(st, op, n, items, nvis, E, ntiles, false, b);
+  enqueue_tile_lists(st, op, n, nvis, nullptr, E, nullptr, ntiles, b);
   HTRY(hipGetLastError());
 
   // ---- stage (c): render ----

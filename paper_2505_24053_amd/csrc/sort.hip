@@ -155,9 +155,9 @@ __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* _
   __syncthreads();
   uint32_t mine = 0u;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-    if (filter && filter[i] == 0u) continue;
+    const uint32_t f = filter ? filter[i] : 1u;  // both loads in flight together
     const uint32_t k = keys[i];
-    if (drop && k == kDropKey) continue;
+    if (f == 0u || (drop && k == kDropKey)) continue;
     ++mine;
     for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (shift0 + bits * p)) & dmask], 1u);
   }
@@ -195,18 +195,29 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
   if (blk >= os_blocks(n, kItems)) return;
   if (status_next) status_next[blk * 256 + tid] = 0u;  // this row is clear for the next pass
 
-  // stable ranks within the wave: wave w owns keys [base, base + 64 kPer)
+  // stable ranks within the wave: wave w owns keys [base, base + 64 kPer).
+  // Every slice's filter word, key and value are loaded first, from an index
+  // clamped into [0, n) (n > 0 here), so the loads are independent and in
+  // flight together; the ranking below only waits for them once.
   const int64_t base = blk * kItems + (int64_t)w * 64 * kPer;
   const uint64_t lt = lanemask_lt();
-  uint32_t key[kPer], val[kPer], rank[kPer];
+  uint32_t key[kPer], val[kPer], rank[kPer], flt[kPer];
+#pragma unroll
+  for (int sl = 0; sl < kPer; ++sl) {
+    const int64_t i = base + sl * 64 + lane;
+    const int64_t ic = i < n ? i : n - 1;
+    flt[sl] = filter ? filter[ic] : 1u;
+    key[sl] = keys_in[ic];
+    val[sl] = vals_in ? vals_in[ic] : (uint32_t)i;
+  }
   uint32_t act = 0u;
 #pragma unroll
   for (int sl = 0; sl < kPer; ++sl) {
     const int64_t i = base + sl * 64 + lane;
-    bool a = i < n && (!filter || filter[i] != 0u);
-    key[sl] = a ? keys_in[i] : 0u;
+    bool a = i < n && flt[sl] != 0u;
     if (drop) a = a && key[sl] != kDropKey;
-    val[sl] = a ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+    if (!a) key[sl] = 0u;
+    if (!a) val[sl] = 0u;
     const uint32_t d = (key[sl] >> shift) & dmask;
     uint64_t m = __builtin_amdgcn_ballot_w64(a);
 #pragma unroll
