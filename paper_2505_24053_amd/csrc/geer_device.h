@@ -478,7 +478,11 @@ __device__ __forceinline__ QuadCone half_tile_cone(const ViewDev& V, const float
 // <= Qc, the largest q that keeps sigma exp(-kappa/2) >= alpha_min (and,
 // with a fixed lambda, q <= qmax), and g_z > 0: a circular cone
 // |g_xy| <= tau g_z, tau^2 = Qc / (1 - Qc).  On the plane g_z = 1 that cone is
-// the disc |p| <= tau, and the part of the block's cone (spanned by the
+// the disc |p| <= tau.  When every corner is well in front (g_z > 0 and
+// |g_x| + |g_y| <= 16 g_z) the block's cone meets that plane in the convex
+// quad of the corners, and the test is the distance from the disc's centre
+// to that quad (the common case, about half the arithmetic).  Otherwise the
+// part of the block's cone (spanned by the
 // corners g_k) in front, g_z > 0, is the intersection of the four half-planes
 // n_k . (p, 1) >= 0 with n_k = g_k x g_(k+1) oriented inward (bounded or
 // not, whatever the signs of the corners' g_z).  The test is whether the
@@ -503,19 +507,53 @@ __device__ __forceinline__ bool cone_meets_quad(const float4& p0, const float4& 
   if (Qc >= 1.0f) return true;
   const float tau2 = Qc * __builtin_amdgcn_rcpf(1.0f - Qc);
   float g[4][3];
-  bool any_front = false;
+  bool bounded = true;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const float* d = C.d[k];
-    float gx = fmaf(G[2], d[2], fmaf(G[1], d[1], G[0] * d[0]));
-    float gy = fmaf(G[5], d[2], fmaf(G[4], d[1], G[3] * d[0]));
-    float gz = fmaf(G[8], d[2], fmaf(G[7], d[1], G[6] * d[0]));
-    const float m = fmaxf(fmaxf(fabsf(gx), fabsf(gy)), fabsf(gz));
+    g[k][0] = fmaf(G[2], d[2], fmaf(G[1], d[1], G[0] * d[0]));
+    g[k][1] = fmaf(G[5], d[2], fmaf(G[4], d[1], G[3] * d[0]));
+    g[k][2] = fmaf(G[8], d[2], fmaf(G[7], d[1], G[6] * d[0]));
+    bounded &= g[k][2] > 0.0f && fabsf(g[k][0]) + fabsf(g[k][1]) <= 16.0f * g[k][2];
+  }
+  if (bounded) {
+    // Every corner in front with |p| <= 16 sqrt 2 on the plane g_z = 1: the
+    // region is the convex quad of the corners p_k, and its distance from
+    // the disc's centre is zero when the centre is on the inner side of
+    // every edge, else the least distance to the four edge segments.
+    float vx[4], vy[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float iz = __builtin_amdgcn_rcpf(g[k][2]);
+      vx[k] = g[k][0] * iz;
+      vy[k] = g[k][1] * iz;
+    }
+    float best = INFINITY;
+    bool pos = true, neg = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int k1 = (k + 1) & 3;
+      const float ex = vx[k1] - vx[k], ey = vy[k1] - vy[k];
+      const float cr = fmaf(vx[k], ey, -vy[k] * ex);  // side of the centre
+      pos &= cr >= 0.0f;
+      neg &= cr <= 0.0f;
+      const float ee = fmaf(ex, ex, ey * ey);
+      float t = ee > 0.0f ? -fmaf(vx[k], ex, vy[k] * ey) * __builtin_amdgcn_rcpf(ee) : 0.0f;
+      t = fminf(fmaxf(t, 0.0f), 1.0f);
+      const float px = fmaf(t, ex, vx[k]), py = fmaf(t, ey, vy[k]);
+      best = fminf(best, fmaf(px, px, py * py));
+    }
+    return pos || neg || best <= fmaf(tau2, 0x1p-8f, tau2) + 0x1p-18f * (1.0f + best);
+  }
+  bool any_front = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float m = fmaxf(fmaxf(fabsf(g[k][0]), fabsf(g[k][1])), fabsf(g[k][2]));
     const float im = m > 0.0f ? __builtin_amdgcn_rcpf(m) : 0.0f;
-    g[k][0] = gx * im;
-    g[k][1] = gy * im;
-    g[k][2] = gz * im;
-    any_front |= gz > 0.0f;
+    any_front |= g[k][2] > 0.0f;
+    g[k][0] *= im;
+    g[k][1] *= im;
+    g[k][2] *= im;
   }
   if (!any_front) return false;  // every ray of the block has g_z <= 0
   float n[4][3];

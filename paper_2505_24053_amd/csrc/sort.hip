@@ -371,12 +371,16 @@ __global__ __launch_bounds__(kBlock) void tile_cones_kernel(const ViewDev* __res
     out[4 * t + k] = make_float4(Q.d[k][0], Q.d[k][1], Q.d[k][2], k == 0 ? (Q.valid ? 1.0f : 0.0f) : 0.0f);
 }
 
-// Each lane expands kExpandPer consecutive entries (one binary search for the
-// owner of its first entry; the tile position is derived once per owner and
-// then stepped along the rectangle's rows), the block stages its 2048 entries
-// in LDS and writes them back lane-striped so every store is coalesced.  With
-// `cull`, an entry whose Gaussian's contribution cone meets no ray of its
-// tile gets the tile id kDropKey and is left out by the tile sort.
+// Each lane expands kExpandPer consecutive entries; the block stages its
+// 2048 entries in LDS and writes them back lane-striped so every store is
+// coalesced.  With `cull`, an entry whose Gaussian's contribution cone meets
+// no ray of its tile gets the tile id kDropKey and is left out by the tile
+// sort.  Latency: one wave finds the owner of the block's first entry with a
+// 64-way search (a few dependent loads instead of ~log2 m), the owners'
+// offsets that can start inside the block are staged in LDS, where each lane
+// finds and walks its owners; the tile ids of all the lane's entries are
+// derived first, so each entry's tile cone is loaded one entry ahead of its
+// test.
 __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restrict__ items,
                                                         const uint32_t* __restrict__ offs, int64_t m_cap,
                                                         const unsigned long long* __restrict__ dyn_m,
@@ -389,74 +393,125 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
                                                         uint32_t* __restrict__ tiles_out,
                                                         uint32_t* __restrict__ items_out,
                                                         uint32_t* __restrict__ hparts, int hpass, int hbits) {
+  constexpr int kSpan = kBlock * kExpandPer;
   const int64_t m = dyn_count(m_cap, dyn_m);
   const int64_t total = dyn_count(total_cap, dyn_total);
-  __shared__ uint32_t s_tile[kBlock * kExpandPer];
-  __shared__ uint32_t s_item[kBlock * kExpandPer];
+  const int64_t block0 = (int64_t)blockIdx.x * kSpan;
+  if (block0 >= total || m <= 0) return;  // uniform over the block
+  __shared__ uint32_t s_tile[kSpan];
+  __shared__ uint32_t s_item[kSpan];
+  __shared__ uint32_t s_offs[kSpan + 1];  // offs[jlo + k]; past the last owner: 0xffffffff
   __shared__ uint32_t s_h[kHistPasses][256];  // this block's digit counts of the kept tile ids
   __shared__ uint32_t s_kept;
+  __shared__ int64_t s_jlo;
   if (hpass) {
 #pragma unroll
     for (int p = 0; p < kHistPasses; ++p) s_h[p][threadIdx.x] = 0u;
     if (threadIdx.x == 0) s_kept = 0u;
-    __syncthreads();
   }
+  if (threadIdx.x < 64) {
+    // owner of block0 (last j with offs[j] <= block0) in [lo, hi): each round
+    // probes 64 evenly spaced offsets; offs is increasing and offs[0] = 0
+    const int lane = threadIdx.x;
+    int64_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+      const int64_t step = (hi - lo + 63) / 64;
+      const int64_t idx = lo + (int64_t)lane * step;
+      const uint64_t le = __builtin_amdgcn_ballot_w64(idx < hi && (int64_t)offs[idx] <= block0);
+      lo += (int64_t)(63 - __builtin_clzll(le)) * step;  // lane 0 always holds
+      hi = min(lo + step, hi);
+    }
+    if (lane == 0) s_jlo = lo;
+  }
+  __syncthreads();
+  // every owner of an entry of the block is one of jlo .. jlo + kSpan - 1
+  const int64_t jlo = s_jlo;
+  const int64_t S = min<int64_t>(kSpan + 1, m - jlo);
+  for (int k = threadIdx.x; k < kSpan + 1; k += kBlock) s_offs[k] = k < S ? offs[jlo + k] : 0xffffffffu;
+  __syncthreads();
+
   uint32_t my_kept = 0u, run_d = 0u, run_n = 0u;  // run of equal upper digits along this lane's entries
-  const int64_t block0 = (int64_t)blockIdx.x * kBlock * kExpandPer;
   const int64_t e0 = block0 + (int64_t)threadIdx.x * kExpandPer;
   const bool fixed = op.lambda_mode == 1;
   if (e0 < total) {
-    // owner of e0: last j with offs[j] <= e0
-    int64_t lo = 0, hi = m;
+    const int cnt = (int)min<int64_t>(kExpandPer, total - e0);
+    // local owner of e0: last k with s_offs[k] <= e0; it is at most
+    // e0 - block0, since every owner covers at least one entry
+    int lo = 0, hi = (int)min<int64_t>(S, (int64_t)threadIdx.x * kExpandPer + 1);
     while (hi - lo > 1) {
-      int64_t mid = (lo + hi) >> 1;
-      if ((int64_t)offs[mid] <= e0) lo = mid; else hi = mid;
+      const int mid = (lo + hi) >> 1;
+      if ((int64_t)s_offs[mid] <= e0) lo = mid; else hi = mid;
     }
-    int64_t j = lo, cur = -1;
-    const int64_t e1 = min(e0 + kExpandPer, total);
-    uint32_t item = 0, tx = 0, ty = 0, tx0 = 0, tx1 = 0, row = 0, base = 0;
-    float4 p0, p1, p2, p3;
-    for (int64_t e = e0; e < e1; ++e) {
-      while (j + 1 < m && (int64_t)offs[j + 1] <= e) ++j;
-      if (j != cur) {
-        cur = j;
-        item = items[j];
-        const uint32_t local = (uint32_t)(e - (int64_t)offs[j]);
-        const uint2 r = rects[item];
-        tx0 = (r.x & 0xffffu) >> 1;
-        tx1 = (r.x >> 16) >> 1;
-        const uint32_t ty0 = (r.y & 0xffffu) >> 1;
-        const uint32_t wt = tx1 - tx0 + 1u;
-        const ViewDev& V = views[item / (uint32_t)n];
-        ty = ty0 + local / wt;
-        tx = tx0 + (local - (ty - ty0) * wt);
-        row = (uint32_t)V.tiles_x;
-        base = (uint32_t)V.tile_base;
-        if (cull) {
-          const float4* rp = reinterpret_cast<const float4*>(recs + item);
-          p0 = rp[0]; p1 = rp[1]; p2 = rp[2]; p3 = rp[3];
+    // tile ids and items of the lane's entries
+    uint32_t tile[kExpandPer], item[kExpandPer];
+    int jl = lo, cur = -1;
+    uint32_t it = 0, tx = 0, ty = 0, tx0 = 0, tx1 = 0, row = 0, base = 0;
+#pragma unroll
+    for (int k = 0; k < kExpandPer; ++k) {
+      tile[k] = kDropKey;
+      item[k] = 0u;
+      if (k < cnt) {
+        const int64_t e = e0 + k;
+        while ((int64_t)s_offs[jl + 1] <= e) ++jl;
+        if (jl != cur) {
+          cur = jl;
+          it = items[jlo + jl];
+          const uint32_t local = (uint32_t)(e - (int64_t)s_offs[jl]);
+          const uint2 r = rects[it];
+          tx0 = (r.x & 0xffffu) >> 1;
+          tx1 = (r.x >> 16) >> 1;
+          const uint32_t ty0 = (r.y & 0xffffu) >> 1;
+          const uint32_t wt = tx1 - tx0 + 1u;
+          const ViewDev& V = views[it / (uint32_t)n];
+          ty = ty0 + local / wt;
+          tx = tx0 + (local - (ty - ty0) * wt);
+          row = (uint32_t)V.tiles_x;
+          base = (uint32_t)V.tile_base;
+        } else if (++tx > tx1) {
+          tx = tx0;
+          ++ty;
         }
-      } else if (++tx > tx1) {
-        tx = tx0;
-        ++ty;
+        tile[k] = base + ty * row + tx;
+        item[k] = it;
       }
-      uint32_t tile = base + ty * row + tx;
-      if (cull) {
-        const float4* cp = tcones + 4 * (size_t)tile;
-        const float4 c0 = cp[0], c1 = cp[1], c2 = cp[2], c3 = cp[3];
+    }
+    if (cull) {
+      // the cone of entry k + 1 is loaded while entry k is tested
+      float4 c0 = tcones[4 * (size_t)tile[0]], c1 = tcones[4 * (size_t)tile[0] + 1];
+      float4 c2 = tcones[4 * (size_t)tile[0] + 2], c3 = tcones[4 * (size_t)tile[0] + 3];
+      const float4* rp = reinterpret_cast<const float4*>(recs + item[0]);
+      float4 p0 = rp[0], p1 = rp[1], p2 = rp[2], p3 = rp[3];
+#pragma unroll
+      for (int k = 0; k < kExpandPer; ++k) {
+        if (k >= cnt) break;
+        float4 n0 = c0, n1 = c1, n2 = c2, n3 = c3;
+        if (k + 1 < cnt) {
+          const float4* cp = tcones + 4 * (size_t)tile[k + 1];
+          n0 = cp[0]; n1 = cp[1]; n2 = cp[2]; n3 = cp[3];
+        }
+        if (k > 0 && item[k] != item[k - 1]) {
+          const float4* rq = reinterpret_cast<const float4*>(recs + item[k]);
+          p0 = rq[0]; p1 = rq[1]; p2 = rq[2]; p3 = rq[3];
+        }
         QuadCone Q;
         Q.d[0][0] = c0.x; Q.d[0][1] = c0.y; Q.d[0][2] = c0.z;
         Q.d[1][0] = c1.x; Q.d[1][1] = c1.y; Q.d[1][2] = c1.z;
         Q.d[2][0] = c2.x; Q.d[2][1] = c2.y; Q.d[2][2] = c2.z;
         Q.d[3][0] = c3.x; Q.d[3][1] = c3.y; Q.d[3][2] = c3.z;
         Q.valid = c0.w != 0.0f;
-        if (!cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, fixed)) tile = kDropKey;
+        if (!cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, fixed)) tile[k] = kDropKey;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
       }
-      if (hpass && tile != kDropKey) {
+    }
+#pragma unroll
+    for (int k = 0; k < kExpandPer; ++k) {
+      if (k >= cnt) break;
+      const uint32_t t = tile[k];
+      if (hpass && t != kDropKey) {
         ++my_kept;
-        atomicAdd(&s_h[0][tile & ((1u << hbits) - 1u)], 1u);
+        atomicAdd(&s_h[0][t & ((1u << hbits) - 1u)], 1u);
         if (hpass > 1) {
-          const uint32_t d1 = tile >> hbits;  // a kept tile id has at most 2 hbits bits
+          const uint32_t d1 = t >> hbits;  // a kept tile id has at most 2 hbits bits
           if (d1 != run_d) {
             if (run_n) atomicAdd(&s_h[1][run_d], run_n);
             run_d = d1;
@@ -465,9 +520,9 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
           ++run_n;
         }
       }
-      const int s = (int)(e - block0);
-      s_tile[s] = tile;
-      s_item[s] = item;
+      const int sl = threadIdx.x * kExpandPer + k;
+      s_tile[sl] = t;
+      s_item[sl] = item[k];
     }
   }
   if (hpass) {
@@ -485,11 +540,11 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   }
 #pragma unroll
   for (int k = 0; k < kExpandPer; ++k) {
-    const int s = k * kBlock + threadIdx.x;
-    const int64_t e = block0 + s;
+    const int sl = k * kBlock + threadIdx.x;
+    const int64_t e = block0 + sl;
     if (e < total) {
-      tiles_out[e] = s_tile[s];
-      items_out[e] = s_item[s];
+      tiles_out[e] = s_tile[sl];
+      items_out[e] = s_item[sl];
     }
   }
 }
