@@ -186,13 +186,16 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
   __shared__ uint32_t s_blk;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // The grid is sized for the capacity; blocks past the live key count leave
+  // before taking a ticket (the tickets, taken one at a time on one counter,
+  // then go to live blocks only, in arrival order, still 0, 1, ...).
+  const int64_t n = dyn_count(n_cap, dyn);
+  if ((int64_t)blockIdx.x >= os_blocks(n, kItems)) return;
   if (tid == 0) s_blk = atomicAdd(ticket, 1u);
 #pragma unroll
   for (int q = 0; q < 4; ++q) s_cnt[q][tid] = 0u;
   __syncthreads();
   const int64_t blk = s_blk;
-  const int64_t n = dyn_count(n_cap, dyn);
-  if (blk >= os_blocks(n, kItems)) return;
   if (status_next) status_next[blk * 256 + tid] = 0u;  // this row is clear for the next pass
 
   // stable ranks within the wave: wave w owns keys [base, base + 64 kPer).
@@ -371,6 +374,21 @@ __global__ __launch_bounds__(kBlock) void tile_cones_kernel(const ViewDev* __res
     out[4 * t + k] = make_float4(Q.d[k][0], Q.d[k][1], Q.d[k][2], k == 0 ? (Q.valid ? 1.0f : 0.0f) : 0.0f);
 }
 
+// floor(a / b), exact, for 0 < b and a quotient below 2^20 (here: a view
+// index, < 4096, and a row of a rectangle, < 2^15): the float estimate has a
+// relative error of a few 2^-24, so it is within one of the quotient, and one
+// integer step each way corrects it (q b <= a + b < 2^32).
+__device__ __forceinline__ uint32_t small_quotient(uint32_t a, uint32_t b) {
+  uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
+  if (q * b > a) --q;
+  else if (a - q * b >= b) ++q;
+  return q;
+}
+
+// LDS slot of staged entry i: one word of padding per 32 so that lanes
+// writing every kExpandPer-th entry hit distinct banks.
+__device__ __forceinline__ int stage_slot(int i) { return i + (i >> 5); }
+
 // Each lane expands kExpandPer consecutive entries; the block stages its
 // 2048 entries in LDS and writes them back lane-striped so every store is
 // coalesced.  With `cull`, an entry whose Gaussian's contribution cone meets
@@ -398,8 +416,8 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   const int64_t total = dyn_count(total_cap, dyn_total);
   const int64_t block0 = (int64_t)blockIdx.x * kSpan;
   if (block0 >= total || m <= 0) return;  // uniform over the block
-  __shared__ uint32_t s_tile[kSpan];
-  __shared__ uint32_t s_item[kSpan];
+  __shared__ uint32_t s_tile[kSpan + kSpan / 32];  // slots spread by stage_slot
+  __shared__ uint32_t s_item[kSpan + kSpan / 32];
   __shared__ uint32_t s_offs[kSpan + 1];  // offs[jlo + k]; past the last owner: 0xffffffff
   __shared__ uint32_t s_h[kHistPasses][256];  // this block's digit counts of the kept tile ids
   __shared__ uint32_t s_kept;
@@ -462,9 +480,10 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
           tx1 = (r.x >> 16) >> 1;
           const uint32_t ty0 = (r.y & 0xffffu) >> 1;
           const uint32_t wt = tx1 - tx0 + 1u;
-          const ViewDev& V = views[it / (uint32_t)n];
-          ty = ty0 + local / wt;
-          tx = tx0 + (local - (ty - ty0) * wt);
+          const ViewDev& V = views[small_quotient(it, (uint32_t)n)];
+          const uint32_t dy = small_quotient(local, wt);
+          ty = ty0 + dy;
+          tx = tx0 + (local - dy * wt);
           row = (uint32_t)V.tiles_x;
           base = (uint32_t)V.tile_base;
         } else if (++tx > tx1) {
@@ -520,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
           ++run_n;
         }
       }
-      const int sl = threadIdx.x * kExpandPer + k;
+      const int sl = stage_slot(threadIdx.x * kExpandPer + k);
       s_tile[sl] = t;
       s_item[sl] = item[k];
     }
@@ -543,8 +562,8 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
     const int sl = k * kBlock + threadIdx.x;
     const int64_t e = block0 + sl;
     if (e < total) {
-      tiles_out[e] = s_tile[sl];
-      items_out[e] = s_item[sl];
+      tiles_out[e] = s_tile[stage_slot(sl)];
+      items_out[e] = s_item[stage_slot(sl)];
     }
   }
 }
