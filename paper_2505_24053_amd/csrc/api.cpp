@@ -319,8 +319,7 @@ void enqueue_depth_order(hipStream_t st, const Opts& op, int64_t n, int64_t item
   // depth order of the visible items (pass 0 compacts them out of all items)
   radix_sort(st, b.keys, nullptr, b.counts, false, items, nullptr, nvis_cap, dV, 0, 4, b.ka, b.va, b.kb, b.vb,
              b.hist, nullptr, err);
-  launch_gather_counts(st, b.vb, nvis_cap, dV, b.counts, b.cnt_sorted);
-  scan_exclusive(st, b.cnt_sorted, b.cnt_sorted, nvis_cap, b.scratch);
+  gather_scan(st, b.vb, nvis_cap, dV, b.counts, b.cnt_sorted, b.scratch);
   if (op.cone_cull) launch_tile_cones(st, b.views, n > 0 ? (int)(items / n) : 1, b.dtab, ntiles, b.tcones);
 }
 

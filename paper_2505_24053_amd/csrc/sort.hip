@@ -93,6 +93,78 @@ __device__ __forceinline__ int64_t dyn_count(int64_t n_cap, const unsigned long 
   return dyn ? min((int64_t)*dyn, n_cap) : n_cap;
 }
 
+// ------------------------------------------------------ gathered scan --
+//
+// Exclusive scan of the gathered values counts[items[j]] (j < m; 0 for
+// m <= j < m_cap) in two kernels: the first gathers and sums each 4096-item
+// tile, the second adds up the sums of the tiles before its own (at most
+// kGatherScanTiles of them) and scans its tile.
+
+constexpr int kGatherScanTiles = 4096;
+
+__global__ __launch_bounds__(kBlock) void gather_reduce_kernel(const uint32_t* __restrict__ items, int64_t m_cap,
+                                                               const unsigned long long* __restrict__ dyn,
+                                                               const uint32_t* __restrict__ counts,
+                                                               uint32_t* __restrict__ out,
+                                                               uint32_t* __restrict__ sums) {
+  const int64_t m = dyn_count(m_cap, dyn);
+  const int64_t base = (int64_t)blockIdx.x * kTileItems;
+  uint32_t it[kPerThread];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {  // independent loads first
+    const int64_t i = base + k * kBlock + threadIdx.x;
+    it[k] = i < m ? items[i] : 0u;
+  }
+  uint32_t s = 0u;
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t i = base + k * kBlock + threadIdx.x;
+    const uint32_t v = i < m ? counts[it[k]] : 0u;
+    if (i < m_cap) out[i] = v;
+    s += v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  __shared__ uint32_t red[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(kBlock) void gathered_scan_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                               const uint32_t* __restrict__ sums,
+                                                               uint32_t* __restrict__ out) {
+  // carried-in offset: the sums of tiles 0 .. blockIdx.x - 1
+  uint32_t pre = 0u;
+  for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBlock) pre += sums[t];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
+  __shared__ uint32_t red[kBlock / 64], wsum[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
+  const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kPerThread;
+  uint32_t v[kPerThread];
+  uint32_t tsum = 0;
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t i = base + k;
+    v[k] = i < n ? in[i] : 0u;
+    tsum += v[k];
+  }
+  const uint32_t incl = wave_incl_scan(tsum);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  uint32_t wpre = 0;
+  for (int w = 0; w < wv; ++w) wpre += wsum[w];
+  uint32_t run = red[0] + red[1] + red[2] + red[3] + wpre + incl - tsum;
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t i = base + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+}
+
 // ----------------------------------------------------------------- radix --
 //
 // Stable LSD radix sort with 8-bit digits, one kernel per pass ("onesweep"
@@ -704,6 +776,21 @@ void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, 
   if (m_cap <= 0) return;
   hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(m_cap, kBlock)), dim3(kBlock), 0, st, items, m_cap, dyn,
                      counts, out);
+}
+
+void gather_scan(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
+                 const uint32_t* counts, uint32_t* out, uint32_t* scratch) {
+  if (m_cap <= 0) return;
+  const int64_t nb = (m_cap + kTileItems - 1) / kTileItems;
+  if (nb > kGatherScanTiles) {
+    launch_gather_counts(st, items, m_cap, dyn, counts, out);
+    scan_exclusive(st, out, out, m_cap, scratch);
+    return;
+  }
+  hipLaunchKernelGGL(gather_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, items, m_cap, dyn, counts, out,
+                     scratch);
+  hipLaunchKernelGGL(gathered_scan_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, out, m_cap,
+                     (const uint32_t*)scratch, out);
 }
 
 void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,

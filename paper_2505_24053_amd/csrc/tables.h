@@ -36,6 +36,10 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
                 const uint32_t* hparts = nullptr, int bits = 8);
 void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
                           const uint32_t* counts, uint32_t* out);
+// out = exclusive scan of counts[items[j]] (j < live count, 0 up to m_cap);
+// scratch: scan_scratch_words(m_cap) words
+void gather_scan(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
+                 const uint32_t* counts, uint32_t* out, uint32_t* scratch);
 void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,
                        float4* out);
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
