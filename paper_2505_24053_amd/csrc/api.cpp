@@ -274,6 +274,13 @@ TileDigits tile_digits(int64_t ntiles) {
   return TileDigits{passes, (tbits + passes - 1) / passes};
 }
 
+// Tile-sort passes whose digit histograms the expansion counts (0: an upsweep
+// counts them).
+int hist_passes(int64_t ntiles) {
+  const int p = tile_digits(ntiles).passes;
+  return p <= 2 ? p : 0;
+}
+
 
 // Device pointers of one forward.
 struct FwdBufs {
@@ -289,6 +296,7 @@ struct FwdBufs {
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr, *hist = nullptr, *scratch = nullptr;
   uint32_t *cnt_sorted = nullptr, *tiles_a = nullptr, *tiles_b = nullptr, *items_b = nullptr;
   uint32_t *list = nullptr, *ranges = nullptr, *nlast = nullptr;
+  bool depth_work_zeroed = false;  // the preprocess launch clears the depth sort's work area
   float* tfinal = nullptr;
   uint32_t *heavy_list = nullptr, *heavy_flag = nullptr;  // heavy-tile work list
   int hmax = 0;
@@ -303,7 +311,11 @@ struct FwdBufs {
 // With per_view_stats the counters of view v are the 8 words at b.stats + 8v.
 void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, const Opts& op, const float* lam,
                         const FwdBufs& b, bool per_view_stats = false) {
-  launch_fill_u32(st, (uint32_t*)b.stats, per_view_stats ? 16 * nviews : 16, 0u);
+  const int64_t nst = per_view_stats ? 16 * nviews : 16;
+  if (b.depth_work_zeroed)
+    launch_zero2_u32(st, (uint32_t*)b.stats, nst, b.hist, radix_zero_words(std::max<int64_t>(sc.n * nviews, 1)));
+  else
+    launch_fill_u32(st, (uint32_t*)b.stats, nst, 0u);
   launch_preprocess(st, sc.n, nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh, b.views, op, lam,
                     b.edges, b.recs, b.rects, b.keys, b.counts, (unsigned long long*)b.stats, per_view_stats ? 8 : 0);
 }
@@ -318,9 +330,14 @@ void enqueue_depth_order(hipStream_t st, const Opts& op, int64_t n, int64_t item
   unsigned long long* err = (unsigned long long*)(b.stats + 4);
   // depth order of the visible items (pass 0 compacts them out of all items)
   radix_sort(st, b.keys, nullptr, b.counts, false, items, nullptr, nvis_cap, dV, 0, 4, b.ka, b.va, b.kb, b.vb,
-             b.hist, nullptr, err);
+             b.hist, nullptr, err, nullptr, 8, b.depth_work_zeroed);
   gather_scan(st, b.vb, nvis_cap, dV, b.counts, b.cnt_sorted, b.scratch);
-  if (op.cone_cull) launch_tile_cones(st, b.views, n > 0 ? (int)(items / n) : 1, b.dtab, ntiles, b.tcones);
+  // the tile cones' launch also clears the expansion's partial histograms
+  if (op.cone_cull) {
+    const int hp = hist_passes(ntiles);
+    launch_tile_cones(st, b.views, n > 0 ? (int)(items / n) : 1, b.dtab, ntiles, b.tcones, hp ? b.hparts : nullptr,
+                      hp ? hist_parts_words() : 0);
+  }
 }
 
 // Second half: expansion, tile sort and ranges.  dV / dE: live counts on the
@@ -344,15 +361,14 @@ void enqueue_tile_lists(hipStream_t st, const Opts& op, int64_t n, int64_t nvis_
     uint32_t* ai = (passes % 2 == 1) ? pi : qi;
     // the expansion also counts the tile digits of the kept entries (one or
     // two passes), which replaces the sort's histogram pass over the list
-    const int hpass = passes <= 2 ? passes : 0;
-    if (hpass) launch_fill_u32(st, b.hparts, hist_parts_words(), 0u);
+    const int hpass = hist_passes(ntiles);
+    if (hpass && !op.cone_cull) launch_fill_u32(st, b.hparts, hist_parts_words(), 0u);  // else cleared already
     launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, b.tcones, b.recs, op, tin,
                   iin, b.hparts, hpass, td.bits);
     radix_sort(st, tin, iin, nullptr, op.cone_cull != 0, ecap, dE, ecap, kept, 0, passes, at, ai, tin, iin, b.hist,
                kept, err, hpass ? b.hparts : nullptr, td.bits);
     uint32_t* tfinal = (passes % 2 == 1) ? at : tin;
-    launch_pad_list(st, b.list, ecap, kept);
-    launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges);
+    launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges, b.list);
   } else {
     launch_fill_u32(st, b.list, 8, 0u);
     launch_ranges(st, nullptr, 0, nullptr, ntiles, b.ranges);
@@ -586,6 +602,23 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   b.keys = (uint32_t*)f->keys.p;
   b.counts = (uint32_t*)f->counts.p;
   b.stats = (uint64_t*)f->stats.p;
+  // depth-sort buffers, sized for all items (the visible count is read on
+  // the device); the preprocess launch also clears the sort's work area
+  const int64_t hist_items = radix_work_words(it1);
+  TRY(acquire(c, 4 * it1, st, ka));
+  TRY(acquire(c, 4 * it1, st, va));
+  TRY(acquire(c, 4 * it1, st, kb));
+  TRY(acquire(c, 4 * it1, st, vb));
+  TRY(acquire(c, 4 * (size_t)hist_items, st, hist));
+  TRY(acquire(c, 4 * (size_t)scan_scratch_words(it1), st, scratch));
+  TRY(acquire(c, 4 * it1, st, cnt_sorted));
+  TRY(acquire(c, 64 * (size_t)std::max<int64_t>(ntiles, 1), st, tcones));
+  TRY(acquire(c, 4 * (size_t)hist_parts_words(), st, hparts));
+  b.tcones = (float4*)tcones.p;
+  b.hparts = (uint32_t*)hparts.p;
+  b.ka = (uint32_t*)ka.p; b.va = (uint32_t*)va.p; b.kb = (uint32_t*)kb.p; b.vb = (uint32_t*)vb.p;
+  b.hist = (uint32_t*)hist.p; b.scratch = (uint32_t*)scratch.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
+  b.depth_work_zeroed = true;
   ProfSlot* ps = prof_slot(c);
   prof_mark(ps, 0, st);
   enqueue_preprocess(st, *scene, n_views, op, lt.dev, b);
@@ -600,18 +633,6 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   HTRY(hipEventRecord(c->totals_ready, st));
 
   // ---- stage (b): depth sort, expansion, tile sort, ranges ----
-  const int64_t hist_items = radix_work_words(it1);
-  TRY(acquire(c, 4 * it1, st, ka));
-  TRY(acquire(c, 4 * it1, st, va));
-  TRY(acquire(c, 4 * it1, st, kb));
-  TRY(acquire(c, 4 * it1, st, vb));
-  TRY(acquire(c, 4 * (size_t)hist_items, st, hist));
-  TRY(acquire(c, 4 * (size_t)scan_scratch_words(it1), st, scratch));
-  TRY(acquire(c, 4 * it1, st, cnt_sorted));
-  TRY(acquire(c, 64 * (size_t)std::max<int64_t>(ntiles, 1), st, tcones));
-  b.tcones = (float4*)tcones.p;
-  b.ka = (uint32_t*)ka.p; b.va = (uint32_t*)va.p; b.kb = (uint32_t*)kb.p; b.vb = (uint32_t*)vb.p;
-  b.hist = (uint32_t*)hist.p; b.scratch = (uint32_t*)scratch.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
   prof_mark(ps, 2, st);
   enqueue_depth_order(st, op, n, items, items, (const unsigned long long*)(b.stats + 1), ntiles, b);
   HTRY(hipGetLastError());
@@ -636,8 +657,6 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   TRY(acquire(c, 4 * (e1 + 8), st, f->list));
   TRY(acquire(c, 4 * (e1 + 8), st, items_b));
   TRY(acquire(c, 4 * (ntiles + 1), st, f->ranges));
-  TRY(acquire(c, 4 * (size_t)hist_parts_words(), st, hparts));
-  b.hparts = (uint32_t*)hparts.p;
   b.tiles_a = (uint32_t*)tiles_a.p; b.tiles_b = (uint32_t*)tiles_b.p; b.items_b = (uint32_t*)items_b.p;
   b.list = (uint32_t*)f->list.p; b.ranges = (uint32_t*)f->ranges.p;
   enqueue_tile_lists(st, op, n, nvis, nullptr, E, nullptr, ntiles, b);
@@ -1024,6 +1043,7 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
   PHIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
+    b.depth_work_zeroed = true;
     enqueue_preprocess(cs, P->scene, n_views, P->op, lt.dev, b);
     enqueue_association(cs, P->op, P->n, items, std::max<int64_t>(items, 1), entry_capacity, P->ntiles, true, b);
     enqueue_render(cs, P->op, P->ntiles, n_views, b, rgb, depth, trans);

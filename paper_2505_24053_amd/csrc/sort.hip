@@ -432,8 +432,10 @@ constexpr int kExpandPer = 8;
 // cone's validity in .w of entry 0.
 __global__ __launch_bounds__(kBlock) void tile_cones_kernel(const ViewDev* __restrict__ views, int nviews,
                                                             const float2* __restrict__ dtab, int64_t ntiles,
-                                                            float4* __restrict__ out) {
+                                                            float4* __restrict__ out, uint32_t* __restrict__ zero,
+                                                            int64_t nzero) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < nzero) zero[t] = 0u;  // a buffer the next kernels accumulate into
   if (t >= ntiles) return;
   int v = 0;
   while (v + 1 < nviews && t >= views[v + 1].tile_base) ++v;
@@ -640,12 +642,16 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   }
 }
 
+// Tile ranges of the sorted tile ids; with `list`, also list[total ..
+// total + 8) = 0 (padding read by the render's window loads).
 __global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t* __restrict__ tiles, int64_t total_cap,
                                                         const unsigned long long* __restrict__ dyn,
-                                                        int64_t ntiles, uint32_t* __restrict__ ranges) {
+                                                        int64_t ntiles, uint32_t* __restrict__ ranges,
+                                                        uint32_t* __restrict__ list) {
   const int64_t total = dyn_count(total_cap, dyn);
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const int64_t e0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (list && e0 < 8) list[total + e0] = 0u;
   if (total == 0) {
     for (int64_t t = e0; t <= ntiles; t += stride) ranges[t] = 0u;
     return;
@@ -665,13 +671,14 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* __restrict__
   if (i < n) p[i] = v;
 }
 
-// list[total .. total + 8) = 0 with total read on the device (padding read by
-// the render's 8-aligned batches); total is clamped to the capacity.
-__global__ void pad_list_kernel(uint32_t* __restrict__ list, int64_t total_cap,
-                                const unsigned long long* __restrict__ dyn) {
-  const int64_t total = dyn_count(total_cap, dyn);
-  if (threadIdx.x < 8) list[total + threadIdx.x] = 0u;
+// p1[0 .. n1) = 0 and p2[0 .. n2) = 0 in one launch.
+__global__ __launch_bounds__(kBlock) void zero2_u32_kernel(uint32_t* __restrict__ p1, int64_t n1,
+                                                           uint32_t* __restrict__ p2, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n1) p1[i] = 0u;
+  else if (i - n1 < n2) p2[i - n1] = 0u;
 }
+
 
 // Capacity guard of capacity-sized launches: stats[3] keeps the entry count;
 // when it exceeds the capacity, the entry and visible counts are cleared so
@@ -726,10 +733,15 @@ int64_t radix_work_words(int64_t n_cap) { return kWorkHead + 2 * 256 * ((n_cap +
 // keys, counting the rest into *kept when given; later passes read n1 keys
 // (the filtered count, read on the device when dyn1 is given).  Passes write
 // A, B, A, ...: the result is in A for odd npass, in B for even.
+int64_t radix_zero_words(int64_t nmax) {
+  const int items = kBlock * (nmax >= kOSBigKeys ? kOSPerBig : kOSPer);
+  return kWorkHead + 256 * os_blocks(nmax, items);
+}
+
 void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, bool drop,
                 int64_t n0_cap, const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1,
                 int shift0, int npass, uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work,
-                unsigned long long* kept, unsigned long long* err, const uint32_t* hparts, int bits) {
+                unsigned long long* kept, unsigned long long* err, const uint32_t* hparts, int bits, bool zeroed) {
   if (n0_cap <= 0 || npass <= 0) return;
   const int64_t nmax = std::max(n0_cap, n1_cap);
   // chunks of 4096 keys for large sorts: runs of one digit per chunk are
@@ -748,8 +760,9 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
                        (int64_t)kWorkHead + rows, hparts, npass, kept);
   } else {
     // histograms, tickets and the first status table start at zero
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
-                       (int64_t)kWorkHead + rows, 0u);
+    if (!zeroed)
+      hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
+                         (int64_t)kWorkHead + rows, 0u);
     // few blocks: every block adds its counts to the same 256 words per pass
     const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(n0_cap, kBlock), 1), 256);
     hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, in_k, filter, drop ? 1 : 0, n0_cap,
@@ -794,10 +807,10 @@ void gather_scan(hipStream_t st, const uint32_t* items, int64_t m_cap, const uns
 }
 
 void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,
-                       float4* out) {
-  if (ntiles <= 0) return;
-  hipLaunchKernelGGL(tile_cones_kernel, dim3(grid_for(ntiles, kBlock)), dim3(kBlock), 0, st, views, nviews, dtab,
-                     ntiles, out);
+                       float4* out, uint32_t* zero, int64_t nzero) {
+  if (ntiles <= 0 && nzero <= 0) return;
+  hipLaunchKernelGGL(tile_cones_kernel, dim3(grid_for(std::max(ntiles, nzero), kBlock)), dim3(kBlock), 0, st, views,
+                     nviews, dtab, ntiles, out, zero, nzero);
 }
 
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
@@ -812,7 +825,7 @@ void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, 
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
-                   int64_t ntiles, uint32_t* ranges) {
+                   int64_t ntiles, uint32_t* ranges, uint32_t* list) {
   if (total_cap <= 0 && !dyn) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(ntiles + 1, kBlock)), dim3(kBlock), 0, st, ranges, ntiles + 1,
                        0u);
@@ -820,15 +833,16 @@ void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, con
   }
   const int64_t g = std::max<int64_t>(total_cap, ntiles + 1);
   hipLaunchKernelGGL(ranges_kernel, dim3(std::min<unsigned>(grid_for(g, kBlock), 8192u)), dim3(kBlock), 0, st, tiles,
-                     total_cap, dyn, ntiles, ranges);
+                     total_cap, dyn, ntiles, ranges, list);
 }
 
 void launch_capacity_guard(hipStream_t st, unsigned long long* stats, int64_t cap) {
   hipLaunchKernelGGL(capacity_guard_kernel, dim3(1), dim3(64), 0, st, stats, cap);
 }
 
-void launch_pad_list(hipStream_t st, uint32_t* list, int64_t total_cap, const unsigned long long* dyn) {
-  hipLaunchKernelGGL(pad_list_kernel, dim3(1), dim3(64), 0, st, list, total_cap, dyn);
+void launch_zero2_u32(hipStream_t st, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2) {
+  if (n1 + n2 <= 0) return;
+  hipLaunchKernelGGL(zero2_u32_kernel, dim3(grid_for(n1 + n2, kBlock)), dim3(kBlock), 0, st, p1, n1, p2, n2);
 }
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v) {

@@ -33,24 +33,29 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
                 int64_t n0_cap, const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1,
                 int shift0, int npass, uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work,
                 unsigned long long* kept, unsigned long long* err,
-                const uint32_t* hparts = nullptr, int bits = 8);
+                const uint32_t* hparts = nullptr, int bits = 8, bool zeroed = false);
+// Words of a sort's work area (for up to nmax keys) that must start at zero;
+// radix_sort(..., zeroed = true) expects them cleared already.
+int64_t radix_zero_words(int64_t nmax);
 void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
                           const uint32_t* counts, uint32_t* out);
 // out = exclusive scan of counts[items[j]] (j < live count, 0 up to m_cap);
 // scratch: scan_scratch_words(m_cap) words
 void gather_scan(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
                  const uint32_t* counts, uint32_t* out, uint32_t* scratch);
+// also zero[0 .. nzero) = 0
 void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,
-                       float4* out);
+                       float4* out, uint32_t* zero, int64_t nzero);
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
                    const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* hparts, int hpass,
                    int hbits);
 int hist_parts_words();
+// with list: also zeroes the 8 words of padding after the list
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
-                   int64_t ntiles, uint32_t* ranges);
-void launch_pad_list(hipStream_t st, uint32_t* list, int64_t total_cap, const unsigned long long* dyn);
+                   int64_t ntiles, uint32_t* ranges, uint32_t* list = nullptr);
+void launch_zero2_u32(hipStream_t st, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2);
 void launch_capacity_guard(hipStream_t st, unsigned long long* stats, int64_t cap);
 void launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v);
 
