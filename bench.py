@@ -51,18 +51,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+# Sources the render kernel is compiled from (its own file and the headers
+# holding its device code).
+RENDER_SOURCES = ("render.hip", "geer_device.h", "geer_common.h")
 
 
-def traffic_record(kernel_src):
+def source_hash(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(csrc_dir):
     """HBM bytes per render launch from the committed rocprofv3 PMC summary,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the kernel's sources changed since the counters were taken."""
     p = os.path.join(ROOT, "profiles", "render_fisheye100k_pmc.json")
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
-    if rec.get("render_src_sha") != source_hash(kernel_src):
+    if rec.get("render_src_sha") != source_hash([os.path.join(csrc_dir, f) for f in RENDER_SOURCES]):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -301,7 +309,7 @@ def main():
     st = frame.stats()
     frame.release()
     per_tile = np.diff(ranges)
-    traffic = traffic_record(os.path.join(ROOT, "paper_2505_24053_amd", "csrc", "render.hip"))
+    traffic = traffic_record(os.path.join(ROOT, "paper_2505_24053_amd", "csrc"))
     roofline = {"kernel": "render_kernel", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS, 4),
                 "traffic": traffic, "launch_ms": round(ms_render, 4), "evaluated_pairs": int(n_eval),
