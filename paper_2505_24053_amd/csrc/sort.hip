@@ -169,16 +169,20 @@ __global__ __launch_bounds__(kBlock) void gathered_scan_kernel(const uint32_t* _
 //
 // Stable LSD radix sort with 8-bit digits, one kernel per pass ("onesweep"
 // with decoupled look-back).  An upsweep kernel first counts the digits of
-// every pass over the (filtered) input.  In a pass, each block takes the next
-// 2048-key chunk in the order blocks start (an atomic ticket, so every block
-// it waits on is already running), ranks its keys stably (per wave: ballot
+// every pass over the (filtered) input.  In a pass, block b takes the b-th
+// 2048-key chunk, ranks its keys stably (per wave: ballot
 // match on the digit; across waves and slices: running counts in LDS),
 // publishes its per-digit counts, and walks back over earlier blocks'
 // published counts -- stopping at the first that already holds its inclusive
 // prefix -- to find where its run of each digit starts.  Keys are then
 // reordered by digit in LDS and written out as contiguous runs.  A status
 // word is [flag:2 | count:30]; the look-back spin is bounded and reports a
-// stall through an error word instead of hanging.
+// stall through an error word instead of hanging.  A block waits only on
+// blocks with lower indices, and each XCD dispatches the workgroups of a
+// launch in index order, so the lowest unfinished block is always resident
+// and the walk always ends.  (A per-block atomic ticket would serialise:
+// tickets come one at a time off one counter, which staggers the 692 blocks
+// of a 2.8M-key pass over about 9 us.)
 
 constexpr int kLookBack = 16;  // statuses read per look-back round
 constexpr int kOSPer = 8;                       // keys per thread (small sorts)
@@ -187,7 +191,7 @@ constexpr int kOSPerBig = 16;                   // keys per thread from kOSBigKe
 constexpr int64_t kOSBigKeys = 1 << 20;
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr int kWorkHead = 1024 + 64;            // histograms of 4 passes + 4 tickets (padded)
+constexpr int kWorkHead = 1024 + 64;            // histograms of 4 passes (padded)
 
 __host__ __device__ __forceinline__ int64_t os_blocks(int64_t n, int items) { return (n + items - 1) / items; }
 
@@ -247,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, const uint32_t* __restrict__ filter,
     int drop, int64_t n_cap, const unsigned long long* __restrict__ dyn, int shift, uint32_t dmask,
     const uint32_t* __restrict__ ghist_p,
-    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next, uint32_t* __restrict__ ticket,
+    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, unsigned long long* __restrict__ err) {
   __shared__ uint32_t s_cnt[4][256];  // per-wave running digit counts, then per-wave offsets
   __shared__ uint32_t s_loc[256];     // block-local start of each digit
@@ -255,19 +259,15 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
   constexpr int kItems = kBlock * kPer;
   __shared__ uint32_t s_key[kItems], s_val[kItems];
   __shared__ uint32_t s_w[4];
-  __shared__ uint32_t s_blk;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // The grid is sized for the capacity; blocks past the live key count leave
-  // before taking a ticket (the tickets, taken one at a time on one counter,
-  // then go to live blocks only, in arrival order, still 0, 1, ...).
+  // the grid is sized for the capacity: blocks past the live key count leave
   const int64_t n = dyn_count(n_cap, dyn);
-  if ((int64_t)blockIdx.x >= os_blocks(n, kItems)) return;
-  if (tid == 0) s_blk = atomicAdd(ticket, 1u);
+  const int64_t blk = blockIdx.x;
+  if (blk >= os_blocks(n, kItems)) return;
 #pragma unroll
   for (int q = 0; q < 4; ++q) s_cnt[q][tid] = 0u;
   __syncthreads();
-  const int64_t blk = s_blk;
   if (status_next) status_next[blk * 256 + tid] = 0u;  // this row is clear for the next pass
 
   // stable ranks within the wave: wave w owns keys [base, base + 64 kPer).
@@ -723,7 +723,7 @@ void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n
                      out);
 }
 
-// Workspace of radix_sort, in u32 words: histograms and tickets, then two
+// Workspace of radix_sort, in u32 words: histograms, then two
 // status tables of 256 words per 2048-key block.
 int64_t radix_work_words(int64_t n_cap) { return kWorkHead + 2 * 256 * ((n_cap + kOSItems - 1) / kOSItems); }
 
@@ -751,15 +751,14 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
   const int64_t rows = 256 * os_blocks(nmax, items);
   const uint32_t dmask = (1u << bits) - 1u;
   uint32_t* ghist = work;
-  uint32_t* tickets = work + 1024;
   uint32_t* stat[2] = {work + kWorkHead, work + kWorkHead + rows};
   if (hparts) {
     // the producer already counted the digits into partial histograms:
-    // sum them into the histograms, clear tickets and the first status table
+    // sum them into the histograms, clear the first status table
     hipLaunchKernelGGL(hist_prepare_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
                        (int64_t)kWorkHead + rows, hparts, npass, kept);
   } else {
-    // histograms, tickets and the first status table start at zero
+    // histograms and the first status table start at zero
     if (!zeroed)
       hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
                          (int64_t)kWorkHead + rows, 0u);
@@ -778,7 +777,7 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
     auto kern = big ? radix_onesweep_kernel<kOSPerBig> : radix_onesweep_kernel<kOSPer>;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, sk, sv, p == 0 ? filter : nullptr, (p == 0 && drop) ? 1 : 0,
                        ncap, dy, shift0 + bits * p, dmask, (const uint32_t*)(ghist + 256 * p), stat[p % 2],
-                       p + 1 < npass ? stat[(p + 1) % 2] : nullptr, tickets + p, ok, ov, err);
+                       p + 1 < npass ? stat[(p + 1) % 2] : nullptr, ok, ov, err);
     sk = ok;
     sv = ov;
   }
