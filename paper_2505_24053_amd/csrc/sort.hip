@@ -185,10 +185,19 @@ __global__ __launch_bounds__(kBlock) void gathered_scan_kernel(const uint32_t* _
 // of a 2.8M-key pass over about 9 us.)
 
 constexpr int kLookBack = 16;  // statuses read per look-back round
-constexpr int kOSPer = 8;                       // keys per thread (small sorts)
-constexpr int kOSItems = kBlock * kOSPer;       // 2048 keys per block: the smallest chunk
+constexpr int kOSPerSmall = 4;                  // keys per thread below kOSSmallKeys keys
+constexpr int64_t kOSSmallKeys = 1 << 18;
+constexpr int kOSPer = 8;                       // keys per thread (mid-size sorts)
 constexpr int kOSPerBig = 16;                   // keys per thread from kOSBigKeys keys on
 constexpr int64_t kOSBigKeys = 1 << 20;
+constexpr int kOSItems = kBlock * kOSPerSmall;  // 1024 keys per block: the smallest chunk
+
+// Keys per thread of a sort of up to nmax keys: small sorts take small chunks
+// (more blocks, each with a shorter chain of loads, ranking and scatter),
+// large ones long chunks (longer runs of one digit per chunk).
+__host__ __device__ __forceinline__ int os_per(int64_t nmax) {
+  return nmax < kOSSmallKeys ? kOSPerSmall : nmax < kOSBigKeys ? kOSPer : kOSPerBig;
+}
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr int kWorkHead = 1024 + 64;            // histograms of 4 passes (padded)
@@ -734,7 +743,7 @@ int64_t radix_work_words(int64_t n_cap) { return kWorkHead + 2 * 256 * ((n_cap +
 // (the filtered count, read on the device when dyn1 is given).  Passes write
 // A, B, A, ...: the result is in A for odd npass, in B for even.
 int64_t radix_zero_words(int64_t nmax) {
-  const int items = kBlock * (nmax >= kOSBigKeys ? kOSPerBig : kOSPer);
+  const int items = kBlock * os_per(nmax);
   return kWorkHead + 256 * os_blocks(nmax, items);
 }
 
@@ -744,10 +753,8 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
                 unsigned long long* kept, unsigned long long* err, const uint32_t* hparts, int bits, bool zeroed) {
   if (n0_cap <= 0 || npass <= 0) return;
   const int64_t nmax = std::max(n0_cap, n1_cap);
-  // chunks of 4096 keys for large sorts: runs of one digit per chunk are
-  // twice as long, so the scattered writes cover more of each cache line
-  const bool big = nmax >= kOSBigKeys;
-  const int items = kBlock * (big ? kOSPerBig : kOSPer);
+  const int per = os_per(nmax);  // chunk size by sort size
+  const int items = kBlock * per;
   const int64_t rows = 256 * os_blocks(nmax, items);
   const uint32_t dmask = (1u << bits) - 1u;
   uint32_t* ghist = work;
@@ -774,7 +781,9 @@ void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, cons
     const int64_t ncap = p == 0 ? n0_cap : n1_cap;
     const unsigned long long* dy = p == 0 ? dyn0 : dyn1;
     const unsigned nb = (unsigned)std::max<int64_t>(os_blocks(ncap, items), 1);
-    auto kern = big ? radix_onesweep_kernel<kOSPerBig> : radix_onesweep_kernel<kOSPer>;
+    auto kern = per == kOSPerBig ? radix_onesweep_kernel<kOSPerBig>
+                : per == kOSPer      ? radix_onesweep_kernel<kOSPer>
+                                     : radix_onesweep_kernel<kOSPerSmall>;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, sk, sv, p == 0 ? filter : nullptr, (p == 0 && drop) ? 1 : 0,
                        ncap, dy, shift0 + bits * p, dmask, (const uint32_t*)(ghist + 256 * p), stat[p % 2],
                        p + 1 < npass ? stat[(p + 1) % 2] : nullptr, ok, ov, err);
