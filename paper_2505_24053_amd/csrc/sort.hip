@@ -131,9 +131,25 @@ __global__ __launch_bounds__(kBlock) void gather_reduce_kernel(const uint32_t* _
   if (threadIdx.x == 0) sums[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// LDS slot of item i of a 4096-item tile: one word of padding per 16, so the
+// 16 consecutive items of each thread start on distinct banks.
+__device__ __forceinline__ int scan_slot(int i) { return i + (i >> 4); }
+
+// kStaged: the tile goes through LDS so that global loads and stores are
+// lane-striped (coalesced); worth its barrier from a few dozen tiles on.
+template <bool kStaged>
 __global__ __launch_bounds__(kBlock) void gathered_scan_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                const uint32_t* __restrict__ sums,
                                                                uint32_t* __restrict__ out) {
+  __shared__ uint32_t s_v[kStaged ? kTileItems + kTileItems / 16 : 1];
+  const int64_t tile0 = (int64_t)blockIdx.x * kTileItems;
+  if (kStaged) {
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int li = k * kBlock + threadIdx.x;
+      s_v[scan_slot(li)] = tile0 + li < n ? in[tile0 + li] : 0u;
+    }
+  }
   // carried-in offset: the sums of tiles 0 .. blockIdx.x - 1
   uint32_t pre = 0u;
   for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBlock) pre += sums[t];
@@ -141,13 +157,15 @@ __global__ __launch_bounds__(kBlock) void gathered_scan_kernel(const uint32_t* _
   for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
   __shared__ uint32_t red[kBlock / 64], wsum[kBlock / 64];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
-  const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kPerThread;
+  __syncthreads();
+  // each thread scans 16 consecutive items
+  const int lbase = threadIdx.x * kPerThread;
   uint32_t v[kPerThread];
   uint32_t tsum = 0;
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
-    const int64_t i = base + k;
-    v[k] = i < n ? in[i] : 0u;
+    if (kStaged) v[k] = s_v[scan_slot(lbase + k)];
+    else v[k] = tile0 + lbase + k < n ? in[tile0 + lbase + k] : 0u;
     tsum += v[k];
   }
   const uint32_t incl = wave_incl_scan(tsum);
@@ -157,11 +175,24 @@ __global__ __launch_bounds__(kBlock) void gathered_scan_kernel(const uint32_t* _
   uint32_t wpre = 0;
   for (int w = 0; w < wv; ++w) wpre += wsum[w];
   uint32_t run = red[0] + red[1] + red[2] + red[3] + wpre + incl - tsum;
+  if (!kStaged) {
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      if (tile0 + lbase + k < n) out[tile0 + lbase + k] = run;
+      run += v[k];
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
-    const int64_t i = base + k;
-    if (i < n) out[i] = run;
+    s_v[scan_slot(lbase + k)] = run;  // only this thread's slots: no barrier before
     run += v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int li = k * kBlock + threadIdx.x;
+    if (tile0 + li < n) out[tile0 + li] = s_v[scan_slot(li)];
   }
 }
 
@@ -239,12 +270,35 @@ __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* _
   if (threadIdx.x == 0) s_kept = 0u;
   __syncthreads();
   uint32_t mine = 0u;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-    const uint32_t f = filter ? filter[i] : 1u;  // both loads in flight together
-    const uint32_t k = keys[i];
-    if (f == 0u || (drop && k == kDropKey)) continue;
-    ++mine;
-    for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (shift0 + bits * p)) & dmask], 1u);
+  // grid-stride; with many keys per thread, 8 keys per step with all their
+  // loads in flight together
+  constexpr int kUp = 8;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  if (n <= 2 * stride) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+      const uint32_t f = filter ? filter[i] : 1u;
+      const uint32_t k = keys[i];
+      if (f == 0u || (drop && k == kDropKey)) continue;
+      ++mine;
+      for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (shift0 + bits * p)) & dmask], 1u);
+    }
+  } else {
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += kUp * stride) {
+      uint32_t f[kUp], k[kUp];
+#pragma unroll
+      for (int u = 0; u < kUp; ++u) {
+        const int64_t i = i0 + u * stride;
+        const int64_t ic = i < n ? i : n - 1;
+        f[u] = filter ? filter[ic] : 1u;
+        k[u] = keys[ic];
+      }
+#pragma unroll
+      for (int u = 0; u < kUp; ++u) {
+        if (i0 + u * stride >= n || f[u] == 0u || (drop && k[u] == kDropKey)) continue;
+        ++mine;
+        for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k[u] >> (shift0 + bits * p)) & dmask], 1u);
+      }
+    }
   }
   if (kept && mine) atomicAdd(&s_kept, mine);
   __syncthreads();
@@ -810,8 +864,8 @@ void gather_scan(hipStream_t st, const uint32_t* items, int64_t m_cap, const uns
   }
   hipLaunchKernelGGL(gather_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, items, m_cap, dyn, counts, out,
                      scratch);
-  hipLaunchKernelGGL(gathered_scan_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, out, m_cap,
-                     (const uint32_t*)scratch, out);
+  hipLaunchKernelGGL(nb >= 64 ? gathered_scan_kernel<true> : gathered_scan_kernel<false>, dim3((unsigned)nb),
+                     dim3(kBlock), 0, st, out, m_cap, (const uint32_t*)scratch, out);
 }
 
 void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,
