@@ -246,6 +246,29 @@ def test_batch_equals_single_views_and_repeats(R):
         assert torch.equal(R.views_of(t_b, cams, 1)[v].reshape(-1), t_s)
 
 
+def test_large_batch_equals_single_views(R):
+    """A batch of 8 views of a 2.2M-Gaussian scene holds 17.6M items, past
+    the 4096 tiles of the two-kernel gathered scan, so its entry offsets come
+    from the multi-level scan and its depth sort takes 4096-key chunks; every
+    view still renders bit for bit as it does alone."""
+    scene = synth.scene_box(2_200_000, seed=4, half=6.0, sh_degree=1)
+    rng = np.random.default_rng(9)
+    cams = []
+    for v in range(8):
+        pose = synth.random_pose(rng, 3.0)
+        cams.append(synth.camera_pinhole(96, 72, 70.0, *pose) if v % 2 == 0
+                    else synth.camera_equidistant(96, 96, 180.0, *pose))
+    assert scene.n * len(cams) > 4096 * 4096
+    sc = R.scene_from_numpy(scene)
+    rgb_b, _, t_b, _ = R.render(sc, cams)
+    torch.cuda.synchronize()
+    for v, cam in enumerate(cams):
+        rgb_s, _, t_s, _ = R.render(sc, [cam])
+        torch.cuda.synchronize()
+        assert torch.equal(R.views_of(rgb_b, cams, 3)[v].reshape(-1), rgb_s)
+        assert torch.equal(R.views_of(t_b, cams, 1)[v].reshape(-1), t_s)
+
+
 def test_invalid_arguments_rejected(R):
     scene, cams = synth.workload_small()
     sc = R.scene_from_numpy(scene)
