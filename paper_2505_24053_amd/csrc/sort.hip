@@ -4,7 +4,8 @@
 //      (the first pass compacts the visible items out of all items);
 //   2. exclusive scan of the items' tile counts in depth order;
 //   3. expansion of every item into (tile, item) entries in depth order,
-//      balanced over entries (one binary search per 8 entries);
+//      balanced over entries (8 per lane; owners found through LDS), with
+//      the contribution-cone cull marking the entries no ray can see;
 //   4. stable LSD radix sort of the entries by global tile id, so each tile's
 //      run stays in (depth key, item) order;
 //   5. run boundaries -> ranges[tile].
@@ -201,12 +202,13 @@ __global__ __launch_bounds__(kBlock) void gathered_scan_kernel(const uint32_t* _
 // Stable LSD radix sort with 8-bit digits, one kernel per pass ("onesweep"
 // with decoupled look-back).  An upsweep kernel first counts the digits of
 // every pass over the (filtered) input.  In a pass, block b takes the b-th
-// 2048-key chunk, ranks its keys stably (per wave: ballot
-// match on the digit; across waves and slices: running counts in LDS),
-// publishes its per-digit counts, and walks back over earlier blocks'
-// published counts -- stopping at the first that already holds its inclusive
-// prefix -- to find where its run of each digit starts.  Keys are then
-// reordered by digit in LDS and written out as contiguous runs.  A status
+// chunk of keys (1024 to 4096 keys by sort size, os_per), ranks its keys
+// stably (per wave: ballot match on the digit; across waves and slices:
+// running counts in LDS), publishes its per-digit counts, and walks back
+// over earlier blocks' published counts -- stopping at the first that
+// already holds its inclusive prefix -- to find where its run of each digit
+// starts.  Keys are then reordered by digit in LDS and written out as
+// contiguous runs.  A status
 // word is [flag:2 | count:30]; the look-back spin is bounded and reports a
 // stall through an error word instead of hanging.  A block waits only on
 // blocks with lower indices, and each XCD dispatches the workgroups of a
