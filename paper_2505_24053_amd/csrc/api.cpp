@@ -303,7 +303,8 @@ struct FwdBufs {
   float4* tcones = nullptr;  // per-tile corner cones of the expansion's cull (4 float4 per tile)
   uint32_t* hparts = nullptr;  // partial tile-digit histograms filled by the expansion
   HeavyTiles heavy() const {
-    return HeavyTiles{heavy_list, heavy_flag, (unsigned long long*)(stats + 6), hmax, heavy_slots(hmax)};
+    return HeavyTiles{heavy_list, heavy_flag, (unsigned long long*)(stats + 6), hmax, heavy_slots(hmax),
+                      (unsigned long long*)(heavy_list + heavy_evals_offset(hmax))};
   }
 };
 
@@ -664,7 +665,7 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
 
   // ---- stage (c): render ----
   f->hmax = heavy_capacity(ntiles);
-  TRY(acquire(c, 4 * (size_t)f->hmax, st, f->heavy_list));
+  TRY(acquire(c, 4 * (size_t)heavy_list_words(ntiles), st, f->heavy_list));
   TRY(acquire(c, 4 * (size_t)ntiles, st, f->heavy_flag));
   b.heavy_list = (uint32_t*)f->heavy_list.p;
   b.heavy_flag = (uint32_t*)f->heavy_flag.p;
@@ -916,7 +917,7 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
   L.items_b = put(4 * (ecap + 8));
   L.list = put(4 * (ecap + 8));
   L.ranges = put(4 * (ntiles + 1));
-  L.heavy_list = put(4 * (size_t)heavy_capacity(ntiles));
+  L.heavy_list = put(4 * (size_t)heavy_list_words(ntiles));
   L.heavy_flag = put(4 * (size_t)ntiles);
   L.tcones = put(64 * (size_t)std::max<int64_t>(ntiles, 1));
   L.hparts = put(4 * (size_t)hist_parts_words());

@@ -58,7 +58,15 @@ struct HeavyTiles {
   unsigned long long* count;
   int hmax;
   int hslots;
+  unsigned long long* evals;  // the render's evaluated-pair counters (kEvalSlots, kEvalStride apart)
 };
+
+// The render's evaluated-pair count is gathered through kEvalSlots counters
+// on separate 128-byte lines (one atomic per wave on a single word was the
+// render's bottleneck: such atomics serialise).
+constexpr int kEvalSlots = 64;
+constexpr int kEvalStride = 16;       // u64 words between counters
+constexpr int kEvalTallyShift = 44;   // a counter's top 20 bits count the waves that added to it
 
 __host__ __device__ inline uint32_t pack16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
 

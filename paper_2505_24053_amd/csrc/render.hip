@@ -102,7 +102,7 @@ __device__ __forceinline__ void render_heavy_block(const WaveBlock& W, const Vie
                                                    float4 (*s_rec)[4], float* __restrict__ rgb,
                                                    float* __restrict__ depth, float* __restrict__ trans,
                                                    uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
-                                                   unsigned long long* __restrict__ stats) {
+                                                   uint64_t& evals_out) {
   const int lane = threadIdx.x & 63;
   const int j = lane & 3, r = lane >> 2;
   const uint32_t hx = (uint32_t)W.bx0 >> 3, hy = (uint32_t)W.by0 >> 3;
@@ -249,10 +249,28 @@ __device__ __forceinline__ void render_heavy_block(const WaveBlock& W, const Vie
       tfinal[gp] = T;
     }
   }
-  if (stats && lane == 0 && evals) atomicAdd(&stats[0], (unsigned long long)evals);
+  evals_out += evals;
 }
 
 constexpr int kRenderWaves = RENDER_WAVES;  // independent waves per workgroup
+
+// Adds a wave's evaluated-pair count to *total; every wave of the grid calls
+// it exactly once.  The wave adds its count, with one wave in the top bits,
+// to the counter of its workgroup's slot; the wave that completes a slot's
+// tally adds the slot's sum to *total, so *total takes kEvalSlots atomics
+// instead of one per wave.
+__device__ __forceinline__ void add_evals(unsigned long long* __restrict__ total,
+                                          unsigned long long* __restrict__ slots, uint64_t evals) {
+  if (!total || (threadIdx.x & 63) != 0) return;
+  const unsigned s = blockIdx.x % kEvalSlots;
+  const unsigned long long waves = (unsigned long long)((gridDim.x - 1 - s) / kEvalSlots + 1) * kRenderWaves;
+  const unsigned long long mine = (1ull << kEvalTallyShift) | evals;
+  const unsigned long long old = atomicAdd(&slots[s * kEvalStride], mine);
+  if ((old >> kEvalTallyShift) + 1 == waves) {
+    const unsigned long long sum = (old + mine) & ((1ull << kEvalTallyShift) - 1);
+    if (sum) atomicAdd(total, sum);
+  }
+}
 
 template <bool kFixed, bool kKeep>
 __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
@@ -269,17 +287,22 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
   const int wi = wave_index(blockIdx.x, gridDim.x, kRenderWaves, wv, heavy_waves);
   if (wi < heavy_waves) {
     // block wi % 16 of the listed heavy tiles wi / 16, wi / 16 + slots, ...
+    uint64_t hevals = 0;
     const int nh = (int)min(*heavy.count, (unsigned long long)heavy.hmax);
     for (int h = wi / kHeavySplit; h < nh; h += heavy.hslots) {
       const WaveBlock Wh = heavy_block((int)heavy.list[h], wi % kHeavySplit, views, nviews);
       if (!Wh.live) continue;
       render_heavy_block<kFixed, kKeep>(Wh, views[Wh.v], dtab, ranges[Wh.tile], ranges[Wh.tile + 1], list, rects,
-                                        recs, op, s_rec, rgb, depth, trans, nlast, tfinal, stats);
+                                        recs, op, s_rec, rgb, depth, trans, nlast, tfinal, hevals);
     }
+    add_evals(stats, heavy.evals, hevals);
     return;
   }
   const WaveBlock W = ordinary_block(wi, heavy_waves, views, nviews, heavy.flag);
-  if (!W.live) return;
+  if (!W.live) {
+    add_evals(stats, heavy.evals, 0);
+    return;
+  }
   const ViewDev& V = views[W.v];
   const int tile = W.tile;
   const uint32_t start = ranges[tile], end = ranges[tile + 1];
@@ -318,6 +341,7 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
         tfinal[gp] = 1.0f;
       }
     }
+    add_evals(stats, heavy.evals, 0);
     return;
   }
   float4 p0, p1, p2, p3;
@@ -376,7 +400,7 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
       tfinal[gp] = T;
     }
   }
-  if (stats && lane == 0 && evals) atomicAdd(&stats[0], (unsigned long long)evals);
+  add_evals(stats, heavy.evals, evals);
 }
 
 // Flags tiles whose list is longer than 3x the mean over their own view's
@@ -388,8 +412,10 @@ __global__ __launch_bounds__(256) void mark_heavy_kernel(const uint32_t* __restr
                                                          const ViewDev* __restrict__ views, int nviews,
                                                          uint32_t* __restrict__ heavy_list,
                                                          uint32_t* __restrict__ heavy_flag,
-                                                         unsigned long long* __restrict__ heavy_count, int hmax) {
+                                                         unsigned long long* __restrict__ heavy_count, int hmax,
+                                                         unsigned long long* __restrict__ evals) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (evals && t < kEvalSlots) evals[t * kEvalStride] = 0ull;  // the render's counters, cleared for it
   if (t >= ntiles) return;
   int v = 0;
   while (v + 1 < nviews && t >= views[v + 1].tile_base) ++v;
@@ -410,13 +436,18 @@ __global__ __launch_bounds__(256) void mark_heavy_kernel(const uint32_t* __restr
 }
 
 int heavy_capacity(int64_t ntiles) { return (int)(ntiles / 3 + 1); }
+// the list, padded to 128 bytes, then the render's evaluated-pair counters
+int64_t heavy_evals_offset(int hmax) { return ((int64_t)hmax + 31) / 32 * 32; }
+int64_t heavy_list_words(int64_t ntiles) {
+  return heavy_evals_offset(heavy_capacity(ntiles)) + 2 * (int64_t)kEvalSlots * kEvalStride;
+}
 int heavy_slots(int hmax) { return std::min(hmax, 256); }
 
 void launch_mark_heavy(hipStream_t st, const uint32_t* ranges, int64_t ntiles, const ViewDev* views, int nviews,
                        const HeavyTiles& h) {
   if (ntiles <= 0) return;
   hipLaunchKernelGGL(mark_heavy_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st, ranges, ntiles,
-                     views, nviews, h.list, h.flag, h.count, h.hmax);
+                     views, nviews, h.list, h.flag, h.count, h.hmax, h.evals);
 }
 
 void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const ViewDev* views, int nviews,

@@ -61,6 +61,8 @@ void launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v);
 
 // render.hip
 int heavy_capacity(int64_t ntiles);
+int64_t heavy_evals_offset(int hmax);     // u32 words from the list to the evaluated-pair counters
+int64_t heavy_list_words(int64_t ntiles);  // u32 words of the list buffer
 int heavy_slots(int hmax);
 void launch_mark_heavy(hipStream_t st, const uint32_t* ranges, int64_t ntiles, const ViewDev* views, int nviews,
                        const HeavyTiles& h);
