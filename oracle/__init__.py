@@ -80,7 +80,8 @@ def lib():
             P = C.POINTER
             L.orc_assoc_fp32.argtypes = [P(SceneC), P(View), P(Opts), C.c_void_p]
             L.orc_render.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p,
-                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_void_p, C.c_int]
             L.orc_render_backward.argtypes = [P(SceneC), P(View), P(Opts), C.c_int64, C.c_void_p, C.c_void_p,
                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_int]
@@ -181,30 +182,75 @@ def tile_list(assoc, cam):
     return tiles, gids, ranges
 
 
-def render(scene, cam, pix=None, nthreads: int = 0, **opts):
-    """Brute-force FP64 render of BEAP pixels (all when ``pix`` is None).
-    Returns dict(rgb [P,3], depth [P], trans [P], ncomp [P], amb [P], amb_tol [P],
-    pix): ``amb`` marks rays with a pair within the FP32 error band of a
-    contribution or termination decision, ``amb_tol`` bounds how much those
-    decisions can move the ray's colour."""
+MAX_BRANCHES = 64
+
+
+def render(scene, cam, pix=None, nthreads: int = 0, branches: bool = True, **opts):
+    """Brute-force FP64 render of BEAP pixels (all when ``pix`` is None),
+    front-to-back compositing of Eq. color with the contribution rule of
+    Sec. 3.2.  Returns dict(rgb [P,3], depth [P], trans [P], ncomp [P],
+    amb [P], pix) from the FP64 decisions; ``amb`` marks rays on which some
+    decision (a contribution threshold, or the termination test) lies within
+    the FP32 error band, so FP32 may take another branch.
+
+    With ``branches`` every flagged ray's alternative outcomes are listed:
+    ``branch_idx`` (positions in ``pix`` of the flagged rays),
+    ``branch_leaves`` [F, MAX_BRANCHES, 5] = (r, g, b, depth, T) of each
+    decision sequence and ``branch_count`` [F] (above MAX_BRANCHES: too many
+    to list)."""
     L = lib()
     w, h = int(cam["width"]), int(cam["height"])
     if pix is None:
         pix = np.arange(w * h, dtype=np.int64)
     pix = np.ascontiguousarray(pix, dtype=np.int64)
-    n = pix.size
-    rgb = np.zeros((n, 3))
-    depth = np.zeros(n)
-    trans = np.zeros(n)
-    ncomp = np.zeros(n, np.int32)
-    amb = np.zeros(n, np.int32)
-    amb_tol = np.zeros(n)
     ref = _SceneRef(scene)
-    rc = L.orc_render(C.byref(ref.c), C.byref(make_view(cam)), C.byref(make_opts(**opts)), n, _ptr(pix),
-                      _ptr(rgb), _ptr(depth), _ptr(trans), _ptr(ncomp), _ptr(amb), _ptr(amb_tol), int(nthreads))
-    if rc != 0:
-        raise MemoryError("oracle render failed")
-    return dict(rgb=rgb, depth=depth, trans=trans, ncomp=ncomp, amb=amb.astype(bool), amb_tol=amb_tol, pix=pix)
+    view, op = make_view(cam), make_opts(**opts)
+
+    def run(p, with_leaves):
+        n = p.size
+        out = dict(rgb=np.zeros((n, 3)), depth=np.zeros(n), trans=np.zeros(n), ncomp=np.zeros(n, np.int32),
+                   amb=np.zeros(n, np.int32))
+        leaves = np.zeros((n, MAX_BRANCHES, 5)) if with_leaves else None
+        nleaves = np.zeros(n, np.int64) if with_leaves else None
+        rc = L.orc_render(C.byref(ref.c), C.byref(view), C.byref(op), n, _ptr(p), _ptr(out["rgb"]),
+                          _ptr(out["depth"]), _ptr(out["trans"]), _ptr(out["ncomp"]), _ptr(out["amb"]),
+                          MAX_BRANCHES, _ptr(leaves), _ptr(nleaves), int(nthreads))
+        if rc != 0:
+            raise MemoryError("oracle render failed")
+        return out, leaves, nleaves
+
+    out, _, _ = run(pix, False)
+    out["amb"] = out["amb"].astype(bool)
+    out["pix"] = pix
+    if branches:
+        idx = np.nonzero(out["amb"])[0]
+        if idx.size:
+            _, leaves, nleaves = run(np.ascontiguousarray(pix[idx]), True)
+        else:
+            leaves, nleaves = np.zeros((0, MAX_BRANCHES, 5)), np.zeros(0, np.int64)
+        out.update(branch_idx=idx, branch_leaves=leaves, branch_count=nleaves)
+    return out
+
+
+def branch_scores(got_rgb, got_depth, got_trans, ref, rgb_tol=2e-4, depth_rel=1e-3):
+    """For each flagged ray of ``ref`` (a render with branches): the smallest,
+    over its decision branches, of the largest gate ratio -- RGB and T
+    max-abs over ``rgb_tol``, depth relative error over ``depth_rel``.  A
+    score <= 1 means the values are one of the outcomes FP32 can produce.
+    ``got_*`` are per-ray arrays aligned with ``ref["pix"]``.  Rays with more
+    branches than listed score +inf."""
+    idx = ref["branch_idx"]
+    L = ref["branch_leaves"]
+    cnt = ref["branch_count"]
+    if idx.size == 0:
+        return np.zeros(0)
+    e_rgb = np.abs(np.asarray(got_rgb)[idx][:, None, :] - L[:, :, 0:3]).max(axis=2) / rgb_tol
+    e_d = np.abs(np.asarray(got_depth)[idx][:, None] - L[:, :, 3]) / (1.0 + np.abs(L[:, :, 3])) / depth_rel
+    e_t = np.abs(np.asarray(got_trans)[idx][:, None] - L[:, :, 4]) / rgb_tol
+    score = np.maximum(np.maximum(e_rgb, e_d), e_t)
+    listed = np.arange(L.shape[1])[None, :] < np.minimum(cnt, L.shape[1])[:, None]
+    score = np.where(listed, score, np.inf).min(axis=1)
+    return np.where(cnt > L.shape[1], np.inf, score)
 
 
 def render_backward(scene, cam, pix, dl_drgb, nthreads: int = 0, **opts):
@@ -252,14 +298,15 @@ def sh_basis(deg: int, dirs):
     return Y, dY
 
 
-def pair(scene, cam, g: int, d, **opts):
-    """(kappa, t*, sigma exp(-kappa/2), lambda_i^2) of one pair, FP64."""
+def pair(scene, cam, g: int, d, with_band: bool = False, **opts):
+    """(kappa, t*, sigma exp(-kappa/2), lambda_i^2) of one pair, FP64; with
+    ``with_band`` also the FP32 error band of kappa that flags decisions."""
     d = np.ascontiguousarray(d, dtype=np.float64)
-    out = np.zeros(4)
+    out = np.zeros(5)
     ref = _SceneRef(scene)
     lib().orc_pair(C.byref(ref.c), C.byref(make_view(cam)), C.byref(make_opts(**opts)), int(g), _ptr(d),
                    _ptr(out))
-    return out
+    return out if with_band else out[:4]
 
 
 def edges(cam):
@@ -324,7 +371,7 @@ def opts_dict(**kw):
     return d
 
 
-__all__ = ["build", "assoc_fp32", "tile_list", "render", "render_backward", "sh_basis", "pair", "edges",
+__all__ = ["build", "assoc_fp32", "tile_list", "render", "branch_scores", "render_backward", "sh_basis", "pair", "edges",
            "lambda2_hat", "contrib_mask", "valid_mask", "pixel_dirs_camera", "pixel_dirs_world", "DEFAULT_OPTS"]
 
 

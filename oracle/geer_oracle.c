@@ -546,7 +546,6 @@ typedef struct {
   int clamped;
   int in64;    /* contributes in FP64 */
   int flag;    /* within the FP32 error band of a contribution decision */
-  double ptol; /* how far flipping that decision can move the colour */
 } contrib;
 
 static int contrib_cmp(const void* a, const void* b) {
@@ -556,11 +555,15 @@ static int contrib_cmp(const void* a, const void* b) {
   return x->g < y->g ? -1 : (x->g > y->g ? 1 : 0);
 }
 
-/* First-order bound on how far FP32 evaluation can move kappa: the ray
- * direction carries a few units in the last place (|grad_d kappa| * 2^-21),
- * the camera-space mean a few ulps of |mu| + |o| (|grad_mu kappa| * that),
- * plus a relative floor.  Both gradients come from the chain of the
- * cookbook appendix (dkappa/dd_u, dkappa/do_u) mapped through W^T. */
+/* Bound on how far FP32 evaluation can move kappa.  First order: the ray
+ * direction carries a few units in the last place (|grad_d kappa| * 2^-21,
+ * four ulps of a unit vector's components), the camera-space mean a few
+ * ulps of |mu| + |o| (|grad_mu kappa| * 2^-21 of that), plus a relative
+ * floor for the rounding of log2(sigma) and of the exponent.  Both
+ * gradients come from the chain of the cookbook appendix (dkappa/dd_u,
+ * dkappa/do_u) mapped through W^T.  Float32 evaluations of kappa near the
+ * threshold, with inputs moved by up to 4 ulps, stay within half of it (the
+ * band's own test). */
 static double kappa_band(const gprep* p, const double u[3], const double m[3], double uu, double kappa,
                          const double o[3]) {
   const double* ou = p->ou;
@@ -578,13 +581,16 @@ static double kappa_band(const gprep* p, const double u[3], const double m[3], d
     gmu2 += b * b;
   }
   double mu_mag = p->dist + sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
-  return 0x1p-20 * sqrt(gd2) + 0x1p-20 * mu_mag * sqrt(gmu2) + 1e-6 * (p->lam2 > 1 ? p->lam2 : 1);
-}
-
-/* Collect the contributors of one ray in order; returns the count. */
-static double cmax_of(const gprep* p) {
-  double c = p->col[0] > p->col[1] ? p->col[0] : p->col[1];
-  return c > p->col[2] ? c : p->col[2];
+  /* second order: kappa = |P o_u|^2 (P projects off d_u) is quadratic in
+   o_u, so a move delta of o_u adds at most |delta|^2 beyond the linear
+   term; a turn by angle e of d_u adds at most |o_u|^2 e^2.  They matter only
+   for needles and disks, whose W amplifies input rounding by 1/s_min. */
+  double wf = 0, r2 = ou[0] * ou[0] + ou[1] * ou[1] + ou[2] * ou[2];
+  for (int q = 0; q < 9; ++q) wf += W[q] * W[q];
+  wf = sqrt(wf);
+  const double dou = 0x1p-21 * mu_mag * wf, dang = 0x1p-21 * wf / sqrt(uu);
+  return 0x1p-21 * sqrt(gd2) + 0x1p-21 * mu_mag * sqrt(gmu2) + dou * dou + r2 * dang * dang +
+         1e-6 * (p->lam2 > 1 ? p->lam2 : 1);
 }
 
 /* The contribution rule for one (ray, Gaussian) pair, FP64: not culled,
@@ -607,8 +613,7 @@ static int pair_contributes64(const gprep* p, const orc_opts* op, const double d
 
 /* Collects, in (key, index) order, every pair that contributes in FP64 and
  * every pair whose contribution decision lies within the FP32 error band of
- * its threshold (flag = 1, with ptol = 2 alpha_raw max(c): the pair's own
- * term and the occlusion it adds to what lies behind). */
+ * its threshold (flag = 1: FP32 may decide either way). */
 static int64_t gather(const gprep* P, int64_t n, const orc_opts* op, const double o[3], const double d[3],
                       contrib** buf, int64_t* cap) {
   int64_t cnt = 0;
@@ -650,7 +655,6 @@ static int64_t gather(const gprep* P, int64_t n, const orc_opts* op, const doubl
     c->uu = uu;
     c->in64 = in64;
     c->flag = flag;
-    c->ptol = flag ? 2.0 * p->sigma * exp(-0.5 * (kappa - band > 0 ? kappa - band : 0)) * (cmax_of(p) + 1e-3) : 0.0;
   }
   qsort(*buf, (size_t)cnt, sizeof(contrib), contrib_cmp);
   return cnt;
@@ -668,15 +672,89 @@ static void camera_centre(const orc_view* v, double o[3]) {
   for (int a = 0; a < 3; ++a) o[a] = -(v->R[0 * 3 + a] * v->t[0] + v->R[1 * 3 + a] * v->t[1] + v->R[2 * 3 + a] * v->t[2]);
 }
 
+/* Relative FP32 error that one compositing step adds to the transmittance:
+ * the step's alpha carries the kappa band (d alpha / alpha = -d kappa / 2),
+ * amplified by 1 / (1 - alpha) in T (1 - alpha), plus rounding. */
+static double step_trel(const contrib* c) {
+  return (c->clamped ? 0.0 : c->alpha * 0.5 * c->band) / (1 - c->alpha) + 0x1p-22;
+}
+
+/* A termination decision T_next < T_min within the FP32 error band. */
+static int term_ambiguous(double Tn, double trel, double t_min) {
+  return fabs(Tn - t_min) <= (trel + 0x1p-20) * Tn;
+}
+
+/* Outcome (RGB, depth, T) of one sequence of decisions. */
+typedef struct {
+  double rgb[3], depth, trans;
+} leaf_t;
+
+/* Enumeration of the decision branches of one ray.  Every decision that lies
+ * within the FP32 error band (a flagged contribution: pair in or out; a
+ * termination step: stop or go on) is taken both ways; every other decision
+ * is the FP64 one.  Each complete sequence is a leaf.  At most maxb leaves
+ * are stored; n counts them all (n > maxb: the enumeration stopped). */
+typedef struct {
+  const contrib* buf;
+  int64_t cnt;
+  const gprep* P;
+  const orc_opts* op;
+  leaf_t* leaves;
+  int64_t maxb, n;
+} branch_walk;
+
+static void emit_leaf(branch_walk* b, double c0, double c1, double c2, double D, double T) {
+  if (b->leaves && b->n < b->maxb) {
+    leaf_t* l = &b->leaves[b->n];
+    l->rgb[0] = c0; l->rgb[1] = c1; l->rgb[2] = c2;
+    l->depth = D;
+    l->trans = T;
+  }
+  b->n++;
+}
+
+/* Front to back from contributor i with transmittance T, colour (c0, c1, c2),
+ * depth D and accumulated relative error trel.  Recursion happens only at
+ * branch points, so its depth is bounded by the number of leaves. */
+static void walk_branches(branch_walk* b, int64_t i, double T, double c0, double c1, double c2, double D,
+                          double trel) {
+  const double t_min = b->op->t_min;
+  for (; i < b->cnt; ++i) {
+    if (b->n > b->maxb) return;
+    const contrib* c = &b->buf[i];
+    if (c->flag) walk_branches(b, i + 1, T, c0, c1, c2, D, trel);  /* the pair left out */
+    else if (!c->in64) continue;
+    const double Tn = T * (1 - c->alpha);
+    const double tr = trel + step_trel(c);
+    if (t_min > 0) {
+      if (term_ambiguous(Tn, tr, t_min)) emit_leaf(b, c0, c1, c2, D, T);  /* stop here; also go on */
+      else if (Tn < t_min) { emit_leaf(b, c0, c1, c2, D, T); return; }
+    }
+    const double w = c->alpha * T;
+    const gprep* p = &b->P[c->g];
+    c0 += w * p->col[0];
+    c1 += w * p->col[1];
+    c2 += w * p->col[2];
+    D += w * c->tstar;
+    T = Tn;
+    trel = tr;
+  }
+  emit_leaf(b, c0, c1, c2, D, T);
+}
+
 /*
  * Render a list of BEAP pixels (linear index y * width + x) of one view.
- * Outputs per pixel: rgb[3], depth (sum of w_i t*_i), final transmittance,
- * number of composited Gaussians, and an ambiguity flag (1 when some pair is
- * within the FP32 error band of a contribution or termination threshold).
+ * Outputs per pixel: rgb[3], depth (sum of w_i t*_i), final transmittance and
+ * the number of composited Gaussians, all from the FP64 decisions; amb = 1
+ * when some decision on that path lies within the FP32 error band (a
+ * contribution threshold, or the termination test), so that FP32 may take
+ * another branch.  With leaves != NULL (maxb slots of 5 doubles per pixel:
+ * rgb, depth, T) every branch's outcome is listed and nleaves[t] holds
+ * their number (above maxb: too many to list).
  */
 int orc_render(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64_t npix,
                const int64_t* pix, double* rgb, double* depth, double* trans, int32_t* ncomp,
-               int32_t* amb, double* amb_tol, int nthreads) {
+               int32_t* amb, int64_t maxb, double* leaves, int64_t* nleaves, int nthreads) {
   int64_t n = sc->n;
   orc_assoc* as = (orc_assoc*)malloc(sizeof(orc_assoc) * (size_t)(n > 0 ? n : 1));
   gprep* P = (gprep*)malloc(sizeof(gprep) * (size_t)(n > 0 ? n : 1));
@@ -698,52 +776,19 @@ int orc_render(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64
       double d[3];
       pixel_dir(v, px, py, d);
       int64_t cnt = gather(P, n, op, o, d, &buf, &cap);
-      double cmax_all = 0;
-      for (int64_t i = 0; i < cnt; ++i) {
-        double cm = cmax_of(&P[buf[i].g]);
-        cmax_all = cm > cmax_all ? cm : cmax_all;
-      }
-      /* Latest possible termination: every flagged pair left out, and a step
-         whose transmittance is within the error band of T_min still taken.
-         Whatever FP32 decides, compositing stops at or before it, so flagged
-         pairs sorted after it cannot change the result. */
-      int64_t late = cnt;
-      if (op->t_min > 0) {
-        double T = 1, trel = 0;
-        for (int64_t i = 0; i < cnt; ++i) {
-          const contrib* c = &buf[i];
-          if (c->flag || !c->in64) continue;
-          double Tn = T * (1 - c->alpha);
-          trel += (c->clamped ? 0.0 : c->alpha * 0.5 * c->band) / (1 - c->alpha) + 0x1p-22;
-          if (Tn < op->t_min * (1 - trel - 0x1p-20)) {
-            late = i;
-            break;
-          }
-          T = Tn;
-        }
-      }
+      /* the FP64 path; a branch point on it means other outcomes exist */
       int a_flag = 0;
-      double tol = 0;
-      for (int64_t i = 0; i < cnt && i <= late; ++i)
-        if (buf[i].flag) {
-          a_flag = 1;
-          tol += buf[i].ptol;
-        }
       double T = 1, C[3] = {0, 0, 0}, D = 0;
-      double trel = 0; /* first-order relative FP32 error of the transmittance */
+      double trel = 0;
       int32_t nc = 0;
       for (int64_t i = 0; i < cnt; ++i) {
         const contrib* c = &buf[i];
+        if (c->flag) a_flag = 1;
         if (!c->in64) continue;
         double Tn = T * (1 - c->alpha);
-        trel += (c->clamped ? 0.0 : c->alpha * 0.5 * c->band) / (1 - c->alpha) + 0x1p-22;
+        trel += step_trel(c);
         if (op->t_min > 0) {
-          if (fabs(Tn - op->t_min) <= (trel + 0x1p-20) * Tn) {
-            /* termination may happen one step earlier or later: the step's
-               own term plus everything behind it */
-            a_flag = 1;
-            tol += T * (c->alpha + 1.0) * (cmax_all + 1e-3);
-          }
+          if (term_ambiguous(Tn, trel, op->t_min)) a_flag = 1;
           if (Tn < op->t_min) break;
         }
         double w = c->alpha * T;
@@ -758,7 +803,15 @@ int orc_render(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64
       trans[t] = T;
       ncomp[t] = nc;
       amb[t] = a_flag;
-      amb_tol[t] = a_flag ? tol : 0.0;
+      if (leaves) {
+        branch_walk bw = {buf, cnt, P, op, (leaf_t*)(leaves + (size_t)t * (size_t)maxb * 5), maxb, 0};
+        if (a_flag) {
+          walk_branches(&bw, 0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0);
+        } else {
+          emit_leaf(&bw, C[0], C[1], C[2], D, T);
+        }
+        nleaves[t] = bw.n;
+      }
     }
     free(buf);
   }
@@ -925,11 +978,11 @@ int orc_render_backward(const orc_scene* sc, const orc_view* v, const orc_opts* 
   return 0;
 }
 
-/* Ray-level query for tests: kappa, t*, sigma exp(-kappa/2) and lambda_i^2 of
+/* Ray-level query for tests: kappa, t*, sigma exp(-kappa/2), lambda_i^2 of
  * one (ray, Gaussian) pair in FP64 (cross-product form), given a world
- * direction d. */
+ * direction d, and the FP32 error band of kappa used to flag decisions. */
 int orc_pair(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64_t g, const double d[3],
-             double out[4]) {
+             double out[5]) {
   int64_t n = sc->n;
   int K = (sc->sh_degree + 1) * (sc->sh_degree + 1);
   double m1[3], s1v[3], q1[4], o1[1], sh1[48];
@@ -953,6 +1006,9 @@ int orc_pair(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64_t
   out[1] = -(ou[0] * u[0] + ou[1] * u[1] + ou[2] * u[2]) / uu;
   out[2] = p.sigma * exp(-0.5 * out[0]);
   out[3] = p.lam2;
+  double o[3];
+  camera_centre(v, o);
+  out[4] = kappa_band(&p, u, m, uu, out[0], o);
   return 0;
 }
 

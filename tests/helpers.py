@@ -1,6 +1,8 @@
 """Shared inputs and comparisons of the test suite."""
 import numpy as np
 
+import oracle
+
 from paper_2505_24053_amd import synth
 
 
@@ -47,24 +49,32 @@ def adversarial_scene(seed, n=48):
 RGB_TOL = 2e-4  # RGB max-abs gate, FP32 GPU vs FP64 oracle
 
 
-def compare_render(got, ref, pix=None, rgb_tol=RGB_TOL):
-    """RGB within rgb_tol on unflagged rays; a flagged ray may also differ by
-    the oracle's bound on the decisions that fall within FP32 error."""
+FLAGGED_MAX = 0.05  # largest share of rays with an FP32-ambiguous decision
+
+
+def compare_render(got, ref, pix=None, rgb_tol=RGB_TOL, flagged_max=FLAGGED_MAX):
+    """GPU rays against the FP64 oracle (Eq. color).  A ray whose decisions
+    all lie outside the FP32 error band must match the FP64 result: RGB and T
+    within rgb_tol, depth within 1e-3 relative.  A flagged ray must match one
+    of its decision branches (each flagged contribution in or out, each
+    ambiguous termination taken or not) within the same gates."""
     sel = slice(None) if pix is None else pix
     g_rgb, g_d, g_t = got["rgb"][sel], got["depth"][sel], got["trans"][sel]
     amb = ref["amb"]
     ok = ~amb
     err = np.abs(g_rgb - ref["rgb"]).max(axis=1)
     assert err[ok].max(initial=0) <= rgb_tol, "max |rgb| err %g at %s" % (err[ok].max(), np.argmax(np.where(ok, err, 0)))
-    over = err[amb] - (rgb_tol + ref["amb_tol"][amb])
-    assert over.max(initial=-1) <= 0, "flagged ray beyond its bound by %g" % over.max()
     terr = np.abs(g_t - ref["trans"])
-    assert terr[ok].max(initial=0) <= rgb_tol
+    assert terr[ok].max(initial=0) <= rgb_tol, "max |T| err %g" % terr[ok].max()
     derr = np.abs(g_d - ref["depth"]) / (1.0 + np.abs(ref["depth"]))
-    assert derr[ok].max(initial=0) <= 1e-3
-    assert amb.mean() < 0.10
-    print("rays %d, flagged %d (%.2f%%), flagged beyond %.0e: %d, max err unflagged %.3g"
-          % (amb.size, amb.sum(), 100 * amb.mean(), rgb_tol, int((err[amb] > rgb_tol).sum()), err[ok].max(initial=0)))
+    assert derr[ok].max(initial=0) <= 1e-3, "max depth rel err %g" % derr[ok].max()
+    score = oracle.branch_scores(g_rgb, g_d, g_t, ref, rgb_tol)
+    assert score.max(initial=0) <= 1.0, "flagged ray matches no branch: score %g at %s (%d branches)" % (
+        score.max(), ref["branch_idx"][np.argmax(score)], ref["branch_count"][np.argmax(score)])
+    assert amb.mean() <= flagged_max, "flagged share %.4f" % amb.mean()
+    print("rays %d, flagged %d (%.3f%%), each within the gates of one branch (max %d branches); "
+          "max err unflagged %.3g" % (amb.size, amb.sum(), 100 * amb.mean(),
+                                      int(ref["branch_count"].max(initial=1)), err[ok].max(initial=0)))
     return float(err[ok].max(initial=0)), int(amb.sum())
 
 

@@ -276,7 +276,38 @@ def test_threshold_flags_only_before_latest_termination(oracle_lib):
     assert behind["rgb"][0, 0] == pytest.approx(c_wall, abs=1e-6)
     front = oracle.render(_concat(edge(1.0), *wall), cam)
     assert front["amb"][0]
-    assert front["amb_tol"][0] >= 2 * sig * 0.9 * math.exp(-0.5 * lam2) * 0.99
+    # its two branches: the edge Gaussian left out (the wall alone) or in,
+    # with alpha = alpha_min in front of the wall
+    n = int(front["branch_count"][0])
+    red = sorted(front["branch_leaves"][0, :n, 0])
+    ae = float(np.float32(sig)) * math.exp(-0.5 * kappa)
+    assert n == 2
+    assert red[0] == pytest.approx(c_wall, abs=1e-6)
+    assert red[1] == pytest.approx(0.9 * ae + (1 - ae) * c_wall, abs=1e-6)
     # with no termination the pair behind is reachable again, hence flagged
     no_stop = oracle.render(_concat(*wall, edge(10.0)), cam, t_min=0.0)
     assert no_stop["amb"][0]
+
+
+def test_termination_branches(oracle_lib):
+    """Two clamped Gaussians (alpha = alpha_max = 0.99) on the ray take the
+    transmittance to (1 - 0.99)^2 = 1e-4 = T_min: whether the second one
+    blends is within FP32 error, so both outcomes are branches: stop before
+    it (C = 0.99 c1) or blend it (C = 0.99 c1 + 0.99 * 0.01 c2)."""
+    cam = synth.camera_pinhole(1, 1, 10.0)
+    q = [1.0, 0.0, 0.0, 0.0]
+    g1 = one_gaussian([0, 0, 2.0], [0.1] * 3, q, 0.999, rgb=(0.3, 0.0, 0.0))
+    g2 = one_gaussian([0, 0, 3.0], [0.1] * 3, q, 0.999, rgb=(0.8, 0.0, 0.0))
+    out = oracle.render(_concat(g1, g2), cam)
+    assert out["amb"][0]
+    n = int(out["branch_count"][0])
+    leaves = out["branch_leaves"][0, :n]
+    red = sorted(leaves[:, 0])
+    assert n == 2
+    assert red[0] == pytest.approx(0.99 * 0.3, abs=1e-6)
+    assert red[1] == pytest.approx(0.99 * 0.3 + 0.99 * 0.01 * 0.8, abs=1e-6)
+    assert sorted(leaves[:, 4]) == pytest.approx([0.01 * 0.01, 0.01], rel=1e-9)
+    # well away from T_min (a third of the opacity) there is one outcome
+    g3 = one_gaussian([0, 0, 3.0], [0.1] * 3, q, 0.3, rgb=(0.8, 0.0, 0.0))
+    one = oracle.render(_concat(g1, g3), cam)
+    assert not one["amb"][0] and one["branch_idx"].size == 0
