@@ -208,7 +208,7 @@ def bench_serving(args, dev):
             serve.poisson_arrivals(len(warm), args.serve_rates[0], seed=args.seed + 201))
     points = []
     for j, rate in enumerate(args.serve_rates):
-        srv.stats = dict(batches=0, overflows=0, views=0, overlapped=0)
+        srv.stats = dict(batches=0, overflows=0, stalls=0, views=0, overlapped=0)
         srv.intervals = []
         cams = synth.workload_serving_requests(args.serve_requests, seed=args.seed + 300 + 10 * j)
         arrivals = serve.poisson_arrivals(len(cams), rate, seed=args.seed + 301 + 10 * j)

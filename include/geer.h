@@ -49,7 +49,10 @@ typedef enum {
   GEER_ERR_OOM = 2,         /* device or host allocation failed */
   GEER_ERR_CAPACITY = 3,    /* more than 2^30 - 16 items (Gaussians x views) or list entries */
   GEER_ERR_HIP = 4,         /* a HIP runtime call failed; see geer_last_error */
-  GEER_ERR_UNSUPPORTED = 5  /* feature not available in this build */
+  GEER_ERR_UNSUPPORTED = 5, /* feature not available in this build */
+  GEER_ERR_STALLED = 6      /* a bounded device-side wait of the association sort gave
+                               up (decoupled look-back spin limit): the outputs of that
+                               forward are invalid and must be rendered again */
 } geer_status;
 
 typedef enum { GEER_CAM_PINHOLE = 0, GEER_CAM_EQUIDISTANT = 1, GEER_CAM_KB = 2 } geer_cam_model;
@@ -107,6 +110,7 @@ typedef struct {
 
 typedef struct geer_ctx geer_ctx;     /* per-device library state */
 typedef struct geer_frame geer_frame; /* forward state kept for the backward */
+typedef struct geer_plan geer_plan;   /* captured forward or training step (below) */
 
 /* Statistics of one forward, counted on the device. */
 typedef struct {
@@ -164,6 +168,23 @@ geer_status geer_render(geer_ctx* ctx, const geer_scene* scene, int32_t n_views,
 geer_status geer_render_backward(geer_ctx* ctx, const geer_frame* frame, const float* dl_drgb,
                                  float* g_mean, float* g_scale, float* g_quat, float* g_opacity,
                                  float* g_sh, int32_t accumulate, void* stream);
+
+/*
+ * Sort stalls.  Each radix pass of the association waits on earlier blocks
+ * with a bounded spin; if it gives up, the outputs of that forward are
+ * invalid.  An eager forward (geer_render) records this in a sticky flag of
+ * the context; it is reported as GEER_ERR_STALLED, and cleared, by the next
+ * geer_render on the context (which then renders nothing), by
+ * geer_frame_get_stats, and by geer_check.  Plans report their own launches'
+ * stalls through geer_plan_entries.
+ */
+/* Waits for the work on `stream` and reports (and clears) a stall of any
+ * earlier forward on the context: GEER_OK or GEER_ERR_STALLED. */
+geer_status geer_check(geer_ctx* ctx, void* stream);
+/* Test hook: marks, from the host, the context (plan = NULL) or the plan's
+ * last launch (after waiting for it) as if a sort had stalled, so that the
+ * reporting paths can be exercised without a device-side stall. */
+geer_status geer_debug_mark_stalled(geer_ctx* ctx, geer_plan* plan);
 
 /* Frees the frame's device state (after any pending backward has completed). */
 void geer_frame_release(geer_frame* frame);
@@ -234,7 +255,6 @@ int32_t geer_profile_read(geer_ctx* ctx, geer_profile_record* out, int32_t max);
  * When a batch's association list exceeds the capacity, that launch renders
  * background and geer_plan_entries reports the overflow.
  */
-typedef struct geer_plan geer_plan;
 
 /* Device workspace a plan of this shape needs, in bytes (same checks as
  * geer_plan_create). */

@@ -15,8 +15,8 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libgeer.so")
 
-OK, ERR_INVALID_ARG, ERR_OOM, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = range(6)
-STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "CAPACITY", 4: "HIP", 5: "UNSUPPORTED"}
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED, ERR_STALLED = range(7)
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "CAPACITY", 4: "HIP", 5: "UNSUPPORTED", 6: "STALLED"}
 MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2}
 BUF_RECT, BUF_COUNT, BUF_KEY, BUF_LIST, BUF_RANGES, BUF_NLAST = range(6)
 
@@ -25,7 +25,8 @@ EXPORTS = ["geer_create", "geer_destroy", "geer_last_error", "geer_default_opts"
            "geer_render_backward", "geer_frame_release", "geer_frame_get_stats", "geer_frame_buffer_bytes",
            "geer_frame_export", "geer_valid_mask", "geer_l1_loss", "geer_set_profiling", "geer_profile_read",
            "geer_plan_workspace_bytes", "geer_plan_create", "geer_train_plan_workspace_bytes",
-           "geer_train_plan_create", "geer_plan_launch", "geer_plan_entries", "geer_plan_device_bytes", "geer_plan_destroy"]
+           "geer_train_plan_create", "geer_plan_launch", "geer_plan_entries", "geer_plan_device_bytes", "geer_plan_destroy",
+           "geer_check", "geer_debug_mark_stalled"]
 
 
 class GeerView(C.Structure):
@@ -111,6 +112,8 @@ def load():
         L.geer_plan_device_bytes.restype = C.c_int64
         L.geer_plan_destroy.argtypes = [V]
         L.geer_plan_destroy.restype = None
+        L.geer_check.argtypes = [V, V]
+        L.geer_debug_mark_stalled.argtypes = [V, V]
         _lib = L
         return L
 

@@ -54,6 +54,10 @@ struct geer_ctx {
   size_t pinned_bytes = 0;
   hipEvent_t totals_ready = nullptr;  // an eager forward's count read-back has landed
   int64_t live_frames = 0;
+  // Sticky flag (device) of the eager forwards' sorts: set when a look-back
+  // gave up; reported (and cleared) by the next forward, geer_check or the
+  // statistics of a frame.
+  unsigned long long* dev_err = nullptr;
 };
 
 // Largest key count of one sort (status words hold 30-bit counts).
@@ -292,7 +296,9 @@ struct FwdBufs {
   uint32_t *keys = nullptr, *counts = nullptr;
   uint64_t* stats = nullptr;  // [0] rectangle entries, [1] visible, [2] evaluated pairs, [3] entries before
                               // the guard, [4] sort stall flag, [5] list length after the cone cull,
-                              // [6] heavy tiles
+                              // [6] heavy tiles, [7] stall flag of earlier eager forwards
+  unsigned long long* err = nullptr;  // where the sorts flag a stall (null: stats[4])
+  unsigned long long* sort_err() const { return err ? err : (unsigned long long*)(stats + 4); }
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr, *hist = nullptr, *scratch = nullptr;
   uint32_t *cnt_sorted = nullptr, *tiles_a = nullptr, *tiles_b = nullptr, *items_b = nullptr;
   uint32_t *list = nullptr, *ranges = nullptr, *nlast = nullptr;
@@ -311,14 +317,15 @@ struct FwdBufs {
 // Stage (a): zero the counters, then preprocess + PBF of every item.
 // With per_view_stats the counters of view v are the 8 words at b.stats + 8v.
 void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, const Opts& op, const float* lam,
-                        const FwdBufs& b, bool per_view_stats = false) {
+                        const FwdBufs& b, bool per_view_stats = false, const unsigned long long* err_in = nullptr) {
   const int64_t nst = per_view_stats ? 16 * nviews : 16;
   if (b.depth_work_zeroed)
     launch_zero2_u32(st, (uint32_t*)b.stats, nst, b.hist, radix_zero_words(std::max<int64_t>(sc.n * nviews, 1)));
   else
     launch_fill_u32(st, (uint32_t*)b.stats, nst, 0u);
   launch_preprocess(st, sc.n, nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh, b.views, op, lam,
-                    b.edges, b.recs, b.rects, b.keys, b.counts, (unsigned long long*)b.stats, per_view_stats ? 8 : 0);
+                    b.edges, b.recs, b.rects, b.keys, b.counts, (unsigned long long*)b.stats, per_view_stats ? 8 : 0,
+                    err_in);
 }
 
 // Stage (b): association list; the tile-sorted list ends in b.list.
@@ -328,7 +335,7 @@ void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, co
 void enqueue_depth_order(hipStream_t st, const Opts& op, int64_t n, int64_t items, int64_t nvis_cap,
                          const unsigned long long* dV, int64_t ntiles, const FwdBufs& b) {
   if (nvis_cap <= 0) return;
-  unsigned long long* err = (unsigned long long*)(b.stats + 4);
+  unsigned long long* err = b.sort_err();
   // depth order of the visible items (pass 0 compacts them out of all items)
   radix_sort(st, b.keys, nullptr, b.counts, false, items, nullptr, nvis_cap, dV, 0, 4, b.ka, b.va, b.kb, b.vb,
              b.hist, nullptr, err, nullptr, 8, b.depth_work_zeroed);
@@ -346,7 +353,7 @@ void enqueue_depth_order(hipStream_t st, const Opts& op, int64_t n, int64_t item
 void enqueue_tile_lists(hipStream_t st, const Opts& op, int64_t n, int64_t nvis_cap, const unsigned long long* dV,
                         int64_t ecap, const unsigned long long* dE, int64_t ntiles, const FwdBufs& b) {
   unsigned long long* kept = (unsigned long long*)(b.stats + 5);  // list length after the cone cull
-  unsigned long long* err = (unsigned long long*)(b.stats + 4);
+  unsigned long long* err = b.sort_err();
   if (nvis_cap > 0) {
     // Expansion in depth order (entries no ray of their tile can see marked
     // for dropping), then the stable tile-id passes -- the first compacts --
@@ -494,6 +501,12 @@ geer_status geer_create(int32_t device, geer_ctx** out) {
   geer_ctx* c = new (std::nothrow) geer_ctx();
   if (!c) return GEER_ERR_OOM;
   c->device = device;
+  if (hipMalloc(&c->dev_err, 256) != hipSuccess || hipMemset(c->dev_err, 0, 256) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->dev_err) (void)hipFree(c->dev_err);
+    delete c;
+    return GEER_ERR_OOM;
+  }
   *out = c;
   return GEER_OK;
 }
@@ -511,6 +524,7 @@ void geer_destroy(geer_ctx* c) {
   for (LamTab& t : c->lams) (void)hipFree(t.dev);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->totals_ready) (void)hipEventDestroy(c->totals_ready);
+  if (c->dev_err) (void)hipFree(c->dev_err);
   delete c;
 }
 
@@ -620,9 +634,10 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   b.ka = (uint32_t*)ka.p; b.va = (uint32_t*)va.p; b.kb = (uint32_t*)kb.p; b.vb = (uint32_t*)vb.p;
   b.hist = (uint32_t*)hist.p; b.scratch = (uint32_t*)scratch.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
   b.depth_work_zeroed = true;
+  b.err = c->dev_err;
   ProfSlot* ps = prof_slot(c);
   prof_mark(ps, 0, st);
-  enqueue_preprocess(st, *scene, n_views, op, lt.dev, b);
+  enqueue_preprocess(st, *scene, n_views, op, lt.dev, b, false, c->dev_err);
   HTRY(hipGetLastError());
   prof_mark(ps, 1, st);
   // The entry count sizes the list, so it is read back; the depth order of
@@ -630,7 +645,7 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   // items, with the live count read on the device), so the device has work
   // while the host waits for the count.
   if (!c->totals_ready) HTRY(hipEventCreateWithFlags(&c->totals_ready, hipEventDisableTiming));
-  HTRY(hipMemcpyAsync(c->pinned, b.stats, 16, hipMemcpyDeviceToHost, st));
+  HTRY(hipMemcpyAsync(c->pinned, b.stats, 64, hipMemcpyDeviceToHost, st));
   HTRY(hipEventRecord(c->totals_ready, st));
 
   // ---- stage (b): depth sort, expansion, tile sort, ranges ----
@@ -639,8 +654,15 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   HTRY(hipGetLastError());
 
   HTRY(hipEventSynchronize(c->totals_ready));
-  uint64_t totals[2];
-  std::memcpy(totals, c->pinned, 16);
+  uint64_t totals[8];
+  std::memcpy(totals, c->pinned, 64);
+  if (totals[7] != 0) {
+    // an earlier forward on this context stalled: its outputs were invalid
+    launch_fill_u32(st, (uint32_t*)c->dev_err, 2, 0u);
+    return cleanup(fail(c, GEER_ERR_STALLED,
+                        "the association sort of an earlier forward on this context stalled (look-back spin limit); "
+                        "its outputs are invalid"));
+  }
   const int64_t E = (int64_t)totals[0], nvis = (int64_t)totals[1];
   if (totals[0] >= (uint64_t)kMaxKeys)
     return cleanup(fail(c, GEER_ERR_CAPACITY, "association list of %llu entries exceeds 2^30",
@@ -740,12 +762,23 @@ void geer_frame_release(geer_frame* f) {
   delete f;
 }
 
+// Reads and clears the context's sticky stall flag (after `stream` drains).
+geer_status take_stall(geer_ctx* c, hipStream_t stream) {
+  uint64_t e = 0;
+  HIP_TRY(c, hipStreamSynchronize(stream));
+  HIP_TRY(c, hipMemcpy(&e, c->dev_err, 8, hipMemcpyDeviceToHost));
+  if (e == 0) return GEER_OK;
+  HIP_TRY(c, hipMemset(c->dev_err, 0, 8));
+  return fail(c, GEER_ERR_STALLED, "an association sort on this context stalled (look-back spin limit); the outputs "
+                                   "of that forward are invalid");
+}
+
 geer_status read_frame_stats(const geer_frame* f, uint64_t st[6]) {
   geer_ctx* c = f->ctx;
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipMemcpyAsync(st, f->stats.p, 6 * sizeof(uint64_t), hipMemcpyDeviceToHost, f->stream));
-  HIP_TRY(c, hipStreamSynchronize(f->stream));
-  if (st[4] != 0) return fail(c, GEER_ERR_HIP, "association sort stalled (look-back spin limit)");
+  geer_status s = take_stall(c, f->stream);
+  if (s != GEER_OK) return s;
   f->kept = f->entries > 0 ? (int64_t)st[5] : 0;
   return GEER_OK;
 }
@@ -1369,7 +1402,8 @@ geer_status geer_plan_entries(geer_plan* P, int64_t* entries, int64_t* capacity)
     stalled |= P->host_stats[8 * i + 4] != 0;
   }
   if (entries) *entries = E;
-  if (stalled) return fail(c, GEER_ERR_HIP, "association sort stalled (look-back spin limit)");
+  if (stalled)
+    return fail(c, GEER_ERR_STALLED, "association sort stalled (look-back spin limit); the launch's outputs are invalid");
   if (E > P->ecap)
     return fail(c, GEER_ERR_CAPACITY, "association list of %lld entries exceeds the plan's %lld", (long long)E,
                 (long long)P->ecap);
@@ -1395,6 +1429,27 @@ void geer_plan_destroy(geer_plan* P) {
   if (P->host_stats) (void)hipHostFree(P->host_stats);
   if (P->owns_ws && P->ws) (void)hipFree(P->ws);
   delete P;
+}
+
+geer_status geer_check(geer_ctx* c, void* stream) {
+  if (!c) return GEER_ERR_INVALID_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  return take_stall(c, (hipStream_t)stream);
+}
+
+geer_status geer_debug_mark_stalled(geer_ctx* c, geer_plan* P) {
+  if (!c) return GEER_ERR_INVALID_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (P) {
+    if (P->ctx != c || !P->launched) return fail(c, GEER_ERR_INVALID_ARG, "plan from another context or not launched");
+    HIP_TRY(c, hipEventSynchronize(P->done));
+    P->host_stats[4] = 1;  // the first segment's stall word, as read back by the launch
+    return GEER_OK;
+  }
+  const uint64_t one = 1;
+  HIP_TRY(c, hipDeviceSynchronize());
+  HIP_TRY(c, hipMemcpy(c->dev_err, &one, 8, hipMemcpyHostToDevice));
+  return GEER_OK;
 }
 
 }  // extern "C"

@@ -55,8 +55,10 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
     const ViewDev* __restrict__ views, Opts op, const float* __restrict__ lam_tab,
     const float* __restrict__ edges, Record* __restrict__ recs, uint2* __restrict__ rects,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ counts, unsigned long long* __restrict__ totals,
-    int totals_stride) {
+    int totals_stride, const unsigned long long* __restrict__ err_in) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // the sticky stall flag of earlier forwards, returned with this one's counts
+  if (err_in && g == 0) totals[7] = *err_in;
   const bool in = g < n;
   unsigned long long my_entries = 0, my_visible = 0;
   float mu[3], s[3], q[4], sigma = 0.0f;
@@ -133,12 +135,12 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
                        const float* scale, const float* quat, const float* opacity, const float* sh,
                        const ViewDev* views, const Opts& op, const float* lam_tab, const float* edges,
                        Record* recs, uint2* rects, uint32_t* keys, uint32_t* counts,
-                       unsigned long long* totals, int totals_stride) {
+                       unsigned long long* totals, int totals_stride, const unsigned long long* err_in) {
   if (n == 0) return;
   const dim3 grid((unsigned)((n + 255) / 256));
 #define GEER_PRE(D)                                                                                               \
   hipLaunchKernelGGL(preprocess_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, scale, quat, opacity, sh,     \
-                     views, op, lam_tab, edges, recs, rects, keys, counts, totals, totals_stride)
+                     views, op, lam_tab, edges, recs, rects, keys, counts, totals, totals_stride, err_in)
   switch (sh_degree) {
     case 0: GEER_PRE(0); break;
     case 1: GEER_PRE(1); break;

@@ -23,7 +23,7 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
                        const float* scale, const float* quat, const float* opacity, const float* sh,
                        const ViewDev* views, const Opts& op, const float* lam_tab, const float* edges,
                        Record* recs, uint2* rects, uint32_t* keys, uint32_t* counts, unsigned long long* totals,
-                       int totals_stride);
+                       int totals_stride, const unsigned long long* err_in = nullptr);
 
 // sort.hip
 int64_t scan_scratch_words(int64_t n);

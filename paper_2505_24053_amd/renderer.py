@@ -31,6 +31,15 @@ def set_profiling(enable: bool, device: int = 0):
     _lib.check(_lib.load().geer_set_profiling(context(device), 1 if enable else 0), context(device))
 
 
+def check_errors(device: int = 0, stream=None):
+    """Waits for the work on `stream` (the current stream by default) and
+    raises GeerError (status STALLED) if an earlier forward's association
+    sort gave up on its bounded wait: that forward's outputs are invalid."""
+    ctx = context(device)
+    st = (stream or torch.cuda.current_stream(device)).cuda_stream
+    _lib.check(_lib.load().geer_check(ctx, C.c_void_p(st)), ctx)
+
+
 def profile_read(max_records: int = 64, device: int = 0):
     """Stage timings of the most recent renders (oldest first)."""
     recs = (_lib.GeerProfileRecord * max_records)()
@@ -259,13 +268,28 @@ class Plan:
             stream = torch.cuda.current_stream()
         _lib.check(_lib.load().geer_plan_launch(self.handle, _views(cams), C.c_void_p(stream.cuda_stream)), self.ctx)
 
-    def entries(self):
-        """(entries, capacity, overflowed) of the last launch (waits for it)."""
+    def status(self) -> dict:
+        """Outcome of the last launch (waits for it): PBF pairs, capacity,
+        whether they overflowed it and whether a sort stalled -- either way
+        the launch's outputs are invalid and must be rendered again."""
         e, cap = C.c_int64(), C.c_int64()
         st = _lib.load().geer_plan_entries(self.handle, C.byref(e), C.byref(cap))
-        if st not in (0, _lib.ERR_CAPACITY):
+        if st not in (0, _lib.ERR_CAPACITY, _lib.ERR_STALLED):
             _lib.check(st, self.ctx)
-        return int(e.value), int(cap.value), st == _lib.ERR_CAPACITY
+        return dict(entries=int(e.value), capacity=int(cap.value), overflow=int(e.value) > int(cap.value),
+                    stalled=st == _lib.ERR_STALLED)
+
+    def entries(self):
+        """(entries, capacity, overflowed) of the last launch (waits for it);
+        raises GeerError if a sort stalled."""
+        s = self.status()
+        if s["stalled"]:
+            _lib.check(_lib.ERR_STALLED, self.ctx)
+        return s["entries"], s["capacity"], s["overflow"]
+
+    def mark_stalled(self):
+        """Test hook: reports the last launch as stalled (host-side flag)."""
+        _lib.check(_lib.load().geer_debug_mark_stalled(self.ctx, self.handle), self.ctx)
 
     def device_bytes(self) -> int:
         return int(_lib.load().geer_plan_device_bytes(self.handle))

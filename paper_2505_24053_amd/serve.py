@@ -15,7 +15,9 @@ copied out of the slot's arena on its stream; a batch whose association list
 overflowed the capacity is re-rendered eagerly (the eager path sizes itself).
 
 Latency is host wall time from a request's arrival to the moment the
-scheduler sees its batch complete.  The same cameras rendered alone give the
+scheduler sees its batch complete.  A batch whose association sort stalled
+(a bounded device-side wait gave up) is re-rendered eagerly like an
+overflowed one.  The same cameras rendered alone give the
 same bits: a view's tiles only ever hold that view's Gaussians, sorted by the
 same (depth key, index) order.
 """
@@ -105,7 +107,7 @@ class Server:
                 out = (torch.empty(3 * max_pix, device=self.dev), torch.empty(max_pix, device=self.dev),
                        torch.empty(max_pix, device=self.dev))
             self.slots.append(_Slot(i, st, ws, out))
-        self.stats = dict(batches=0, overflows=0, views=0, overlapped=0)
+        self.stats = dict(batches=0, overflows=0, stalls=0, views=0, overlapped=0)
         self.intervals = []  # (slot, start event, end event) per batch
 
     # ------------------------------------------------------------ sizing --
@@ -188,9 +190,11 @@ class Server:
 
     def retire(self, slot: _Slot, now: float) -> list:
         batch, plan = slot.batch, slot.plan
-        _, _, overflow = plan.entries()
-        if overflow:
-            self.stats["overflows"] += 1
+        st = plan.status()
+        if st["overflow"] or st["stalled"]:
+            # the batch's outputs are invalid: render its views again eagerly
+            # (the eager path sizes its list exactly)
+            self.stats["overflows" if st["overflow"] else "stalls"] += 1
             with torch.cuda.stream(slot.stream):
                 for r in batch:
                     r.rgb, r.depth, r.trans, _ = renderer.render(self.scene, [r.cam], opts=self.opts)
