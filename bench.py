@@ -9,19 +9,26 @@ HBM before the timed region; outputs are preallocated.
 
 Printed (one JSON line on stdout):
   value          rays rendered per second (Mrays/s, whole job)
-  roofline       the render kernel (dominant) against the FP32 VALU peak,
-                 timed with HIP events on its own stream inside the library
-  cpu_baseline   the FP64 oracle on a bounded sample of the same rays,
-                 on the host cores, with the GPU's RGB error on that sample
+  roofline       the render kernel (dominant) against the FP32 vector peak,
+                 its duration from HIP events recorded on its stream inside
+                 the library; frame_roofline: the frame's algorithmic time
+                 against the measured one
+  cpu_baseline   the FP64 oracle on a bounded sample of the same rays, on the
+                 host cores (and on one core), with the GPU's rays checked
+                 against it on that sample
   fwd_bwd        forward + L1 loss + backward of 500,000 Gaussians (SH 3)
                  through a Kannala-Brandt 190-degree fisheye at 1280 x 960
-                 against a target rendered from perturbed parameters
+                 against a target rendered from perturbed parameters, with
+                 its own roofline (the backward replay kernel) and oracle leg
   train_batched  one captured training step (per view: forward, L1, backward)
                  of 3M Gaussians (SH 3) over 8 views of 1920 x 1080, four
-                 pinhole 90-degree and four equidistant 180-degree
-  serving        Poisson stream of render requests (pinhole 640 x 480,
-                 equidistant 1024 x 1024, KB 200-degree 1920 x 1080) over a
-                 resident 1M-Gaussian scene: p50/p99 latency, req/s, Mrays/s
+                 pinhole 90-degree and four equidistant 180-degree, with its
+                 roofline and oracle leg
+  serving        render requests (pinhole 640 x 480, equidistant 1024 x 1024,
+                 KB 200-degree 1920 x 1080) over a resident 1M-Gaussian scene:
+                 saturated throughput (closed loop), then Poisson arrivals at
+                 70% and 90% of it; p50/p99 latency to device completion,
+                 req/s, Mrays/s, mean batch, device overlap
 """
 from __future__ import annotations
 
@@ -37,14 +44,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s fwd and fwd+bwd vs plain, p50/p99 frame latency, RGB err vs FP64"
-# Render kernel work per evaluated (ray, entry) pair, in FP32 operations of its
-# formulation (FMA = 2): g = G d (15), |g_perp|^2 (3), |g|^2 (2), 1/|g|^2 (1),
-# q (1), exponent and exp2 (3), alpha clamp (1), T(1 - alpha) (2), weight (1),
-# colour (6), depth (4).
-FLOP_PER_PAIR = 39
-# FP32 vector peak without packed FP32 (which the build disables): 256 CUs x
-# 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz.
-PEAK_TFLOPS = 78.6432
+# MI355X published peaks: FP32 vector 157.3 TFLOP/s (the figure counts packed
+# FP32, two lanes' FMAs per instruction; this build keeps packed FP32 off, so
+# 78.6 TFLOP/s is the most its scalar-FP32 code can issue, reported beside
+# it), HBM3E 8 TB/s.
+PEAK_TFLOPS = 157.3
+UNPACKED_TFLOPS = 78.6
+HBM_BPS = 8.0e12
+# Algorithmic work of one evaluated (ray, Gaussian) pair of the render:
+# whitened direction (9 FMA), cross product (9), the two squared norms (5 + 5),
+# closest approach (5), contribution test, alpha, blend and transmittance
+# (~10): 48 FLOP, plus one exp and one reciprocal.  The backward replay does
+# about 2.5 times that per pair (recovering T, the colour behind, and the
+# 16 partial derivatives of App. C).
+FLOP_FWD_PAIR = 48
+FLOP_BWD_PAIR = 120
 
 
 def log(*a):
@@ -75,7 +89,122 @@ def traffic_record(csrc_dir):
     return rec.get("hbm_bytes_per_launch")
 
 
-def bench_fwd_bwd(args, dev):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    threads = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS"):
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    return threads
+
+
+# ----------------------------------------------------- algorithmic time --
+
+def t_forward(gaussians, views, sh_degree, visible, entries, evaluated, rays):
+    """Algorithmic time (s) of one forward at the MI355X peaks, by term:
+    preprocess reads the scene once (44 + 12K B per Gaussian) and writes an
+    80-B item per (Gaussian, view); the association moves ~44 B per list entry
+    (expansion write, two tile passes, the render's read) and 32 B per
+    visible item (four depth passes); the render does 48 FLOP per evaluated
+    pair and writes 24 B per ray."""
+    K = (sh_degree + 1) ** 2
+    return {"preprocess": (gaussians * (44 + 12 * K) + gaussians * views * 80) / HBM_BPS,
+            "association": (entries * 44 + visible * 32) / HBM_BPS,
+            "render": evaluated * FLOP_FWD_PAIR / (PEAK_TFLOPS * 1e12) + rays * 24 / HBM_BPS}
+
+
+def t_backward(gaussians, sh_degree, visible, evaluated_bwd, rays):
+    """Algorithmic time (s) of the L1 loss and the backward: the loss reads
+    RGB, target and mask and writes dL/dRGB (37 B per ray); the replay does
+    120 FLOP per replayed pair and reads dL/dRGB, T_final and the last index
+    (20 B per ray); the Gaussian-wise stage reads the parameters and the
+    64-B accumulator of each visible item and writes the gradients."""
+    K = (sh_degree + 1) ** 2
+    return {"l1": rays * 37 / HBM_BPS,
+            "replay": evaluated_bwd * FLOP_BWD_PAIR / (PEAK_TFLOPS * 1e12) + rays * 20 / HBM_BPS,
+            "gaussian_wise": (2 * gaussians * (44 + 12 * K) + visible * 64) / HBM_BPS}
+
+
+def frame_roofline(terms_s, measured_ms):
+    t = sum(terms_s.values())
+    return {"t_roof_ms": round(t * 1e3, 4), "t_measured_ms": round(measured_ms, 4),
+            "frac": round(t * 1e3 / measured_ms, 4) if measured_ms > 0 else None,
+            "terms_ms": {k: round(v * 1e3, 4) for k, v in terms_s.items()}}
+
+
+def kernel_roofline(kernel, flop_per_pair, pairs, ms, traffic=None):
+    """Achieved FLOP rate of one launch of `kernel`: pairs it evaluated
+    times the algorithmic FLOP per pair, over its event-timed duration."""
+    achieved = flop_per_pair * pairs / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"kernel": kernel, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": traffic,
+            "launch_ms": round(ms, 4), "evaluated_pairs": int(pairs), "flop_per_pair": flop_per_pair,
+            "frac_of_unpacked_78_6": round(achieved / UNPACKED_TFLOPS, 4)}
+
+
+# ------------------------------------------------------------ oracle legs --
+
+def oracle_leg(scene_np, cam, pix, threads, got, what):
+    """The FP64 oracle on `pix` (all host threads), timed, and the GPU's rays
+    `got` = (rgb [P,3], depth [P], trans [P]) checked against it: unflagged
+    rays at the RGB/T 2e-4 and depth 1e-3 gates, flagged rays against their
+    decision branches."""
+    import numpy as np
+
+    import oracle
+
+    c0 = time.perf_counter()
+    ref = oracle.render(scene_np, cam, pix=pix, nthreads=threads)
+    c1 = time.perf_counter()
+    rgb, depth, trans = got
+    err = np.abs(rgb - ref["rgb"]).max(axis=1)
+    okm = ~ref["amb"]
+    terr = np.abs(trans - ref["trans"])
+    derr = np.abs(depth - ref["depth"]) / (1 + np.abs(ref["depth"]))
+    score = oracle.branch_scores(rgb, depth, trans, ref)
+    check = {"rays": int(pix.size), "max_abs_rgb_unflagged": float(err[okm].max(initial=0)),
+             "max_abs_t_unflagged": float(terr[okm].max(initial=0)),
+             "max_rel_depth_unflagged": float(derr[okm].max(initial=0)),
+             "flagged_frac": round(float(ref["amb"].mean()), 5),
+             "flagged_match_a_branch": bool(np.all(score <= 1.0)),
+             "pass": bool(err[okm].max(initial=0) <= 2e-4 and terr[okm].max(initial=0) <= 2e-4
+                          and derr[okm].max(initial=0) <= 1e-3 and np.all(score <= 1.0))}
+    cpu = {"value": round(pix.size / (c1 - c0) / 1e6, 6), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+           "seconds": round(c1 - c0, 2), "cpu_model": cpu_model(),
+           "sample": "%d seeded random rays of %s, FP64 brute force over all %d Gaussians (with the decision "
+                     "branches of flagged rays)" % (pix.size, what, scene_np.n)}
+    return cpu, check
+
+
+def single_thread(scene_np, cam, pix):
+    import oracle
+
+    c0 = time.perf_counter()
+    oracle.render(scene_np, cam, pix=pix, nthreads=1, branches=False)
+    return round(pix.size / (time.perf_counter() - c0) / 1e6, 7)
+
+
+def gpu_rays(rgb, depth, trans, rays, pix, dev):
+    import torch
+
+    tp = torch.as_tensor(pix, device=dev)
+    g = rgb.view(3, rays).T[tp].double().cpu().numpy()
+    d = depth[tp].double().cpu().numpy() if depth is not None else None
+    t = trans[tp].double().cpu().numpy() if trans is not None else None
+    return g, d, t
+
+
+# -------------------------------------------------------------- workloads --
+
+def bench_fwd_bwd(args, dev, threads):
     """Forward + L1 + backward steps of the 500k-Gaussian KB 190-degree frame."""
     import numpy as np
     import torch
@@ -120,21 +249,48 @@ def bench_fwd_bwd(args, dev):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.train_steps
-    # stage split: the same steps again with events between the stages
+    # stage split: the same steps again with events between the stages, and
+    # with the library's kernel events and pair counters
+    renderer.set_profiling(True)
+    renderer.profile_read()
     for _ in range(args.train_steps):
         step(True)
         torch.cuda.synchronize()
         times.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
+    recs = renderer.profile_read(64)
+    renderer.set_profiling(False)
+    fw = [r for r in recs if r["kind"] == 0]
+    bw = [r for r in recs if r["kind"] == 1]
     med = np.median(np.array(times), axis=0)
-    return {"workload": "fwd_bwd_kb190_500k_sh3_1280x960_l1", "gaussians": scene_np.n, "rays": rays,
-            "steps": args.train_steps, "ms_per_step": round(ms_step, 4),
-            "mrays_per_s": round(rays / (ms_step * 1e-3) / 1e6, 3),
-            "stages_ms": {"forward": round(float(med[0]), 4), "l1_loss": round(float(med[1]), 4),
-                          "backward": round(float(med[2]), 4)},
-            "loss": round(float(loss.item()), 6)}
+    _, _, _, frame = renderer.render(sc, cams, keep_frame=True)
+    st = frame.stats()
+    frame.release()
+    ms_replay = statistics.mean(r["ms_render"] for r in bw)
+    ms_fwd_render = statistics.mean(r["ms_render"] for r in fw)
+    n_bwd = bw[-1]["n_evaluated"]
+    terms = t_forward(scene_np.n, 1, scene_np.sh_degree, st["n_visible"], st["n_entries"], st["n_evaluated"], rays)
+    terms.update(t_backward(scene_np.n, scene_np.sh_degree, st["n_visible"], n_bwd, rays))
+    res = {"workload": "fwd_bwd_kb190_500k_sh3_1280x960_l1", "gaussians": scene_np.n, "rays": rays,
+           "steps": args.train_steps, "ms_per_step": round(ms_step, 4),
+           "mrays_per_s": round(rays / (ms_step * 1e-3) / 1e6, 3),
+           "stages_ms": {"forward": round(float(med[0]), 4), "l1_loss": round(float(med[1]), 4),
+                         "backward": round(float(med[2]), 4), "render_kernel": round(ms_fwd_render, 4),
+                         "replay_kernel": round(ms_replay, 4),
+                         "gaussian_wise_kernel": round(statistics.mean(r["ms_preprocess"] for r in bw), 4)},
+           "loss": round(float(loss.item()), 6),
+           "roofline": kernel_roofline("render_backward_kernel", FLOP_BWD_PAIR, n_bwd, ms_replay),
+           "roofline_render": kernel_roofline("render_kernel", FLOP_FWD_PAIR, fw[-1]["n_evaluated"], ms_fwd_render),
+           "frame_roofline": frame_roofline(terms, ms_step)}
+    if args.cpu_rays > 0 and args.cpu_rays_c3 > 0:
+        valid = np.nonzero(_lib.valid_mask(cam).reshape(-1))[0]
+        pix = np.sort(np.random.default_rng(args.seed + 2).choice(valid, args.cpu_rays_c3, replace=False))
+        got = gpu_rays(out[0], out[1], out[2], rays, pix, dev)
+        res["cpu_baseline"], res["rgb_err_vs_fp64"] = oracle_leg(scene_np, cam, pix, threads, got,
+                                                                 "the 1280x960 KB 190 frame's valid rays")
+    return res
 
 
-def bench_train_batched(args, dev):
+def bench_train_batched(args, dev, threads):
     """Captured batched training steps: 3M Gaussians SH3, 8 views of 1920x1080."""
     import numpy as np
     import torch
@@ -145,7 +301,6 @@ def bench_train_batched(args, dev):
     cams = synth.workload_batched_views(seed=args.seed)
     sc = renderer.scene_from_numpy(scene_np, device=dev)
     tsc = renderer.scene_from_numpy(synth.perturb(scene_np, args.seed + 1), device=dev)
-    del scene_np
     target, _, _, _ = renderer.render(tsc, cams)
     del tsc
     mask = torch.as_tensor(np.concatenate([_lib.valid_mask(c).reshape(-1) for c in cams]).astype(np.uint8),
@@ -167,18 +322,82 @@ def bench_train_batched(args, dev):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     E, cap, over = plan.entries()
+    pst = plan.stats()
     ms = (t1 - t0) * 1e3 / args.batched_steps
-    out = {"workload": "train_step_3m_sh3_8x1920x1080_pinhole90_fisheye180_l1", "gaussians": sc["mean"].shape[1],
+    # the same per-view kernels, eagerly, with the library's kernel events and
+    # pair counters: forward, L1 and backward of each view
+    renderer.set_profiling(True)
+    renderer.profile_read()
+    grads = {k: torch.zeros_like(sc[k]) for k in ("mean", "scale", "quat", "opacity", "sh")}
+    off = 0
+    for c in cams:
+        hw = c["width"] * c["height"]
+        rgb, _, _, frame = renderer.render(sc, [c], keep_frame=True, want_depth=False, want_trans=False)
+        _, dl = renderer.l1_loss(rgb, target[3 * off: 3 * (off + hw)], mask[off: off + hw])
+        renderer.backward(frame, sc, dl, accumulate=True, grads=grads)
+        torch.cuda.synchronize()
+        frame.release()
+        off += hw
+    recs = renderer.profile_read(64)
+    renderer.set_profiling(False)
+    del grads
+    bw = [r for r in recs if r["kind"] == 1]
+    fw = [r for r in recs if r["kind"] == 0]
+    n_bwd = sum(r["n_evaluated"] for r in bw)
+    ms_replay = sum(r["ms_render"] for r in bw)
+    n_fwd = sum(r["n_evaluated"] for r in fw)
+    ms_render = sum(r["ms_render"] for r in fw)
+    terms = t_forward(scene_np.n, len(cams), scene_np.sh_degree, pst["n_visible"], pst["n_entries"],
+                      pst["n_evaluated"], rays)
+    terms.update(t_backward(scene_np.n, scene_np.sh_degree, pst["n_visible"], n_bwd, rays))
+    # per launch: the average view's pairs over the average launch
+    roof = kernel_roofline("render_backward_kernel (one view of the step, launched eagerly)", FLOP_BWD_PAIR,
+                           n_bwd / len(bw), ms_replay / len(bw))
+    roof_r = kernel_roofline("render_kernel (one view of the step, launched eagerly)", FLOP_FWD_PAIR,
+                             n_fwd / len(fw), ms_render / len(fw))
+    out = {"workload": "train_step_3m_sh3_8x1920x1080_pinhole90_fisheye180_l1", "gaussians": scene_np.n,
            "views": len(cams), "rays": rays, "steps": args.batched_steps, "ms_per_step": round(ms, 3),
            "mrays_per_s": round(rays / (ms * 1e-3) / 1e6, 2), "loss": round(float(plan.loss.item()), 6),
            "max_pbf_pairs_per_view": int(E), "capacity": int(cap), "overflow": bool(over),
-           "device_workspace_gib": round(plan.device_bytes() / 2**30, 2)}
+           "association": {"pbf_pairs": pst["n_candidates"], "entries": pst["n_entries"],
+                           "visible": pst["n_visible"], "evaluated_pairs": pst["n_evaluated"]},
+           "device_workspace_gib": round(plan.device_bytes() / 2**30, 2),
+           "roofline": roof, "roofline_render": roof_r, "frame_roofline": frame_roofline(terms, ms)}
+    if args.cpu_rays > 0 and args.cpu_rays_c5 > 0:
+        import oracle
+
+        per = max(args.cpu_rays_c5 // len(cams), 1)
+        rng = np.random.default_rng(args.seed + 3)
+        secs, checks, off = 0.0, [], 0
+        for c in cams:
+            hw = c["width"] * c["height"]
+            pix = np.sort(rng.choice(hw, per, replace=False))
+            rgb_v = plan.rgb[3 * off: 3 * (off + hw)]
+            g = rgb_v.view(3, hw).T[torch.as_tensor(pix, device=dev)].double().cpu().numpy()
+            c0 = time.perf_counter()
+            ref = oracle.render(scene_np, c, pix=pix, nthreads=threads)
+            secs += time.perf_counter() - c0
+            err = np.abs(g - ref["rgb"]).max(axis=1)
+            # the step keeps no depth or T: flagged rays are matched on RGB
+            score = oracle.branch_scores(g, ref["depth"], ref["trans"], ref)
+            checks.append((float(err[~ref["amb"]].max(initial=0)), float(ref["amb"].mean()),
+                           bool(np.all(score <= 1))))
+            off += hw
+        out["cpu_baseline"] = {"value": round(per * len(cams) / secs / 1e6, 7), "unit": "Mrays/s",
+                               "cores": threads, "kind": "oracle", "seconds": round(secs, 2),
+                               "cpu_model": cpu_model(),
+                               "sample": "%d seeded random rays per view of the 8 views, FP64 brute force over "
+                                         "all 3M Gaussians" % per}
+        out["rgb_err_vs_fp64"] = {"rays": per * len(cams), "max_abs_rgb_unflagged": max(c[0] for c in checks),
+                                  "flagged_frac": round(float(np.mean([c[1] for c in checks])), 5),
+                                  "flagged_match_a_branch": all(c[2] for c in checks)}
     plan.destroy()
     return out
 
 
 def bench_serving(args, dev):
-    """Continuous batching over the resident 1M-Gaussian scene at a fixed rate."""
+    """Continuous batching over the resident 1M-Gaussian scene: the saturated
+    throughput, then Poisson arrivals at fractions of it."""
     import numpy as np
     import torch
 
@@ -204,33 +423,45 @@ def bench_serving(args, dev):
                        max_views=4)
     graphs = srv.prepare(shapes)
     warm = synth.workload_serving_requests(args.serve_warmup, seed=args.seed + 200)
-    srv.run([serve.Request(i, c) for i, c in enumerate(warm)],
-            serve.poisson_arrivals(len(warm), args.serve_rates[0], seed=args.seed + 201))
-    points = []
-    for j, rate in enumerate(args.serve_rates):
+    srv.run([serve.Request(i, c) for i, c in enumerate(warm)])
+
+    def point(rate, j):
         srv.stats = dict(batches=0, overflows=0, stalls=0, views=0, overlapped=0)
         srv.intervals = []
+        srv.evaluated = 0
         cams = synth.workload_serving_requests(args.serve_requests, seed=args.seed + 300 + 10 * j)
-        arrivals = serve.poisson_arrivals(len(cams), rate, seed=args.seed + 301 + 10 * j)
+        arrivals = None if rate is None else serve.poisson_arrivals(len(cams), rate, seed=args.seed + 301 + 10 * j)
         done = srv.run([serve.Request(i, c) for i, c in enumerate(cams)], arrivals)
         summ = serve.latency_summary(done)
         st = dict(srv.stats)
-        points.append({"rate_req_per_s": rate, "requests": summ["requests"], "p50_ms": round(summ["p50_ms"], 3),
-                       "p99_ms": round(summ["p99_ms"], 3), "mean_ms": round(summ["mean_ms"], 3),
-                       "max_ms": round(summ["max_ms"], 3), "req_per_s": round(float(summ["req_per_s"]), 2),
-                       "mrays_per_s": round(float(summ["mrays_per_s"]), 2), "batches": st["batches"],
-                       "mean_batch": round(st["views"] / max(st["batches"], 1), 2),
-                       "admitted_while_busy": st["overlapped"],
-                       "device_overlap_frac": round(srv.device_overlap(), 3), "overflow_batches": st["overflows"]})
-        log("serving at %.0f req/s:" % rate, points[-1])
+        span = max(r.t_done for r in done) - min(r.t_arrive for r in done)
+        res = {"rate_req_per_s": rate, "requests": summ["requests"], "p50_ms": round(summ["p50_ms"], 3),
+               "p99_ms": round(summ["p99_ms"], 3), "mean_ms": round(summ["mean_ms"], 3),
+               "max_ms": round(summ["max_ms"], 3), "req_per_s": round(float(summ["req_per_s"]), 2),
+               "mrays_per_s": round(float(summ["mrays_per_s"]), 2), "batches": st["batches"],
+               "mean_batch": round(st["views"] / max(st["batches"], 1), 2),
+               "admitted_while_busy": st["overlapped"], "device_overlap_frac": round(srv.device_overlap(), 3),
+               "overflow_batches": st["overflows"], "stalled_batches": st["stalls"],
+               "render_tflops": round(FLOP_FWD_PAIR * srv.evaluated / span / 1e12, 3)}
+        log("serving %s:" % ("saturated" if rate is None else "at %.0f req/s" % rate), res)
+        return res
+
+    sat = point(None, 0)
+    cap = sat["req_per_s"]
+    points = [point(round(f * cap, 1), j + 1) for j, f in enumerate(args.serve_loads)]
     ws_gb = srv.slot_bytes * len(srv.slots) / 2**30
     srv.close()
     out = {"workload": "serving_1m_sh3_mixed_pinhole640x480_fisheye1024_kb200_1920x1080"}
-    out.update(points[0])
-    out.update({"slots": len(srv.slots), "workspace_gib": round(ws_gb, 2), "graphs_per_slot": graphs,
+    out.update(points[0] if points else sat)
+    out.update({"load_of_saturated": args.serve_loads[0] if points else 1.0, "saturated": sat,
+                "slots": len(srv.slots), "workspace_gib": round(ws_gb, 2), "graphs_per_slot": graphs,
                 "entries_per_tile_capacity": round(1.5 * per_tile, 1),
                 "alone_ms": {k: round(float(np.median(v)), 3) for k, v in alone_ms.items()},
-                "rates": points})
+                "rates": points,
+                "roofline": {"kernel": "render_kernel (whole-job rate over the saturated run)", "bound": "alu",
+                             "achieved": sat["render_tflops"], "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(sat["render_tflops"] / PEAK_TFLOPS, 4), "traffic": None,
+                             "flop_per_pair": FLOP_FWD_PAIR}})
     return out
 
 
@@ -239,7 +470,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-rays", type=int, default=16384, help="oracle sample size (0: skip)")
+    ap.add_argument("--cpu-rays", type=int, default=16384, help="oracle sample of the 1024^2 frame (0: no oracle)")
+    ap.add_argument("--cpu-rays-single", type=int, default=384, help="single-thread oracle sample")
+    ap.add_argument("--cpu-rays-c3", type=int, default=2048, help="oracle sample of the fwd+bwd frame")
+    ap.add_argument("--cpu-rays-c5", type=int, default=512, help="oracle sample of the 8-view step")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after timing, copy this many MiB device-to-device once (a plain copy kernel of known "
@@ -247,10 +481,11 @@ def main():
     ap.add_argument("--train-steps", type=int, default=10, help="fwd+bwd steps (0: skip)")
     ap.add_argument("--train-warmup", type=int, default=3)
     ap.add_argument("--batched-steps", type=int, default=5, help="captured 8-view training steps (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=600, help="served requests (0: skip)")
-    ap.add_argument("--serve-warmup", type=int, default=60)
-    ap.add_argument("--serve-rates", type=lambda t: [float(x) for x in t.split(",")], default=[200.0, 500.0],
-                    help="Poisson arrival rates (requests/s), comma-separated; the first is the headline point")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per serving point (0: skip)")
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-loads", type=lambda t: [float(x) for x in t.split(",")], default=[0.7, 0.9],
+                    help="Poisson arrival rates as fractions of the saturated throughput; the first is the "
+                         "headline point")
     ap.add_argument("--serve-slots", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -268,6 +503,7 @@ def main():
 
         __graft_entry__.build()
     dev = torch.device("cuda:0")
+    threads = host_threads()
     scene_np, cams = synth.workload_fisheye_forward(seed=args.seed)
     cam = cams[0]
     W, H = cam["width"], cam["height"]
@@ -286,6 +522,7 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = rays / (ms_step * 1e-3) / 1e6
+    renderer.check_errors()
     # stage split and the render kernel's launch time: the same frames again
     # with device events between the stages (outside the timed loop, since the
     # events themselves cost time)
@@ -294,7 +531,7 @@ def main():
     for _ in range(args.steps):
         renderer.render(sc, cams, out=out)
     torch.cuda.synchronize()
-    recs = renderer.profile_read(max(args.steps, 1))
+    recs = [r for r in renderer.profile_read(64) if r["kind"] == 0]
     renderer.set_profiling(False)
 
     ms_render = statistics.mean(r["ms_render"] for r in recs)
@@ -303,17 +540,15 @@ def main():
     ms_total = statistics.mean(r["ms_total"] for r in recs)
     n_eval = recs[-1]["n_evaluated"]
     n_entries = recs[-1]["n_entries"]
-    achieved = FLOP_PER_PAIR * n_eval / (ms_render * 1e-3) / 1e12
     _, _, _, frame = renderer.render(sc, cams, keep_frame=True)
     ranges = frame.export(_lib.BUF_RANGES).astype(np.int64)
     st = frame.stats()
     frame.release()
     per_tile = np.diff(ranges)
     traffic = traffic_record(os.path.join(ROOT, "paper_2505_24053_amd", "csrc"))
-    roofline = {"kernel": "render_kernel", "bound": "alu", "achieved": round(achieved, 3),
-                "peak": PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS, 4),
-                "traffic": traffic, "launch_ms": round(ms_render, 4), "evaluated_pairs": int(n_eval),
-                "flop_per_pair": FLOP_PER_PAIR}
+    roofline = kernel_roofline("render_kernel", FLOP_FWD_PAIR, n_eval, ms_render, traffic)
+    frame_roof = frame_roofline(t_forward(scene_np.n, 1, scene_np.sh_degree, st["n_visible"], n_entries, n_eval,
+                                          rays), ms_step)
 
     if args.copy_probe > 0:
         nb = args.copy_probe << 20
@@ -328,44 +563,30 @@ def main():
     cpu = None
     rgb_err = None
     if args.cpu_rays > 0:
-        import oracle
-
-        threads = len(os.sched_getaffinity(0))
-        if os.environ.get("OMP_NUM_THREADS"):
-            threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
-        pix = np.random.default_rng(args.seed + 1).choice(rays, args.cpu_rays, replace=False)
-        oracle.lib()
-        c0 = time.perf_counter()
-        ref = oracle.render(scene_np, cam, pix=pix, nthreads=threads)
-        c1 = time.perf_counter()
-        cpu = {"value": round(args.cpu_rays / (c1 - c0) / 1e6, 6), "unit": "Mrays/s", "cores": threads,
-               "kind": "oracle", "seconds": round(c1 - c0, 2),
-               "sample": "%d seeded random rays of the same 1024x1024 frame, FP64 brute force over all %d "
-                         "Gaussians" % (args.cpu_rays, scene_np.n)}
-        tp = torch.as_tensor(pix, device=dev)
-        got = out[0].view(3, rays).T[tp].double().cpu().numpy()
-        err = np.abs(got - ref["rgb"]).max(axis=1)
-        okm = ~ref["amb"]
-        score = oracle.branch_scores(got, out[1][tp].double().cpu().numpy(), out[2][tp].double().cpu().numpy(), ref)
-        rgb_err = {"max_abs_unflagged": float(err[okm].max()), "rays": int(args.cpu_rays),
-                   "flagged_frac": round(float(ref["amb"].mean()), 5),
-                   "flagged_match_a_branch": bool(np.all(score <= 1.0))}
+        pix = np.sort(np.random.default_rng(args.seed + 1).choice(rays, args.cpu_rays, replace=False))
+        got = gpu_rays(out[0], out[1], out[2], rays, pix, dev)
+        cpu, rgb_err = oracle_leg(scene_np, cam, pix, threads, got, "the same 1024x1024 frame")
+        if args.cpu_rays_single > 0:
+            cpu["single_thread_value"] = single_thread(scene_np, cam, pix[: args.cpu_rays_single])
+            cpu["single_thread_sample"] = "the first %d rays of the sample on one thread" % args.cpu_rays_single
 
     fwd_bwd = None
     if args.train_steps > 0:
         log("fwd+bwd: 500k Gaussians, KB 190 deg 1280x960")
-        fwd_bwd = bench_fwd_bwd(args, dev)
+        fwd_bwd = bench_fwd_bwd(args, dev, threads)
         log("fwd+bwd:", fwd_bwd)
     train_batched = None
     if args.batched_steps > 0:
         log("batched training step: 3M Gaussians, 8 views of 1920x1080")
-        train_batched = bench_train_batched(args, dev)
+        train_batched = bench_train_batched(args, dev, threads)
         log("batched:", train_batched)
     serving = None
     if args.serve_requests > 0:
-        log("serving: 1M Gaussians, %d requests at %s req/s" % (args.serve_requests, args.serve_rates))
+        log("serving: 1M Gaussians, %d requests per point, saturated then %s of it" % (args.serve_requests,
+                                                                                    args.serve_loads))
         serving = bench_serving(args, dev)
         log("serving:", serving)
+    renderer.check_errors()
 
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
@@ -381,6 +602,7 @@ def main():
                         "entries_per_tile_std": round(float(per_tile.std()), 1)},
         "rgb_err_vs_fp64": rgb_err,
         "roofline": roofline,
+        "frame_roofline": frame_roof,
         "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd,
         "train_batched": train_batched,

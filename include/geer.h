@@ -58,12 +58,23 @@ typedef enum {
 typedef enum { GEER_CAM_PINHOLE = 0, GEER_CAM_EQUIDISTANT = 1, GEER_CAM_KB = 2 } geer_cam_model;
 
 /* One view: camera model, native intrinsics (used for the valid-ray mask of
- * the loss), BEAP grid, pose.  The camera models are those of App. E
- * (pinhole; Kannala-Brandt with k1..k4; equidistant = KB with k = 0). */
+ * the loss), ray grid, pose.  The camera models are those of App. E
+ * (pinhole; Kannala-Brandt with k1..k4; equidistant = KB with k = 0).
+ * grid GEER_GRID_BEAP: the BEAP grid of width x height rays over
+ * fov_x x fov_y (below).  grid GEER_GRID_NATIVE (pinhole only): the native
+ * pixels of the pinhole sensor, width x height, pixel (i, j) looking along
+ * ((i + 1/2 - cx) / fx, (j + 1/2 - cy) / fy, 1); fov_x / fov_y are then
+ * ignored.  Since x / z = tan(theta) and y / z = tan(phi) for a pinhole ray
+ * (App. E), its columns and rows are lines of constant BEAP angles, so each
+ * 16 x 16 tile's sub-frustum is the angular box of its rays and the same
+ * association and render apply unchanged; only the edge and direction tables
+ * differ. */
+#define GEER_GRID_BEAP 0
+#define GEER_GRID_NATIVE 1
 typedef struct {
   int32_t model;         /* geer_cam_model */
-  int32_t width, height; /* BEAP grid in pixels, 1 .. 65536 */
-  int32_t reserved;      /* must be 0 */
+  int32_t width, height; /* grid in pixels, 1 .. 65536 */
+  int32_t grid;          /* GEER_GRID_BEAP (0) or GEER_GRID_NATIVE (1) */
   double fx, fy, cx, cy; /* native pinhole / fisheye intrinsics */
   double k[4];           /* KB distortion k1..k4 (0 for pinhole, equidistant) */
   double fov_x, fov_y;   /* BEAP angular extents in radians */
@@ -208,6 +219,27 @@ geer_status geer_frame_export(const geer_frame* frame, int32_t which, void* dst,
 geer_status geer_valid_mask(const geer_view* view, uint8_t* mask);
 
 /*
+ * Native camera-space output (App. E inverse interpolation): resamples a
+ * rendered BEAP image of `view` (device, `channels` planes [C][H][W] of the
+ * view's grid, e.g. rgb then depth then trans) onto the native sensor of the
+ * same camera model, native_width x native_height pixels (0: the view's grid
+ * size), into `native` (device, [C][Hn][Wn]).  Native pixel (i, j) has its
+ * centre at (i + 1/2, j + 1/2) in the sensor coordinates of fx, fy, cx, cy;
+ * its ray is the pinhole back-projection, or for Kannala-Brandt (and
+ * equidistant) the incidence angle solving theta (1 + k1 theta^2 + ... +
+ * k4 theta^8) = |offset| on the polynomial's increasing branch, at the
+ * offset's azimuth.  The ray's BEAP angles give a position in the grid; the
+ * output is the bilinear interpolation of the four neighbouring BEAP pixels
+ * (positions within half a pixel outside the grid are clamped to it).  Native
+ * pixels no BEAP ray of the grid reaches get 0 and valid = 0 (valid: device
+ * uint8 [Hn][Wn], may be NULL).  The sampling map is computed once per camera
+ * (intrinsics, FoV and sizes; the pose does not enter) in FP64 on the host and
+ * cached in the context (at most 16 maps of 16 B per native pixel).
+ */
+geer_status geer_reproject(geer_ctx* ctx, const geer_view* view, int32_t native_width, int32_t native_height,
+                           int32_t channels, const float* beap, float* native, uint8_t* valid, void* stream);
+
+/*
  * L1 loss over valid rays and its gradient (device):
  *   L = sum_{valid rays, channels} |rgb - target| / (3 * n_valid),
  *   dl_drgb = sign(rgb - target) / (3 * n_valid) on valid rays, 0 elsewhere.
@@ -220,17 +252,21 @@ geer_status geer_l1_loss(geer_ctx* ctx, int64_t pixels, const float* rgb, const 
 /*
  * Stage timing.  While enabled, every geer_render records HIP events on its
  * stream around its stages (the preprocess / PBF kernel; the sort, expansion
- * and ranges; the render kernel) and copies its device counters; up to 64
- * records are kept, oldest overwritten.  These are the Prep / Dup+Sort /
- * Render stages of the paper's timing tables.
+ * and ranges; the render kernel) and copies its device counters, and every
+ * geer_render_backward records events around its ray-wise replay kernel and
+ * its Gaussian-wise kernel and copies the replay's pair count; up to 64
+ * records are kept, oldest overwritten.  The forward stages are the Prep /
+ * Dup+Sort / Render stages of the paper's timing tables.
  */
 typedef struct {
-  float ms_preprocess; /* stage (a) kernel */
-  float ms_sort;       /* stage (b): depth sort, count scan, expansion, tile sort, ranges */
-  float ms_render;     /* stage (c) render kernel */
-  float ms_total;      /* first event to last, including the host read-back of the list size */
-  int64_t n_entries;   /* association list length */
-  int64_t n_evaluated; /* (ray, entry) pairs evaluated by the render kernel */
+  float ms_preprocess; /* forward: stage (a) kernel; backward: Gaussian-wise kernel */
+  float ms_sort;       /* forward: stage (b): depth sort, count scan, expansion, tile sort, ranges */
+  float ms_render;     /* forward: stage (c) render kernel; backward: ray-wise replay kernel */
+  float ms_total;      /* first event to last (forward: including the host read-back of the list size) */
+  int64_t n_entries;   /* forward: association list length */
+  int64_t n_evaluated; /* (ray, entry) pairs evaluated by the render (replayed by the backward) kernel */
+  int32_t kind;        /* 0: geer_render, 1: geer_render_backward */
+  int32_t reserved;
 } geer_profile_record;
 
 /* Turns stage timing on (1) or off (0) for the context. */
@@ -300,6 +336,11 @@ geer_status geer_plan_launch(geer_plan* plan, const geer_view* views, void* stre
  * fit (the outputs of that launch are then background and must be
  * re-rendered). */
 geer_status geer_plan_entries(geer_plan* plan, int64_t* entries, int64_t* capacity);
+/* Waits for the last launch and fills the device-counted statistics of its
+ * forward (summed over a training plan's views): visible items, PBF pairs
+ * (n_candidates), list entries after the cone cull, evaluated (ray, entry)
+ * pairs of the render kernel.  Before any launch only the sizes are set. */
+geer_status geer_plan_get_stats(geer_plan* plan, geer_frame_stats* out);
 /* Device memory the plan allocated itself (0 with a caller workspace). */
 int64_t geer_plan_device_bytes(const geer_plan* plan);
 /* Waits for the plan's last launch and releases it (before geer_destroy). */

@@ -37,7 +37,7 @@ DEFAULT_OPTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, lambda_mo
 
 
 class View(C.Structure):
-    _fields_ = [("model", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("pad_", C.c_int32),
+    _fields_ = [("model", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("grid", C.c_int32),
                 ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
                 ("k", C.c_double * 4), ("fov_x", C.c_double), ("fov_y", C.c_double),
                 ("R", C.c_double * 9), ("t", C.c_double * 3)]
@@ -105,6 +105,7 @@ def make_view(cam: dict) -> View:
     v = View()
     v.model = MODELS[cam["model"]]
     v.width, v.height = int(cam["width"]), int(cam["height"])
+    v.grid = 1 if cam.get("grid", "beap") == "native" else 0
     v.fx, v.fy, v.cx, v.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
     for i in range(4):
         v.k[i] = float(cam["k"][i])
@@ -324,12 +325,18 @@ def lambda2_hat(sigma: float, alpha_min: float = 1 / 255, mode: int = 0, lam_fix
 
 
 def pixel_dirs_camera(cam, pix):
-    """FP64 camera-space unit directions of BEAP pixel centres (App. E)."""
+    """FP64 camera-space unit directions of BEAP pixel centres (App. E); on
+    a native pinhole grid the pixel's own ray, whose BEAP angles have the
+    normalised image coordinates as tangents."""
     w, h = int(cam["width"]), int(cam["height"])
     pix = np.asarray(pix, dtype=np.int64)
     px, py = pix % w, pix // w
-    th = -cam["fov_x"] / 2 + (px + 0.5) * cam["fov_x"] / w
-    ph = -cam["fov_y"] / 2 + (py + 0.5) * cam["fov_y"] / h
+    if cam.get("grid", "beap") == "native":
+        th = np.arctan((px + 0.5 - cam["cx"]) / cam["fx"])
+        ph = np.arctan((py + 0.5 - cam["cy"]) / cam["fy"])
+    else:
+        th = -cam["fov_x"] / 2 + (px + 0.5) * cam["fov_x"] / w
+        ph = -cam["fov_y"] / 2 + (py + 0.5) * cam["fov_y"] / h
     d = np.stack([np.sin(th) * np.cos(ph), np.cos(th) * np.sin(ph), np.cos(th) * np.cos(ph)], -1)
     return d / np.linalg.norm(d, axis=-1, keepdims=True)
 
@@ -344,6 +351,8 @@ def valid_mask(cam):
     incidence angle is atan2(sqrt(x^2+y^2), z) so rays beyond 90 degrees are
     handled; pinhole rays need z > 0."""
     w, h = int(cam["width"]), int(cam["height"])
+    if cam.get("grid", "beap") == "native":
+        return np.ones((h, w), bool)  # the sensor's own pixels
     d = pixel_dirs_camera(cam, np.arange(w * h)).reshape(h, w, 3)
     x, y, z = d[..., 0], d[..., 1], d[..., 2]
     rxy = np.hypot(x, y)
@@ -365,6 +374,88 @@ def valid_mask(cam):
     return ok & (u >= 0) & (u < w) & (v >= 0) & (v < h)
 
 
+def _distort(theta, k):
+    t2 = theta * theta
+    return theta * (1 + k[0] * t2 + k[1] * t2**2 + k[2] * t2**3 + k[3] * t2**4)
+
+
+def kb_incidence(td, k):
+    """Incidence angle theta of distorted radii td on the increasing branch of
+    theta (1 + k1 theta^2 + ... + k4 theta^8) (App. E), by bisection to the
+    last bit; NaN where td lies beyond that branch.  The branch ends at the
+    first of 4096 even steps over [0, pi] where the derivative is <= 0."""
+    td = np.asarray(td, dtype=np.float64)
+    ts = np.pi * np.arange(1, 4097) / 4096
+    t2 = ts * ts
+    d = 1 + t2 * (3 * k[0] + t2 * (5 * k[1] + t2 * (7 * k[2] + t2 * 9 * k[3])))
+    stop = np.nonzero(d <= 0)[0]
+    hi_t = ts[stop[0]] if stop.size else np.pi
+    lo = np.zeros_like(td)
+    hi = np.full_like(td, hi_t)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        below = _distort(mid, k) < td
+        lo = np.where(below, mid, lo)
+        hi = np.where(below, hi, mid)
+    theta = 0.5 * (lo + hi)
+    return np.where(td <= _distort(hi_t, k), theta, np.nan)
+
+
+def reproject_positions(cam, native_size=None):
+    """Continuous BEAP grid positions (x, y) of the native sensor's pixel
+    centres (i + 1/2, j + 1/2) and whether a BEAP ray reaches them (App. E):
+    the pinhole back-projection ((u - cx)/fx, (v - cy)/fy, 1), or the KB ray
+    at incidence kb_incidence(|offset|) and the offset's azimuth; then
+    theta = atan2(x, z), phi = atan(y / z), position = (angle + fov/2) n / fov
+    - 1/2.  Positions more than half a pixel outside the grid are not
+    reached."""
+    w, h = int(cam["width"]), int(cam["height"])
+    nw, nh = native_size if native_size else (w, h)
+    jj, ii = np.mgrid[0:nh, 0:nw].astype(np.float64)
+    mx = (ii + 0.5 - cam["cx"]) / cam["fx"]
+    my = (jj + 0.5 - cam["cy"]) / cam["fy"]
+    if cam["model"] == "pinhole":
+        x, y, z = mx, my, np.ones_like(mx)
+        ok = np.ones(mx.shape, bool)
+    else:
+        td = np.hypot(mx, my)
+        th = kb_incidence(td, cam["k"])
+        ok = np.isfinite(th)
+        th = np.where(ok, th, 0.0)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            x = np.where(td > 0, np.sin(th) * mx / td, 0.0)
+            y = np.where(td > 0, np.sin(th) * my / td, 0.0)
+        z = np.cos(th)
+    tb = np.arctan2(x, z)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        pb = np.where(z != 0, np.arctan(y / np.where(z != 0, z, 1.0)), np.sign(y) * np.pi / 2)
+    gx = (tb + cam["fov_x"] / 2) * w / cam["fov_x"] - 0.5
+    gy = (pb + cam["fov_y"] / 2) * h / cam["fov_y"] - 0.5
+    ok &= (gx >= -0.5) & (gx <= w - 0.5) & (gy >= -0.5) & (gy <= h - 0.5)
+    return gx, gy, ok
+
+
+def reproject(cam, beap, native_size=None):
+    """BEAP image [C, H, W] of `cam` resampled onto its native sensor
+    (App. E inverse interpolation): at each reached native pixel the bilinear
+    interpolation of the four BEAP pixels around its grid position (clamped
+    into the grid), FP64; unreached pixels are 0.  Returns (native [C, Hn,
+    Wn], valid [Hn, Wn])."""
+    beap = np.asarray(beap, dtype=np.float64)
+    C_, h, w = beap.shape
+    gx, gy, ok = reproject_positions(cam, native_size)
+    x = np.clip(np.where(ok, gx, 0.0), 0, w - 1)
+    y = np.clip(np.where(ok, gy, 0.0), 0, h - 1)
+    x0 = np.floor(x).astype(np.int64)
+    y0 = np.floor(y).astype(np.int64)
+    x1 = np.minimum(x0 + 1, w - 1)
+    y1 = np.minimum(y0 + 1, h - 1)
+    fx, fy = x - x0, y - y0
+    out = ((1 - fx) * (1 - fy) * beap[:, y0, x0] + fx * (1 - fy) * beap[:, y0, x1] +
+           (1 - fx) * fy * beap[:, y1, x0] + fx * fy * beap[:, y1, x1])
+    return np.where(ok[None], out, 0.0), ok
+
+
 def opts_dict(**kw):
     d = dict(DEFAULT_OPTS)
     d.update(kw)
@@ -372,7 +463,7 @@ def opts_dict(**kw):
 
 
 __all__ = ["build", "assoc_fp32", "tile_list", "render", "branch_scores", "render_backward", "sh_basis", "pair", "edges",
-           "lambda2_hat", "contrib_mask", "valid_mask", "pixel_dirs_camera", "pixel_dirs_world", "DEFAULT_OPTS"]
+           "lambda2_hat", "contrib_mask", "valid_mask", "kb_incidence", "reproject_positions", "reproject", "pixel_dirs_camera", "pixel_dirs_world", "DEFAULT_OPTS"]
 
 
 def tile_pairs_contribute(scene, cam, tiles, gids, nthreads: int = 0, **opts):

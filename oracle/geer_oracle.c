@@ -56,7 +56,8 @@
 /* ------------------------------------------------------------- records -- */
 
 typedef struct {
-  int32_t model, width, height, pad_;
+  int32_t model, width, height;
+  int32_t grid; /* 0: BEAP grid over fov_x x fov_y; 1: native pinhole pixels */
   double fx, fy, cx, cy, k[4];
   double fov_x, fov_y;
   double R[9], t[3];
@@ -93,12 +94,25 @@ typedef struct {
 static float f_max(float a, float b) { return a > b ? a : b; }
 static float f_min(float a, float b) { return a < b ? a : b; }
 
+/* BEAP angles at pixel coordinate x (columns) / y (rows): uniform over the
+ * field of view, or for a native pinhole grid the angle whose tangent is
+ * the normalised image coordinate (x / z = tan(theta), y / z = tan(phi) of
+ * the pinhole model, App. E). */
+static double col_angle(const orc_view* v, double x) {
+  if (v->grid == 1) return atan((x - v->cx) / v->fx);
+  return -v->fov_x / 2 + x * v->fov_x / v->width;
+}
+static double row_angle(const orc_view* v, double y) {
+  if (v->grid == 1) return atan((y - v->cy) / v->fy);
+  return -v->fov_y / 2 + y * v->fov_y / v->height;
+}
+
 /* half-tile column edges: mirrored tan(theta / 2) at pixel boundaries 8h, w */
 static void edges_theta(const orc_view* v, float* e, int* nh) {
   int w = v->width, n = (w + HALF - 1) / HALF;
   for (int h = 0; h <= n; ++h) {
     int b = h < n ? h * HALF : w;
-    double th = -v->fov_x / 2 + (double)b * v->fov_x / w;
+    double th = col_angle(v, (double)b);
     e[h] = (float)tan(th / 2);
   }
   *nh = n;
@@ -109,7 +123,7 @@ static void edges_phi(const orc_view* v, float* e, int* nh) {
   int hh = v->height, n = (hh + HALF - 1) / HALF;
   for (int h = 0; h <= n; ++h) {
     int b = h < n ? h * HALF : hh;
-    double ph = -v->fov_y / 2 + (double)b * v->fov_y / hh;
+    double ph = row_angle(v, (double)b);
     e[h] = (float)tan(ph);
   }
   *nh = n;
@@ -528,8 +542,8 @@ static void prep_gaussians(const orc_scene* sc, const orc_view* vw, const orc_op
 }
 
 static void pixel_dir(const orc_view* v, int px, int py, double d[3]) {
-  double th = -v->fov_x / 2 + (px + 0.5) * v->fov_x / v->width;
-  double ph = -v->fov_y / 2 + (py + 0.5) * v->fov_y / v->height;
+  double th = col_angle(v, px + 0.5);
+  double ph = row_angle(v, py + 0.5);
   double dc[3] = {sin(th) * cos(ph), cos(th) * sin(ph), cos(th) * cos(ph)};
   double nn = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
   for (int a = 0; a < 3; ++a) dc[a] /= nn;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libgeer.so")
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED, ERR_STALLED = range(7)
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "CAPACITY", 4: "HIP", 5: "UNSUPPORTED", 6: "STALLED"}
 MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2}
+GRIDS = {"beap": 0, "native": 1}
 BUF_RECT, BUF_COUNT, BUF_KEY, BUF_LIST, BUF_RANGES, BUF_NLAST = range(6)
 
 # every symbol include/geer.h declares
@@ -26,11 +27,12 @@ EXPORTS = ["geer_create", "geer_destroy", "geer_last_error", "geer_default_opts"
            "geer_frame_export", "geer_valid_mask", "geer_l1_loss", "geer_set_profiling", "geer_profile_read",
            "geer_plan_workspace_bytes", "geer_plan_create", "geer_train_plan_workspace_bytes",
            "geer_train_plan_create", "geer_plan_launch", "geer_plan_entries", "geer_plan_device_bytes", "geer_plan_destroy",
-           "geer_check", "geer_debug_mark_stalled"]
+           "geer_check", "geer_debug_mark_stalled", "geer_plan_get_stats",
+           "geer_reproject"]
 
 
 class GeerView(C.Structure):
-    _fields_ = [("model", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("model", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("grid", C.c_int32),
                 ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
                 ("k", C.c_double * 4), ("fov_x", C.c_double), ("fov_y", C.c_double),
                 ("R", C.c_double * 9), ("t", C.c_double * 3)]
@@ -55,7 +57,8 @@ class GeerFrameStats(C.Structure):
 
 class GeerProfileRecord(C.Structure):
     _fields_ = [("ms_preprocess", C.c_float), ("ms_sort", C.c_float), ("ms_render", C.c_float),
-                ("ms_total", C.c_float), ("n_entries", C.c_int64), ("n_evaluated", C.c_int64)]
+                ("ms_total", C.c_float), ("n_entries", C.c_int64), ("n_evaluated", C.c_int64),
+                ("kind", C.c_int32), ("reserved", C.c_int32)]
 
 
 class GeerError(RuntimeError):
@@ -108,6 +111,8 @@ def load():
                                              C.c_int64, V, V, V, V, V, V, V, V, V, P(V)]
         L.geer_plan_launch.argtypes = [V, P(GeerView), V]
         L.geer_plan_entries.argtypes = [V, P(C.c_int64), P(C.c_int64)]
+        L.geer_plan_get_stats.argtypes = [V, P(GeerFrameStats)]
+        L.geer_reproject.argtypes = [V, P(GeerView), C.c_int32, C.c_int32, C.c_int32, V, V, V, V]
         L.geer_plan_device_bytes.argtypes = [V]
         L.geer_plan_device_bytes.restype = C.c_int64
         L.geer_plan_destroy.argtypes = [V]
@@ -121,7 +126,8 @@ def load():
 def make_view(cam: dict) -> GeerView:
     v = GeerView()
     v.model = MODELS[cam["model"]]
-    v.width, v.height, v.reserved = int(cam["width"]), int(cam["height"]), 0
+    v.width, v.height = int(cam["width"]), int(cam["height"])
+    v.grid = GRIDS[cam.get("grid", "beap")]
     v.fx, v.fy, v.cx, v.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
     for i in range(4):
         v.k[i] = float(cam["k"][i])

@@ -19,7 +19,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgeer.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "tables.cpp", "preprocess.hip", "sort.hip", "render.hip", "backward.hip", "loss.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "preprocess.hip", "sort.hip", "render.hip", "backward.hip", "loss.hip",
+           "reproject.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
           "-Wall", "-Wno-unused-command-line-argument"]

@@ -32,6 +32,7 @@ struct Block {
 struct ProfSlot {
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   uint64_t* host_stats = nullptr;  // pinned copy of the frame's device counters
+  int kind = 0;                    // 0: forward, 1: backward
 };
 
 // Conservative lambda^2 table for one alpha_min (device copy).
@@ -41,8 +42,17 @@ struct LamTab {
   int lo = 0, n = 0;
 };
 
+// Cached native-sensor sampling map of one camera (intrinsics and grids;
+// the pose does not enter).
+struct ReprojMap {
+  geer_view key{};
+  int nw = 0, nh = 0;
+  void* dev = nullptr;
+};
+
 struct geer_ctx {
   int device = 0;
+  std::vector<ReprojMap> maps;  // most recent last
   bool profiling = false;
   std::vector<ProfSlot> prof;  // ring of stage-timing records
   int prof_next = 0, prof_count = 0;
@@ -199,9 +209,15 @@ geer_status check_view(geer_ctx* c, const geer_view& v, int i) {
     return fail(c, GEER_ERR_INVALID_ARG, "view %d: unknown camera model %d", i, v.model);
   if (v.width < 1 || v.height < 1 || v.width > 65536 || v.height > 65536)
     return fail(c, GEER_ERR_INVALID_ARG, "view %d: grid %dx%d out of range", i, v.width, v.height);
-  if (v.reserved != 0) return fail(c, GEER_ERR_INVALID_ARG, "view %d: reserved field must be 0", i);
-  if (!(v.fov_x > 0 && v.fov_x <= 2 * M_PI) || !(v.fov_y > 0 && v.fov_y <= M_PI))
+  if (v.grid != GEER_GRID_BEAP && v.grid != GEER_GRID_NATIVE)
+    return fail(c, GEER_ERR_INVALID_ARG, "view %d: unknown grid %d", i, v.grid);
+  if (v.grid == GEER_GRID_NATIVE) {
+    if (v.model != GEER_CAM_PINHOLE)
+      return fail(c, GEER_ERR_INVALID_ARG, "view %d: native pixel grids are for pinhole cameras", i);
+    if (!(v.fx > 0 && v.fy > 0)) return fail(c, GEER_ERR_INVALID_ARG, "view %d: focal lengths must be positive", i);
+  } else if (!(v.fov_x > 0 && v.fov_x <= 2 * M_PI) || !(v.fov_y > 0 && v.fov_y <= M_PI)) {
     return fail(c, GEER_ERR_INVALID_ARG, "view %d: fov (%g, %g) outside (0, 2pi] x (0, pi]", i, v.fov_x, v.fov_y);
+  }
   if (!finite_all(v.R, 9) || !finite_all(v.t, 3) || !finite_all(v.k, 4) || !std::isfinite(v.fx) ||
       !std::isfinite(v.fy) || !std::isfinite(v.cx) || !std::isfinite(v.cy))
     return fail(c, GEER_ERR_INVALID_ARG, "view %d: non-finite camera parameter", i);
@@ -525,6 +541,7 @@ void geer_destroy(geer_ctx* c) {
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->totals_ready) (void)hipEventDestroy(c->totals_ready);
   if (c->dev_err) (void)hipFree(c->dev_err);
+  for (ReprojMap& m : c->maps) (void)hipFree(m.dev);
   delete c;
 }
 
@@ -636,6 +653,7 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   b.depth_work_zeroed = true;
   b.err = c->dev_err;
   ProfSlot* ps = prof_slot(c);
+  if (ps) ps->kind = 0;
   prof_mark(ps, 0, st);
   enqueue_preprocess(st, *scene, n_views, op, lt.dev, b, false, c->dev_err);
   HTRY(hipGetLastError());
@@ -729,9 +747,12 @@ geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* 
   if (!f->nlast.p || !f->tfinal.p) return fail(c, GEER_ERR_INVALID_ARG, "frame holds no forward state");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(c, hipSetDevice(c->device));
+  // per-item accumulators, then the replay's pair counters and their total
   Block acc;
-  geer_status s = acquire(c, sizeof(float) * 16 * (size_t)std::max<int64_t>(f->items, 1), st, acc);
+  const size_t acc_bytes = round_up(sizeof(float) * 16 * (size_t)std::max<int64_t>(f->items, 1), 256);
+  geer_status s = acquire(c, acc_bytes + 8 * (size_t)(kEvalSlots + 1) * kEvalStride, st, acc);
   if (s != GEER_OK) return s;
+  unsigned long long* counters = (unsigned long long*)((char*)acc.p + acc_bytes);
   const char* meta = (const char*)f->meta.p;
   const ViewDev* d_views = (const ViewDev*)meta;
   const float* d_edges = (const float*)(meta + f->edges_off);
@@ -739,12 +760,24 @@ geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* 
   const geer_scene& sc = f->scene;
   const HeavyTiles heavy{(uint32_t*)f->heavy_list.p, (uint32_t*)f->heavy_flag.p,
                          (unsigned long long*)((uint64_t*)f->stats.p + 6), f->hmax, heavy_slots(f->hmax)};
-  launch_backward(st, f->op.lambda_mode == 1, f->ntiles, f->n, f->nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat,
-                  sc.opacity, sc.sh, d_views, d_dtab, d_edges, f->lam, f->op, heavy, (const uint32_t*)f->ranges.p,
-                  (const uint32_t*)f->list.p, (const uint2*)f->rects.p, (const Record*)f->recs.p,
-                  (const uint32_t*)f->counts.p, (const uint32_t*)f->nlast.p, (const float*)f->tfinal.p, dl_drgb,
-                  (float*)acc.p, accumulate != 0,
-                  g_mean, g_scale, g_quat, g_opacity, g_sh);
+  ProfSlot* ps = prof_slot(c);
+  if (ps) ps->kind = 1;
+  launch_zero_acc(st, (float*)acc.p, (const uint32_t*)f->counts.p, f->items, counters);
+  prof_mark(ps, 0, st);
+  launch_render_backward(st, f->op.lambda_mode == 1, f->ntiles, f->nviews, d_views, d_dtab, f->op, heavy,
+                         (const uint32_t*)f->ranges.p, (const uint32_t*)f->list.p, (const uint2*)f->rects.p,
+                         (const Record*)f->recs.p, (const uint32_t*)f->nlast.p, (const float*)f->tfinal.p, dl_drgb,
+                         (float*)acc.p, counters);
+  prof_mark(ps, 1, st);
+  launch_preprocess_backward(st, f->n, f->nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh,
+                             d_views, d_edges, f->lam, f->op, (const uint32_t*)f->counts.p, (const float*)acc.p,
+                             accumulate != 0, g_mean, g_scale, g_quat, g_opacity, g_sh);
+  prof_mark(ps, 2, st);
+  if (ps) {
+    prof_mark(ps, 3, st);
+    prof_mark(ps, 4, st);
+    (void)hipMemcpyAsync(ps->host_stats, counters + kEvalSlots * kEvalStride, 8, hipMemcpyDeviceToHost, st);
+  }
   hipError_t e = hipGetLastError();
   release(c, acc);
   if (e != hipSuccess) return fail(c, GEER_ERR_HIP, "backward launch: %s", hipGetErrorString(e));
@@ -867,17 +900,29 @@ int32_t geer_profile_read(geer_ctx* c, geer_profile_record* out, int32_t max) {
     int idx = ((c->prof_next - n + i) % size + size) % size;
     ProfSlot& ps = c->prof[idx];
     if (hipEventSynchronize(ps.ev[4]) != hipSuccess) return -GEER_ERR_HIP;
-    float t01 = 0, t23 = 0, t34 = 0, t04 = 0;
+    float t01 = 0, t12 = 0, t23 = 0, t34 = 0, t04 = 0;
     (void)hipEventElapsedTime(&t01, ps.ev[0], ps.ev[1]);
+    (void)hipEventElapsedTime(&t12, ps.ev[1], ps.ev[2]);
     (void)hipEventElapsedTime(&t23, ps.ev[2], ps.ev[3]);
     (void)hipEventElapsedTime(&t34, ps.ev[3], ps.ev[4]);
     (void)hipEventElapsedTime(&t04, ps.ev[0], ps.ev[4]);
-    out[i].ms_preprocess = t01;
-    out[i].ms_sort = t23;
-    out[i].ms_render = t34;
-    out[i].ms_total = t04;
-    out[i].n_entries = (int64_t)ps.host_stats[5];
-    out[i].n_evaluated = (int64_t)ps.host_stats[2];
+    out[i].kind = ps.kind;
+    out[i].reserved = 0;
+    if (ps.kind == 1) {  // backward: ray-wise replay, Gaussian-wise stage
+      out[i].ms_render = t01;
+      out[i].ms_preprocess = t12;
+      out[i].ms_sort = 0.0f;
+      out[i].ms_total = t04;
+      out[i].n_entries = 0;
+      out[i].n_evaluated = (int64_t)ps.host_stats[0];
+    } else {
+      out[i].ms_preprocess = t01;
+      out[i].ms_sort = t23;
+      out[i].ms_render = t34;
+      out[i].ms_total = t04;
+      out[i].n_entries = (int64_t)ps.host_stats[5];
+      out[i].n_evaluated = (int64_t)ps.host_stats[2];
+    }
   }
   c->prof_count = 0;
   return n;
@@ -910,7 +955,6 @@ geer_status geer_l1_loss(geer_ctx* c, int64_t pixels, const float* rgb, const fl
   if (e != hipSuccess) return fail(c, GEER_ERR_HIP, "loss launch: %s", hipGetErrorString(e));
   return GEER_OK;
 }
-
 
 // Workspace layout of a plan: every buffer of the capacity-sized forward,
 // 256-byte aligned, carved from one block.
@@ -1410,6 +1454,31 @@ geer_status geer_plan_entries(geer_plan* P, int64_t* entries, int64_t* capacity)
   return GEER_OK;
 }
 
+geer_status geer_plan_get_stats(geer_plan* P, geer_frame_stats* out) {
+  if (!P || !out) return GEER_ERR_INVALID_ARG;
+  geer_ctx* c = P->ctx;
+  std::memset(out, 0, sizeof *out);
+  out->n_items = P->items * (P->nseg ? P->nseg : 1);
+  out->n_tiles = P->ntiles;
+  out->n_pixels = P->npix;
+  if (!P->launched) return GEER_OK;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipEventSynchronize(P->done));
+  int64_t tiles = 0;
+  for (int i = 0; i < P->nstat; ++i) {
+    const uint64_t* h = P->host_stats + 8 * i;
+    out->n_visible += (int64_t)h[1];
+    out->n_evaluated += (int64_t)h[2];
+    out->n_candidates += (int64_t)h[3];
+    out->n_entries += h[0] ? (int64_t)h[5] : 0;
+  }
+  if (P->nseg) {
+    for (const geer_view& v : P->shapes) tiles += (int64_t)((v.width + 15) / 16) * ((v.height + 15) / 16);
+    out->n_tiles = tiles;
+  }
+  return GEER_OK;
+}
+
 int64_t geer_plan_device_bytes(const geer_plan* P) { return P ? P->bytes : -1; }
 
 void geer_plan_destroy(geer_plan* P) {
@@ -1429,6 +1498,71 @@ void geer_plan_destroy(geer_plan* P) {
   if (P->host_stats) (void)hipHostFree(P->host_stats);
   if (P->owns_ws && P->ws) (void)hipFree(P->ws);
   delete P;
+}
+
+bool same_camera(const geer_view& a, const geer_view& b) {
+  if (a.model != b.model || a.grid != b.grid || a.width != b.width || a.height != b.height || a.fx != b.fx ||
+      a.fy != b.fy ||
+      a.cx != b.cx || a.cy != b.cy || a.fov_x != b.fov_x || a.fov_y != b.fov_y)
+    return false;
+  for (int i = 0; i < 4; ++i)
+    if (a.k[i] != b.k[i]) return false;
+  return true;
+}
+
+geer_status geer_reproject(geer_ctx* c, const geer_view* view, int32_t native_width, int32_t native_height,
+                           int32_t channels, const float* beap, float* native, uint8_t* valid, void* stream) {
+  if (!c) return GEER_ERR_INVALID_ARG;
+  if (!view || !beap || !native) return fail(c, GEER_ERR_INVALID_ARG, "null argument");
+  geer_status s = check_view(c, *view, 0);
+  if (s != GEER_OK) return s;
+  if (view->grid != GEER_GRID_BEAP) return fail(c, GEER_ERR_INVALID_ARG, "reprojection takes a BEAP grid");
+  const int nw = native_width > 0 ? native_width : view->width;
+  const int nh = native_height > 0 ? native_height : view->height;
+  if (nw > 65536 || nh > 65536 || native_width < 0 || native_height < 0)
+    return fail(c, GEER_ERR_INVALID_ARG, "native size %dx%d out of range", native_width, native_height);
+  if (channels < 1 || channels > 64) return fail(c, GEER_ERR_INVALID_ARG, "channels %d out of range", channels);
+  if (!(view->fx > 0 && view->fy > 0)) return fail(c, GEER_ERR_INVALID_ARG, "focal lengths must be positive");
+  HIP_TRY(c, hipSetDevice(c->device));
+  void* map = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (size_t i = 0; i < c->maps.size(); ++i)
+      if (c->maps[i].nw == nw && c->maps[i].nh == nh && same_camera(c->maps[i].key, *view)) {
+        ReprojMap m = c->maps[i];
+        c->maps.erase(c->maps.begin() + i);
+        c->maps.push_back(m);
+        map = m.dev;
+        break;
+      }
+  }
+  if (!map) {
+    std::vector<int32_t> host;
+    reproject_map(*view, nw, nh, host);
+    const size_t bytes = host.size() * sizeof(int32_t);
+    if (hipMalloc(&map, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, GEER_ERR_OOM, "sampling map of %zu bytes", bytes);
+    }
+    HIP_TRY(c, hipMemcpy(map, host.data(), bytes, hipMemcpyHostToDevice));
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->maps.size() >= 16) {  // drop the least recently used map once nothing can still read it
+      (void)hipDeviceSynchronize();
+      (void)hipFree(c->maps.front().dev);
+      c->maps.erase(c->maps.begin());
+    }
+    ReprojMap m;
+    m.key = *view;
+    m.nw = nw;
+    m.nh = nh;
+    m.dev = map;
+    c->maps.push_back(m);
+  }
+  launch_reproject((hipStream_t)stream, (const int4*)map, (int64_t)nw * nh, view->width, view->height, channels, beap,
+                   native, valid);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, GEER_ERR_HIP, "reprojection launch: %s", hipGetErrorString(e));
+  return GEER_OK;
 }
 
 geer_status geer_check(geer_ctx* c, void* stream) {

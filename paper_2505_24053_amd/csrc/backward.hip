@@ -26,6 +26,8 @@
 // dq through the four dW/dq matrices (Eq. rotation) and the normalisation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "geer_common.h"
 #include "geer_device.h"
 
@@ -96,7 +98,7 @@ __device__ __forceinline__ void backward_block(const WaveBlock& W, const ViewDev
                                                const Record* __restrict__ recs, const Opts& op,
                                                const uint32_t* __restrict__ nlast, const float* __restrict__ tfinal,
                                                const float* __restrict__ dl_drgb, float* __restrict__ acc,
-                                               float4 (*s_rec)[4], uint32_t* s_item) {
+                                               float4 (*s_rec)[4], uint32_t* s_item, uint64_t& evals) {
   const ViewDev& V = views[W.v];
   const int tile = W.tile;
   const uint32_t hx = (uint32_t)W.bx0 >> 3, hy = (uint32_t)W.by0 >> 3;  // half-tile of the block
@@ -172,7 +174,9 @@ __device__ __forceinline__ void backward_block(const WaveBlock& W, const ViewDev
       float4* rr = reinterpret_cast<float4*>(&R);
       rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
       const PairEval E = eval_pair(R, dx, dy, dz);
-      const bool on = valid & (e < last) & pair_contributes<kFixed>(R, E, op);
+      const bool in_range = valid & (e < last);
+      evals += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(in_range));
+      const bool on = in_range & pair_contributes<kFixed>(R, E, op);
       if (__ballot(on) == 0) continue;
       const float a = clamp_alpha(E.a_raw, op);
       const bool clamped = !(E.a_raw < op.alpha_max);
@@ -214,7 +218,8 @@ __global__ __launch_bounds__(64 * kBackWaves) void render_backward_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
     const Record* __restrict__ recs, Opts op, HeavyTiles heavy, const uint32_t* __restrict__ nlast,
-    const float* __restrict__ tfinal, const float* __restrict__ dl_drgb, float* __restrict__ acc) {
+    const float* __restrict__ tfinal, const float* __restrict__ dl_drgb, float* __restrict__ acc,
+    unsigned long long* __restrict__ evals_total, unsigned long long* __restrict__ eval_slots) {
   __shared__ float4 s_rec_all[kBackWaves][kWinB][4];  // each wave's own window
   __shared__ uint32_t s_item_all[kBackWaves][kWinB];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -227,14 +232,17 @@ __global__ __launch_bounds__(64 * kBackWaves) void render_backward_kernel(
   // replay is inlined once)
   const bool hw = wi < heavy_waves;
   const int nh = hw ? (int)min(*heavy.count, (unsigned long long)heavy.hmax) : 0;
+  uint64_t evals = 0;  // (ray, entry) pairs replayed, as the forward counts them
   for (int h = wi / kHeavySplit;; h += heavy.hslots) {
     if (hw && h >= nh) break;
     const WaveBlock W = hw ? heavy_block((int)heavy.list[h], wi % kHeavySplit, views, nviews)
                            : ordinary_block(wi, heavy_waves, views, nviews, heavy.flag);
     if (W.live)
-      backward_block<kFixed>(W, views, dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc, s_rec, s_item);
+      backward_block<kFixed>(W, views, dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc, s_rec, s_item,
+                             evals);
     if (!hw) break;
   }
+  add_evals<kBackWaves>(evals_total, eval_slots, evals);
 }
 
 // ------------------------------------------------------------------------
@@ -385,33 +393,37 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
 // above zero); the others are never written by the ray-wise backward and
 // never read by the Gaussian-wise one.
 __global__ __launch_bounds__(256) void zero_acc_kernel(float* __restrict__ acc, const uint32_t* __restrict__ counts,
-                                                       int64_t nitems) {
+                                                       int64_t nitems, unsigned long long* __restrict__ counters) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (counters && i <= kEvalSlots) counters[i * kEvalStride] = 0ull;  // the replay's pair counters and total
   if (i >= nitems || counts[i] == 0u) return;
   float4* a = reinterpret_cast<float4*>(acc + i * kAcc);
   const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   a[0] = z; a[1] = z; a[2] = z; a[3] = z;
 }
 
-void launch_zero_acc(hipStream_t st, float* acc, const uint32_t* counts, int64_t nitems) {
-  if (nitems > 0)
-    hipLaunchKernelGGL(zero_acc_kernel, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, st, acc, counts,
-                       nitems);
+void launch_zero_acc(hipStream_t st, float* acc, const uint32_t* counts, int64_t nitems,
+                     unsigned long long* counters) {
+  const int64_t n = std::max<int64_t>(nitems, counters ? kEvalSlots + 1 : 0);
+  if (n > 0)
+    hipLaunchKernelGGL(zero_acc_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, acc, counts, nitems,
+                       counters);
 }
 
 void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int32_t n_views, const ViewDev* views,
                             const float2* dtab, const Opts& op, const HeavyTiles& heavy, const uint32_t* ranges,
                             const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
-                            const float* tfinal, const float* dl_drgb, float* acc) {
+                            const float* tfinal, const float* dl_drgb, float* acc, unsigned long long* counters) {
   if (ntiles <= 0) return;
   // waves: 16 per heavy slot, 4 per tile (both multiples of kBackWaves)
   const unsigned grid = (unsigned)((kHeavySplit * heavy.hslots + 4 * ntiles) / kBackWaves);
+  unsigned long long* total = counters ? counters + kEvalSlots * kEvalStride : nullptr;
   if (fixed_lambda)
     hipLaunchKernelGGL(render_backward_kernel<true>, dim3(grid), dim3(64 * kBackWaves), 0, st, views, n_views, dtab,
-                       ranges, list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
+                       ranges, list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc, total, counters);
   else
     hipLaunchKernelGGL(render_backward_kernel<false>, dim3(grid), dim3(64 * kBackWaves), 0, st, views, n_views, dtab,
-                       ranges, list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc);
+                       ranges, list, rects, recs, op, heavy, nlast, tfinal, dl_drgb, acc, total, counters);
 }
 
 void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
@@ -440,10 +452,10 @@ void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t 
                      const uint32_t* ranges, const uint32_t* list, const uint2* rects, const Record* recs,
                      const uint32_t* counts, const uint32_t* nlast, const float* tfinal, const float* dl_drgb,
                      float* acc, int accumulate, float* g_mean, float* g_scale, float* g_quat, float* g_opacity,
-                     float* g_sh) {
-  launch_zero_acc(st, acc, counts, n * n_views);
+                     float* g_sh, unsigned long long* counters) {
+  launch_zero_acc(st, acc, counts, n * n_views, counters);
   launch_render_backward(st, fixed_lambda, ntiles, n_views, views, dtab, op, heavy, ranges, list, rects, recs, nlast,
-                         tfinal, dl_drgb, acc);
+                         tfinal, dl_drgb, acc, counters);
   launch_preprocess_backward(st, n, n_views, sh_degree, mean, scale, quat, opacity, sh, views, edges, lam_tab, op,
                              counts, acc, accumulate, g_mean, g_scale, g_quat, g_opacity, g_sh);
 }

@@ -358,6 +358,26 @@ __device__ __forceinline__ void canonical_frame(const AssocOut& A, const float s
   ortho_basis(F.nn, F.e1, F.e2);
 }
 
+// Adds a wave's evaluated-pair count to *total; every wave of the grid calls
+// it exactly once (kWaves waves per workgroup).  The wave adds its count,
+// with one wave in the top bits, to the counter of its workgroup's slot; the
+// wave that completes a slot's tally adds the slot's sum to *total, so
+// *total takes kEvalSlots atomics instead of one per wave (contended atomics
+// on one word serialise).  The slots must start at zero.
+template <int kWaves>
+__device__ __forceinline__ void add_evals(unsigned long long* __restrict__ total,
+                                          unsigned long long* __restrict__ slots, uint64_t evals) {
+  if (!total || (threadIdx.x & 63) != 0) return;
+  const unsigned s = blockIdx.x % kEvalSlots;
+  const unsigned long long waves = (unsigned long long)((gridDim.x - 1 - s) / kEvalSlots + 1) * kWaves;
+  const unsigned long long mine = (1ull << kEvalTallyShift) | evals;
+  const unsigned long long old = atomicAdd(&slots[s * kEvalStride], mine);
+  if ((old >> kEvalTallyShift) + 1 == waves) {
+    const unsigned long long sum = (old + mine) & ((1ull << kEvalTallyShift) - 1);
+    if (sum) atomicAdd(total, sum);
+  }
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // band of tiles so that neighbouring tiles share its L2.
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {

@@ -254,24 +254,6 @@ __device__ __forceinline__ void render_heavy_block(const WaveBlock& W, const Vie
 
 constexpr int kRenderWaves = RENDER_WAVES;  // independent waves per workgroup
 
-// Adds a wave's evaluated-pair count to *total; every wave of the grid calls
-// it exactly once.  The wave adds its count, with one wave in the top bits,
-// to the counter of its workgroup's slot; the wave that completes a slot's
-// tally adds the slot's sum to *total, so *total takes kEvalSlots atomics
-// instead of one per wave.
-__device__ __forceinline__ void add_evals(unsigned long long* __restrict__ total,
-                                          unsigned long long* __restrict__ slots, uint64_t evals) {
-  if (!total || (threadIdx.x & 63) != 0) return;
-  const unsigned s = blockIdx.x % kEvalSlots;
-  const unsigned long long waves = (unsigned long long)((gridDim.x - 1 - s) / kEvalSlots + 1) * kRenderWaves;
-  const unsigned long long mine = (1ull << kEvalTallyShift) | evals;
-  const unsigned long long old = atomicAdd(&slots[s * kEvalStride], mine);
-  if ((old >> kEvalTallyShift) + 1 == waves) {
-    const unsigned long long sum = (old + mine) & ((1ull << kEvalTallyShift) - 1);
-    if (sum) atomicAdd(total, sum);
-  }
-}
-
 template <bool kFixed, bool kKeep>
 __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
     const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
@@ -295,12 +277,12 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
       render_heavy_block<kFixed, kKeep>(Wh, views[Wh.v], dtab, ranges[Wh.tile], ranges[Wh.tile + 1], list, rects,
                                         recs, op, s_rec, rgb, depth, trans, nlast, tfinal, hevals);
     }
-    add_evals(stats, heavy.evals, hevals);
+    add_evals<kRenderWaves>(stats, heavy.evals, hevals);
     return;
   }
   const WaveBlock W = ordinary_block(wi, heavy_waves, views, nviews, heavy.flag);
   if (!W.live) {
-    add_evals(stats, heavy.evals, 0);
+    add_evals<kRenderWaves>(stats, heavy.evals, 0);
     return;
   }
   const ViewDev& V = views[W.v];
@@ -341,7 +323,7 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
         tfinal[gp] = 1.0f;
       }
     }
-    add_evals(stats, heavy.evals, 0);
+    add_evals<kRenderWaves>(stats, heavy.evals, 0);
     return;
   }
   float4 p0, p1, p2, p3;
@@ -400,7 +382,7 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
       tfinal[gp] = T;
     }
   }
-  add_evals(stats, heavy.evals, evals);
+  add_evals<kRenderWaves>(stats, heavy.evals, evals);
 }
 
 // Flags tiles whose list is longer than 3x the mean over their own view's

@@ -17,6 +17,12 @@ void edge_tables(const geer_view& v, std::vector<float>& ex, std::vector<float>&
 void direction_tables(const geer_view& v, std::vector<float>& dx, std::vector<float>& dy);
 void view_constants(const geer_view& v, ViewDev& d);
 void valid_mask(const geer_view& v, uint8_t* mask);
+// native-sensor sampling map of a view's BEAP grid: 4 int32 per native pixel
+void reproject_map(const geer_view& v, int nw, int nh, std::vector<int32_t>& map);
+
+// reproject.hip
+void launch_reproject(hipStream_t st, const int4* map, int64_t npix, int W, int H, int C, const float* beap,
+                      float* native, uint8_t* valid);
 
 // preprocess.hip
 void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
@@ -79,13 +85,18 @@ void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t 
                      const uint32_t* ranges, const uint32_t* list, const uint2* rects, const Record* recs,
                      const uint32_t* counts, const uint32_t* nlast,
                      const float* tfinal, const float* dl_drgb, float* acc, int accumulate, float* g_mean,
-                     float* g_scale, float* g_quat, float* g_opacity, float* g_sh);
+                     float* g_scale, float* g_quat, float* g_opacity, float* g_sh,
+                     unsigned long long* counters = nullptr);
 
-void launch_zero_acc(hipStream_t st, float* acc, const uint32_t* counts, int64_t nitems);
+// counters: optional replay pair counters (kEvalSlots slots kEvalStride apart,
+// then the total), cleared here and filled by launch_render_backward
+void launch_zero_acc(hipStream_t st, float* acc, const uint32_t* counts, int64_t nitems,
+                     unsigned long long* counters = nullptr);
 void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int32_t n_views, const ViewDev* views,
                             const float2* dtab, const Opts& op, const HeavyTiles& heavy, const uint32_t* ranges,
                             const uint32_t* list, const uint2* rects, const Record* recs, const uint32_t* nlast,
-                            const float* tfinal, const float* dl_drgb, float* acc);
+                            const float* tfinal, const float* dl_drgb, float* acc,
+                            unsigned long long* counters = nullptr);
 void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
                                 const float* scale, const float* quat, const float* opacity, const float* sh,
                                 const ViewDev* views, const float* edges, const float* lam_tab, const Opts& op,

@@ -182,6 +182,27 @@ def l1_loss(rgb: torch.Tensor, target: torch.Tensor, mask: torch.Tensor):
     return loss, dl
 
 
+def reproject(beap: torch.Tensor, cam: dict, native_size=None, with_valid: bool = True):
+    """Resamples a rendered BEAP image of `cam` ([C, H, W] or flat C*H*W,
+    float32 on the device) onto the camera's native sensor (App. E inverse
+    interpolation).  Returns (native [C, Hn, Wn], valid [Hn, Wn] uint8 or
+    None); native_size = (Wn, Hn), default the grid's size."""
+    w, h = int(cam["width"]), int(cam["height"])
+    if beap.numel() % (w * h) != 0 or beap.dtype != torch.float32 or not beap.is_cuda:
+        raise ValueError("beap must be a float32 device tensor of C x %d x %d values" % (h, w))
+    C_ = beap.numel() // (w * h)
+    nw, nh = native_size if native_size else (w, h)
+    dev = beap.device
+    src = beap.contiguous()
+    out = torch.empty(C_ * nw * nh, device=dev, dtype=torch.float32)
+    valid = torch.empty(nw * nh, device=dev, dtype=torch.uint8) if with_valid else None
+    ctx = context(dev.index or 0)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    _lib.check(_lib.load().geer_reproject(ctx, C.byref(_lib.make_view(cam)), int(nw), int(nh), C_, _ptr(src),
+                                          _ptr(out), _ptr(valid), C.c_void_p(st)), ctx)
+    return out.view(C_, nh, nw), (valid.view(nh, nw) if valid is not None else None)
+
+
 class _Render(torch.autograd.Function):
     """Differentiable render: RGB depends on (mean, scale, quat, opacity, sh);
     depth and transmittance are returned without gradient."""
@@ -286,6 +307,12 @@ class Plan:
         if s["stalled"]:
             _lib.check(_lib.ERR_STALLED, self.ctx)
         return s["entries"], s["capacity"], s["overflow"]
+
+    def stats(self) -> dict:
+        """Device-counted statistics of the last launch (waits for it)."""
+        st = _lib.GeerFrameStats()
+        _lib.check(_lib.load().geer_plan_get_stats(self.handle, C.byref(st)), self.ctx)
+        return {k: int(getattr(st, k)) for k, _ in _lib.GeerFrameStats._fields_}
 
     def mark_stalled(self):
         """Test hook: reports the last launch as stalled (host-side flag)."""

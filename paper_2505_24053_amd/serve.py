@@ -14,8 +14,10 @@ batches on different slots run concurrently on the device.  Results are
 copied out of the slot's arena on its stream; a batch whose association list
 overflowed the capacity is re-rendered eagerly (the eager path sizes itself).
 
-Latency is host wall time from a request's arrival to the moment the
-scheduler sees its batch complete.  A batch whose association sort stalled
+Latency runs from a request's arrival (host clock) to the completion of its
+batch on the device: an event recorded after the batch's result copies, put
+on the host clock through a reference event that the host waited for when
+the run started.  A batch whose association sort stalled
 (a bounded device-side wait gave up) is re-rendered eagerly like an
 overflowed one.  The same cameras rendered alone give the
 same bits: a view's tiles only ever hold that view's Gaussians, sorted by the
@@ -40,6 +42,7 @@ class Request:
     t_arrive: float = 0.0
     t_start: float = 0.0
     t_done: float = 0.0
+    t_done_host: float = 0.0
     rgb: torch.Tensor | None = None
     depth: torch.Tensor | None = None
     trans: torch.Tensor | None = None
@@ -109,6 +112,8 @@ class Server:
             self.slots.append(_Slot(i, st, ws, out))
         self.stats = dict(batches=0, overflows=0, stalls=0, views=0, overlapped=0)
         self.intervals = []  # (slot, start event, end event) per batch
+        self.evaluated = 0   # evaluated (ray, entry) pairs of the render kernel, over retired batches
+        self._ref = None     # (event, host time) pairing the device clock with the host clock
 
     # ------------------------------------------------------------ sizing --
     def capacity(self, shapes) -> int:
@@ -188,9 +193,15 @@ class Server:
         self.stats["batches"] += 1
         self.stats["views"] += len(batch)
 
+    def _device_time(self, ev) -> float:
+        """Host-clock time of a completed device event."""
+        ref, t_ref = self._ref
+        return t_ref + ref.elapsed_time(ev) * 1e-3
+
     def retire(self, slot: _Slot, now: float) -> list:
         batch, plan = slot.batch, slot.plan
         st = plan.status()
+        t_dev = self._device_time(slot.ev_done)
         if st["overflow"] or st["stalled"]:
             # the batch's outputs are invalid: render its views again eagerly
             # (the eager path sizes its list exactly)
@@ -200,9 +211,12 @@ class Server:
                     r.rgb, r.depth, r.trans, _ = renderer.render(self.scene, [r.cam], opts=self.opts)
                     r.retried = True
             slot.stream.synchronize()
-            now = time.perf_counter()
+            now = t_dev = time.perf_counter()
+        else:
+            self.evaluated += plan.stats()["n_evaluated"]
         for r in batch:
-            r.t_done = now
+            r.t_done = t_dev
+            r.t_done_host = now
         self.intervals.append((slot.index, slot.ev_start, slot.ev_done))
         slot.batch, slot.plan = [], None
         return batch
@@ -215,6 +229,10 @@ class Server:
         order = np.argsort(arrivals, kind="stable")
         queue, done = [], []
         nxt = 0
+        ref = torch.cuda.Event(enable_timing=True)
+        ref.record(self.slots[0].stream)
+        ref.synchronize()
+        self._ref = (ref, time.perf_counter())
         t0 = time.perf_counter()
         while len(done) < len(requests):
             now = time.perf_counter()
@@ -267,6 +285,8 @@ def poisson_arrivals(count: int, rate: float, seed: int = 0) -> np.ndarray:
 
 
 def latency_summary(done: list) -> dict:
+    """Latency percentiles (arrival to device completion) and throughput over
+    the span from the first arrival to the last completion."""
     lat = np.array([r.latency for r in done]) * 1e3
     span = max(r.t_done for r in done) - min(r.t_arrive for r in done)
     rays = sum(r.shape[0] * r.shape[1] for r in done)

@@ -143,6 +143,20 @@ def camera_pinhole(width: int, height: int, fov_x_deg: float, R=None, position=N
                 fov_y=2 * math.atan((height / 2) / f), R=Rw, t=t)
 
 
+def camera_pinhole_native(width: int, height: int, fov_x_deg: float, R=None, position=None,
+                          principal=(0.5, 0.5), aspect: float = 1.0) -> dict:
+    """Pinhole camera rendered on its own pixel grid (one ray per native
+    pixel); the principal point at the given fractions of the sensor and
+    fy = aspect * fx.  fov_x / fov_y record the sensor's angular extent."""
+    f = (width / 2) / math.tan(math.radians(fov_x_deg) / 2)
+    Rw, t = _pose(R, position)
+    cx, cy = principal[0] * width, principal[1] * height
+    fy = aspect * f
+    return dict(model="pinhole", grid="native", width=width, height=height, fx=f, fy=fy, cx=cx, cy=cy,
+                k=[0.0, 0.0, 0.0, 0.0], fov_x=math.atan(cx / f) + math.atan((width - cx) / f),
+                fov_y=math.atan(cy / fy) + math.atan((height - cy) / fy), R=Rw, t=t)
+
+
 def camera_equidistant(width: int, height: int, fov_deg: float, R=None, position=None) -> dict:
     """Equidistant fisheye (Kannala-Brandt with zero distortion). The BEAP grid
     has equal angular pitch along both axes."""
