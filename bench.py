@@ -395,6 +395,83 @@ def bench_train_batched(args, dev, threads):
     return out
 
 
+def bench_assoc_variants(args, dev, sc, scene_np, cams, base_rgb):
+    """The PBF against the projected-footprint associations (EWA and UT, square
+    and snug boxes) in the same pipeline on the forward frame: frame time
+    with and without the contribution-cone cull, PBF/box pairs per tile (the
+    list without the cull), and how far each image is from the PBF's (pairs
+    the footprint boxes lose)."""
+    import numpy as np
+    import torch
+
+    from paper_2505_24053_amd import _lib, renderer
+
+    rays = cams[0]["width"] * cams[0]["height"]
+    out = (torch.empty(3 * rays, device=dev), torch.empty(rays, device=dev), torch.empty(rays, device=dev))
+    res = {}
+    for method in ("pbf", "ewa", "ewa_snug", "ut", "ut_snug"):
+        row = {}
+        for cull in (True, False):
+            opts = dict(assoc=method, cone_cull=cull)
+            for _ in range(2):
+                renderer.render(sc, cams, opts=opts, out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.variant_steps):
+                renderer.render(sc, cams, opts=opts, out=out)
+            torch.cuda.synchronize()
+            row["ms_frame" if cull else "ms_frame_no_cull"] = round((time.perf_counter() - t0) * 1e3 /
+                                                                    args.variant_steps, 4)
+            if cull:
+                diff = (out[0].view(3, rays) - base_rgb.view(3, rays)).abs().amax(dim=0)
+                row["rgb_vs_pbf"] = {"max_abs": round(float(diff.max().item()), 6),
+                                     "rays_over_2e-4": round(float((diff > 2e-4).float().mean().item()), 6)}
+            else:
+                _, _, _, fr = renderer.render(sc, cams, opts=opts, keep_frame=True)
+                per_tile = np.diff(fr.export(_lib.BUF_RANGES).astype(np.int64))
+                st = fr.stats()
+                fr.release()
+                row.update(pairs=int(st["n_candidates"]), per_tile_mean=round(float(per_tile.mean()), 1),
+                           per_tile_std=round(float(per_tile.std()), 1), visible=int(st["n_visible"]))
+        res[method] = row
+        log("association %s:" % method, row)
+    return res
+
+
+def bench_native(args, dev):
+    """Native-space output: the 1280x960 KB 190 frame (RGB, depth, T) resampled
+    onto its native sensor; the kernel is HBM-bound (16 B of sampling map,
+    ~4C B of image read and 4C B written per native pixel, C = 5)."""
+    import torch
+
+    from paper_2505_24053_amd import renderer, synth
+
+    scene_np, cams, _ = synth.workload_kb_train(seed=args.seed)
+    cam = cams[0]
+    sc = renderer.scene_from_numpy(scene_np, device=dev)
+    rgb, depth, trans, _ = renderer.render(sc, cams)
+    beap = torch.cat([rgb.view(3, -1), depth.view(1, -1), trans.view(1, -1)]).contiguous()
+    renderer.reproject(beap, cam)  # builds and caches the sampling map
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        nat, valid = renderer.reproject(beap, cam)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    npix = nat.shape[1] * nat.shape[2]
+    C = beap.shape[0]
+    nbytes = npix * (16 + 8 * C + 1)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": "reproject_kb190_1280x960_rgb_depth_t", "native_pixels": npix,
+            "reached_frac": round(float(valid.float().mean().item()), 4), "channels": C, "ms": round(ms, 4),
+            "roofline": {"kernel": "reproject_kernel", "bound": "hbm", "achieved": round(gbs, 1),
+                         "peak": HBM_BPS / 1e9, "unit": "GB/s", "frac": round(gbs / (HBM_BPS / 1e9), 4),
+                         "traffic": None, "bytes_per_launch": nbytes,
+                         "note": "per launch time from events around back-to-back launches on the stream"}}
+
+
 def bench_serving(args, dev):
     """Continuous batching over the resident 1M-Gaussian scene: the saturated
     throughput, then Poisson arrivals at fractions of it."""
@@ -487,6 +564,8 @@ def main():
                     help="Poisson arrival rates as fractions of the saturated throughput; the first is the "
                          "headline point")
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--variant-steps", type=int, default=10, help="frames per association variant (0: skip)")
+    ap.add_argument("--native", type=int, default=1, help="native-space output section (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -570,6 +649,15 @@ def main():
             cpu["single_thread_value"] = single_thread(scene_np, cam, pix[: args.cpu_rays_single])
             cpu["single_thread_sample"] = "the first %d rays of the sample on one thread" % args.cpu_rays_single
 
+    variants = None
+    if args.variant_steps > 0:
+        log("association variants on the forward frame")
+        variants = bench_assoc_variants(args, dev, sc, scene_np, cams, out[0].clone())
+    native = None
+    if args.native:
+        native = bench_native(args, dev)
+        log("native output:", native)
+
     fwd_bwd = None
     if args.train_steps > 0:
         log("fwd+bwd: 500k Gaussians, KB 190 deg 1280x960")
@@ -604,6 +692,8 @@ def main():
         "roofline": roofline,
         "frame_roofline": frame_roof,
         "cpu_baseline": cpu,
+        "association_variants": variants,
+        "native_output": native,
         "fwd_bwd": fwd_bwd,
         "train_batched": train_batched,
         "serving": serving,

@@ -110,6 +110,31 @@ typedef struct {
  * or of the half-tile (render) are skipped; the outputs are the same bits
  * either way (the flag is for verification and measurement of the cull). */
 #define GEER_OPT_NO_CONE_CULL 1
+/* Association (bits 1-3 of flags): the PBF rectangle (0, default), or, for
+ * comparison with the splatting pipelines (App. on EWA splatting; the
+ * association-method tables), the box of a projected footprint in BEAP
+ * angles: EWA -- angles of the mean and J Sigma_c J^T, J the Jacobian of
+ * (atan2(x, z), atan(y / z)) at the mean (local affine approximation); UT --
+ * the seven unscented sigma points mu_c, mu_c +- sqrt(3) m_k (m_k the columns
+ * of the camera-space factor R_c R S) projected exactly, weights of alpha = 1,
+ * beta = 2, kappa = 0.  Square box: centre +- lambda sqrt(largest eigenvalue);
+ * snug box: the ellipse's axis-aligned extents lambda sqrt(C_00),
+ * lambda sqrt(C_11); lambda is the PBF's.  These boxes are not supersets of
+ * the contributing rays: pairs outside them are lost from the image. */
+#define GEER_OPT_ASSOC_EWA (1 << 1)
+#define GEER_OPT_ASSOC_EWA_SNUG (2 << 1)
+#define GEER_OPT_ASSOC_UT (3 << 1)
+#define GEER_OPT_ASSOC_UT_SNUG (4 << 1)
+#define GEER_OPT_ASSOC_MASK (7 << 1)
+/* Render-time splat opacity (the local-affine ablation): each pair's alpha is
+ * sigma exp(-m / 2), m = d^T C^-1 d with d the ray's BEAP angles minus the
+ * mean's (theta wrapped to (-pi, pi]) and C the EWA footprint covariance
+ * J Sigma_c J^T plus a 0.3-squared-pixel low-pass term per axis; a pair
+ * contributes when that alpha >= alpha_min and the ray's half-tile lies in the
+ * (exact) association rectangle; depth accumulates the means' camera
+ * distances.  Forward only on BEAP grids (no frame backward, no training
+ * plans: GEER_ERR_UNSUPPORTED); the contribution-cone cull is off. */
+#define GEER_OPT_SPLAT_ALPHA (1 << 4)
 typedef struct {
   float alpha_min;    /* default 1/255, in (0, 1) */
   float alpha_max;    /* default 0.99, in [alpha_min, 1) */

@@ -33,7 +33,7 @@ SRC = os.path.join(HERE, "geer_oracle.c")
 LIB = os.path.join(HERE, "libgeer_oracle.so")
 
 MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2}
-DEFAULT_OPTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, lambda_mode=0, lambda_fixed=3.0)
+DEFAULT_OPTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, lambda_mode=0, lambda_fixed=3.0, splat=False)
 
 
 class View(C.Structure):
@@ -45,7 +45,7 @@ class View(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
-                ("lambda_fixed", C.c_double), ("lambda_mode", C.c_int32), ("pad_", C.c_int32)]
+                ("lambda_fixed", C.c_double), ("lambda_mode", C.c_int32), ("splat", C.c_int32)]
 
 
 class SceneC(C.Structure):
@@ -125,6 +125,7 @@ def make_opts(**kw) -> Opts:
     o = Opts()
     o.alpha_min, o.alpha_max, o.t_min = float(d["alpha_min"]), float(d["alpha_max"]), float(d["t_min"])
     o.lambda_fixed, o.lambda_mode = float(d["lambda_fixed"]), int(d["lambda_mode"])
+    o.splat = 1 if d["splat"] else 0
     return o
 
 
@@ -456,6 +457,116 @@ def reproject(cam, beap, native_size=None):
     return np.where(ok[None], out, 0.0), ok
 
 
+def _rotation(q):
+    """Local-to-world rotations [N, 3, 3] of quaternions (r, i, j, k) [4, N]."""
+    q = q / np.linalg.norm(q, axis=0, keepdims=True)
+    r, i, j, k = q
+    return np.stack([np.stack([1 - 2 * (j * j + k * k), 2 * (i * j - r * k), 2 * (i * k + r * j)], -1),
+                     np.stack([2 * (i * j + r * k), 1 - 2 * (i * i + k * k), 2 * (j * k - r * i)], -1),
+                     np.stack([2 * (i * k - r * j), 2 * (j * k + r * i), 1 - 2 * (i * i + j * j)], -1)], 1)
+
+
+def _beap(x, y, z):
+    th = np.arctan2(x, z)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ph = np.where(z != 0, np.arctan(y / np.where(z != 0, z, 1.0)), np.sign(y) * np.pi / 2)
+    return th, ph
+
+
+FOOTPRINTS = ("ewa", "ewa_snug", "ut", "ut_snug")
+
+
+def footprint_bounds(scene, cam, method, **opts):
+    """Projected-footprint association boxes in BEAP angles, FP64 -- the
+    splatting associations the PBF is compared with (the EWA appendix and the
+    association-method tables).  The camera-space Gaussian (mean mu_c, factor
+    M = R_c R S, Sigma_c = M M^T) is projected by
+      'ewa': the local affine approximation, angles of the mean and
+             J Sigma_c J^T with J the Jacobian of (atan2(x, z), atan(y / z));
+      'ut':  the unscented transform, sigma points mu_c and mu_c +- sqrt(3) m_k
+             (columns of M) projected exactly, weights of alpha = 1, beta = 2,
+             kappa = 0 (mean 1/6 per off-centre point; covariance 2 for the
+             centre, 1/6 for the others), theta unwrapped around the centre's;
+    and the box is centre +- lambda sqrt(largest eigenvalue) or, '_snug',
+    centre +- lambda (sqrt(C_00), sqrt(C_11)), with lambda^2 the PBF's
+    (conservative table value).  Returns dict(visible [N], tlo, thi, plo,
+    phi) in radians; visible follows the FP32 cull and opacity decisions of
+    the association reference."""
+    a = assoc_fp32(scene, cam, **opts)
+    o = opts_dict(**opts)
+    n = scene.n
+    Rc = np.asarray(cam["R"], np.float64)
+    t = np.asarray(cam["t"], np.float64)
+    mc = (Rc @ scene.mean.astype(np.float64)) + t[:, None]
+    M = np.einsum("ab,nbc,cn->nac", Rc, _rotation(scene.quat.astype(np.float64)), scene.scale.astype(np.float64))
+    L = np.array([lambda2_hat(float(sg), o["alpha_min"], o["lambda_mode"], o["lambda_fixed"]) for sg in
+                  scene.opacity], np.float64)
+    x, y, z = mc
+    if method.startswith("ewa"):
+        tc, pc = _beap(x, y, z)
+        rxz, ryz = x * x + z * z, y * y + z * z
+        with np.errstate(divide="ignore", invalid="ignore"):
+            J = np.stack([np.stack([z / rxz, np.zeros(n), -x / rxz], -1),
+                          np.stack([np.zeros(n), z / ryz, -y / ryz], -1)], 1)
+        JM = J @ M
+        Cv = JM @ np.transpose(JM, (0, 2, 1))
+    else:
+        t0, p0 = _beap(x, y, z)
+        ts, ps = [], []
+        for k in range(3):
+            for sg in (np.sqrt(3.0), -np.sqrt(3.0)):
+                pt = mc + sg * M[:, :, k].T
+                tk, pk = _beap(*pt)
+                ts.append(t0 + np.remainder(tk - t0 + np.pi, 2 * np.pi) - np.pi)
+                ps.append(pk)
+        ts, ps = np.array(ts), np.array(ps)
+        tc, pc = ts.mean(0), ps.mean(0)
+        dt, dp = np.vstack([t0 - tc, ts - tc]), np.vstack([p0 - pc, ps - pc])
+        w = np.array([2.0] + [1 / 6] * 6)[:, None]
+        Cv = np.stack([np.stack([(w * dt * dt).sum(0), (w * dt * dp).sum(0)], -1),
+                       np.stack([(w * dt * dp).sum(0), (w * dp * dp).sum(0)], -1)], 1)
+    c00, c01, c11 = Cv[:, 0, 0], Cv[:, 0, 1], Cv[:, 1, 1]
+    if method.endswith("snug"):
+        rt, rp = np.sqrt(L * c00), np.sqrt(L * c11)
+    else:
+        lam = 0.5 * (c00 + c11) + np.sqrt(0.25 * (c00 - c11) ** 2 + c01 ** 2)
+        rt = rp = np.sqrt(L * lam)
+    vis = (a["culled"] == 0) & (scene.opacity.astype(np.float32) > np.float32(o["alpha_min"]))
+    vis &= np.isfinite(rt) & np.isfinite(rp) & np.isfinite(tc) & np.isfinite(pc)
+    return dict(visible=vis, tlo=tc - rt, thi=tc + rt, plo=pc - rp, phi=pc + rp)
+
+
+def angle_cells(edges, lo, hi, half, slack=0.0):
+    """Half-tile cells [e[h], e[h+1]] met by the angle interval [lo, hi]
+    (edges: tan(theta / 2) when `half`, else tan(phi)), with the interval
+    grown by `slack` radians; an interval past -pi / pi wraps.  Returns
+    (c0, c1), c0 > c1 when none."""
+    lo, hi = lo - slack, hi + slack
+    n = edges.size - 1
+    pieces = []
+    if half:
+        if hi - lo >= 2 * np.pi:
+            return 0, n - 1
+        a = -np.inf if lo <= -np.pi else np.tan(lo / 2)
+        b = np.inf if hi >= np.pi else np.tan(hi / 2)
+        pieces.append((a, b))
+        if lo < -np.pi:
+            pieces.append((np.tan((lo + 2 * np.pi) / 2), np.inf))
+        elif hi > np.pi:
+            pieces.append((-np.inf, np.tan((hi - 2 * np.pi) / 2)))
+    else:
+        a = -np.inf if lo <= -np.pi / 2 else np.tan(lo)
+        b = np.inf if hi >= np.pi / 2 else np.tan(hi)
+        pieces.append((a, b))
+    e = edges.astype(np.float64)
+    c0, c1 = n, -1
+    for a, b in pieces:
+        hit = np.nonzero((e[1:] >= a) & (e[:-1] <= b))[0]
+        if hit.size:
+            c0, c1 = min(c0, hit[0]), max(c1, hit[-1])
+    return c0, c1
+
+
 def opts_dict(**kw):
     d = dict(DEFAULT_OPTS)
     d.update(kw)
@@ -463,7 +574,7 @@ def opts_dict(**kw):
 
 
 __all__ = ["build", "assoc_fp32", "tile_list", "render", "branch_scores", "render_backward", "sh_basis", "pair", "edges",
-           "lambda2_hat", "contrib_mask", "valid_mask", "kb_incidence", "reproject_positions", "reproject", "pixel_dirs_camera", "pixel_dirs_world", "DEFAULT_OPTS"]
+           "lambda2_hat", "contrib_mask", "valid_mask", "kb_incidence", "reproject_positions", "reproject", "footprint_bounds", "angle_cells", "FOOTPRINTS", "pixel_dirs_camera", "pixel_dirs_world", "DEFAULT_OPTS"]
 
 
 def tile_pairs_contribute(scene, cam, tiles, gids, nthreads: int = 0, **opts):

@@ -65,7 +65,8 @@ typedef struct {
 
 typedef struct {
   double alpha_min, alpha_max, t_min, lambda_fixed;
-  int32_t lambda_mode, pad_; /* 0 opacity-aware, 1 fixed lambda */
+  int32_t lambda_mode; /* 0 opacity-aware, 1 fixed lambda */
+  int32_t splat;       /* 1: splat opacity (local affine footprint) instead of the exact one */
 } orc_opts;
 
 typedef struct {
@@ -489,6 +490,11 @@ typedef struct {
   double qh[4], qn, s[3];
   int active;      /* not culled and sigma > alpha_min */
   uint32_t key;
+  int hx0, hx1, hy0, hy1, vis; /* FP32 association: half-tile rectangle, visible */
+  /* splat opacity: BEAP angles of the mean, conic C^-1 = [ia ib; ib ic] of
+     the local affine footprint, its largest eigenvalue, the condition
+     c00 c11 / det(C), and the mean's camera distance */
+  double tc, pc, ia, ib, ic, icmax, ccond, mdist;
 } gprep;
 
 static void prep_gaussians(const orc_scene* sc, const orc_view* vw, const orc_opts* op, gprep* P,
@@ -538,6 +544,38 @@ static void prep_gaussians(const orc_scene* sc, const orc_view* vw, const orc_op
     }
     p->key = as[g].key;
     p->active = !as[g].culled && ((float)sc->opacity[g] > (float)op->alpha_min);
+    p->hx0 = as[g].hx0; p->hx1 = as[g].hx1; p->hy0 = as[g].hy0; p->hy1 = as[g].hy1;
+    p->vis = as[g].count > 0;
+    if (op->splat) {
+      /* camera-space mean and covariance Sigma_c = (Rc R S)(Rc R S)^T */
+      double mc[3], A[9];
+      for (int a = 0; a < 3; ++a) {
+        mc[a] = Rc[a * 3 + 0] * mu[0] + Rc[a * 3 + 1] * mu[1] + Rc[a * 3 + 2] * mu[2] + vw->t[a];
+        for (int b = 0; b < 3; ++b)
+          A[a * 3 + b] = (Rc[a * 3 + 0] * p->R[0 * 3 + b] + Rc[a * 3 + 1] * p->R[1 * 3 + b] +
+                          Rc[a * 3 + 2] * p->R[2 * 3 + b]) * s[b];
+      }
+      p->tc = atan2(mc[0], mc[2]);
+      p->pc = mc[2] != 0 ? atan(mc[1] / mc[2]) : (mc[1] > 0 ? M_PI / 2 : (mc[1] < 0 ? -M_PI / 2 : 0));
+      /* J: derivatives of (atan2(x, z), atan(y / z)) at the mean */
+      double rxz = mc[0] * mc[0] + mc[2] * mc[2], ryz = mc[1] * mc[1] + mc[2] * mc[2];
+      double jt[3] = {mc[2] / rxz, 0, -mc[0] / rxz}, jp[3] = {0, mc[2] / ryz, -mc[1] / ryz};
+      double vt[3], vp[3];
+      for (int k = 0; k < 3; ++k) {
+        vt[k] = jt[0] * A[0 * 3 + k] + jt[1] * A[1 * 3 + k] + jt[2] * A[2 * 3 + k];
+        vp[k] = jp[0] * A[0 * 3 + k] + jp[1] * A[1 * 3 + k] + jp[2] * A[2 * 3 + k];
+      }
+      double pt = vw->fov_x / vw->width, pp = vw->fov_y / vw->height;
+      double c00 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2] + 0.3 * pt * pt;
+      double c01 = vt[0] * vp[0] + vt[1] * vp[1] + vt[2] * vp[2];
+      double c11 = vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2] + 0.3 * pp * pp;
+      double det = c00 * c11 - c01 * c01;
+      p->ia = c11 / det; p->ib = -c01 / det; p->ic = c00 / det;
+      double mid = 0.5 * (p->ia + p->ic), dd = sqrt(0.25 * (p->ia - p->ic) * (p->ia - p->ic) + p->ib * p->ib);
+      p->icmax = mid + dd;
+      p->ccond = c00 * c11 / det;
+      p->mdist = sqrt(mc[0] * mc[0] + mc[1] * mc[1] + mc[2] * mc[2]);
+    }
   }
 }
 
@@ -623,6 +661,59 @@ static int pair_contributes64(const gprep* p, const orc_opts* op, const double d
   double tstar = -od / uu;
   double araw = p->sigma * exp(-0.5 * kappa);
   return tstar > 0 && kappa <= p->lam2 && !(op->lambda_mode == 1 && !(araw >= op->alpha_min));
+}
+
+static int contrib_cmp(const void* a, const void* b);
+
+/* The splat opacity's pairs of one ray (px, py) of a BEAP grid: Gaussians
+ * whose FP32 association rectangle holds the ray's half-tile, with
+ * alpha_raw = sigma exp(-m / 2), m = d^T C^-1 d the conic distance of the
+ * ray's BEAP angles from the mean's (theta difference wrapped to (-pi, pi]).
+ * A pair contributes iff alpha_raw >= alpha_min, i.e. m <= 2 ln(sigma /
+ * alpha_min); it is flagged when m is within the FP32 band of that
+ * threshold: angle differences good to 2e-6 rad (2 sqrt(m |C^-1|) 2e-6 +
+ * |C^-1| 4e-12), the conic's rounding amplified by its condition
+ * (1e-6 c00 c11 / det (1 + m)), and 1e-4 (1 + m) relative.  The depth is the
+ * mean's camera distance.  In (key, index) order. */
+static int64_t gather_splat(const gprep* P, int64_t n, const orc_opts* op, const orc_view* v, int px, int py,
+                            contrib** buf, int64_t* cap) {
+  const double th = col_angle(v, px + 0.5), ph = row_angle(v, py + 0.5);
+  const int hx = px / HALF, hy = py / HALF;
+  int64_t cnt = 0;
+  for (int64_t g = 0; g < n; ++g) {
+    const gprep* p = &P[g];
+    if (!p->active || !p->vis || hx < p->hx0 || hx > p->hx1 || hy < p->hy0 || hy > p->hy1) continue;
+    double dt = th - p->tc;
+    if (dt > M_PI) dt -= 2 * M_PI;
+    if (dt < -M_PI) dt += 2 * M_PI;
+    const double dp = ph - p->pc;
+    const double m = p->ia * dt * dt + 2 * p->ib * dt * dp + p->ic * dp * dp;
+    const double araw = p->sigma * exp(-0.5 * m);
+    const double thr = 2.0 * log(p->sigma / op->alpha_min);
+    const double band = 2 * sqrt((m > 0 ? m : 0) * p->icmax) * 2e-6 + p->icmax * 4e-12 +
+                        1e-6 * p->ccond * (1 + m) + 1e-4 * (1 + m);
+    const int in64 = araw >= op->alpha_min;
+    const int flag = fabs(m - thr) <= band;
+    if (!in64 && !flag) continue;
+    if (cnt == *cap) {
+      *cap = *cap ? *cap * 2 : 256;
+      *buf = (contrib*)realloc(*buf, sizeof(contrib) * (size_t)*cap);
+    }
+    contrib* c = &(*buf)[cnt++];
+    memset(c, 0, sizeof *c);
+    c->key = p->key;
+    c->g = g;
+    c->araw = araw;
+    c->clamped = araw > op->alpha_max;
+    c->alpha = c->clamped ? op->alpha_max : araw;
+    c->kappa = m;
+    c->tstar = p->mdist;
+    c->band = band;
+    c->in64 = in64;
+    c->flag = flag;
+  }
+  qsort(*buf, (size_t)cnt, sizeof(contrib), contrib_cmp);
+  return cnt;
 }
 
 /* Collects, in (key, index) order, every pair that contributes in FP64 and
@@ -789,7 +880,7 @@ int orc_render(const orc_scene* sc, const orc_view* v, const orc_opts* op, int64
       int px = (int)(pix[t] % v->width), py = (int)(pix[t] / v->width);
       double d[3];
       pixel_dir(v, px, py, d);
-      int64_t cnt = gather(P, n, op, o, d, &buf, &cap);
+      int64_t cnt = op->splat ? gather_splat(P, n, op, v, px, py, &buf, &cap) : gather(P, n, op, o, d, &buf, &cap);
       /* the FP64 path; a branch point on it means other outcomes exist */
       int a_flag = 0;
       double T = 1, C[3] = {0, 0, 0}, D = 0;

@@ -142,14 +142,18 @@ def make_view(cam: dict) -> GeerView:
 
 
 OPT_NO_CONE_CULL = 1
+ASSOC = {"pbf": 0, "ewa": 1, "ewa_snug": 2, "ut": 3, "ut_snug": 4}
+
+
+OPT_SPLAT_ALPHA = 1 << 4
 
 
 def make_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, lambda_mode=0, lambda_fixed=3.0,
-              cone_cull=True) -> GeerOpts:
+              cone_cull=True, assoc="pbf", splat=False) -> GeerOpts:
     o = GeerOpts()
     o.alpha_min, o.alpha_max, o.t_min = float(alpha_min), float(alpha_max), float(t_min)
     o.lambda_fixed, o.lambda_mode = float(lambda_fixed), int(lambda_mode)
-    o.flags = 0 if cone_cull else OPT_NO_CONE_CULL
+    o.flags = (0 if cone_cull else OPT_NO_CONE_CULL) | (ASSOC[assoc] << 1) | (OPT_SPLAT_ALPHA if splat else 0)
     return o
 
 

@@ -232,7 +232,9 @@ geer_status check_opts(geer_ctx* c, const geer_opts& o) {
   if (o.lambda_mode != 0 && o.lambda_mode != 1) return fail(c, GEER_ERR_INVALID_ARG, "lambda_mode must be 0 or 1");
   if (o.lambda_mode == 1 && !(o.lambda_fixed > 0 && o.lambda_fixed < 100))
     return fail(c, GEER_ERR_INVALID_ARG, "lambda_fixed must be in (0, 100)");
-  if ((o.flags & ~GEER_OPT_NO_CONE_CULL) != 0) return fail(c, GEER_ERR_INVALID_ARG, "unknown opts.flags bits");
+  if ((o.flags & ~(GEER_OPT_NO_CONE_CULL | GEER_OPT_ASSOC_MASK | GEER_OPT_SPLAT_ALPHA)) != 0 ||
+      (o.flags & GEER_OPT_ASSOC_MASK) > GEER_OPT_ASSOC_UT_SNUG)
+    return fail(c, GEER_ERR_INVALID_ARG, "unknown opts.flags bits");
   return GEER_OK;
 }
 
@@ -414,6 +416,10 @@ void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t item
 // Stage (c): the render kernel.
 void enqueue_render(hipStream_t st, const Opts& op, int64_t ntiles, int32_t nviews, const FwdBufs& b, float* rgb,
                     float* depth, float* trans) {
+  if (op.splat) {
+    launch_render_splat(st, ntiles, b.views, nviews, b.dtab, b.ranges, b.list, b.rects, b.recs, op, rgb, depth, trans);
+    return;
+  }
   launch_mark_heavy(st, b.ranges, ntiles, b.views, nviews, b.heavy());
   launch_render(st, op.lambda_mode == 1, ntiles, b.views, nviews, b.dtab, b.ranges, b.list, b.rects, b.recs, op,
                 b.heavy(), rgb, depth, trans, b.nlast, b.tfinal, (unsigned long long*)(b.stats + 2));
@@ -478,6 +484,9 @@ Opts make_opts(const LamTab& lt, const geer_opts& o) {
   op.lam_n = lt.n;
   op.log2_amin = (float)std::log2((double)o.alpha_min);
   op.cone_cull = (o.flags & GEER_OPT_NO_CONE_CULL) ? 0 : 1;
+  op.assoc = (o.flags & GEER_OPT_ASSOC_MASK) >> 1;
+  op.splat = (o.flags & GEER_OPT_SPLAT_ALPHA) ? 1 : 0;
+  if (op.splat) op.cone_cull = 0;  // the cull's cone is the exact opacity's
   return op;
 }
 
@@ -560,8 +569,11 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   const int64_t n = scene->n;
   const int64_t items = n * n_views;
   if (items >= kMaxKeys) return fail(c, GEER_ERR_CAPACITY, "Gaussians x views exceeds 2^30");
-  for (int i = 0; i < n_views; ++i)
+  for (int i = 0; i < n_views; ++i) {
     if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
+    if ((opts->flags & GEER_OPT_SPLAT_ALPHA) && views[i].grid != GEER_GRID_BEAP)
+      return fail(c, GEER_ERR_UNSUPPORTED, "the splat opacity is defined on BEAP grids");
+  }
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(c, hipSetDevice(c->device));
   ViewTables tab;
@@ -744,6 +756,7 @@ geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* 
   if (!dl_drgb) return fail(c, GEER_ERR_INVALID_ARG, "null dL/dRGB");
   if (f->n > 0 && (!g_mean || !g_scale || !g_quat || !g_opacity || !g_sh))
     return fail(c, GEER_ERR_INVALID_ARG, "null gradient array");
+  if (f->op.splat) return fail(c, GEER_ERR_UNSUPPORTED, "the splat-opacity render has no backward");
   if (!f->nlast.p || !f->tfinal.p) return fail(c, GEER_ERR_INVALID_ARG, "frame holds no forward state");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(c, hipSetDevice(c->device));
@@ -1220,6 +1233,7 @@ geer_status train_check(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   geer_status s;
   if ((s = check_scene(c, scene)) != GEER_OK) return s;
   if ((s = check_opts(c, *opts)) != GEER_OK) return s;
+  if (opts->flags & GEER_OPT_SPLAT_ALPHA) return fail(c, GEER_ERR_UNSUPPORTED, "no training with the splat opacity");
   for (int i = 0; i < n_views; ++i)
     if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
   if (scene->n < 1) return fail(c, GEER_ERR_INVALID_ARG, "a plan needs a non-empty scene");

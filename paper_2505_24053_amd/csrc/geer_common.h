@@ -21,7 +21,8 @@ struct ViewDev {
   int32_t pix_base;   // first pixel of this view in the concatenated outputs
   int32_t ex_off, ey_off;  // offsets of the edge tables in the edge buffer
   int32_t dx_off, dy_off;  // offsets of the direction tables (2 floats per entry)
-  int32_t pad_[5];
+  float dil_t, dil_p;      // splat low-pass dilation: 0.3 x the squared angular pixel pitch
+  int32_t pad_[3];
 };
 static_assert(sizeof(ViewDev) % 16 == 0, "ViewDev alignment");
 
@@ -46,8 +47,17 @@ struct Opts {
   int32_t lam_n;      // number of buckets
   float log2_amin;    // log2(alpha_min), for the half-tile cone test
   int32_t cone_cull;  // 1: skip entries whose contribution cone misses the half-tile
-  int32_t pad_[1];
+  int32_t assoc;      // association: 0 PBF, else a projected-footprint box (kAssoc*)
+  int32_t splat;      // 1: render-time splat opacity (2D conic in BEAP angles) instead of the exact one
+  int32_t pad_[3];
 };
+
+// Associations compared against the PBF (the splatting baselines): the box of
+// a projected 2D footprint in BEAP angles, from the local affine (EWA) or
+// unscented (UT) projection of the Gaussian, either square (lambda times the
+// largest standard deviation) or snug (the footprint ellipse's axis-aligned
+// extents).
+constexpr int kAssocPBF = 0, kAssocEWA = 1, kAssocEWASnug = 2, kAssocUT = 3, kAssocUTSnug = 4;
 
 // Heavy-tile work list of a frame (device buffers): up to hmax tile ids (a
 // capacity no frame can exceed), a flag per tile, the device count of listed

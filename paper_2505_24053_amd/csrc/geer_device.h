@@ -60,6 +60,143 @@ __device__ __forceinline__ bool pieces_range(const float* __restrict__ e, int n,
   return any;
 }
 
+// Cells of the edge table e (n cells) met by the angle interval [lo, hi] of
+// theta (e holds tan(theta / 2)) or of phi (e holds tan(phi)); an interval
+// wider than a turn, or reaching past -pi / pi, wraps into two pieces.
+__device__ __forceinline__ bool angle_cells(const float* __restrict__ e, int n, float lo, float hi, bool half,
+                                            int& c0, int& c1) {
+  const float PI = 3.14159265358979f;
+  float a[2], b[2];
+  int np = 1;
+  if (half) {
+    if (hi - lo >= 2.0f * PI) {
+      c0 = 0;
+      c1 = n - 1;
+      return true;
+    }
+    a[0] = lo <= -PI ? -INFINITY : tanf(0.5f * lo);
+    b[0] = hi >= PI ? INFINITY : tanf(0.5f * hi);
+    if (lo < -PI) {  // the part beyond -pi comes back from +pi
+      a[1] = tanf(0.5f * (lo + 2.0f * PI));
+      b[1] = INFINITY;
+      np = 2;
+    } else if (hi > PI) {
+      a[1] = -INFINITY;
+      b[1] = tanf(0.5f * (hi - 2.0f * PI));
+      np = 2;
+    }
+  } else {
+    const float H = 0.5f * PI;
+    a[0] = lo <= -H ? -INFINITY : tanf(lo);
+    b[0] = hi >= H ? INFINITY : tanf(hi);
+  }
+  return pieces_range(e, n, np, a, b, c0, c1);
+}
+
+// BEAP angles of a camera-space point: theta = atan2(x, z), phi = atan(y / z).
+__device__ __forceinline__ void beap_angles(float x, float y, float z, float& th, float& ph) {
+  th = atan2f(x, z);
+  ph = z != 0.0f ? atanf(y / z) : (y > 0.0f ? 1.57079632679f : (y < 0.0f ? -1.57079632679f : 0.0f));
+}
+
+// Half-tile rectangle of a projected-footprint association (kAssocEWA ..
+// kAssocUTSnug): centre and 2x2 angular covariance C of the Gaussian
+// (mean mc, camera-space factor M, Sigma_c = M M^T) in BEAP angles --
+//   EWA: the angles of the mean and J Sigma_c J^T, J the Jacobian of the
+//        angles at the mean (the local affine approximation);
+//   UT:  the seven sigma points mc and mc +- sqrt(3) m_k (m_k the columns of
+//        M) projected exactly, with the unscented weights of alpha = 1,
+//        beta = 2, kappa = 0 (mean: 1/6 each off-centre point; covariance:
+//        2 for the centre, 1/6 each other), theta unwrapped around the
+//        centre point's;
+// then the box centre +- sqrt(L) sqrt(lambda_max(C)) (square) or
+// +- sqrt(L C_00), sqrt(L C_11) (snug), with L the same lambda^2 as the PBF.
+__device__ __forceinline__ bool footprint_cells(int mode, const float mc[3], const float M[9], float L,
+                                                const ViewDev& V, const float* __restrict__ edges, int& hx0,
+                                                int& hx1, int& hy0, int& hy1) {
+  const float PI = 3.14159265358979f;
+  float tc, pc, c00, c01, c11;
+  if (mode == kAssocEWA || mode == kAssocEWASnug) {
+    beap_angles(mc[0], mc[1], mc[2], tc, pc);
+    const float rxz = mc[0] * mc[0] + mc[2] * mc[2], ryz = mc[1] * mc[1] + mc[2] * mc[2];
+    // d theta = (z dx - x dz) / (x^2 + z^2), d phi = (z dy - y dz) / (y^2 + z^2)
+    const float jt[3] = {mc[2] / rxz, 0.0f, -mc[0] / rxz};
+    const float jp[3] = {0.0f, mc[2] / ryz, -mc[1] / ryz};
+    float vt[3], vp[3];  // J_t M and J_p M (rows of J M)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      vt[k] = jt[0] * M[0 * 3 + k] + jt[1] * M[1 * 3 + k] + jt[2] * M[2 * 3 + k];
+      vp[k] = jp[0] * M[0 * 3 + k] + jp[1] * M[1 * 3 + k] + jp[2] * M[2 * 3 + k];
+    }
+    c00 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
+    c01 = vt[0] * vp[0] + vt[1] * vp[1] + vt[2] * vp[2];
+    c11 = vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2];
+  } else {
+    float t0, p0;
+    beap_angles(mc[0], mc[1], mc[2], t0, p0);
+    float ts[6], ps[6];
+    const float sq3 = 1.7320508075688772f;
+    float mt = 0.0f, mp = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const int k = i >> 1;
+      const float sg = (i & 1) ? -sq3 : sq3;
+      float t, p;
+      beap_angles(mc[0] + sg * M[0 * 3 + k], mc[1] + sg * M[1 * 3 + k], mc[2] + sg * M[2 * 3 + k], t, p);
+      float dt = t - t0;
+      dt = dt > PI ? dt - 2.0f * PI : (dt < -PI ? dt + 2.0f * PI : dt);
+      ts[i] = t0 + dt;
+      ps[i] = p;
+      mt += ts[i] * (1.0f / 6.0f);
+      mp += p * (1.0f / 6.0f);
+    }
+    tc = mt;
+    pc = mp;
+    c00 = 2.0f * (t0 - mt) * (t0 - mt);
+    c01 = 2.0f * (t0 - mt) * (p0 - mp);
+    c11 = 2.0f * (p0 - mp) * (p0 - mp);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const float a = ts[i] - mt, b = ps[i] - mp;
+      c00 += (1.0f / 6.0f) * a * a;
+      c01 += (1.0f / 6.0f) * a * b;
+      c11 += (1.0f / 6.0f) * b * b;
+    }
+  }
+  float rt, rp;
+  if (mode == kAssocEWASnug || mode == kAssocUTSnug) {
+    rt = sqrtf(L * c00);
+    rp = sqrtf(L * c11);
+  } else {
+    const float mid = 0.5f * (c00 + c11);
+    const float dd = sqrtf(fmaxf(0.25f * (c00 - c11) * (c00 - c11) + c01 * c01, 0.0f));
+    rt = rp = sqrtf(L * (mid + dd));
+  }
+  if (!(rt == rt) || !(rp == rp)) return false;  // degenerate projection (NaN)
+  const bool okx = angle_cells(edges + V.ex_off, V.nhx, tc - rt, tc + rt, true, hx0, hx1);
+  const bool oky = angle_cells(edges + V.ey_off, V.nhy, pc - rp, pc + rp, false, hy0, hy1);
+  return okx && oky;
+}
+
+// EWA covariance of the BEAP angles at the camera-space mean mc for the
+// camera-space axes A = Rc R and scales s (Sigma_c = A S S A^T): J Sigma_c J^T
+// with J the Jacobian of (atan2(x, z), atan(y / z)) at mc.
+__device__ __forceinline__ void splat_cov(const float mc[3], const float A[9], const float s[3], float& c00,
+                                          float& c01, float& c11) {
+  const float rxz = mc[0] * mc[0] + mc[2] * mc[2], ryz = mc[1] * mc[1] + mc[2] * mc[2];
+  const float jt[3] = {mc[2] / rxz, 0.0f, -mc[0] / rxz};
+  const float jp[3] = {0.0f, mc[2] / ryz, -mc[1] / ryz};
+  float vt[3], vp[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    vt[k] = (jt[0] * A[0 * 3 + k] + jt[2] * A[2 * 3 + k]) * s[k];
+    vp[k] = (jp[1] * A[1 * 3 + k] + jp[2] * A[2 * 3 + k]) * s[k];
+  }
+  c00 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
+  c01 = vt[0] * vp[0] + vt[1] * vp[1] + vt[2] * vp[2];
+  c11 = vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2];
+}
+
 struct AssocOut {
   float R[9];   // local-to-world rotation of the unit quaternion
   float qh[4];  // unit quaternion
@@ -164,6 +301,13 @@ __device__ __forceinline__ void associate(const float mu[3], const float s[3], c
   const float* ey = edges + V.ey_off;
 
   int hx0, hx1;
+  if (op.assoc != kAssocPBF) {
+    int hy0, hy1;
+    if (!footprint_cells(op.assoc, mc, M, L, V, edges, hx0, hx1, hy0, hy1)) return;
+    o.hx0 = hx0; o.hx1 = hx1; o.hy0 = hy0; o.hy1 = hy1;
+    o.visible = true;
+    return;
+  }
   {
     float e0 = mc[0] * M[6] - mc[2] * M[0];
     float e1 = mc[0] * M[7] - mc[2] * M[1];

@@ -122,6 +122,29 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
         for (int c = 0; c < 3; ++c) acc[c] = fmaf(B[kk], sh[(int64_t)(kk * 3 + c) * n + g], acc[c]);
 #pragma unroll
       for (int c = 0; c < 3; ++c) rec.rgb[c] = fmaxf(acc[c], 0.0f);
+      if (op.splat) {
+        // splat record: the mean's BEAP angles and the conic of the local
+        // affine footprint C = J Sigma_c J^T + dilation (C^-1 = [a b; b c]),
+        // log2(sigma), the mean's camera distance as the depth
+        float tc, pc;
+        beap_angles(A.mc[0], A.mc[1], A.mc[2], tc, pc);
+        float c00, c01, c11;
+        splat_cov(A.mc, A.A, s, c00, c01, c11);
+        c00 += V.dil_t;
+        c11 += V.dil_p;
+        const float det = c00 * c11 - c01 * c01;
+        const float idet = det > 0.0f ? 1.0f / det : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) rec.g[k] = 0.0f;
+        rec.g[0] = tc;
+        rec.g[1] = pc;
+        rec.g[2] = c11 * idet;
+        rec.g[3] = -c01 * idet;
+        rec.g[4] = c00 * idet;
+        rec.c0 = 0.0f;
+        rec.c1 = sqrtf(A.mc[0] * A.mc[0] + A.mc[1] * A.mc[1] + A.mc[2] * A.mc[2]);
+        rec.qmax = INFINITY;
+      }
       float4* dst = reinterpret_cast<float4*>(recs + item);
       const float4* src = reinterpret_cast<const float4*>(&rec);
       dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];

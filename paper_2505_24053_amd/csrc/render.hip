@@ -385,6 +385,95 @@ __global__ __launch_bounds__(64 * kRenderWaves) void render_kernel(
   add_evals<kRenderWaves>(stats, heavy.evals, evals);
 }
 
+// Render with the splat opacity instead of the exact one (the render-time
+// swap of the paper's local-affine ablation): alpha = sigma exp(-m / 2) with
+// m = d^T C^-1 d the conic distance of the ray's BEAP angles from the mean's,
+// C the local affine footprint.  The association stays the exact PBF one and
+// nothing is culled beyond its half-tile rectangles, so a splat footprint
+// reaching past the rectangle is cut there (the culling mismatch the swap
+// exposes).  Ordinary 8x8 half-tile waves for every tile; depth accumulates
+// the means' camera distances.  No backward state is kept.
+__global__ __launch_bounds__(64 * kRenderWaves) void render_splat_kernel(
+    const ViewDev* __restrict__ views, int nviews, const float2* __restrict__ dtab,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ list, const uint2* __restrict__ rects,
+    const Record* __restrict__ recs, Opts op, float* __restrict__ rgb, float* __restrict__ depth,
+    float* __restrict__ trans) {
+  __shared__ float4 s_all[kRenderWaves][kWin][4];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float4(*s_rec)[4] = s_all[wv];
+  const int wi = wave_index(blockIdx.x, gridDim.x, kRenderWaves, wv, 0);
+  const WaveBlock W = ordinary_block(wi, 0, views, nviews, nullptr);
+  if (!W.live) return;
+  const ViewDev& V = views[W.v];
+  const uint32_t start = ranges[W.tile], end = ranges[W.tile + 1];
+  const uint32_t hx = (uint32_t)W.bx0 >> 3, hy = (uint32_t)W.by0 >> 3;
+  const int lane = threadIdx.x & 63;
+  const int px = W.bx0 + (lane & 7), py = W.by0 + (lane >> 3);
+  const bool valid = px < V.width && py < V.height;
+  const float2 cth = dtab[V.dx_off + min(px, V.width - 1)];
+  const float2 cph = dtab[V.dy_off + min(py, V.height - 1)];
+  const float th = atan2f(cth.x, cth.y), ph = atan2f(cph.x, cph.y);
+  const float PI = 3.14159265358979f;
+  float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, D = 0.0f;
+  uint64_t done = __builtin_amdgcn_ballot_w64(!valid);
+  for (uint32_t base = start; base < end && ~done != 0; base += kWin) {
+    const uint32_t e = base + lane;
+    bool hit = false;
+    if (e < end) {
+      const uint32_t item = list[e];
+      const uint2 rc = rects[item];
+      hit = (rc.x & 0xffffu) <= hx && hx <= (rc.x >> 16) && (rc.y & 0xffffu) <= hy && hy <= (rc.y >> 16);
+      if (hit) {
+        const float4* r = reinterpret_cast<const float4*>(recs + item);
+        s_rec[lane][0] = r[0]; s_rec[lane][1] = r[1]; s_rec[lane][2] = r[2]; s_rec[lane][3] = r[3];
+      }
+    }
+    uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    while (m != 0 && ~done != 0) {
+      const int k = __builtin_ctzll(m);
+      m &= m - 1;
+      Record R;
+      float4* rr = reinterpret_cast<float4*>(&R);
+      rr[0] = s_rec[k][0]; rr[1] = s_rec[k][1]; rr[2] = s_rec[k][2]; rr[3] = s_rec[k][3];
+      float dt = th - R.g[0];
+      dt = dt > PI ? dt - 2.0f * PI : (dt < -PI ? dt + 2.0f * PI : dt);
+      const float dp = ph - R.g[1];
+      const float q = fmaf(R.g[2] * dt, dt, fmaf(2.0f * R.g[3] * dt, dp, R.g[4] * dp * dp));
+      const float a_raw = __builtin_amdgcn_exp2f(fmaf(-0.72134752044448170f, q, R.lsig));
+      const uint64_t ok = ~done & __builtin_amdgcn_ballot_w64(a_raw >= op.alpha_min);
+      const float a = fminf(a_raw, op.alpha_max);
+      const float Tn = fmaf(-a, T, T);
+      const uint64_t term = ok & __builtin_amdgcn_ballot_w64(Tn < op.t_min);
+      const bool blend = __builtin_amdgcn_inverse_ballot_w64(ok & ~term);
+      done |= term;
+      const float Tnew = blend ? Tn : T;
+      const float w = T - Tnew;
+      T = Tnew;
+      cr = fmaf(w, R.rgb[0], cr);
+      cg = fmaf(w, R.rgb[1], cg);
+      cb = fmaf(w, R.rgb[2], cb);
+      D = fmaf(w, R.c1, D);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (valid) {
+    const int64_t hw = (int64_t)V.width * V.height;
+    const int64_t p = (int64_t)py * V.width + px;
+    float* out = rgb + 3 * (int64_t)V.pix_base;
+    out[p] = cr;
+    out[hw + p] = cg;
+    out[2 * hw + p] = cb;
+    const int64_t gp = (int64_t)V.pix_base + p;
+    if (depth) depth[gp] = D;
+    if (trans) trans[gp] = T;
+  }
+}
+
 // Flags tiles whose list is longer than 3x the mean over their own view's
 // tiles (+64) as heavy and lists them (in any order).  A view has fewer than
 // a third of its tiles above that bound, so hmax = ntiles / 3 + 1 slots never
@@ -430,6 +519,15 @@ void launch_mark_heavy(hipStream_t st, const uint32_t* ranges, int64_t ntiles, c
   if (ntiles <= 0) return;
   hipLaunchKernelGGL(mark_heavy_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st, ranges, ntiles,
                      views, nviews, h.list, h.flag, h.count, h.hmax, h.evals);
+}
+
+void launch_render_splat(hipStream_t st, int64_t ntiles, const ViewDev* views, int nviews, const float2* dtab,
+                         const uint32_t* ranges, const uint32_t* list, const uint2* rects, const Record* recs,
+                         const Opts& op, float* rgb, float* depth, float* trans) {
+  if (ntiles <= 0) return;
+  const unsigned grid = (unsigned)(4 * ntiles / kRenderWaves);
+  hipLaunchKernelGGL(render_splat_kernel, dim3(grid), dim3(64 * kRenderWaves), 0, st, views, nviews, dtab, ranges,
+                     list, rects, recs, op, rgb, depth, trans);
 }
 
 void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const ViewDev* views, int nviews,

@@ -108,6 +108,10 @@ void view_constants(const geer_view& v, ViewDev& d) {
   d.tiles_y = (v.height + kTile - 1) / kTile;
   d.nhx = (v.width + kHalf - 1) / kHalf;
   d.nhy = (v.height + kHalf - 1) / kHalf;
+  // the splat opacity's low-pass filter: 0.3 squared pixels, in BEAP angles
+  const double pt = v.fov_x / v.width, pp = v.fov_y / v.height;
+  d.dil_t = (float)(0.3 * pt * pt);
+  d.dil_p = (float)(0.3 * pp * pp);
 }
 
 // Valid-ray mask through the native camera model (App. E); the incidence

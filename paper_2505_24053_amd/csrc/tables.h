@@ -77,6 +77,10 @@ void launch_render(hipStream_t st, bool fixed_lambda, int64_t ntiles, const View
                    const Record* recs, const Opts& op, const HeavyTiles& heavy, float* rgb, float* depth,
                    float* trans, uint32_t* nlast, float* tfinal, unsigned long long* stats);
 
+void launch_render_splat(hipStream_t st, int64_t ntiles, const ViewDev* views, int nviews, const float2* dtab,
+                         const uint32_t* ranges, const uint32_t* list, const uint2* rects, const Record* recs,
+                         const Opts& op, float* rgb, float* depth, float* trans);
+
 // backward.hip
 void launch_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, int64_t n, int32_t n_views,
                      int32_t sh_degree, const float* mean, const float* scale, const float* quat,
