@@ -363,6 +363,31 @@ def bench_train_batched(args, dev, threads):
                            "visible": pst["n_visible"], "evaluated_pairs": pst["n_evaluated"]},
            "device_workspace_gib": round(plan.device_bytes() / 2**30, 2),
            "roofline": roof, "roofline_render": roof_r, "frame_roofline": frame_roofline(terms, ms)}
+    # the optimiser step on the step's gradients: one fused Adam kernel over
+    # the raw parameters, moments and statistics (HBM-bound: per Gaussian it
+    # reads raw, m, v and the gradient rows, writes raw, m, v, the activated
+    # scale and opacity, and updates the two statistics)
+    from paper_2505_24053_amd import train
+
+    st = train.TrainState.from_scene(scene_np, device=dev)
+    for t in range(1, 3):
+        st.adam_step(plan.grads, t)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for t in range(3, 3 + args.batched_steps):
+        st.adam_step(plan.grads, t)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_adam = e0.elapsed_time(e1) / args.batched_steps
+    nr = train.rows(scene_np.sh_degree)
+    adam_bytes = scene_np.n * 4 * (4 * nr + 3 * nr + 4 + 4)
+    out["adam"] = {"ms": round(ms_adam, 4), "ms_step_with_adam": round(ms + ms_adam, 3),
+                   "roofline": {"kernel": "adam_kernel", "bound": "hbm",
+                                "achieved": round(adam_bytes / (ms_adam * 1e-3) / 1e9, 1), "peak": HBM_BPS / 1e9,
+                                "unit": "GB/s", "frac": round(adam_bytes / (ms_adam * 1e-3) / HBM_BPS, 4),
+                                "traffic": None, "bytes_per_launch": adam_bytes}}
+    del st
     if args.cpu_rays > 0 and args.cpu_rays_c5 > 0:
         import oracle
 

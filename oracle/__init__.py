@@ -567,6 +567,103 @@ def angle_cells(edges, lo, hi, half, slack=0.0):
     return c0, c1
 
 
+def train_rows(sh_degree):
+    return 11 + 3 * (sh_degree + 1) ** 2
+
+
+def activate(raw):
+    """Activated scale exp(log s) [3, n] and opacity sigmoid(logit) [n] of raw
+    training rows (mean 3, log scale 3, quaternion 4, opacity logit 1, SH)."""
+    raw = np.asarray(raw, np.float64)
+    return np.exp(raw[3:6]), 1.0 / (1.0 + np.exp(-raw[10]))
+
+
+def raw_gradients(raw, grads):
+    """Gradients with respect to the raw rows from those with respect to the
+    rendered parameters (mean, linear scale, quaternion, opacity, SH): the
+    chain through s = exp(log s) and sigma = sigmoid(logit)."""
+    scale, op = activate(raw)
+    return np.concatenate([grads["mean"], grads["scale"] * scale, grads["quat"],
+                           (grads["opacity"] * op * (1 - op))[None], grads["sh"]]).astype(np.float64)
+
+
+def adam_step(raw, m, v, grads, step, lr, betas=(0.9, 0.999), eps=1e-15, accum=None, count=None):
+    """One Adam step (Alg. "3DGEER Initialization and Training Framework") on
+    raw rows, FP64: g = raw_gradients; m = b1 m + (1 - b1) g, v = b2 v +
+    (1 - b2) g^2; raw -= lr_group m_hat / (sqrt(v_hat) + eps) with m_hat =
+    m / (1 - b1^t), v_hat = v / (1 - b2^t); lr per group (mean, log scale,
+    quaternion, opacity logit, SH).  The densification statistics add the
+    mean gradient's norm and 1 where it is non-zero."""
+    raw = np.asarray(raw, np.float64)
+    g = raw_gradients(raw, grads)
+    b1, b2 = betas
+    m = b1 * np.asarray(m, np.float64) + (1 - b1) * g
+    v = b2 * np.asarray(v, np.float64) + (1 - b2) * g * g
+    rate = np.concatenate([np.full(3, lr[0]), np.full(3, lr[1]), np.full(4, lr[2]), [lr[3]],
+                           np.full(raw.shape[0] - 11, lr[4])])[:, None]
+    new = raw - rate * (m / (1 - b1**step)) / (np.sqrt(v / (1 - b2**step)) + eps)
+    out = dict(raw=new, m=m, v=v)
+    out["scale"], out["opacity"] = activate(new)
+    if accum is not None:
+        gn = np.sqrt((g[0:3] ** 2).sum(0))
+        out["accum"] = np.asarray(accum, np.float64) + gn
+        out["count"] = np.asarray(count, np.float64) + (gn > 0)
+    return out
+
+
+def densify_kinds(raw, accum, count, grad_threshold, split_scale, min_opacity):
+    """3DGS-style refinement decisions per Gaussian, in FP32 as the raw rows
+    are held: 0 prune (opacity logit below logit(min_opacity)), 1 keep,
+    2 clone, 3 split -- the last two when accum / count >= grad_threshold,
+    split when the largest log scale exceeds log(split_scale)."""
+    raw = np.asarray(raw, np.float32)
+    prune = raw[10] < np.float32(math.log(min_opacity / (1 - min_opacity)))
+    c = np.asarray(count, np.float32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        avg = np.where(c > 0, np.asarray(accum, np.float32) / np.where(c > 0, c, np.float32(1)), np.float32(0))
+    hot = (c > 0) & (avg >= np.float32(grad_threshold))
+    big = raw[3:6].max(axis=0) > np.float32(math.log(split_scale))
+    return np.where(prune, 0, np.where(hot, np.where(big, 3, 2), 1))
+
+
+def densify(raw, m, v, accum, count, noise, grad_threshold, split_scale, min_opacity, split_shrink=1.6):
+    """The refined training state, FP64, in input order: a kept Gaussian
+    copied with its moments; a clone copied twice, the copy with zero
+    moments; a split Gaussian replaced by two at mean + R S xi_c (xi_c =
+    noise[3c:3c+3], R from the normalised quaternion) with log scale reduced
+    by log(split_shrink) and zero moments; statistics reset."""
+    raw = np.asarray(raw, np.float64)
+    kinds = densify_kinds(raw, accum, count, grad_threshold, split_scale, min_opacity)
+    cols, mm, vv = [], [], []
+    Rall = _rotation(raw[6:10])
+    s = np.exp(raw[3:6])
+    for gi, k in enumerate(kinds):
+        if k == 0:
+            continue
+        if k == 1 or k == 2:
+            cols.append(raw[:, gi])
+            mm.append(m[:, gi])
+            vv.append(v[:, gi])
+        if k == 2:
+            cols.append(raw[:, gi])
+            mm.append(np.zeros(raw.shape[0]))
+            vv.append(np.zeros(raw.shape[0]))
+        if k == 3:
+            for c in range(2):
+                x = raw[:, gi].copy()
+                x[0:3] += Rall[gi] @ (s[:, gi] * np.asarray(noise, np.float64)[3 * c: 3 * c + 3, gi])
+                x[3:6] -= math.log(split_shrink)
+                cols.append(x)
+                mm.append(np.zeros(raw.shape[0]))
+                vv.append(np.zeros(raw.shape[0]))
+    n = len(cols)
+    R = raw.shape[0]
+    out = dict(kinds=kinds, raw=np.array(cols).T.reshape(R, n), m=np.array(mm).T.reshape(R, n),
+               v=np.array(vv).T.reshape(R, n), accum=np.zeros(n), count=np.zeros(n))
+    out["scale"], out["opacity"] = activate(out["raw"])
+    return out
+
+
 def opts_dict(**kw):
     d = dict(DEFAULT_OPTS)
     d.update(kw)
@@ -574,7 +671,8 @@ def opts_dict(**kw):
 
 
 __all__ = ["build", "assoc_fp32", "tile_list", "render", "branch_scores", "render_backward", "sh_basis", "pair", "edges",
-           "lambda2_hat", "contrib_mask", "valid_mask", "kb_incidence", "reproject_positions", "reproject", "footprint_bounds", "angle_cells", "FOOTPRINTS", "pixel_dirs_camera", "pixel_dirs_world", "DEFAULT_OPTS"]
+           "lambda2_hat", "contrib_mask", "valid_mask", "kb_incidence", "reproject_positions", "reproject", "footprint_bounds", "angle_cells", "FOOTPRINTS",
+           "train_rows", "activate", "raw_gradients", "adam_step", "densify_kinds", "densify", "pixel_dirs_camera", "pixel_dirs_world", "DEFAULT_OPTS"]
 
 
 def tile_pairs_contribute(scene, cam, tiles, gids, nthreads: int = 0, **opts):

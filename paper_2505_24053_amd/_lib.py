@@ -28,7 +28,7 @@ EXPORTS = ["geer_create", "geer_destroy", "geer_last_error", "geer_default_opts"
            "geer_plan_workspace_bytes", "geer_plan_create", "geer_train_plan_workspace_bytes",
            "geer_train_plan_create", "geer_plan_launch", "geer_plan_entries", "geer_plan_device_bytes", "geer_plan_destroy",
            "geer_check", "geer_debug_mark_stalled", "geer_plan_get_stats",
-           "geer_reproject"]
+           "geer_reproject", "geer_activate", "geer_adam_step", "geer_densify"]
 
 
 class GeerView(C.Structure):
@@ -59,6 +59,23 @@ class GeerProfileRecord(C.Structure):
     _fields_ = [("ms_preprocess", C.c_float), ("ms_sort", C.c_float), ("ms_render", C.c_float),
                 ("ms_total", C.c_float), ("n_entries", C.c_int64), ("n_evaluated", C.c_int64),
                 ("kind", C.c_int32), ("reserved", C.c_int32)]
+
+
+class GeerTrainState(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32), ("raw", C.c_void_p),
+                ("scale", C.c_void_p), ("opacity", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("accum", C.c_void_p), ("count", C.c_void_p)]
+
+
+class GeerAdamOpts(C.Structure):
+    _fields_ = [("lr_mean", C.c_float), ("lr_scale", C.c_float), ("lr_quat", C.c_float), ("lr_opacity", C.c_float),
+                ("lr_sh", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32), ("reserved", C.c_int32)]
+
+
+class GeerDensifyOpts(C.Structure):
+    _fields_ = [("grad_threshold", C.c_float), ("split_scale", C.c_float), ("min_opacity", C.c_float),
+                ("split_shrink", C.c_float)]
 
 
 class GeerError(RuntimeError):
@@ -113,6 +130,9 @@ def load():
         L.geer_plan_entries.argtypes = [V, P(C.c_int64), P(C.c_int64)]
         L.geer_plan_get_stats.argtypes = [V, P(GeerFrameStats)]
         L.geer_reproject.argtypes = [V, P(GeerView), C.c_int32, C.c_int32, C.c_int32, V, V, V, V]
+        L.geer_activate.argtypes = [V, P(GeerTrainState), V]
+        L.geer_adam_step.argtypes = [V, P(GeerTrainState), P(GeerAdamOpts), V, V, V, V, V, V]
+        L.geer_densify.argtypes = [V, P(GeerTrainState), P(GeerDensifyOpts), V, P(GeerTrainState), V]
         L.geer_plan_device_bytes.argtypes = [V]
         L.geer_plan_device_bytes.restype = C.c_int64
         L.geer_plan_destroy.argtypes = [V]

@@ -1579,6 +1579,107 @@ geer_status geer_reproject(geer_ctx* c, const geer_view* view, int32_t native_wi
   return GEER_OK;
 }
 
+geer_status check_train_state(geer_ctx* c, const geer_train_state* t, bool stats) {
+  if (!t) return fail(c, GEER_ERR_INVALID_ARG, "null training state");
+  if (t->n < 0 || t->n > ((int64_t)1 << 28) || t->sh_degree < 0 || t->sh_degree > 3 || t->reserved != 0)
+    return fail(c, GEER_ERR_INVALID_ARG, "training state: n %lld, sh_degree %d", (long long)t->n, t->sh_degree);
+  if (t->n > 0 && (!t->raw || !t->scale || !t->opacity || !t->m || !t->v || (stats && (!t->accum || !t->count))))
+    return fail(c, GEER_ERR_INVALID_ARG, "training state: null array");
+  return GEER_OK;
+}
+
+geer_status geer_activate(geer_ctx* c, const geer_train_state* t, void* stream) {
+  if (!c) return GEER_ERR_INVALID_ARG;
+  if (!t) return fail(c, GEER_ERR_INVALID_ARG, "null training state");
+  if (t->n < 0 || (t->n > 0 && (!t->raw || !t->scale || !t->opacity)))
+    return fail(c, GEER_ERR_INVALID_ARG, "training state: null array");
+  HIP_TRY(c, hipSetDevice(c->device));
+  launch_activate((hipStream_t)stream, t->n, t->raw, t->scale, t->opacity);
+  HIP_TRY(c, hipGetLastError());
+  return GEER_OK;
+}
+
+geer_status geer_adam_step(geer_ctx* c, const geer_train_state* t, const geer_adam_opts* o, const float* g_mean,
+                           const float* g_scale, const float* g_quat, const float* g_opacity, const float* g_sh,
+                           void* stream) {
+  if (!c) return GEER_ERR_INVALID_ARG;
+  geer_status s = check_train_state(c, t, false);
+  if (s != GEER_OK) return s;
+  if (!o || o->step < 1 || o->reserved != 0 || !(o->beta1 >= 0 && o->beta1 < 1) || !(o->beta2 >= 0 && o->beta2 < 1) ||
+      !(o->eps >= 0))
+    return fail(c, GEER_ERR_INVALID_ARG, "bad Adam options");
+  if (t->n > 0 && (!g_mean || !g_scale || !g_quat || !g_opacity || !g_sh))
+    return fail(c, GEER_ERR_INVALID_ARG, "null gradient array");
+  if ((t->accum == nullptr) != (t->count == nullptr))
+    return fail(c, GEER_ERR_INVALID_ARG, "accum and count go together");
+  HIP_TRY(c, hipSetDevice(c->device));
+  AdamParams ap;
+  ap.lr[0] = o->lr_mean;
+  ap.lr[1] = o->lr_scale;
+  ap.lr[2] = o->lr_quat;
+  ap.lr[3] = o->lr_opacity;
+  ap.lr[4] = o->lr_sh;
+  ap.b1 = o->beta1;
+  ap.b2 = o->beta2;
+  ap.eps = o->eps;
+  ap.c1 = (float)(1.0 / (1.0 - std::pow((double)o->beta1, (double)o->step)));
+  ap.c2 = (float)(1.0 / (1.0 - std::pow((double)o->beta2, (double)o->step)));
+  launch_adam((hipStream_t)stream, t->n, t->sh_degree, t->raw, g_mean, g_scale, g_quat, g_opacity, g_sh, t->m, t->v,
+              t->scale, t->opacity, t->accum, t->count, ap);
+  HIP_TRY(c, hipGetLastError());
+  return GEER_OK;
+}
+
+geer_status geer_densify(geer_ctx* c, const geer_train_state* in, const geer_densify_opts* o, const float* noise,
+                         geer_train_state* out, void* stream) {
+  if (!c) return GEER_ERR_INVALID_ARG;
+  geer_status s = check_train_state(c, in, true);
+  if (s != GEER_OK) return s;
+  if (!out || !o || (in->n > 0 && !noise)) return fail(c, GEER_ERR_INVALID_ARG, "null argument");
+  if ((s = check_train_state(c, out, true)) != GEER_OK) return s;
+  if (out->sh_degree != in->sh_degree) return fail(c, GEER_ERR_INVALID_ARG, "SH degrees differ");
+  if (!(o->min_opacity > 0 && o->min_opacity < 1) || !(o->split_scale > 0) || !(o->split_shrink >= 1) ||
+      !(o->grad_threshold >= 0))
+    return fail(c, GEER_ERR_INVALID_ARG, "bad densification options");
+  const int64_t n = in->n;
+  const int64_t cap = out->n;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(c, hipSetDevice(c->device));
+  Block kind, offs, scratch;
+  auto done = [&](geer_status r) {
+    release(c, kind);
+    release(c, offs);
+    release(c, scratch);
+    return r;
+  };
+  const int64_t n1 = std::max<int64_t>(n, 1);
+  if ((s = acquire(c, 4 * (size_t)n1, st, kind)) != GEER_OK) return done(s);
+  if ((s = acquire(c, 4 * (size_t)(n1 + 1), st, offs)) != GEER_OK) return done(s);
+  if ((s = acquire(c, 4 * (size_t)scan_scratch_words(n1 + 1), st, scratch)) != GEER_OK) return done(s);
+  DensifyParams dp;
+  const double mo = o->min_opacity;
+  dp.prune_logit = (float)std::log(mo / (1.0 - mo));
+  dp.grad_threshold = o->grad_threshold;
+  dp.split_log_scale = (float)std::log((double)o->split_scale);
+  uint32_t* cnt = (uint32_t*)offs.p;  // counts, scanned in place into offsets; entry n is the total
+  launch_fill_u32(st, cnt + n, 1, 0u);
+  launch_densify_count(st, n, in->raw, in->accum, in->count, dp, cnt, (uint32_t*)kind.p);
+  scan_exclusive(st, cnt, cnt, n + 1, (uint32_t*)scratch.p);
+  uint32_t total = 0;
+  hipError_t e = hipMemcpyAsync(&total, cnt + n, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return done(fail(c, GEER_ERR_HIP, "densify count: %s", hipGetErrorString(e)));
+  if ((int64_t)total > cap)
+    return done(fail(c, GEER_ERR_CAPACITY, "densification gives %u Gaussians, capacity %lld", total, (long long)cap));
+  launch_densify_apply(st, n, in->sh_degree, in->raw, in->m, in->v, (const uint32_t*)kind.p, cnt, noise, total,
+                       out->raw, out->m, out->v, out->scale, out->opacity, out->accum, out->count,
+                       (float)std::log((double)o->split_shrink));
+  e = hipGetLastError();
+  if (e != hipSuccess) return done(fail(c, GEER_ERR_HIP, "densify launch: %s", hipGetErrorString(e)));
+  out->n = total;
+  return done(GEER_OK);
+}
+
 geer_status geer_check(geer_ctx* c, void* stream) {
   if (!c) return GEER_ERR_INVALID_ARG;
   HIP_TRY(c, hipSetDevice(c->device));

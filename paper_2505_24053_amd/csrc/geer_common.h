@@ -59,6 +59,21 @@ struct Opts {
 // extents).
 constexpr int kAssocPBF = 0, kAssocEWA = 1, kAssocEWASnug = 2, kAssocUT = 3, kAssocUTSnug = 4;
 
+// One Adam step: learning rates of the mean, log-scale, quaternion, opacity
+// logit and SH groups; moment decays, epsilon and the bias corrections
+// 1 / (1 - b1^t), 1 / (1 - b2^t) of step t.
+struct AdamParams {
+  float lr[5];
+  float b1, b2, eps, c1, c2;
+};
+
+// Refinement thresholds: mean-gradient norm averaged over the steps that saw
+// a Gaussian; the largest log scale above which a Gaussian is split rather
+// than cloned; the opacity logit below which it is pruned.
+struct DensifyParams {
+  float grad_threshold, split_log_scale, prune_logit;
+};
+
 // Heavy-tile work list of a frame (device buffers): up to hmax tile ids (a
 // capacity no frame can exceed), a flag per tile, the device count of listed
 // tiles, and the number of heavy wave slots that walk the list.

@@ -107,6 +107,18 @@ void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int3
                                 const uint32_t* counts, const float* acc, int accumulate, float* g_mean, float* g_scale, float* g_quat,
                                 float* g_opacity, float* g_sh);
 
+// train.hip (raw parameter rows: mean 3, log scale 3, quaternion 4, opacity logit 1, SH 3K)
+void launch_activate(hipStream_t st, int64_t n, const float* raw, float* scale_out, float* opac_out);
+void launch_adam(hipStream_t st, int64_t n, int sh_degree, float* raw, const float* g_mean, const float* g_scale,
+                 const float* g_quat, const float* g_opac, const float* g_sh, float* m, float* v, float* scale_out,
+                 float* opac_out, float* accum, float* count, const AdamParams& ap);
+void launch_densify_count(hipStream_t st, int64_t n, const float* raw, const float* accum, const float* count,
+                          const DensifyParams& dp, uint32_t* nout, uint32_t* kind);
+void launch_densify_apply(hipStream_t st, int64_t n, int sh_degree, const float* raw, const float* m, const float* v,
+                          const uint32_t* kind, const uint32_t* offs, const float* noise, int64_t n_out, float* raw_o,
+                          float* m_o, float* v_o, float* scale_o, float* opac_o, float* accum_o, float* count_o,
+                          float split_shrink);
+
 // loss.hip
 int64_t l1_partial_count(int64_t P);
 void launch_l1(hipStream_t st, int64_t P, const float* rgb, const float* target, const uint8_t* mask, float* dl,
