@@ -275,6 +275,84 @@ geer_status geer_l1_loss(geer_ctx* ctx, int64_t pixels, const float* rgb, const 
                          const uint8_t* mask, float* dl_drgb, float* loss, void* stream);
 
 /*
+ * Training step (Alg. "3DGEER Initialization and Training Framework": Adam
+ * on the loss gradient, and the periodic refinement of the Gaussian set,
+ * driven by view-space mean gradients).  The optimiser holds the raw
+ * parameters in one device block of (11 + 3K) rows of n floats -- mean 3, log
+ * scale 3, quaternion 4 (any non-zero norm), opacity logit 1, SH 3K (K = (deg
+ * + 1)^2, row k*3 + channel) -- and writes the activated scale = exp(log s)
+ * [3][n] and opacity = sigmoid(logit) [n] the renderer reads, so a scene of
+ * (raw, scale, raw + 6n, opacity, raw + 11n) renders what the optimiser holds.
+ * m, v: Adam moments, same shape as raw; accum, count: per-Gaussian
+ * densification statistics [n] (sum of mean-gradient norms, steps that saw
+ * the Gaussian).  All pointers are device memory owned by the caller.
+ */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree;
+  int32_t reserved; /* must be 0 */
+  float* raw;
+  float* scale;
+  float* opacity;
+  float* m;
+  float* v;
+  float* accum;
+  float* count;
+} geer_train_state;
+
+typedef struct {
+  float lr_mean, lr_scale, lr_quat, lr_opacity, lr_sh; /* per parameter group */
+  float beta1, beta2, eps;                             /* e.g. 0.9, 0.999, 1e-15 */
+  int32_t step;                                        /* 1, 2, ...: bias correction of step t */
+  int32_t reserved;                                    /* must be 0 */
+} geer_adam_opts;
+
+typedef struct {
+  float grad_threshold; /* mean-gradient norm averaged over the steps that saw a Gaussian */
+  float split_scale;    /* largest linear scale above which a Gaussian is split, not cloned */
+  float min_opacity;    /* opacity below which a Gaussian is pruned */
+  float split_shrink;   /* scale divisor of split children, e.g. 1.6 */
+} geer_densify_opts;
+
+/* Writes state->scale and state->opacity from the raw rows (initialisation). */
+geer_status geer_activate(geer_ctx* ctx, const geer_train_state* state, void* stream);
+
+/*
+ * One fused Adam step.  g_*: the gradients geer_render_backward (or a
+ * training plan) gives for the scene (raw, scale, raw + 6n, opacity, raw +
+ * 11n), i.e. with respect to the linear scale and the opacity; they are
+ * chained through the activations (d/dlog s = s d/ds, d/dlogit = sigma (1 -
+ * sigma) d/dsigma), then m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * raw -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), and the
+ * activated scale and opacity are rewritten.  The norm of each Gaussian's
+ * mean gradient, when non-zero, is added to accum and 1 to count.  One
+ * kernel; accum / count may be NULL (no statistics).
+ */
+geer_status geer_adam_step(geer_ctx* ctx, const geer_train_state* state, const geer_adam_opts* opts,
+                           const float* g_mean, const float* g_scale, const float* g_quat, const float* g_opacity,
+                           const float* g_sh, void* stream);
+
+/*
+ * Refinement of the Gaussian set (3DGS-style clone / split / prune).  Per
+ * Gaussian of `in`: pruned if its opacity is below min_opacity; else, if
+ * accum / count >= grad_threshold, cloned (kept plus a copy with zero
+ * moments) when its largest scale is at most split_scale, split otherwise
+ * into two Gaussians at mean + R S xi_c (xi_c the caller's standard normal
+ * draws: noise is device [6][n], rows c*3 + axis for child c) with log scale
+ * reduced by log(split_shrink), other parameters copied and zero moments.
+ * The decisions compare raw rows with thresholds mapped to raw space
+ * (logit(min_opacity), log(split_scale)), in FP32.  Outputs keep the input
+ * order (a Gaussian's outputs at its place), statistics reset to zero.
+ * `out` holds caller buffers for up to out->n Gaussians (its n on entry is
+ * that capacity; 2 * in->n always suffices); on return out->n is the new
+ * count n', and every array holds its rows back to back with n' floats each
+ * (the layout of a state of n' Gaussians), or GEER_ERR_CAPACITY with nothing
+ * written if n' exceeds the capacity.  Synchronises once for the count.
+ */
+geer_status geer_densify(geer_ctx* ctx, const geer_train_state* in, const geer_densify_opts* opts, const float* noise,
+                         geer_train_state* out, void* stream);
+
+/*
  * Stage timing.  While enabled, every geer_render records HIP events on its
  * stream around its stages (the preprocess / PBF kernel; the sort, expansion
  * and ranges; the render kernel) and copies its device counters, and every
