@@ -301,8 +301,10 @@ typedef struct {
 } geer_train_state;
 
 typedef struct {
+  double beta1, beta2, eps;                            /* e.g. 0.9, 0.999, 1e-15; 1 - beta and the bias
+                                                          corrections are formed in double, then rounded
+                                                          once to FP32 */
   float lr_mean, lr_scale, lr_quat, lr_opacity, lr_sh; /* per parameter group */
-  float beta1, beta2, eps;                             /* e.g. 0.9, 0.999, 1e-15 */
   int32_t step;                                        /* 1, 2, ...: bias correction of step t */
   int32_t reserved;                                    /* must be 0 */
 } geer_adam_opts;

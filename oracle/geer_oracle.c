@@ -633,13 +633,22 @@ static double kappa_band(const gprep* p, const double u[3], const double m[3], d
     gmu2 += b * b;
   }
   double mu_mag = p->dist + sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
-  /* second order: kappa = |P o_u|^2 (P projects off d_u) is quadratic in
-   o_u, so a move delta of o_u adds at most |delta|^2 beyond the linear
-   term; a turn by angle e of d_u adds at most |o_u|^2 e^2.  They matter only
-   for needles and disks, whose W amplifies input rounding by 1/s_min. */
+  /* second order: kappa = |P o_u|^2 with P = I - u u^T / |u|^2 the projection
+   off d_u, so a move delta of o_u adds |P delta|^2 beyond the linear term,
+   and a turn of d_u by the angle e = |P delta_u| / |d_u| adds at most
+   |o_u|^2 e^2.  Both moves are W times a move of the mean or of the
+   direction, so |P W| (Frobenius) bounds the amplification.  They matter
+   only for needles, whose W amplifies input rounding by 1/s_min across every
+   direction; for a disk P removes the amplified normal axis (nearly d_u). */
   double wf = 0, r2 = ou[0] * ou[0] + ou[1] * ou[1] + ou[2] * ou[2];
-  for (int q = 0; q < 9; ++q) wf += W[q] * W[q];
-  wf = sqrt(wf);
+  for (int q = 0; q < 3; ++q) {
+    const double ud = (u[0] * W[0 * 3 + q] + u[1] * W[1 * 3 + q] + u[2] * W[2 * 3 + q]) / uu;
+    for (int a = 0; a < 3; ++a) {
+      const double pw = W[a * 3 + q] - u[a] * ud;
+      wf += pw * pw;
+    }
+  }
+  wf = sqrt(wf) * 1.01;
   const double dou = 0x1p-21 * mu_mag * wf, dang = 0x1p-21 * wf / sqrt(uu);
   return 0x1p-21 * sqrt(gd2) + 0x1p-21 * mu_mag * sqrt(gmu2) + dou * dou + r2 * dang * dang +
          1e-6 * (p->lam2 > 1 ? p->lam2 : 1);

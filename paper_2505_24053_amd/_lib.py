@@ -68,8 +68,8 @@ class GeerTrainState(C.Structure):
 
 
 class GeerAdamOpts(C.Structure):
-    _fields_ = [("lr_mean", C.c_float), ("lr_scale", C.c_float), ("lr_quat", C.c_float), ("lr_opacity", C.c_float),
-                ("lr_sh", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+    _fields_ = [("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double), ("lr_mean", C.c_float),
+                ("lr_scale", C.c_float), ("lr_quat", C.c_float), ("lr_opacity", C.c_float), ("lr_sh", C.c_float),
                 ("step", C.c_int32), ("reserved", C.c_int32)]
 
 

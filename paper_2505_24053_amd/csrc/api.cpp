@@ -1619,11 +1619,13 @@ geer_status geer_adam_step(geer_ctx* c, const geer_train_state* t, const geer_ad
   ap.lr[2] = o->lr_quat;
   ap.lr[3] = o->lr_opacity;
   ap.lr[4] = o->lr_sh;
-  ap.b1 = o->beta1;
-  ap.b2 = o->beta2;
-  ap.eps = o->eps;
-  ap.c1 = (float)(1.0 / (1.0 - std::pow((double)o->beta1, (double)o->step)));
-  ap.c2 = (float)(1.0 / (1.0 - std::pow((double)o->beta2, (double)o->step)));
+  ap.b1 = (float)o->beta1;
+  ap.b2 = (float)o->beta2;
+  ap.eps = (float)o->eps;
+  ap.omb1 = (float)(1.0 - o->beta1);
+  ap.omb2 = (float)(1.0 - o->beta2);
+  ap.c1 = (float)(1.0 / (1.0 - std::pow(o->beta1, (double)o->step)));
+  ap.c2 = (float)(1.0 / (1.0 - std::pow(o->beta2, (double)o->step)));
   launch_adam((hipStream_t)stream, t->n, t->sh_degree, t->raw, g_mean, g_scale, g_quat, g_opacity, g_sh, t->m, t->v,
               t->scale, t->opacity, t->accum, t->count, ap);
   HIP_TRY(c, hipGetLastError());

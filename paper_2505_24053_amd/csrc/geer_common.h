@@ -65,6 +65,7 @@ constexpr int kAssocPBF = 0, kAssocEWA = 1, kAssocEWASnug = 2, kAssocUT = 3, kAs
 struct AdamParams {
   float lr[5];
   float b1, b2, eps, c1, c2;
+  float omb1, omb2;  // 1 - b1 and 1 - b2 formed in double, rounded once (1 - 0.999f is 1.3e-5 off 1e-3)
 };
 
 // Refinement thresholds: mean-gradient norm averaged over the steps that saw

@@ -78,8 +78,8 @@ __global__ __launch_bounds__(256) void adam_kernel(int64_t n, float* __restrict_
       gr = g_sh[(int64_t)(r - 11) * n + g];
       lr = ap.lr[4];
     }
-    const float m = fmaf(ap.b1, mom1[i], (1.0f - ap.b1) * gr);
-    const float v = fmaf(ap.b2, mom2[i], (1.0f - ap.b2) * gr * gr);
+    const float m = fmaf(ap.b1, mom1[i], ap.omb1 * gr);
+    const float v = fmaf(ap.b2, mom2[i], ap.omb2 * gr * gr);
     mom1[i] = m;
     mom2[i] = v;
     p -= lr * (m * ap.c1) / (sqrtf(v * ap.c2) + ap.eps);

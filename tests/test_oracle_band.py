@@ -145,13 +145,27 @@ def kappa_frame32(mu, s, q, Rc, tc, d_cam):
     return float(r2) * float(f32(mm / ss))
 
 
+def flat_scene(n, tiny_axes, seed):
+    """Disks (one scale 10^-6 of the largest) or needles (two), in front of
+    the camera at 0.5-4 m, random orientations."""
+    rng = np.random.default_rng(seed)
+    mu = np.stack([rng.uniform(-2, 2, n), rng.uniform(-2, 2, n), rng.uniform(0.5, 4, n)])
+    s = np.exp(rng.uniform(np.log(0.01), np.log(0.6), (3, n)))
+    for g in range(n):
+        s[rng.permutation(3)[:tiny_axes], g] = 1e-6 * s[:, g].max()
+    return synth.Scene(mu.astype(np.float32), s.astype(np.float32), rng.standard_normal((4, n)).astype(np.float32),
+                       rng.uniform(0.02, 0.99, n).astype(np.float32), rng.normal(0, 0.3, (3, n)).astype(np.float32), 0)
+
+
 def scenes():
     small = synth.scene_small(400, seed=5)
     box = synth.scene_box(400, seed=6)
     adv = adversarial_scene(7, n=200)
     return [("pinhole60_small", small, synth.camera_pinhole(64, 64, 60.0)),
             ("fisheye180_box", box, synth.camera_equidistant(256, 256, 180.0)),
-            ("kb190_adversarial", adv, synth.camera_kb(128, 96, 190.0, seed=0))]
+            ("kb190_adversarial", adv, synth.camera_kb(128, 96, 190.0, seed=0)),
+            ("fisheye180_disks", flat_scene(200, 1, seed=8), synth.camera_equidistant(128, 128, 180.0)),
+            ("pinhole90_needles", flat_scene(200, 2, seed=9), synth.camera_pinhole(96, 96, 90.0))]
 
 
 @pytest.mark.parametrize("name,scene,cam", scenes(), ids=[s[0] for s in scenes()])
