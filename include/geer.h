@@ -206,6 +206,35 @@ geer_status geer_render_backward(geer_ctx* ctx, const geer_frame* frame, const f
                                  float* g_sh, int32_t accumulate, void* stream);
 
 /*
+ * Allocation-free forward, for callers that cannot allocate device memory
+ * (serving loops and harnesses that forbid hipMalloc / hipFree).  Same
+ * arguments, outputs and bits as geer_render without a frame, but every
+ * buffer of the forward lives in one fixed device array of
+ * GEER_STATIC_SCRATCH_BYTES inside the library (one per device, held from
+ * geer_create until the process ends); the call allocates no device or
+ * pinned memory.  The caller owns and passes the scene and the outputs.
+ *
+ * Sizes: the per-item buffers (about 100 B per Gaussian x view) and the view
+ * tables must fit the array with room for at least one list entry, else the
+ * call returns GEER_ERR_CAPACITY before any launch; the rest of the array
+ * bounds the association list (16 B per PBF pair: a 100k-Gaussian scene in
+ * a 1024 x 1024 fisheye view, 2.8M pairs, fits).  A list beyond that is
+ * caught on the device: the outputs are background (rgb 0, depth 0, trans 1)
+ * and the call returns GEER_ERR_CAPACITY.
+ *
+ * The call waits for its stream before returning (it reads the entry count
+ * and the sort-stall flag back: GEER_ERR_CAPACITY, GEER_ERR_STALLED).  All
+ * calls on one device share the array and leave their contents in it; every
+ * call clears what must start at zero.  Calls that overlapped on one device
+ * would race on the array, so the library serialises its calls per device
+ * (a lock held until the call's work has finished).
+ */
+#define GEER_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+geer_status geer_render_static(geer_ctx* ctx, const geer_scene* scene, int32_t n_views,
+                               const geer_view* views, const geer_opts* opts, float* rgb, float* depth,
+                               float* trans, void* stream);
+
+/*
  * Sort stalls.  Each radix pass of the association waits on earlier blocks
  * with a bounded spin; if it gives up, the outputs of that forward are
  * invalid.  An eager forward (geer_render) records this in a sticky flag of

@@ -28,7 +28,7 @@ EXPORTS = ["geer_create", "geer_destroy", "geer_last_error", "geer_default_opts"
            "geer_plan_workspace_bytes", "geer_plan_create", "geer_train_plan_workspace_bytes",
            "geer_train_plan_create", "geer_plan_launch", "geer_plan_entries", "geer_plan_device_bytes", "geer_plan_destroy",
            "geer_check", "geer_debug_mark_stalled", "geer_plan_get_stats",
-           "geer_reproject", "geer_activate", "geer_adam_step", "geer_densify"]
+           "geer_reproject", "geer_activate", "geer_adam_step", "geer_densify", "geer_render_static"]
 
 
 class GeerView(C.Structure):
@@ -106,6 +106,7 @@ def load():
         L.geer_default_opts.argtypes = [P(GeerOpts)]
         L.geer_default_opts.restype = None
         L.geer_render.argtypes = [V, P(GeerScene), C.c_int32, P(GeerView), P(GeerOpts), V, V, V, P(V), V]
+        L.geer_render_static.argtypes = [V, P(GeerScene), C.c_int32, P(GeerView), P(GeerOpts), V, V, V, V]
         L.geer_render_backward.argtypes = [V, V, V, V, V, V, V, V, C.c_int32, V]
         L.geer_frame_release.argtypes = [V]
         L.geer_frame_release.restype = None

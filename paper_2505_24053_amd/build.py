@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libgeer.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.cpp", "tables.cpp", "preprocess.hip", "sort.hip", "render.hip", "backward.hip", "loss.hip",
-           "reproject.hip", "train.hip"]
+           "reproject.hip", "train.hip", "static_scratch.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
           "-Wall", "-Wno-unused-command-line-argument"]

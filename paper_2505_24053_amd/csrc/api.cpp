@@ -68,6 +68,9 @@ struct geer_ctx {
   // gave up; reported (and cleared) by the next forward, geer_check or the
   // statistics of a frame.
   unsigned long long* dev_err = nullptr;
+  // Look-up of the allocation-free forward's fixed device array on this
+  // device (geer_create).
+  hipError_t static_init = hipErrorNotInitialized;
 };
 
 // Largest key count of one sort (status words hold 30-bit counts).
@@ -500,6 +503,23 @@ geer_status check_scene(geer_ctx* c, const geer_scene* scene) {
   return GEER_OK;
 }
 
+// Argument checks of a forward (geer_render, geer_render_static).
+geer_status check_render_args(geer_ctx* c, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                              const geer_opts* opts, const float* rgb) {
+  if (!scene || !views || !opts || !rgb) return fail(c, GEER_ERR_INVALID_ARG, "null argument");
+  if (n_views < 1 || n_views > 4096) return fail(c, GEER_ERR_INVALID_ARG, "n_views %d out of range", n_views);
+  geer_status s;
+  if ((s = check_scene(c, scene)) != GEER_OK) return s;
+  if ((s = check_opts(c, *opts)) != GEER_OK) return s;
+  if (scene->n * n_views >= kMaxKeys) return fail(c, GEER_ERR_CAPACITY, "Gaussians x views exceeds 2^30");
+  for (int i = 0; i < n_views; ++i) {
+    if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
+    if ((opts->flags & GEER_OPT_SPLAT_ALPHA) && views[i].grid != GEER_GRID_BEAP)
+      return fail(c, GEER_ERR_UNSUPPORTED, "the splat opacity is defined on BEAP grids");
+  }
+  return GEER_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -526,6 +546,8 @@ geer_status geer_create(int32_t device, geer_ctx** out) {
   geer_ctx* c = new (std::nothrow) geer_ctx();
   if (!c) return GEER_ERR_OOM;
   c->device = device;
+  c->static_init = static_scratch_init(device);
+  if (c->static_init != hipSuccess) (void)hipGetLastError();
   if (hipMalloc(&c->dev_err, 256) != hipSuccess || hipMemset(c->dev_err, 0, 256) != hipSuccess) {
     (void)hipGetLastError();
     if (c->dev_err) (void)hipFree(c->dev_err);
@@ -561,19 +583,10 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
                         void* stream) {
   if (!c) return GEER_ERR_INVALID_ARG;
   if (frame_out) *frame_out = nullptr;
-  if (!scene || !views || !opts || !rgb) return fail(c, GEER_ERR_INVALID_ARG, "null argument");
-  if (n_views < 1 || n_views > 4096) return fail(c, GEER_ERR_INVALID_ARG, "n_views %d out of range", n_views);
   geer_status s;
-  if ((s = check_scene(c, scene)) != GEER_OK) return s;
-  if ((s = check_opts(c, *opts)) != GEER_OK) return s;
+  if ((s = check_render_args(c, scene, n_views, views, opts, rgb)) != GEER_OK) return s;
   const int64_t n = scene->n;
   const int64_t items = n * n_views;
-  if (items >= kMaxKeys) return fail(c, GEER_ERR_CAPACITY, "Gaussians x views exceeds 2^30");
-  for (int i = 0; i < n_views; ++i) {
-    if ((s = check_view(c, views[i], i)) != GEER_OK) return s;
-    if ((opts->flags & GEER_OPT_SPLAT_ALPHA) && views[i].grid != GEER_GRID_BEAP)
-      return fail(c, GEER_ERR_UNSUPPORTED, "the splat opacity is defined on BEAP grids");
-  }
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(c, hipSetDevice(c->device));
   ViewTables tab;
@@ -1015,6 +1028,37 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
   return L;
 }
 
+// Device pointers of a capacity-sized forward carved from the block at w.
+FwdBufs carve_plan(char* w, const PlanLayout& lay, const ViewTables& tab, int64_t ntiles) {
+  FwdBufs b;
+  b.views = (const ViewDev*)(w + lay.meta);
+  b.edges = (const float*)(w + lay.meta + tab.edges_off);
+  b.dtab = (const float2*)(w + lay.meta + tab.dtab_off);
+  b.recs = (Record*)(w + lay.recs);
+  b.rects = (uint2*)(w + lay.rects);
+  b.keys = (uint32_t*)(w + lay.keys);
+  b.counts = (uint32_t*)(w + lay.counts);
+  b.stats = (uint64_t*)(w + lay.stats);
+  b.ka = (uint32_t*)(w + lay.ka);
+  b.va = (uint32_t*)(w + lay.va);
+  b.kb = (uint32_t*)(w + lay.kb);
+  b.vb = (uint32_t*)(w + lay.vb);
+  b.hist = (uint32_t*)(w + lay.hist);
+  b.scratch = (uint32_t*)(w + lay.scratch);
+  b.cnt_sorted = (uint32_t*)(w + lay.cnt_sorted);
+  b.tiles_a = (uint32_t*)(w + lay.tiles_a);
+  b.tiles_b = (uint32_t*)(w + lay.tiles_b);
+  b.items_b = (uint32_t*)(w + lay.items_b);
+  b.list = (uint32_t*)(w + lay.list);
+  b.ranges = (uint32_t*)(w + lay.ranges);
+  b.heavy_list = (uint32_t*)(w + lay.heavy_list);
+  b.heavy_flag = (uint32_t*)(w + lay.heavy_flag);
+  b.tcones = (float4*)(w + lay.tcones);
+  b.hparts = (uint32_t*)(w + lay.hparts);
+  b.hmax = heavy_capacity(ntiles);
+  return b;
+}
+
 // Shared argument checks of geer_plan_workspace_bytes and geer_plan_create.
 geer_status plan_check(geer_ctx* c, const geer_scene* scene, int32_t n_views, const geer_view* views,
                        const geer_opts* opts, int64_t entry_capacity, ViewTables& tab) {
@@ -1093,34 +1137,9 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
     P->bytes = (int64_t)lay.total;
   }
   char* w = (char*)P->ws;
-  FwdBufs b;
+  FwdBufs b = carve_plan(w, lay, tab, P->ntiles);
   P->meta = w + lay.meta;
-  b.views = (const ViewDev*)P->meta;
-  b.edges = (const float*)((char*)P->meta + tab.edges_off);
-  b.dtab = (const float2*)((char*)P->meta + tab.dtab_off);
-  b.recs = (Record*)(w + lay.recs);
-  b.rects = (uint2*)(w + lay.rects);
-  b.keys = (uint32_t*)(w + lay.keys);
-  b.counts = (uint32_t*)(w + lay.counts);
-  b.stats = (uint64_t*)(w + lay.stats);
   P->stats = b.stats;
-  b.ka = (uint32_t*)(w + lay.ka);
-  b.va = (uint32_t*)(w + lay.va);
-  b.kb = (uint32_t*)(w + lay.kb);
-  b.vb = (uint32_t*)(w + lay.vb);
-  b.hist = (uint32_t*)(w + lay.hist);
-  b.scratch = (uint32_t*)(w + lay.scratch);
-  b.cnt_sorted = (uint32_t*)(w + lay.cnt_sorted);
-  b.tiles_a = (uint32_t*)(w + lay.tiles_a);
-  b.tiles_b = (uint32_t*)(w + lay.tiles_b);
-  b.items_b = (uint32_t*)(w + lay.items_b);
-  b.list = (uint32_t*)(w + lay.list);
-  b.ranges = (uint32_t*)(w + lay.ranges);
-  b.heavy_list = (uint32_t*)(w + lay.heavy_list);
-  b.heavy_flag = (uint32_t*)(w + lay.heavy_flag);
-  b.tcones = (float4*)(w + lay.tcones);
-  b.hparts = (uint32_t*)(w + lay.hparts);
-  b.hmax = heavy_capacity(P->ntiles);
   for (int k = 0; k < 2; ++k) {
     PHIP(hipHostMalloc(&P->staging[k], std::max<size_t>(tab.bytes, 64), hipHostMallocDefault));
     PHIP(hipEventCreateWithFlags(&P->staged[k], hipEventDisableTiming));
@@ -1147,6 +1166,78 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
   *out = P;
   return GEER_OK;
 #undef PHIP
+}
+
+// ------------------------------------------------ allocation-free forward
+
+geer_status geer_render_static(geer_ctx* c, const geer_scene* scene, int32_t n_views, const geer_view* views,
+                               const geer_opts* opts, float* rgb, float* depth, float* trans, void* stream) {
+  if (!c) return GEER_ERR_INVALID_ARG;
+  geer_status s;
+  if ((s = check_render_args(c, scene, n_views, views, opts, rgb)) != GEER_OK) return s;
+  HIP_TRY(c, hipSetDevice(c->device));
+  char* base = (char*)static_scratch_addr(c->device);
+  if (c->static_init != hipSuccess || !base)
+    return fail(c, GEER_ERR_HIP, "fixed scratch array of device %d unavailable: %s", c->device,
+                hipGetErrorString(c->static_init));
+  ViewTables tab;
+  if ((s = build_tables(c, n_views, views, tab)) != GEER_OK) return s;
+  // the lambda^2 table travels with the view tables (no device table is created)
+  LamTab lt;
+  std::vector<float> lam;
+  lt.amin = opts->alpha_min;
+  lambda_table(opts->alpha_min, lam, lt.lo, lt.n);
+  const Opts op = make_opts(lt, *opts);
+  const size_t lam_off = round_up(tab.bytes, 256);
+  const size_t meta_bytes = lam_off + sizeof(float) * lam.size();
+  const int64_t n = scene->n, items = n * n_views, ntiles = tab.ntiles, npix = tab.npix;
+  const size_t limit = GEER_STATIC_SCRATCH_BYTES;
+  // the largest association list that fits beside the per-item buffers
+  if (plan_layout(meta_bytes, items, 1, ntiles).total > limit)
+    return fail(c, GEER_ERR_CAPACITY,
+                "%lld Gaussians x views over %lld tiles need %zu bytes before any list entry; the fixed scratch "
+                "array holds %zu",
+                (long long)items, (long long)ntiles, plan_layout(meta_bytes, items, 1, ntiles).total, limit);
+  int64_t lo = 1, hi = kMaxKeys - 1;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (plan_layout(meta_bytes, items, mid, ntiles).total <= limit) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t ecap = lo;
+  const PlanLayout lay = plan_layout(meta_bytes, items, ecap, ntiles);
+  std::vector<char> host(meta_bytes);
+  pack_tables(tab, host.data());
+  std::memcpy(host.data() + lam_off, lam.data(), sizeof(float) * lam.size());
+
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(static_scratch_lock(c->device));
+  if (n == 0) {  // nothing to associate: background
+    launch_fill_u32(st, (uint32_t*)rgb, 3 * npix, 0u);
+    if (depth) launch_fill_u32(st, (uint32_t*)depth, npix, 0u);
+    if (trans) launch_fill_u32(st, (uint32_t*)trans, npix, 0x3f800000u);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(st));
+    return GEER_OK;
+  }
+  FwdBufs b = carve_plan(base, lay, tab, ntiles);
+  b.depth_work_zeroed = true;
+  HIP_TRY(c, hipMemcpyAsync(base + lay.meta, host.data(), meta_bytes, hipMemcpyHostToDevice, st));
+  enqueue_preprocess(st, *scene, n_views, op, (const float*)(base + lay.meta + lam_off), b);
+  enqueue_association(st, op, n, items, items, ecap, ntiles, true, b);
+  enqueue_render(st, op, ntiles, n_views, b, rgb, depth, trans);
+  HIP_TRY(c, hipGetLastError());
+  uint64_t h[8];
+  HIP_TRY(c, hipMemcpyAsync(h, b.stats, sizeof h, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  if (h[4] != 0)
+    return fail(c, GEER_ERR_STALLED, "association sort stalled (look-back spin limit); the outputs are invalid");
+  if ((int64_t)h[3] > ecap)
+    return fail(c, GEER_ERR_CAPACITY,
+                "association list of %lld entries exceeds the %lld that fit in the fixed scratch array; the outputs "
+                "are background",
+                (long long)h[3], (long long)ecap);
+  return GEER_OK;
 }
 
 // ---------------------------------------------------------- training plans

@@ -3,12 +3,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <vector>
 
 #include "geer.h"
 #include "geer_common.h"
 
 namespace geer {
+
+// static_scratch.hip: the fixed device array of geer_render_static
+hipError_t static_scratch_init(int device);  // with `device` current; looks its address up once
+void* static_scratch_addr(int device);        // null until static_scratch_init succeeded
+std::mutex& static_scratch_lock(int device);  // held by a call for as long as it uses the array
 
 // tables.cpp
 void lambda_table(float alpha_min, std::vector<float>& tab, int& lo, int& n);

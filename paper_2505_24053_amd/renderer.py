@@ -140,6 +140,34 @@ def render(scene: dict, cams, opts: dict | None = None, keep_frame: bool = False
     return rgb, depth, trans, frame
 
 
+def render_static(scene: dict, cams, opts: dict | None = None, out=None, want_depth=True, want_trans=True):
+    """The same forward as render(), through the library's allocation-free
+    entry point: every intermediate buffer lives in its fixed device array
+    (the outputs are the caller's).  Waits for the stream; raises GeerError
+    (GEER_ERR_CAPACITY) when the scene or its association list does not fit
+    the array.  Returns (rgb, depth | None, trans | None)."""
+    n, deg = _check_scene(scene)
+    dev = scene["mean"].device
+    ctx = context(dev.index or 0)
+    npix = sum(view_pixels(cams))
+    if out is None:
+        rgb = torch.empty(3 * npix, device=dev, dtype=torch.float32)
+        depth = torch.empty(npix, device=dev, dtype=torch.float32) if want_depth else None
+        trans = torch.empty(npix, device=dev, dtype=torch.float32) if want_trans else None
+    else:
+        rgb, depth, trans = out
+    views = (_lib.GeerView * len(cams))(*[_lib.make_view(c) for c in cams])
+    sc = _lib.GeerScene()
+    sc.n, sc.sh_degree, sc.reserved = n, deg, 0
+    sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh = (scene[k].data_ptr() for k in
+                                                    ("mean", "scale", "quat", "opacity", "sh"))
+    op = _lib.make_opts(**(opts or {}))
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    _lib.check(_lib.load().geer_render_static(ctx, C.byref(sc), len(cams), views, C.byref(op), _ptr(rgb),
+                                              _ptr(depth), _ptr(trans), C.c_void_p(stream)), ctx)
+    return rgb, depth, trans
+
+
 def views_of(flat: torch.Tensor, cams, channels: int):
     """Split a flat concatenated output into per-view [C,H,W] tensors."""
     outs, off = [], 0
