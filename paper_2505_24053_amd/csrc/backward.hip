@@ -42,6 +42,12 @@ template <int kCtrl>
 __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xF, 0xF, true));
 }
+// A quad or row permute that leaves the lanes' own values where the source
+// lane is outside the rule's reach (bound_ctrl off: the old value stays).
+template <int kCtrl>
+__device__ __forceinline__ float qdppb(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), kCtrl, 0xF, 0xF, false));
+}
 constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
 constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
 constexpr int kDppRowMirror = 0x140;   // lane i <-> 15 - i within each row of 16
@@ -86,6 +92,212 @@ __device__ __forceinline__ void wave_reduce16_add(const float v[16], float* __re
   a1 += dpp<kDppXor2>(a1);
   const int idx = (h32 ? 8 : 0) + (h16 ? 4 : 0) + (h8 ? 2 : 0) + (h4 ? 1 : 0);
   if ((lane & 3) == 0 && a1 != 0.0f) unsafeAtomicAdd(dst + idx, a1);
+}
+
+// Row rotations (DPP row_ror) for the heavy blocks' reduction: within a row
+// of 16 lanes, lane i reads lane (i - n) mod 16.
+constexpr int kDppRor4 = 0x124, kDppRor8 = 0x128, kDppRor12 = 0x12C;
+// Quad permutes for the heavy blocks' scans: lane j of a quad reads lane
+// j - 1 (j - 2), and lane 3.
+constexpr int kQuadPrev1 = 0x90;  // quad_perm [0, 0, 1, 2]
+constexpr int kQuadPrev2 = 0x44;  // quad_perm [0, 1, 0, 1]
+constexpr int kQuadLast = 0xFF;   // quad_perm [3, 3, 3, 3]
+
+// Sum v[0..15] over the 16 lanes that share lane & 3 (the rays of one hit in
+// a heavy block), by value splitting on lane bits 5, 4, 3 and 2: the row
+// swaps for bits 5 and 4, row_ror 8 for bit 3 (the xor within a row), and
+// for bit 2 row_ror 12 (lane i + 4) or row_ror 4 (lane i - 4).  Lane i ends
+// with value (i >> 2) & 15, summed.
+__device__ __forceinline__ float quad_reduce16(const float v[16]) {
+  const int lane = threadIdx.x & 63;
+  const bool h8 = lane & 8, h4 = lane & 4;
+  float a8[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a8[j] = swap32_add(v[j], v[8 + j]);
+  float a4[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) a4[j] = swap16_add(a8[j], a8[4 + j]);
+  float a2[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float send = h8 ? a4[j] : a4[2 + j];
+    const float keep = h8 ? a4[2 + j] : a4[j];
+    a2[j] = keep + dpp<kDppRor8>(send);
+  }
+  const float send = h4 ? a2[0] : a2[1];
+  const float from_up = dpp<kDppRor12>(send), from_down = dpp<kDppRor4>(send);
+  return (h4 ? a2[1] : a2[0]) + (h4 ? from_down : from_up);
+}
+
+// Back-to-front replay of a heavy tile's 4x4 block with all 64 lanes: lane
+// 4 r + j holds ray r and, in each step, the j-th of the next four hits of
+// the window, back to front.  The sequential replay is kept: the
+// transmittance in front of hit j is T divided by the quad's inclusive
+// prefix product of (1 - alpha) over the replayed hits, and the colour behind
+// it is the quad's exclusive prefix composition of the maps
+// cb -> alpha c + (1 - alpha) cb applied to the colour behind the step.  The
+// 16 partials of each hit are summed over its 16 rays (quad_reduce16) and
+// added by one lane each.
+template <bool kFixed>
+__device__ __forceinline__ void backward_heavy_block(const WaveBlock& W, const ViewDev* __restrict__ views,
+                                                     const float2* __restrict__ dtab,
+                                                     const uint32_t* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ list,
+                                                     const uint2* __restrict__ rects, const Record* __restrict__ recs,
+                                                     const Opts& op, const uint32_t* __restrict__ nlast,
+                                                     const float* __restrict__ tfinal,
+                                                     const float* __restrict__ dl_drgb, float* __restrict__ acc,
+                                                     float4 (*s_rec)[4], uint32_t* s_item, uint64_t& evals) {
+  const ViewDev& V = views[W.v];
+  const int tile = W.tile;
+  const uint32_t hx = (uint32_t)W.bx0 >> 3, hy = (uint32_t)W.by0 >> 3;
+  const int lane = threadIdx.x & 63;
+  const int j = lane & 3, r = lane >> 2;
+  const int px = W.bx0 + (r & 3), py = W.by0 + (r >> 2);
+  const bool valid = px < V.width && py < V.height;
+  float dx, dy, dz;
+  pixel_direction(V, dtab, px, py, dx, dy, dz);
+  const QuadCone Q = block_cone(V, dtab, W.bx0, W.by0, 4);
+
+  const uint32_t start = ranges[tile];
+  const int64_t hw = (int64_t)V.width * V.height;
+  const int64_t p = (int64_t)py * V.width + px;
+  const int64_t gp = (int64_t)V.pix_base + p;
+  float T = 1.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
+  uint32_t last = start;
+  if (valid) {
+    T = tfinal[gp];
+    last = nlast[gp];
+    const float* g = dl_drgb + 3 * (int64_t)V.pix_base;
+    G0 = g[p];
+    G1 = g[hw + p];
+    G2 = g[2 * hw + p];
+  }
+  float cb0 = 0.0f, cb1 = 0.0f, cb2 = 0.0f;  // colour of everything behind the step
+
+  uint32_t top = last;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, off));
+
+  float4 p0, p1, p2, p3;
+  uint32_t pitem = 0;
+  bool phit = false;
+  auto fetch = [&](uint32_t b, uint32_t e_end) {
+    const uint32_t e = b + lane;
+    phit = false;
+    if (e < e_end) {
+      pitem = list[e];
+      const uint2 rc = rects[pitem];
+      phit = (rc.x & 0xffffu) <= hx && hx <= (rc.x >> 16) && (rc.y & 0xffffu) <= hy && hy <= (rc.y >> 16);
+      if (phit) {
+        const float4* rp = reinterpret_cast<const float4*>(recs + pitem);
+        p0 = rp[0]; p1 = rp[1]; p2 = rp[2]; p3 = rp[3];
+      }
+    }
+  };
+  uint32_t bend = top;
+  uint32_t bbase = bend > start + kWinB ? bend - kWinB : start;
+  if (start < top) fetch(bbase, bend);
+
+  while (bend > start) {
+    if (phit && op.cone_cull) phit = cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, kFixed);
+    uint64_t m = __builtin_amdgcn_ballot_w64(phit);
+    if (phit) {
+      s_rec[lane][0] = p0; s_rec[lane][1] = p1; s_rec[lane][2] = p2; s_rec[lane][3] = p3;
+      s_item[lane] = pitem;
+    }
+    const uint32_t base = bbase;
+    bend = bbase;
+    bbase = bend > start + kWinB ? bend - kWinB : start;
+    if (bend > start) fetch(bbase, bend);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    while (m != 0) {
+      // the next (up to) four hits, back to front
+      int kh[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        kh[q] = m != 0 ? 63 - __builtin_clzll(m) : -1;
+        if (m != 0) m &= ~(1ull << kh[q]);
+      }
+      const int k = j == 0 ? kh[0] : (j == 1 ? kh[1] : (j == 2 ? kh[2] : kh[3]));
+      // a lane without a hit reads the group's first hit so that everything
+      // it computes is finite; it replays nothing
+      const bool has = k >= 0;
+      const int ks = has ? k : kh[0];
+      Record R;
+      float4* rr = reinterpret_cast<float4*>(&R);
+      rr[0] = s_rec[ks][0]; rr[1] = s_rec[ks][1]; rr[2] = s_rec[ks][2]; rr[3] = s_rec[ks][3];
+      const PairEval E = eval_pair(R, dx, dy, dz);
+      const uint32_t e = base + (uint32_t)ks;
+      const bool in_range = valid & has & (e < last);
+      evals += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(in_range));
+      const bool on = in_range & pair_contributes<kFixed>(R, E, op);
+      const float a = clamp_alpha(E.a_raw, op);
+      const bool clamped = !(E.a_raw < op.alpha_max);
+      // per-slot map cb -> A cb + B of the hit (identity when not replayed)
+      const float fa = on ? 1.0f - a : 1.0f;
+      float Ai = fa, B0 = on ? a * R.rgb[0] : 0.0f, B1 = on ? a * R.rgb[1] : 0.0f, B2 = on ? a * R.rgb[2] : 0.0f;
+      // inclusive prefix over the quad (slot 0 is the furthest back): the
+      // later map after the earlier one, x -> A2 (A1 x + B1) + B2
+      {
+        const float pA = qdppb<kQuadPrev1>(Ai), pB0 = qdppb<kQuadPrev1>(B0), pB1 = qdppb<kQuadPrev1>(B1),
+                    pB2 = qdppb<kQuadPrev1>(B2);
+        if (j >= 1) {
+          B0 = fmaf(Ai, pB0, B0);
+          B1 = fmaf(Ai, pB1, B1);
+          B2 = fmaf(Ai, pB2, B2);
+          Ai *= pA;
+        }
+        const float qA = qdppb<kQuadPrev2>(Ai), qB0 = qdppb<kQuadPrev2>(B0), qB1 = qdppb<kQuadPrev2>(B1),
+                    qB2 = qdppb<kQuadPrev2>(B2);
+        if (j >= 2) {
+          B0 = fmaf(Ai, qB0, B0);
+          B1 = fmaf(Ai, qB1, B1);
+          B2 = fmaf(Ai, qB2, B2);
+          Ai *= qA;
+        }
+      }
+      // exclusive prefix (the maps of the hits behind this one) applied to the step's colour
+      const float eA = qdppb<kQuadPrev1>(Ai), eB0 = qdppb<kQuadPrev1>(B0), eB1 = qdppb<kQuadPrev1>(B1),
+                  eB2 = qdppb<kQuadPrev1>(B2);
+      const float c0 = j >= 1 ? fmaf(eA, cb0, eB0) : cb0;
+      const float c1 = j >= 1 ? fmaf(eA, cb1, eB1) : cb1;
+      const float c2 = j >= 1 ? fmaf(eA, cb2, eB2) : cb2;
+      // transmittance in front of this hit: T over the inclusive product of (1 - alpha)
+      const float Tb = T * __builtin_amdgcn_rcpf(Ai);
+      const float w = on ? a * Tb : 0.0f;
+      float part[kAcc];
+      part[1] = w * G0;
+      part[2] = w * G1;
+      part[3] = w * G2;
+      const float dla = on ? Tb * ((R.rgb[0] - c0) * G0 + (R.rgb[1] - c1) * G1 + (R.rgb[2] - c2) * G2) : 0.0f;
+      const float dlk = clamped ? 0.0f : -0.5f * a * dla;  // dL/dkappa
+      part[0] = clamped ? 0.0f : dla * a;                  // dL/dlog(sigma)
+      const float rr_ = __builtin_amdgcn_sqrtf(R.c1);
+      const float f = 2.0f * rr_ * E.inv * dlk;
+      part[4] = f * E.gx * E.gz;
+      part[5] = f * E.gy * E.gz;
+      part[6] = f * E.mm;
+      const float h = f * (R.c1 * E.inv);
+      const float gz2 = E.gz * E.gz;
+      const float du0 = h * gz2 * E.gx, du1 = h * gz2 * E.gy, du2 = h * E.mm * E.gz;
+      part[7] = du0 * dx; part[8] = du0 * dy; part[9] = du0 * dz;
+      part[10] = du1 * dx; part[11] = du1 * dy; part[12] = du1 * dz;
+      part[13] = du2 * dx; part[14] = du2 * dy; part[15] = du2 * dz;
+      // the step's state for the next one: the whole quad's map and product
+      T *= __builtin_amdgcn_rcpf(qdppb<kQuadLast>(Ai));
+      cb0 = fmaf(qdppb<kQuadLast>(Ai), cb0, qdppb<kQuadLast>(B0));
+      cb1 = fmaf(qdppb<kQuadLast>(Ai), cb1, qdppb<kQuadLast>(B1));
+      cb2 = fmaf(qdppb<kQuadLast>(Ai), cb2, qdppb<kQuadLast>(B2));
+      const float sum = quad_reduce16(part);
+      if (has && sum != 0.0f) unsafeAtomicAdd(acc + (int64_t)s_item[ks] * kAcc + ((lane >> 2) & 15), sum);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 constexpr int kBackWaves = 2;  // independent waves per workgroup
@@ -235,12 +447,18 @@ __global__ __launch_bounds__(64 * kBackWaves) void render_backward_kernel(
   uint64_t evals = 0;  // (ray, entry) pairs replayed, as the forward counts them
   for (int h = wi / kHeavySplit;; h += heavy.hslots) {
     if (hw && h >= nh) break;
-    const WaveBlock W = hw ? heavy_block((int)heavy.list[h], wi % kHeavySplit, views, nviews)
-                           : ordinary_block(wi, heavy_waves, views, nviews, heavy.flag);
+    if (hw) {
+      const WaveBlock W = heavy_block((int)heavy.list[h], wi % kHeavySplit, views, nviews);
+      if (W.live)
+        backward_heavy_block<kFixed>(W, views, dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc,
+                                     s_rec, s_item, evals);
+      continue;
+    }
+    const WaveBlock W = ordinary_block(wi, heavy_waves, views, nviews, heavy.flag);
     if (W.live)
       backward_block<kFixed>(W, views, dtab, ranges, list, rects, recs, op, nlast, tfinal, dl_drgb, acc, s_rec, s_item,
                              evals);
-    if (!hw) break;
+    break;
   }
   add_evals<kBackWaves>(evals_total, eval_slots, evals);
 }

@@ -112,6 +112,36 @@ def test_kb190_full_size_masked_rays(R):
         assert e <= 1e-3, (k, e)
 
 
+def test_heavy_tile_rays(R):
+    """Gradients from rays of heavy tiles only (the 4x4 blocks replayed four
+    hits per step) against the FP64 oracle: the 100k-Gaussian fisheye frame,
+    whose corner tiles carry the longest lists, dL/dRGB on 1024 rays drawn
+    from its heavy tiles."""
+    from helpers import heavy_pixel_mask
+
+    scene, cams = synth.workload_fisheye_forward(seed=0)
+    cam = cams[0]
+    W, H = cam["width"], cam["height"]
+    sc = R.scene_from_numpy(scene)
+    _, _, _, fr = R.render(sc, cams, keep_frame=True)
+    heavy = heavy_pixel_mask(fr.export(_lib.BUF_RANGES), cams)
+    fr.release()
+    cand = np.nonzero(heavy)[0]
+    assert cand.size >= 4096, cand.size
+    pix = np.random.default_rng(12).choice(cand, 1024, replace=False)
+    keep = ~oracle.render(scene, cam, pix=pix)["amb"]
+    pix = pix[keep]
+    G = np.random.default_rng(13).normal(size=(pix.size, 3))
+    ref = oracle.render_backward(scene, cam, pix, G)
+    Gfull = np.zeros((W * H, 3))
+    Gfull[pix] = G
+    got = gpu_grads(R, scene, cams, to_planar(Gfull, cam))
+    err = rel_errors(got, ref)
+    print("heavy-tile rays: %d heavy pixels, errors %s" % (cand.size, err))
+    for k, e in err.items():
+        assert e <= 1e-3, (k, e)
+
+
 def test_multiview_gradients_add_up(R):
     scene = synth.scene_box(3000, seed=4, half=4.0)
     rng = np.random.default_rng(6)
