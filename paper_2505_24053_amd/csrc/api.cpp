@@ -320,15 +320,16 @@ struct FwdBufs {
                               // [6] heavy tiles, [7] stall flag of earlier eager forwards
   unsigned long long* err = nullptr;  // where the sorts flag a stall (null: stats[4])
   unsigned long long* sort_err() const { return err ? err : (unsigned long long*)(stats + 4); }
-  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr, *hist = nullptr, *scratch = nullptr;
+  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
+  uint32_t* hist = nullptr;   // the depth order's work (depth_work_words)
+  uint32_t* twork = nullptr;  // the expansion's and tile sort's work (tile_work_words)
   uint32_t *cnt_sorted = nullptr, *tiles_a = nullptr, *tiles_b = nullptr, *items_b = nullptr;
   uint32_t *list = nullptr, *ranges = nullptr, *nlast = nullptr;
   bool depth_work_zeroed = false;  // the preprocess launch clears the depth sort's work area
   float* tfinal = nullptr;
   uint32_t *heavy_list = nullptr, *heavy_flag = nullptr;  // heavy-tile work list
   int hmax = 0;
-  float4* tcones = nullptr;  // per-tile corner cones of the expansion's cull (4 float4 per tile)
-  uint32_t* hparts = nullptr;  // partial tile-digit histograms filled by the expansion
+  float4* tcones = nullptr;  // per-tile cones of the expansion's cull (tile_cone_bytes)
   HeavyTiles heavy() const {
     return HeavyTiles{heavy_list, heavy_flag, (unsigned long long*)(stats + 6), hmax, heavy_slots(hmax),
                       (unsigned long long*)(heavy_list + heavy_evals_offset(hmax))};
@@ -341,7 +342,7 @@ void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, co
                         const FwdBufs& b, bool per_view_stats = false, const unsigned long long* err_in = nullptr) {
   const int64_t nst = per_view_stats ? 16 * nviews : 16;
   if (b.depth_work_zeroed)
-    launch_zero2_u32(st, (uint32_t*)b.stats, nst, b.hist, radix_zero_words(std::max<int64_t>(sc.n * nviews, 1)));
+    launch_zero2_u32(st, (uint32_t*)b.stats, nst, b.hist, depth_zero_words(sc.n * nviews));
   else
     launch_fill_u32(st, (uint32_t*)b.stats, nst, 0u);
   launch_preprocess(st, sc.n, nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh, b.views, op, lam,
@@ -350,37 +351,31 @@ void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, co
 }
 
 // Stage (b): association list; the tile-sorted list ends in b.list.
-// First half: the depth order of the visible items, their entry offsets and
-// the per-tile cones; none of it depends on the entry count.  dV: the live
-// visible count on the device, or null when nvis_cap is exact.
-void enqueue_depth_order(hipStream_t st, const Opts& op, int64_t n, int64_t items, int64_t nvis_cap,
-                         const unsigned long long* dV, int64_t ntiles, const FwdBufs& b) {
+// First half: the depth order of the visible items and their entry offsets;
+// none of it depends on the entry count.  dV: the live visible count on the
+// device, or null when nvis_cap is exact.
+void enqueue_depth_order(hipStream_t st, int64_t items, int64_t nvis_cap, const unsigned long long* dV,
+                         const FwdBufs& b) {
   if (nvis_cap <= 0) return;
-  unsigned long long* err = b.sort_err();
-  // depth order of the visible items (pass 0 compacts them out of all items)
-  radix_sort(st, b.keys, nullptr, b.counts, false, items, nullptr, nvis_cap, dV, 0, 4, b.ka, b.va, b.kb, b.vb,
-             b.hist, nullptr, err, nullptr, 8, b.depth_work_zeroed);
-  gather_scan(st, b.vb, nvis_cap, dV, b.counts, b.cnt_sorted, b.scratch);
-  // the tile cones' launch also clears the expansion's partial histograms
-  if (op.cone_cull) {
-    const int hp = hist_passes(ntiles);
-    launch_tile_cones(st, b.views, n > 0 ? (int)(items / n) : 1, b.dtab, ntiles, b.tcones, hp ? b.hparts : nullptr,
-                      hp ? hist_parts_words() : 0);
-  }
+  // items in depth order to b.vb, their entry offsets to b.cnt_sorted
+  depth_order(st, b.keys, b.counts, items, nvis_cap, dV, b.hist, b.depth_work_zeroed, b.ka, b.va, b.kb, b.vb,
+              b.cnt_sorted, b.sort_err());
 }
 
-// Second half: expansion, tile sort and ranges.  dV / dE: live counts on the
-// device, or null when nvis_cap / ecap are exact.
-void enqueue_tile_lists(hipStream_t st, const Opts& op, int64_t n, int64_t nvis_cap, const unsigned long long* dV,
-                        int64_t ecap, const unsigned long long* dE, int64_t ntiles, const FwdBufs& b) {
+// Second half: per-tile cones, expansion, tile sort and ranges.  dV / dE:
+// live counts on the device, or null when nvis_cap / ecap are exact.
+void enqueue_tile_lists(hipStream_t st, const Opts& op, int64_t n, int64_t items, int64_t nvis_cap,
+                        const unsigned long long* dV, int64_t ecap, const unsigned long long* dE, int64_t ntiles,
+                        const FwdBufs& b) {
   unsigned long long* kept = (unsigned long long*)(b.stats + 5);  // list length after the cone cull
   unsigned long long* err = b.sort_err();
-  if (nvis_cap > 0) {
+  if (nvis_cap > 0 && ecap > 0) {
+    // The tile cones' launch also clears the expansion's and the sort's work.
     // Expansion in depth order (entries no ray of their tile can see marked
-    // for dropping), then the stable tile-id passes -- the first compacts --
-    // arranged so that the sorted items end in b.list: pair P = (tiles_b,
-    // list), Q = (tiles_a, items_b); odd pass counts run Q -> P -> Q ...,
-    // even ones P -> Q -> P ...
+    // for dropping), then the stable tile-id passes -- the first drops them
+    // and counts the kept ones into stats[5] --, arranged so that the sorted
+    // items end in b.list: pair P = (tiles_b, list), Q = (tiles_a, items_b);
+    // odd pass counts run Q -> P -> Q ..., even ones P -> Q -> P ...
     const TileDigits td = tile_digits(ntiles);
     const int passes = td.passes;
     uint32_t *pt = b.tiles_b, *pi = b.list, *qt = b.tiles_a, *qi = b.items_b;
@@ -388,14 +383,17 @@ void enqueue_tile_lists(hipStream_t st, const Opts& op, int64_t n, int64_t nvis_
     uint32_t* iin = (passes % 2 == 1) ? qi : pi;
     uint32_t* at = (passes % 2 == 1) ? pt : qt;
     uint32_t* ai = (passes % 2 == 1) ? pi : qi;
+    if (op.cone_cull)
+      launch_tile_cones(st, b.views, n > 0 ? (int)(items / n) : 1, b.dtab, ntiles, b.tcones, b.twork,
+                        tile_zero_words(ecap));
+    else
+      launch_fill_u32(st, b.twork, tile_zero_words(ecap), 0u);
     // the expansion also counts the tile digits of the kept entries (one or
     // two passes), which replaces the sort's histogram pass over the list
     const int hpass = hist_passes(ntiles);
-    if (hpass && !op.cone_cull) launch_fill_u32(st, b.hparts, hist_parts_words(), 0u);  // else cleared already
     launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, b.tcones, b.recs, op, tin,
-                  iin, b.hparts, hpass, td.bits);
-    radix_sort(st, tin, iin, nullptr, op.cone_cull != 0, ecap, dE, ecap, kept, 0, passes, at, ai, tin, iin, b.hist,
-               kept, err, hpass ? b.hparts : nullptr, td.bits);
+                  iin, b.twork, hpass, td.bits);
+    tile_sort(st, tin, iin, ecap, dE, kept, passes, td.bits, at, ai, tin, iin, b.twork, hpass, err);
     uint32_t* tfinal = (passes % 2 == 1) ? at : tin;
     launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges, b.list);
   } else {
@@ -412,8 +410,8 @@ void enqueue_association(hipStream_t st, const Opts& op, int64_t n, int64_t item
   const unsigned long long* dE = dyn ? (const unsigned long long*)b.stats : nullptr;
   const unsigned long long* dV = dyn ? (const unsigned long long*)(b.stats + 1) : nullptr;
   if (dyn) launch_capacity_guard(st, (unsigned long long*)b.stats, ecap);
-  enqueue_depth_order(st, op, n, items, nvis_cap, dV, ntiles, b);
-  enqueue_tile_lists(st, op, n, nvis_cap, dV, ecap, dE, ntiles, b);
+  enqueue_depth_order(st, items, nvis_cap, dV, b);
+  enqueue_tile_lists(st, op, n, items, nvis_cap, dV, ecap, dE, ntiles, b);
 }
 
 // Stage (c): the render kernel.
@@ -614,10 +612,9 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   f->dtab_off = tab.dtab_off;
 
   // Temporaries of the sort; released at the end of the call.
-  Block ka, va, kb, vb, hist, hist2, scratch, tiles_a, tiles_b, items_b, cnt_sorted, tcones, hparts;
+  Block ka, va, kb, vb, hist, twork, tiles_a, tiles_b, items_b, cnt_sorted, tcones;
   auto cleanup = [&](geer_status st_) {
-    for (Block* b : {&ka, &va, &kb, &vb, &hist, &hist2, &scratch, &tiles_a, &tiles_b, &items_b, &cnt_sorted,
-                     &tcones, &hparts})
+    for (Block* b : {&ka, &va, &kb, &vb, &hist, &twork, &tiles_a, &tiles_b, &items_b, &cnt_sorted, &tcones})
       release(c, *b);
     if (st_ != GEER_OK) {
       free_frame_buffers(f);
@@ -661,20 +658,16 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   b.stats = (uint64_t*)f->stats.p;
   // depth-sort buffers, sized for all items (the visible count is read on
   // the device); the preprocess launch also clears the sort's work area
-  const int64_t hist_items = radix_work_words(it1);
   TRY(acquire(c, 4 * it1, st, ka));
   TRY(acquire(c, 4 * it1, st, va));
   TRY(acquire(c, 4 * it1, st, kb));
   TRY(acquire(c, 4 * it1, st, vb));
-  TRY(acquire(c, 4 * (size_t)hist_items, st, hist));
-  TRY(acquire(c, 4 * (size_t)scan_scratch_words(it1), st, scratch));
+  TRY(acquire(c, 4 * (size_t)depth_work_words(it1), st, hist));
   TRY(acquire(c, 4 * it1, st, cnt_sorted));
-  TRY(acquire(c, 64 * (size_t)std::max<int64_t>(ntiles, 1), st, tcones));
-  TRY(acquire(c, 4 * (size_t)hist_parts_words(), st, hparts));
+  TRY(acquire(c, tile_cone_bytes(ntiles), st, tcones));
   b.tcones = (float4*)tcones.p;
-  b.hparts = (uint32_t*)hparts.p;
   b.ka = (uint32_t*)ka.p; b.va = (uint32_t*)va.p; b.kb = (uint32_t*)kb.p; b.vb = (uint32_t*)vb.p;
-  b.hist = (uint32_t*)hist.p; b.scratch = (uint32_t*)scratch.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
+  b.hist = (uint32_t*)hist.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
   b.depth_work_zeroed = true;
   b.err = c->dev_err;
   ProfSlot* ps = prof_slot(c);
@@ -693,7 +686,7 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
 
   // ---- stage (b): depth sort, expansion, tile sort, ranges ----
   prof_mark(ps, 2, st);
-  enqueue_depth_order(st, op, n, items, items, (const unsigned long long*)(b.stats + 1), ntiles, b);
+  enqueue_depth_order(st, items, items, (const unsigned long long*)(b.stats + 1), b);
   HTRY(hipGetLastError());
 
   HTRY(hipEventSynchronize(c->totals_ready));
@@ -714,10 +707,8 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   f->visible = nvis;
 
   const int64_t e1 = std::max<int64_t>(E, 1);
-  if (radix_work_words(e1) > hist_items) {  // the tile sort's own (larger) work area
-    TRY(acquire(c, 4 * (size_t)radix_work_words(e1), st, hist2));
-    b.hist = (uint32_t*)hist2.p;
-  }
+  TRY(acquire(c, 4 * (size_t)tile_work_words(e1), st, twork));
+  b.twork = (uint32_t*)twork.p;
   TRY(acquire(c, 4 * (e1 + 8), st, tiles_a));
   TRY(acquire(c, 4 * (e1 + 8), st, tiles_b));
   TRY(acquire(c, 4 * (e1 + 8), st, f->list));
@@ -725,7 +716,7 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   TRY(acquire(c, 4 * (ntiles + 1), st, f->ranges));
   b.tiles_a = (uint32_t*)tiles_a.p; b.tiles_b = (uint32_t*)tiles_b.p; b.items_b = (uint32_t*)items_b.p;
   b.list = (uint32_t*)f->list.p; b.ranges = (uint32_t*)f->ranges.p;
-  enqueue_tile_lists(st, op, n, nvis, nullptr, E, nullptr, ntiles, b);
+  enqueue_tile_lists(st, op, n, items, nvis, nullptr, E, nullptr, ntiles, b);
   HTRY(hipGetLastError());
 
   // ---- stage (c): render ----
@@ -986,8 +977,8 @@ geer_status geer_l1_loss(geer_ctx* c, int64_t pixels, const float* rgb, const fl
 // 256-byte aligned, carved from one block.
 struct PlanLayout {
   size_t meta = 0, recs = 0, rects = 0, keys = 0, counts = 0, stats = 0, ka = 0, va = 0, kb = 0, vb = 0, hist = 0,
-         scratch = 0, cnt_sorted = 0, tiles_a = 0, tiles_b = 0, items_b = 0, list = 0, ranges = 0, heavy_list = 0,
-         heavy_flag = 0, tcones = 0, hparts = 0, total = 0;
+         twork = 0, cnt_sorted = 0, tiles_a = 0, tiles_b = 0, items_b = 0, list = 0, ranges = 0, heavy_list = 0,
+         heavy_flag = 0, tcones = 0, total = 0;
 };
 
 // pre_items (default: items) sizes the per-item outputs of the preprocess.
@@ -1000,7 +991,6 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
     return at;
   };
   const int64_t it1 = std::max<int64_t>(items, 1);
-  const int64_t hist_words = radix_work_words(std::max(it1, ecap));
   L.meta = put(meta_bytes);
   const int64_t pre1 = pre_items < 0 ? it1 : std::max<int64_t>(pre_items, 1);
   L.recs = put(sizeof(Record) * pre1);
@@ -1012,8 +1002,8 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
   L.va = put(4 * it1);
   L.kb = put(4 * it1);
   L.vb = put(4 * it1);
-  L.hist = put(4 * (size_t)hist_words);
-  L.scratch = put(4 * (size_t)scan_scratch_words(it1));
+  L.hist = put(4 * (size_t)depth_work_words(it1));
+  L.twork = put(4 * (size_t)tile_work_words(ecap));
   L.cnt_sorted = put(4 * it1);
   L.tiles_a = put(4 * (ecap + 8));
   L.tiles_b = put(4 * (ecap + 8));
@@ -1022,8 +1012,7 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
   L.ranges = put(4 * (ntiles + 1));
   L.heavy_list = put(4 * (size_t)heavy_list_words(ntiles));
   L.heavy_flag = put(4 * (size_t)ntiles);
-  L.tcones = put(64 * (size_t)std::max<int64_t>(ntiles, 1));
-  L.hparts = put(4 * (size_t)hist_parts_words());
+  L.tcones = put(tile_cone_bytes(ntiles));
   L.total = off;
   return L;
 }
@@ -1044,7 +1033,7 @@ FwdBufs carve_plan(char* w, const PlanLayout& lay, const ViewTables& tab, int64_
   b.kb = (uint32_t*)(w + lay.kb);
   b.vb = (uint32_t*)(w + lay.vb);
   b.hist = (uint32_t*)(w + lay.hist);
-  b.scratch = (uint32_t*)(w + lay.scratch);
+  b.twork = (uint32_t*)(w + lay.twork);
   b.cnt_sorted = (uint32_t*)(w + lay.cnt_sorted);
   b.tiles_a = (uint32_t*)(w + lay.tiles_a);
   b.tiles_b = (uint32_t*)(w + lay.tiles_b);
@@ -1054,7 +1043,6 @@ FwdBufs carve_plan(char* w, const PlanLayout& lay, const ViewTables& tab, int64_
   b.heavy_list = (uint32_t*)(w + lay.heavy_list);
   b.heavy_flag = (uint32_t*)(w + lay.heavy_flag);
   b.tcones = (float4*)(w + lay.tcones);
-  b.hparts = (uint32_t*)(w + lay.hparts);
   b.hmax = heavy_capacity(ntiles);
   return b;
 }
@@ -1412,7 +1400,7 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
   b.kb = (uint32_t*)(w + F.kb);
   b.vb = (uint32_t*)(w + F.vb);
   b.hist = (uint32_t*)(w + F.hist);
-  b.scratch = (uint32_t*)(w + F.scratch);
+  b.twork = (uint32_t*)(w + F.twork);
   b.cnt_sorted = (uint32_t*)(w + F.cnt_sorted);
   b.tiles_a = (uint32_t*)(w + F.tiles_a);
   b.tiles_b = (uint32_t*)(w + F.tiles_b);
@@ -1422,7 +1410,6 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
   b.heavy_list = (uint32_t*)(w + F.heavy_list);
   b.heavy_flag = (uint32_t*)(w + F.heavy_flag);
   b.tcones = (float4*)(w + F.tcones);
-  b.hparts = (uint32_t*)(w + F.hparts);
   b.hmax = heavy_capacity(S.ntiles_max);
   b.nlast = (uint32_t*)(w + lay.nlast);
   b.tfinal = (float*)(w + lay.tfinal);

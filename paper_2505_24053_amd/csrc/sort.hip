@@ -1,16 +1,17 @@
 // Stage (b): association list.  Alg. 1 DuplicateWithKeys / SortByKeys /
 // IdentifyFrustumRanges, arranged so the wide sort only touches tile ids:
 //   1. stable LSD radix sort of the visible items by their 32-bit depth key
-//      (the first pass compacts the visible items out of all items);
-//   2. exclusive scan of the items' tile counts in depth order;
-//   3. expansion of every item into (tile, item) entries in depth order,
+//      in four 8-bit passes: the first compacts the visible items out of all
+//      items, the last also writes the exclusive scan of the items' tile
+//      counts in depth order (the entry offsets);
+//   2. expansion of every item into (tile, item) entries in depth order,
 //      balanced over entries (8 per lane; owners found through LDS), with
 //      the contribution-cone cull marking the entries no ray can see;
-//   4. stable LSD radix sort of the entries by global tile id, so each tile's
-//      run stays in (depth key, item) order;
-//   5. run boundaries -> ranges[tile].
-// Radix passes use 8-bit digits, one kernel per pass with decoupled
-// look-back (below).
+//   3. stable LSD radix sort of the entries by global tile id, so each tile's
+//      run stays in (depth key, item) order; the first pass leaves out the
+//      marked entries;
+//   4. run boundaries -> ranges[tile].
+// Every radix pass is one kernel with decoupled look-back (below).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -94,128 +95,34 @@ __device__ __forceinline__ int64_t dyn_count(int64_t n_cap, const unsigned long 
   return dyn ? min((int64_t)*dyn, n_cap) : n_cap;
 }
 
-// ------------------------------------------------------ gathered scan --
-//
-// Exclusive scan of the gathered values counts[items[j]] (j < m; 0 for
-// m <= j < m_cap) in two kernels: the first gathers and sums each 4096-item
-// tile, the second adds up the sums of the tiles before its own (at most
-// kGatherScanTiles of them) and scans its tile.
-
-constexpr int kGatherScanTiles = 4096;
-
-__global__ __launch_bounds__(kBlock) void gather_reduce_kernel(const uint32_t* __restrict__ items, int64_t m_cap,
-                                                               const unsigned long long* __restrict__ dyn,
-                                                               const uint32_t* __restrict__ counts,
-                                                               uint32_t* __restrict__ out,
-                                                               uint32_t* __restrict__ sums) {
-  const int64_t m = dyn_count(m_cap, dyn);
-  const int64_t base = (int64_t)blockIdx.x * kTileItems;
-  uint32_t it[kPerThread];
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {  // independent loads first
-    const int64_t i = base + k * kBlock + threadIdx.x;
-    it[k] = i < m ? items[i] : 0u;
-  }
-  uint32_t s = 0u;
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    const int64_t i = base + k * kBlock + threadIdx.x;
-    const uint32_t v = i < m ? counts[it[k]] : 0u;
-    if (i < m_cap) out[i] = v;
-    s += v;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  __shared__ uint32_t red[kBlock / 64];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) sums[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-// LDS slot of item i of a 4096-item tile: one word of padding per 16, so the
-// 16 consecutive items of each thread start on distinct banks.
-__device__ __forceinline__ int scan_slot(int i) { return i + (i >> 4); }
-
-// kStaged: the tile goes through LDS so that global loads and stores are
-// lane-striped (coalesced); worth its barrier from a few dozen tiles on.
-template <bool kStaged>
-__global__ __launch_bounds__(kBlock) void gathered_scan_kernel(const uint32_t* __restrict__ in, int64_t n,
-                                                               const uint32_t* __restrict__ sums,
-                                                               uint32_t* __restrict__ out) {
-  __shared__ uint32_t s_v[kStaged ? kTileItems + kTileItems / 16 : 1];
-  const int64_t tile0 = (int64_t)blockIdx.x * kTileItems;
-  if (kStaged) {
-#pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-      const int li = k * kBlock + threadIdx.x;
-      s_v[scan_slot(li)] = tile0 + li < n ? in[tile0 + li] : 0u;
-    }
-  }
-  // carried-in offset: the sums of tiles 0 .. blockIdx.x - 1
-  uint32_t pre = 0u;
-  for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBlock) pre += sums[t];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
-  __shared__ uint32_t red[kBlock / 64], wsum[kBlock / 64];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
-  __syncthreads();
-  // each thread scans 16 consecutive items
-  const int lbase = threadIdx.x * kPerThread;
-  uint32_t v[kPerThread];
-  uint32_t tsum = 0;
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    if (kStaged) v[k] = s_v[scan_slot(lbase + k)];
-    else v[k] = tile0 + lbase + k < n ? in[tile0 + lbase + k] : 0u;
-    tsum += v[k];
-  }
-  const uint32_t incl = wave_incl_scan(tsum);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 63) wsum[wv] = incl;
-  __syncthreads();
-  uint32_t wpre = 0;
-  for (int w = 0; w < wv; ++w) wpre += wsum[w];
-  uint32_t run = red[0] + red[1] + red[2] + red[3] + wpre + incl - tsum;
-  if (!kStaged) {
-#pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-      if (tile0 + lbase + k < n) out[tile0 + lbase + k] = run;
-      run += v[k];
-    }
-    return;
-  }
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    s_v[scan_slot(lbase + k)] = run;  // only this thread's slots: no barrier before
-    run += v[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    const int li = k * kBlock + threadIdx.x;
-    if (tile0 + li < n) out[tile0 + li] = s_v[scan_slot(li)];
-  }
-}
-
 // ----------------------------------------------------------------- radix --
 //
 // Stable LSD radix sort with 8-bit digits, one kernel per pass ("onesweep"
-// with decoupled look-back).  An upsweep kernel first counts the digits of
-// every pass over the (filtered) input.  In a pass, block b takes the b-th
-// chunk of keys (1024 to 4096 keys by sort size, os_per), ranks its keys
-// stably (per wave: ballot match on the digit; across waves and slices:
-// running counts in LDS), publishes its per-digit counts, and walks back
-// over earlier blocks' published counts -- stopping at the first that
-// already holds its inclusive prefix -- to find where its run of each digit
-// starts.  Keys are then reordered by digit in LDS and written out as
-// contiguous runs.  A status
-// word is [flag:2 | count:30]; the look-back spin is bounded and reports a
-// stall through an error word instead of hanging.  A block waits only on
-// blocks with lower indices, and each XCD dispatches the workgroups of a
-// launch in index order, so the lowest unfinished block is always resident
-// and the walk always ends.  (A per-block atomic ticket would serialise:
-// tickets come one at a time off one counter, which staggers the 692 blocks
-// of a 2.8M-key pass over about 9 us.)
+// with decoupled look-back).  The digit counts of every pass are known before
+// the first pass: an upsweep kernel counts them over the (filtered) input,
+// or the producer of the keys counted them into partial copies that each
+// pass sums for itself.  In a pass, block b takes the b-th chunk of keys
+// (1024 to 4096 keys by sort size, os_per), ranks its keys stably (per wave:
+// ballot match on the digit; across waves and slices: running counts in
+// LDS), publishes its per-digit counts, and walks back over earlier blocks'
+// published counts -- stopping at the first that already holds its inclusive
+// prefix -- to find where its run of each digit starts.  Keys are then
+// reordered by digit in LDS and written out as contiguous runs.
+//
+// A status word is [flag:2 | count:30].  A weighted pass also carries each
+// key's weight (wts[value]): its status words are 64 bits wide, the word
+// above in the high half and the digit's weight sum (mod 2^32) in the low
+// half, loaded and stored as one, and it writes for every output position the
+// exclusive prefix sum of the weights in sorted order.  The depth order's last
+// pass is weighted by the items' tile counts, so it also yields the entry
+// offsets of the expansion.
+//
+// The look-back spin is bounded and reports a stall through an error word
+// instead of hanging.  A block waits only on blocks with lower indices, and
+// each XCD dispatches the workgroups of a launch in index order, so the
+// lowest unfinished block is always resident and the walk always ends.  (A
+// per-block atomic ticket would serialise: tickets come one at a time off one
+// counter, which staggers the 692 blocks of a 2.8M-key pass over about 9 us.)
 
 constexpr int kLookBack = 16;  // statuses read per look-back round
 constexpr int kOSPerSmall = 4;                  // keys per thread below kOSSmallKeys keys
@@ -233,7 +140,9 @@ __host__ __device__ __forceinline__ int os_per(int64_t nmax) {
 }
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr int kWorkHead = 1024 + 64;            // histograms of 4 passes (padded)
+// Work head: the digit counts of up to 4 passes, then the weighted counts of
+// the last pass's digits (padded).
+constexpr int kWorkHead = 5 * 256 + 64;
 
 __host__ __device__ __forceinline__ int64_t os_blocks(int64_t n, int items) { return (n + items - 1) / items; }
 
@@ -252,26 +161,34 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s_w
 }
 
 // A key equal to kDropKey is not sorted when `drop` is set (entries the
-// expansion found unable to contribute); the pass-0 output count is then
-// added to *kept.
+// expansion found unable to contribute).
 constexpr uint32_t kDropKey = 0xffffffffu;
 
+// Digit counts (digits of `bits` bits from shift0) of every pass over the
+// keys i < live count with filter[i] != 0 (every key without a filter; with
+// drop, not kDropKey), added into ghist (npass rows of 256 words); with
+// whist, the filter values summed per digit of the last pass are added into
+// whist.
 __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* __restrict__ keys,
                                                                const uint32_t* __restrict__ filter, int drop,
                                                                int64_t n_cap,
                                                                const unsigned long long* __restrict__ dyn,
                                                                int shift0, int bits, int npass,
                                                                uint32_t* __restrict__ ghist,
-                                                               unsigned long long* __restrict__ kept) {
+                                                               uint32_t* __restrict__ whist) {
   const uint32_t dmask = (1u << bits) - 1u;
   const int64_t n = dyn_count(n_cap, dyn);
   __shared__ uint32_t h[4][256];
-  __shared__ uint32_t s_kept;
+  __shared__ uint32_t hw[256];
 #pragma unroll
   for (int p = 0; p < 4; ++p) h[p][threadIdx.x] = 0u;
-  if (threadIdx.x == 0) s_kept = 0u;
+  hw[threadIdx.x] = 0u;
   __syncthreads();
-  uint32_t mine = 0u;
+  const int lshift = shift0 + bits * (npass - 1);
+  auto count = [&](uint32_t f, uint32_t k) {
+    for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (shift0 + bits * p)) & dmask], 1u);
+    if (whist) atomicAdd(&hw[(k >> lshift) & dmask], f);
+  };
   // grid-stride; with many keys per thread, 8 keys per step with all their
   // loads in flight together
   constexpr int kUp = 8;
@@ -280,9 +197,7 @@ __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* _
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
       const uint32_t f = filter ? filter[i] : 1u;
       const uint32_t k = keys[i];
-      if (f == 0u || (drop && k == kDropKey)) continue;
-      ++mine;
-      for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (shift0 + bits * p)) & dmask], 1u);
+      if (f != 0u && !(drop && k == kDropKey)) count(f, k);
     }
   } else {
     for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += kUp * stride) {
@@ -295,45 +210,104 @@ __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint32_t* _
         k[u] = keys[ic];
       }
 #pragma unroll
-      for (int u = 0; u < kUp; ++u) {
-        if (i0 + u * stride >= n || f[u] == 0u || (drop && k[u] == kDropKey)) continue;
-        ++mine;
-        for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k[u] >> (shift0 + bits * p)) & dmask], 1u);
-      }
+      for (int u = 0; u < kUp; ++u)
+        if (i0 + u * stride < n && f[u] != 0u && !(drop && k[u] == kDropKey)) count(f[u], k[u]);
     }
   }
-  if (kept && mine) atomicAdd(&s_kept, mine);
   __syncthreads();
   for (int p = 0; p < npass; ++p) {
     const uint32_t c = h[p][threadIdx.x];
     if (c) atomicAdd(&ghist[p * 256 + threadIdx.x], c);
   }
-  if (kept && threadIdx.x == 0 && s_kept) atomicAdd(kept, (unsigned long long)s_kept);
+  if (whist && hw[threadIdx.x]) atomicAdd(&whist[threadIdx.x], hw[threadIdx.x]);
 }
 
-template <int kPer>
-__global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, const uint32_t* __restrict__ filter,
-    int drop, int64_t n_cap, const unsigned long long* __restrict__ dyn, int shift, uint32_t dmask,
-    const uint32_t* __restrict__ ghist_p,
-    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, unsigned long long* __restrict__ err) {
+// Partial digit histograms filled by a producer kernel: kHistCopies copies
+// (block b adds to copy b % kHistCopies), each with 256 words per pass for
+// up to kHistPasses passes; every pass of the sort sums the copies of its
+// digits.
+constexpr int kHistCopies = 16;
+constexpr int kHistPasses = 2;
+constexpr int kHistStride = 256 * kHistPasses + 64;
+
+// Arguments of one radix pass.
+struct PassArgs {
+  const uint32_t* keys_in;
+  const uint32_t* vals_in;  // null: the key's index
+  const uint32_t* filter;   // null: every key; else only keys with filter[i] != 0
+  int drop;                 // leave out kDropKey keys
+  int64_t n_cap;
+  const unsigned long long* dyn;  // live key count (null: n_cap)
+  int shift;
+  uint32_t dmask;  // digit = (key >> shift) & dmask, below 256
+  const uint32_t* ghist;  // this pass's digit counts, summed over hcopies copies hstride words apart
+  int hcopies, hstride;
+  unsigned long long* kept_out;  // with it, block 0 stores the number of keys sorted
+  const uint32_t* whist;  // weighted pass: weight totals per digit
+  const uint32_t* wts;    // weighted pass: weight of value v
+  void* status;           // this pass's status table, one row per block
+  void* status_next;      // the next pass's table (row b cleared by block b), or null
+  int next_row_words;     // u32 words of a row of the next pass's table
+  uint32_t* keys_out;     // null: keys are not written
+  uint32_t* vals_out;
+  uint32_t* wout;         // weighted pass: exclusive prefix of the weights in sorted order
+  unsigned long long* err;
+};
+
+template <bool kW>
+struct StatusWord;
+template <>
+struct StatusWord<false> {
+  using T = uint32_t;
+  __device__ static T make(uint32_t flag, uint32_t cnt, uint32_t) { return flag | cnt; }
+  __device__ static uint32_t flag(T v) { return v & ~kValMask; }
+  __device__ static uint32_t cnt(T v) { return v & kValMask; }
+  __device__ static uint32_t wsum(T) { return 0u; }
+};
+template <>
+struct StatusWord<true> {
+  using T = unsigned long long;
+  __device__ static T make(uint32_t flag, uint32_t cnt, uint32_t ws) {
+    return ((unsigned long long)(flag | cnt) << 32) | ws;
+  }
+  __device__ static uint32_t flag(T v) { return (uint32_t)(v >> 32) & ~kValMask; }
+  __device__ static uint32_t cnt(T v) { return (uint32_t)(v >> 32) & kValMask; }
+  __device__ static uint32_t wsum(T v) { return (uint32_t)v; }
+};
+
+template <int kPer, bool kWeighted>
+__global__ __launch_bounds__(kBlock) void radix_pass_kernel(const PassArgs a) {
+  constexpr int kItems = kBlock * kPer;
+  using SW = StatusWord<kWeighted>;
+  using Stat = typename SW::T;
   __shared__ uint32_t s_cnt[4][256];  // per-wave running digit counts, then per-wave offsets
   __shared__ uint32_t s_loc[256];     // block-local start of each digit
   __shared__ uint32_t s_glob[256];    // global start of this block's run of each digit
-  constexpr int kItems = kBlock * kPer;
   __shared__ uint32_t s_key[kItems], s_val[kItems];
+  __shared__ uint32_t s_wt[kWeighted ? kItems : 1];  // weights, then their exclusive prefix
+  __shared__ uint32_t s_wsum[kWeighted ? 256 : 1];   // the block's weight per digit
+  __shared__ uint32_t s_wglob[kWeighted ? 256 : 1];  // weight before this block's run of each digit
   __shared__ uint32_t s_w[4];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // the grid is sized for the capacity: blocks past the live key count leave
-  const int64_t n = dyn_count(n_cap, dyn);
+  const int64_t n = dyn_count(a.n_cap, a.dyn);
   const int64_t blk = blockIdx.x;
   if (blk >= os_blocks(n, kItems)) return;
 #pragma unroll
   for (int q = 0; q < 4; ++q) s_cnt[q][tid] = 0u;
+  if (kWeighted) s_wsum[tid] = 0u;
+  if (a.status_next) {  // this block's row of the next pass's table starts clear
+    uint32_t* nx = (uint32_t*)a.status_next + blk * (int64_t)a.next_row_words;
+    for (int i = tid; i < a.next_row_words; i += kBlock) nx[i] = 0u;
+  }
   __syncthreads();
-  if (status_next) status_next[blk * 256 + tid] = 0u;  // this row is clear for the next pass
+  // this pass's count of digit tid: the loads go out with the keys' and are
+  // only summed after the look-back
+  uint32_t gh[kHistCopies];
+#pragma unroll
+  for (int c = 0; c < kHistCopies; ++c) gh[c] = c < a.hcopies ? a.ghist[(int64_t)c * a.hstride + tid] : 0u;
+  const uint32_t wh = kWeighted ? a.whist[tid] : 0u;
 
   // stable ranks within the wave: wave w owns keys [base, base + 64 kPer).
   // Every slice's filter word, key and value are loaded first, from an index
@@ -341,35 +315,43 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
   // flight together; the ranking below only waits for them once.
   const int64_t base = blk * kItems + (int64_t)w * 64 * kPer;
   const uint64_t lt = lanemask_lt();
-  uint32_t key[kPer], val[kPer], rank[kPer], flt[kPer];
+  uint32_t key[kPer], val[kPer], rank[kPer], flt[kPer], wt[kPer];
 #pragma unroll
   for (int sl = 0; sl < kPer; ++sl) {
     const int64_t i = base + sl * 64 + lane;
     const int64_t ic = i < n ? i : n - 1;
-    flt[sl] = filter ? filter[ic] : 1u;
-    key[sl] = keys_in[ic];
-    val[sl] = vals_in ? vals_in[ic] : (uint32_t)i;
+    flt[sl] = a.filter ? a.filter[ic] : 1u;
+    key[sl] = a.keys_in[ic];
+    val[sl] = a.vals_in ? a.vals_in[ic] : (uint32_t)i;
+  }
+  if (kWeighted) {
+#pragma unroll
+    for (int sl = 0; sl < kPer; ++sl) wt[sl] = a.wts[val[sl]];  // a weighted pass always has values
   }
   uint32_t act = 0u;
 #pragma unroll
   for (int sl = 0; sl < kPer; ++sl) {
     const int64_t i = base + sl * 64 + lane;
-    bool a = i < n && flt[sl] != 0u;
-    if (drop) a = a && key[sl] != kDropKey;
-    if (!a) key[sl] = 0u;
-    if (!a) val[sl] = 0u;
-    const uint32_t d = (key[sl] >> shift) & dmask;
-    uint64_t m = __builtin_amdgcn_ballot_w64(a);
+    bool on = i < n && flt[sl] != 0u;
+    if (a.drop) on = on && key[sl] != kDropKey;
+    if (!on) {
+      key[sl] = 0u;
+      val[sl] = 0u;
+      wt[sl] = 0u;
+    }
+    const uint32_t d = (key[sl] >> a.shift) & a.dmask;
+    uint64_t m = __builtin_amdgcn_ballot_w64(on);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const uint64_t bb = __builtin_amdgcn_ballot_w64(((d >> b) & 1u) != 0u);
       m &= ((d >> b) & 1u) ? bb : ~bb;
     }
     const uint32_t r = (uint32_t)__popcll(m & lt);
-    const uint32_t pre = a ? s_cnt[w][d] : 0u;  // every lane of a digit reads before its leader writes
+    const uint32_t pre = on ? s_cnt[w][d] : 0u;  // every lane of a digit reads before its leader writes
     rank[sl] = pre + r;
-    if (a && r == 0u) s_cnt[w][d] = pre + (uint32_t)__popcll(m);
-    act |= (a ? 1u : 0u) << sl;
+    if (on && r == 0u) s_cnt[w][d] = pre + (uint32_t)__popcll(m);
+    if (kWeighted && on) atomicAdd(&s_wsum[d], wt[sl]);
+    act |= (on ? 1u : 0u) << sl;
     // the wave's next slice reads these counts (LDS order within a wave)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -377,36 +359,40 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
   }
   __syncthreads();
 
-  // per digit (thread tid): wave offsets and the block's count
+  // per digit (thread tid): wave offsets and the block's count, published
+  Stat* const status = (Stat*)a.status;
   const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
   const uint32_t tot = c0 + c1 + c2 + c3;
+  const uint32_t bw = kWeighted ? s_wsum[tid] : 0u;
   s_cnt[0][tid] = 0u;
   s_cnt[1][tid] = c0;
   s_cnt[2][tid] = c0 + c1;
   s_cnt[3][tid] = c0 + c1 + c2;
-  __hip_atomic_store(&status[blk * 256 + tid], kFlagAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&status[blk * 256 + tid], SW::make(blk == 0 ? kFlagInc : kFlagAgg, tot, bw),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
   // decoupled look-back over the earlier blocks, kLookBack statuses per
   // round (independent loads in flight together): add aggregates from the
   // nearest block back until an inclusive prefix; stop at a block that has
   // not published yet and poll again from it.  Block 0's aggregate is its
   // inclusive prefix, so the walk also ends after it.
-  uint32_t excl = 0u, spins = 0u;
+  uint32_t excl = 0u, wexcl = 0u, spins = 0u;
   for (int64_t j = blk - 1; j >= 0;) {
-    uint32_t v[kLookBack];
+    Stat v[kLookBack];
 #pragma unroll
     for (int q = 0; q < kLookBack; ++q)
       v[q] = j - q >= 0 ? __hip_atomic_load(&status[(j - q) * 256 + tid], __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT)
-                        : kFlagInc;
+                        : SW::make(kFlagInc, 0u, 0u);
     int q = 0;
     bool done = false;
 #pragma unroll
     for (int r = 0; r < kLookBack; ++r) {
       if (q != r) continue;
-      const uint32_t f = v[r] & ~kValMask;
+      const uint32_t f = SW::flag(v[r]);
       if (f == 0u) continue;  // not published: poll from here again
-      excl += v[r] & kValMask;
+      excl += SW::cnt(v[r]);
+      wexcl += SW::wsum(v[r]);
       if (f == kFlagInc) done = true;
       else q = r + 1;
     }
@@ -414,87 +400,88 @@ __global__ __launch_bounds__(kBlock) void radix_onesweep_kernel(
     j -= q;
     if (q < kLookBack) {
       if (++spins > kSpinLimit) {
-        atomicOr(err, 1ull);
+        atomicOr(a.err, 1ull);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
   }
-  __hip_atomic_store(&status[blk * 256 + tid], kFlagInc | (excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (blk > 0)
+    __hip_atomic_store(&status[blk * 256 + tid], SW::make(kFlagInc, excl + tot, wexcl + bw), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 
-  uint32_t gtotal, ltotal;
-  const uint32_t gstart = block_excl_scan256(ghist_p[tid], s_w, gtotal);
+  // global starts of the digits (counts of smaller digits) and block-local ones
+  uint32_t ghs = 0u;
+#pragma unroll
+  for (int c = 0; c < kHistCopies; ++c) ghs += gh[c];
+  uint32_t gtotal, ltotal, wtotal;
+  const uint32_t gstart = block_excl_scan256(ghs, s_w, gtotal);
   const uint32_t lstart = block_excl_scan256(tot, s_w, ltotal);
   s_glob[tid] = gstart + excl;
   s_loc[tid] = lstart;
+  if (kWeighted) s_wglob[tid] = block_excl_scan256(wh, s_w, wtotal) + wexcl;
+  if (a.kept_out && blk == 0 && tid == 0) *a.kept_out = gtotal;  // the keys this sort keeps
   __syncthreads();
 
   // reorder by digit in LDS, then write contiguous runs
 #pragma unroll
   for (int sl = 0; sl < kPer; ++sl) {
     if ((act >> sl) & 1u) {
-      const uint32_t d = (key[sl] >> shift) & dmask;
+      const uint32_t d = (key[sl] >> a.shift) & a.dmask;
       const uint32_t lp = s_loc[d] + s_cnt[w][d] + rank[sl];
       s_key[lp] = key[sl];
       s_val[lp] = val[sl];
+      if (kWeighted) s_wt[lp] = wt[sl];
     }
   }
   __syncthreads();
+  if (kWeighted) {
+    // exclusive prefix of the weights in the block's sorted order (in place;
+    // thread t scans kPer consecutive positions)
+    uint32_t v[kPer], s = 0u;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t i = (uint32_t)(tid * kPer + k);
+      v[k] = i < ltotal ? s_wt[i] : 0u;
+      s += v[k];
+    }
+    uint32_t wt_total;
+    uint32_t run = block_excl_scan256(s, s_w, wt_total);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t i = (uint32_t)(tid * kPer + k);
+      if (i < ltotal) s_wt[i] = run;
+      run += v[k];
+    }
+    __syncthreads();
+  }
   for (uint32_t i = tid; i < ltotal; i += kBlock) {
     const uint32_t k = s_key[i];
-    const uint32_t d = (k >> shift) & dmask;
+    const uint32_t d = (k >> a.shift) & a.dmask;
     const uint32_t g = s_glob[d] + (i - s_loc[d]);
-    keys_out[g] = k;
-    vals_out[g] = s_val[i];
+    if (a.keys_out) a.keys_out[g] = k;
+    a.vals_out[g] = s_val[i];
+    if (kWeighted) a.wout[g] = s_wglob[d] + (s_wt[i] - s_wt[s_loc[d]]);
   }
 }
-
-// Partial digit histograms filled by a producer kernel: kHistCopies copies
-// (block b adds to copy b % kHistCopies), each with 256 words per pass for
-// up to kHistPasses passes and the count of kept keys at kHistKept.
-constexpr int kHistCopies = 64;
-constexpr int kHistPasses = 2;
-constexpr int kHistKept = 256 * kHistPasses;
-constexpr int kHistStride = kHistKept + 8;
 
 int hist_parts_words() { return kHistCopies * kHistStride; }
 
-// Writes the sort's work head and first status table: the pass histograms
-// summed over the copies, zero elsewhere; *kept = the summed kept count.
-__global__ __launch_bounds__(kBlock) void hist_prepare_kernel(uint32_t* __restrict__ work, int64_t nwords,
-                                                              const uint32_t* __restrict__ hparts, int npass,
-                                                              unsigned long long* __restrict__ kept) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= nwords) return;
-  uint32_t v = 0u;
-  if (i < 256 * npass) {
-    for (int c = 0; c < kHistCopies; ++c) v += hparts[c * kHistStride + i];
-  }
-  work[i] = v;
-  if (i == 0 && kept) {
-    unsigned long long k = 0;
-    for (int c = 0; c < kHistCopies; ++c) k += hparts[c * kHistStride + kHistKept];
-    *kept = k;
-  }
-}
-
 // ------------------------------------------------------------ expansion --
 
-__global__ __launch_bounds__(kBlock) void gather_counts_kernel(const uint32_t* __restrict__ items, int64_t m_cap,
-                                                               const unsigned long long* __restrict__ dyn,
-                                                               const uint32_t* __restrict__ counts,
-                                                               uint32_t* __restrict__ out) {
-  const int64_t m = dyn_count(m_cap, dyn);
-  int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j < m) out[j] = counts[items[j]];
-  else if (j < m_cap) out[j] = 0u;
-}
-
 constexpr int kExpandPer = 8;
+constexpr int kExpandSpan = kBlock * kExpandPer;  // entries per expansion block
+constexpr int kConeStride = 5;                    // float4 per tile in the cull's table
+constexpr int kWaveSlots = kExpandSpan / 4 + kExpandSpan / 128;  // staging slots of one wave
 
-// Corner directions of every 16x16 tile of every view (the expansion's
-// culling cone), four float4 per tile: corner k in .xyz of entry k, the
-// cone's validity in .w of entry 0.
+// Cone of every 16x16 tile of every view for the expansion's cull,
+// kConeStride float4 per tile: corner direction k in .xyz of entry k and the
+// cone's validity in .w of entry 0; entry 4 holds a centre direction c and a
+// radius rho with |d - c| <= rho for every ray d of the tile (rho = -1 when
+// the corners do not span the tile's rays, or rho would exceed 1).  The
+// corners span the tile's rays, and the cap of angular radius
+// max_k angle(c, corner k) < 90 degrees around c holds them and so their
+// spherical hull; rho is rounded up.
 __global__ __launch_bounds__(kBlock) void tile_cones_kernel(const ViewDev* __restrict__ views, int nviews,
                                                             const float2* __restrict__ dtab, int64_t ntiles,
                                                             float4* __restrict__ out, uint32_t* __restrict__ zero,
@@ -510,7 +497,25 @@ __global__ __launch_bounds__(kBlock) void tile_cones_kernel(const ViewDev* __res
   const QuadCone Q = block_cone(V, dtab, tx * kTile, ty * kTile, kTile);
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    out[4 * t + k] = make_float4(Q.d[k][0], Q.d[k][1], Q.d[k][2], k == 0 ? (Q.valid ? 1.0f : 0.0f) : 0.0f);
+    out[kConeStride * t + k] =
+        make_float4(Q.d[k][0], Q.d[k][1], Q.d[k][2], k == 0 ? (Q.valid ? 1.0f : 0.0f) : 0.0f);
+  float c[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) c[i] = (Q.d[0][i] + Q.d[1][i]) + (Q.d[2][i] + Q.d[3][i]);
+  const float cn = sqrtf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  float rho = -1.0f;
+  if (Q.valid && cn > 0.0f) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) c[i] = c[i] / cn;
+    rho = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float dx = Q.d[k][0] - c[0], dy = Q.d[k][1] - c[1], dz = Q.d[k][2] - c[2];
+      rho = fmaxf(rho, sqrtf(dx * dx + dy * dy + dz * dz));
+    }
+    rho = rho < 1.0f ? fmaf(rho, 0x1p-10f, rho) + 0x1p-20f : -1.0f;
+  }
+  out[kConeStride * t + 4] = make_float4(c[0], c[1], c[2], rho);
 }
 
 // floor(a / b), exact, for 0 < b and a quotient below 2^20 (here: a view
@@ -550,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
                                                         uint32_t* __restrict__ tiles_out,
                                                         uint32_t* __restrict__ items_out,
                                                         uint32_t* __restrict__ hparts, int hpass, int hbits) {
-  constexpr int kSpan = kBlock * kExpandPer;
+  constexpr int kSpan = kExpandSpan;
   const int64_t m = dyn_count(m_cap, dyn_m);
   const int64_t total = dyn_count(total_cap, dyn_total);
   const int64_t block0 = (int64_t)blockIdx.x * kSpan;
@@ -558,13 +563,12 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   __shared__ uint32_t s_tile[kSpan + kSpan / 32];  // slots spread by stage_slot
   __shared__ uint32_t s_item[kSpan + kSpan / 32];
   __shared__ uint32_t s_offs[kSpan + 1];  // offs[jlo + k]; past the last owner: 0xffffffff
+  __shared__ uint8_t s_keep[kSpan];        // verdicts of the exact cull test, per wave
   __shared__ uint32_t s_h[kHistPasses][256];  // this block's digit counts of the kept tile ids
-  __shared__ uint32_t s_kept;
   __shared__ int64_t s_jlo;
   if (hpass) {
 #pragma unroll
     for (int p = 0; p < kHistPasses; ++p) s_h[p][threadIdx.x] = 0u;
-    if (threadIdx.x == 0) s_kept = 0u;
   }
   if (threadIdx.x < 64) {
     // owner of block0 (last j with offs[j] <= block0) in [lo, hi): each round
@@ -587,14 +591,16 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   for (int k = threadIdx.x; k < kSpan + 1; k += kBlock) s_offs[k] = k < S ? offs[jlo + k] : 0xffffffffu;
   __syncthreads();
 
-  uint32_t my_kept = 0u, run_d = 0u, run_n = 0u;  // run of equal upper digits along this lane's entries
+  uint32_t run_d = 0u, run_n = 0u;  // run of equal upper digits along this lane's entries
   const int64_t e0 = block0 + (int64_t)threadIdx.x * kExpandPer;
   const bool fixed = op.lambda_mode == 1;
-  if (e0 < total) {
-    const int cnt = (int)min<int64_t>(kExpandPer, total - e0);
+  // every lane of the block goes through the cull (its wave-wide queue);
+  // lanes past the end have no entries
+  const int cnt = e0 < total ? (int)min<int64_t>(kExpandPer, total - e0) : 0;
+  {
     // local owner of e0: last k with s_offs[k] <= e0; it is at most
     // e0 - block0, since every owner covers at least one entry
-    int lo = 0, hi = (int)min<int64_t>(S, (int64_t)threadIdx.x * kExpandPer + 1);
+    int lo = 0, hi = cnt > 0 ? (int)min<int64_t>(S, (int64_t)threadIdx.x * kExpandPer + 1) : 0;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if ((int64_t)s_offs[mid] <= e0) lo = mid; else hi = mid;
@@ -634,31 +640,101 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
       }
     }
     if (cull) {
-      // the cone of entry k + 1 is loaded while entry k is tested
-      float4 c0 = tcones[4 * (size_t)tile[0]], c1 = tcones[4 * (size_t)tile[0] + 1];
-      float4 c2 = tcones[4 * (size_t)tile[0] + 2], c3 = tcones[4 * (size_t)tile[0] + 3];
-      const float4* rp = reinterpret_cast<const float4*>(recs + item[0]);
-      float4 p0 = rp[0], p1 = rp[1], p2 = rp[2], p3 = rp[3];
+      // (1) Every entry: a cheap conservative verdict from the tile's centre
+      // ray.  With g = G d and h(d) = |g_xy| - tau g_z, a ray contributes only
+      // if h(d) <= 0, and |h(d) - h(c)| <= L |d - c| with
+      // L = (1 + tau) |G|_F; so h(c) > L rho means no ray of the tile
+      // contributes.  The margin 2^-16 L covers the FP32 rounding of h(c)
+      // (about 2^-20 L) and of the tables' directions.  Entries it cannot
+      // settle go to (2).
+      float4 cr[kExpandPer];
+#pragma unroll
+      for (int k = 0; k < kExpandPer; ++k)
+        cr[k] = k < cnt ? tcones[kConeStride * (size_t)tile[k] + 4] : make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+      uint32_t survive = 0u, cur = 0xffffffffu;
+      int cls = 0;  // the item's verdict: 0 no ray reaches alpha_min, 1 every tile kept, 2 per tile
+      float G[9] = {}, tau = 0.0f, lip = 0.0f;
 #pragma unroll
       for (int k = 0; k < kExpandPer; ++k) {
         if (k >= cnt) break;
-        float4 n0 = c0, n1 = c1, n2 = c2, n3 = c3;
-        if (k + 1 < cnt) {
-          const float4* cp = tcones + 4 * (size_t)tile[k + 1];
-          n0 = cp[0]; n1 = cp[1]; n2 = cp[2]; n3 = cp[3];
+        if (item[k] != cur) {
+          cur = item[k];
+          const float4* rp = reinterpret_cast<const float4*>(recs + cur);
+          const float4 p0 = rp[0], p1 = rp[1], p2 = rp[2], p3 = rp[3];
+          G[0] = p0.x; G[1] = p0.y; G[2] = p0.z; G[3] = p0.w;
+          G[4] = p1.x; G[5] = p1.y; G[6] = p1.z; G[7] = p1.w; G[8] = p2.x;
+          // the contribution threshold of the exact test, with its margins
+          float Qc = (p2.z - op.log2_amin) * __builtin_amdgcn_rcpf(-p2.y);
+          if (fixed) Qc = fminf(Qc, p3.w);
+          Qc = fmaf(Qc, 0x1p-8f, Qc) + 0x1p-20f;
+          cls = !(Qc > 0.0f) ? 0 : Qc >= 1.0f ? 1 : 2;
+          if (cls == 2) {
+            tau = __builtin_sqrtf(Qc * __builtin_amdgcn_rcpf(1.0f - Qc));
+            float gg = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) gg = fmaf(G[i], G[i], gg);
+            lip = (1.0f + tau) * __builtin_sqrtf(gg);
+          }
         }
-        if (k > 0 && item[k] != item[k - 1]) {
-          const float4* rq = reinterpret_cast<const float4*>(recs + item[k]);
-          p0 = rq[0]; p1 = rq[1]; p2 = rq[2]; p3 = rq[3];
+        if (cls == 0) {
+          tile[k] = kDropKey;
+          continue;
         }
-        QuadCone Q;
-        Q.d[0][0] = c0.x; Q.d[0][1] = c0.y; Q.d[0][2] = c0.z;
-        Q.d[1][0] = c1.x; Q.d[1][1] = c1.y; Q.d[1][2] = c1.z;
-        Q.d[2][0] = c2.x; Q.d[2][1] = c2.y; Q.d[2][2] = c2.z;
-        Q.d[3][0] = c3.x; Q.d[3][1] = c3.y; Q.d[3][2] = c3.z;
-        Q.valid = c0.w != 0.0f;
-        if (!cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, fixed)) tile[k] = kDropKey;
-        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        if (cls == 1 || !(cr[k].w >= 0.0f)) continue;  // kept, as by the exact test
+        const float gx = fmaf(G[2], cr[k].z, fmaf(G[1], cr[k].y, G[0] * cr[k].x));
+        const float gy = fmaf(G[5], cr[k].z, fmaf(G[4], cr[k].y, G[3] * cr[k].x));
+        const float gz = fmaf(G[8], cr[k].z, fmaf(G[7], cr[k].y, G[6] * cr[k].x));
+        const float hc = __builtin_sqrtf(fmaf(gx, gx, gy * gy)) - tau * gz;
+        if (hc > lip * (cr[k].w + 0x1p-16f)) tile[k] = kDropKey;
+        else survive |= 1u << k;
+      }
+      // (2) The exact quad test of the entries (1) left open, compacted over
+      // the wave so that every lane tests one: the wave's open entries are
+      // queued in its staging slots, tested 64 at a time, and each verdict is
+      // read back by the entry's lane.
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      const uint32_t mine = (uint32_t)__popc(survive);
+      const uint32_t incl = wave_incl_scan(mine);
+      const uint32_t nq = __shfl(incl, 63);
+      uint32_t* const qt = s_tile + wv * kWaveSlots;
+      uint32_t* const qi = s_item + wv * kWaveSlots;
+      uint8_t* const qk = s_keep + wv * (kExpandSpan / 4);
+      uint32_t pos = incl - mine;
+#pragma unroll
+      for (int k = 0; k < kExpandPer; ++k) {
+        if (!((survive >> k) & 1u)) continue;
+        qt[pos] = tile[k];
+        qi[pos] = item[k];
+        ++pos;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (uint32_t r = 0; r < nq; r += 64) {  // nq is uniform over the wave
+        const uint32_t q = r + (uint32_t)lane;
+        if (q < nq) {
+          const float4* cp = tcones + kConeStride * (size_t)qt[q];
+          const float4* rq = reinterpret_cast<const float4*>(recs + qi[q]);
+          const float4 c0 = cp[0], c1 = cp[1], c2 = cp[2], c3 = cp[3];
+          const float4 p0 = rq[0], p1 = rq[1], p2 = rq[2], p3 = rq[3];
+          QuadCone Q;
+          Q.d[0][0] = c0.x; Q.d[0][1] = c0.y; Q.d[0][2] = c0.z;
+          Q.d[1][0] = c1.x; Q.d[1][1] = c1.y; Q.d[1][2] = c1.z;
+          Q.d[2][0] = c2.x; Q.d[2][1] = c2.y; Q.d[2][2] = c2.z;
+          Q.d[3][0] = c3.x; Q.d[3][1] = c3.y; Q.d[3][2] = c3.z;
+          Q.valid = c0.w != 0.0f;
+          qk[q] = cone_meets_quad(p0, p1, p2, p3, Q, op.log2_amin, fixed) ? 1 : 0;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      pos = incl - mine;
+#pragma unroll
+      for (int k = 0; k < kExpandPer; ++k) {
+        if (!((survive >> k) & 1u)) continue;
+        if (!qk[pos]) tile[k] = kDropKey;
+        ++pos;
       }
     }
 #pragma unroll
@@ -666,7 +742,6 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
       if (k >= cnt) break;
       const uint32_t t = tile[k];
       if (hpass && t != kDropKey) {
-        ++my_kept;
         atomicAdd(&s_h[0][t & ((1u << hbits) - 1u)], 1u);
         if (hpass > 1) {
           const uint32_t d1 = t >> hbits;  // a kept tile id has at most 2 hbits bits
@@ -683,10 +758,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
       s_item[sl] = item[k];
     }
   }
-  if (hpass) {
-    if (run_n) atomicAdd(&s_h[1][run_d], run_n);
-    if (my_kept) atomicAdd(&s_kept, my_kept);
-  }
+  if (hpass && run_n) atomicAdd(&s_h[1][run_d], run_n);
   __syncthreads();
   if (hpass) {
     uint32_t* hp = hparts + (blockIdx.x % kHistCopies) * kHistStride;
@@ -694,7 +766,6 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
       const uint32_t c = s_h[p][threadIdx.x];
       if (c) atomicAdd(&hp[p * 256 + threadIdx.x], c);
     }
-    if (threadIdx.x == 0 && s_kept) atomicAdd(&hp[kHistKept], s_kept);
   }
 #pragma unroll
   for (int k = 0; k < kExpandPer; ++k) {
@@ -788,87 +859,149 @@ void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n
                      out);
 }
 
-// Workspace of radix_sort, in u32 words: histograms, then two
-// status tables of 256 words per 2048-key block.
-int64_t radix_work_words(int64_t n_cap) { return kWorkHead + 2 * 256 * ((n_cap + kOSItems - 1) / kOSItems); }
+// Depth order of the visible items: an upsweep (digit counts of the four
+// passes and the count-weighted counts of the last) and four passes.  Pass 0
+// compacts the items with counts[i] != 0 out of all n0 items; passes 1 to 3
+// read the live visible count (dyn1, or n1_cap).  Work layout (u32 words):
+// the head, status table 0 (passes 0 and 2), status table 1 (pass 1, then the
+// 64-bit rows of pass 3).
+static int64_t depth_blocks(int64_t n0) { return os_blocks(n0, kBlock * os_per(n0)); }
 
-// Stable sort of n0 keys (filtered; values = in_v, or the key index when
-// in_v is null) by npass 8-bit digits from bit shift0.  Pass 0 reads (in_k,
-// in_v) with the n0 count, the filter and (with drop) leaves out kDropKey
-// keys, counting the rest into *kept when given; later passes read n1 keys
-// (the filtered count, read on the device when dyn1 is given).  Passes write
-// A, B, A, ...: the result is in A for odd npass, in B for even.
-int64_t radix_zero_words(int64_t nmax) {
-  const int items = kBlock * os_per(nmax);
-  return kWorkHead + 256 * os_blocks(nmax, items);
+int64_t depth_work_words(int64_t n0) { return kWorkHead + 3 * 256 * depth_blocks(std::max<int64_t>(n0, 1)); }
+
+int64_t depth_zero_words(int64_t n0) { return kWorkHead + 256 * depth_blocks(std::max<int64_t>(n0, 1)); }
+
+void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, int64_t n0, int64_t n1_cap,
+                 const unsigned long long* dyn1, uint32_t* work, bool zeroed, uint32_t* ka, uint32_t* va,
+                 uint32_t* kb, uint32_t* vb, uint32_t* offs, unsigned long long* err) {
+  if (n0 <= 0 || n1_cap <= 0) return;
+  const int per = os_per(n0);
+  const int items = kBlock * per;
+  const int64_t nb0 = os_blocks(n0, items), nb1 = std::max<int64_t>(os_blocks(n1_cap, items), 1);
+  uint32_t* ghist = work;
+  uint32_t* whist = work + 4 * 256;
+  uint32_t* t0 = work + kWorkHead;
+  uint32_t* t1 = t0 + 256 * nb0;
+  if (!zeroed)
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(depth_zero_words(n0), kBlock)), dim3(kBlock), 0, st, work,
+                       depth_zero_words(n0), 0u);
+  const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(n0, kBlock), 1), 256);
+  hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, keys, counts, 0, n0,
+                     (const unsigned long long*)nullptr, 0, 8, 4, ghist, whist);
+  auto plain = per == kOSPerBig ? radix_pass_kernel<kOSPerBig, false>
+               : per == kOSPer  ? radix_pass_kernel<kOSPer, false>
+                                : radix_pass_kernel<kOSPerSmall, false>;
+  auto weighted = per == kOSPerBig ? radix_pass_kernel<kOSPerBig, true>
+                  : per == kOSPer  ? radix_pass_kernel<kOSPer, true>
+                                   : radix_pass_kernel<kOSPerSmall, true>;
+  PassArgs p{};
+  p.hcopies = 1;
+  p.dmask = 255u;
+  p.next_row_words = 256;
+  p.err = err;
+  // pass 0: all items, the visible ones out (value = item index)
+  p.keys_in = keys;
+  p.filter = counts;
+  p.n_cap = n0;
+  p.ghist = ghist;
+  p.status = t0;
+  p.status_next = t1;
+  p.keys_out = ka;
+  p.vals_out = va;
+  hipLaunchKernelGGL(plain, dim3((unsigned)nb0), dim3(kBlock), 0, st, p);
+  // passes 1 and 2 over the visible items: (ka, va) -> (kb, vb) -> (ka, va)
+  p.filter = nullptr;
+  p.n_cap = n1_cap;
+  p.dyn = dyn1;
+  for (int q = 1; q <= 2; ++q) {
+    p.keys_in = q == 1 ? ka : kb;
+    p.vals_in = q == 1 ? va : vb;
+    p.shift = 8 * q;
+    p.ghist = ghist + 256 * q;
+    p.status = q == 1 ? t1 : t0;
+    p.status_next = q == 1 ? t0 : t1;
+    p.next_row_words = q == 1 ? 256 : 512;  // pass 3's rows are 64-bit
+    p.keys_out = q == 1 ? kb : ka;
+    p.vals_out = q == 1 ? vb : va;
+    hipLaunchKernelGGL(plain, dim3((unsigned)nb1), dim3(kBlock), 0, st, p);
+  }
+  // pass 3, weighted by the tile counts: items in depth order to vb, their
+  // entry offsets to offs
+  p.keys_in = ka;
+  p.vals_in = va;
+  p.shift = 24;
+  p.ghist = ghist + 3 * 256;
+  p.whist = whist;
+  p.wts = counts;
+  p.status = t1;
+  p.status_next = nullptr;
+  p.keys_out = nullptr;
+  p.vals_out = vb;
+  p.wout = offs;
+  hipLaunchKernelGGL(weighted, dim3((unsigned)nb1), dim3(kBlock), 0, st, p);
 }
 
-void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, bool drop,
-                int64_t n0_cap, const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1,
-                int shift0, int npass, uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work,
-                unsigned long long* kept, unsigned long long* err, const uint32_t* hparts, int bits, bool zeroed) {
-  if (n0_cap <= 0 || npass <= 0) return;
-  const int64_t nmax = std::max(n0_cap, n1_cap);
-  const int per = os_per(nmax);  // chunk size by sort size
-  const int items = kBlock * per;
-  const int64_t rows = 256 * os_blocks(nmax, items);
-  const uint32_t dmask = (1u << bits) - 1u;
-  uint32_t* ghist = work;
-  uint32_t* stat[2] = {work + kWorkHead, work + kWorkHead + rows};
-  if (hparts) {
-    // the producer already counted the digits into partial histograms:
-    // sum them into the histograms, clear the first status table
-    hipLaunchKernelGGL(hist_prepare_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
-                       (int64_t)kWorkHead + rows, hparts, npass, kept);
-  } else {
-    // histograms and the first status table start at zero
-    if (!zeroed)
-      hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(kWorkHead + rows, kBlock)), dim3(kBlock), 0, st, work,
-                         (int64_t)kWorkHead + rows, 0u);
-    // few blocks: every block adds its counts to the same 256 words per pass
-    const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(n0_cap, kBlock), 1), 256);
-    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, in_k, filter, drop ? 1 : 0, n0_cap,
-                       dyn0, shift0, bits, npass, ghist, kept);
+// Work of the expansion and the tile sort, u32 words: the expansion's partial
+// histograms, the sort's head (digit counts when an upsweep counts them) and
+// two status tables.  The first three parts must start at zero.
+static int64_t tile_rows(int64_t ecap) {
+  ecap = std::max<int64_t>(ecap, 1);
+  return 256 * os_blocks(ecap, kBlock * os_per(ecap));
+}
+
+int64_t tile_zero_words(int64_t ecap) { return hist_parts_words() + kWorkHead + tile_rows(ecap); }
+
+int64_t tile_work_words(int64_t ecap) { return tile_zero_words(ecap) + tile_rows(ecap); }
+
+void tile_sort(hipStream_t st, const uint32_t* tin, const uint32_t* iin, int64_t ecap,
+               const unsigned long long* dE, unsigned long long* kept, int passes, int bits, uint32_t* at,
+               uint32_t* ai, uint32_t* bt, uint32_t* bi, uint32_t* twork, int hpass, unsigned long long* err) {
+  if (ecap <= 0 || passes <= 0) return;
+  const int per = os_per(ecap);
+  const unsigned nb = (unsigned)std::max<int64_t>(os_blocks(ecap, kBlock * per), 1);
+  uint32_t* hparts = twork;
+  uint32_t* head = hparts + hist_parts_words();
+  uint32_t* t0 = head + kWorkHead;
+  uint32_t* t1 = t0 + tile_rows(ecap);
+  if (!hpass) {
+    const unsigned ug = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(ecap, kBlock), 1), 256);
+    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(ug), dim3(kBlock), 0, st, tin, (const uint32_t*)nullptr, 1, ecap,
+                       dE, 0, bits, passes, head, (uint32_t*)nullptr);
   }
-  const uint32_t *sk = in_k, *sv = in_v;
-  for (int p = 0; p < npass; ++p) {
-    uint32_t* ok = (p % 2 == 0) ? ak : bk;
-    uint32_t* ov = (p % 2 == 0) ? av : bv;
-    const int64_t ncap = p == 0 ? n0_cap : n1_cap;
-    const unsigned long long* dy = p == 0 ? dyn0 : dyn1;
-    const unsigned nb = (unsigned)std::max<int64_t>(os_blocks(ncap, items), 1);
-    auto kern = per == kOSPerBig ? radix_onesweep_kernel<kOSPerBig>
-                : per == kOSPer      ? radix_onesweep_kernel<kOSPer>
-                                     : radix_onesweep_kernel<kOSPerSmall>;
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, sk, sv, p == 0 ? filter : nullptr, (p == 0 && drop) ? 1 : 0,
-                       ncap, dy, shift0 + bits * p, dmask, (const uint32_t*)(ghist + 256 * p), stat[p % 2],
-                       p + 1 < npass ? stat[(p + 1) % 2] : nullptr, ok, ov, err);
+  auto kern = per == kOSPerBig ? radix_pass_kernel<kOSPerBig, false>
+              : per == kOSPer  ? radix_pass_kernel<kOSPer, false>
+                               : radix_pass_kernel<kOSPerSmall, false>;
+  PassArgs p{};
+  p.n_cap = ecap;
+  p.dmask = (1u << bits) - 1u;
+  p.hstride = kHistStride;
+  p.hcopies = hpass ? kHistCopies : 1;
+  p.next_row_words = 256;
+  p.err = err;
+  const uint32_t *sk = tin, *sv = iin;
+  for (int q = 0; q < passes; ++q) {
+    uint32_t* ok = (q % 2 == 0) ? at : bt;
+    uint32_t* ov = (q % 2 == 0) ? ai : bi;
+    // pass 0 reads the whole list and leaves the culled entries out, counting
+    // the kept ones into *kept; later passes read those
+    p.dyn = q == 0 ? dE : kept;
+    p.drop = q == 0 ? 1 : 0;
+    p.kept_out = q == 0 ? kept : nullptr;
+    p.keys_in = sk;
+    p.vals_in = sv;
+    p.shift = bits * q;
+    p.ghist = (hpass ? hparts : head) + 256 * q;
+    p.status = (q % 2 == 0) ? t0 : t1;
+    p.status_next = q + 1 < passes ? ((q % 2 == 0) ? t1 : t0) : nullptr;
+    p.keys_out = ok;
+    p.vals_out = ov;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, p);
     sk = ok;
     sv = ov;
   }
 }
 
-void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
-                          const uint32_t* counts, uint32_t* out) {
-  if (m_cap <= 0) return;
-  hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(m_cap, kBlock)), dim3(kBlock), 0, st, items, m_cap, dyn,
-                     counts, out);
-}
-
-void gather_scan(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
-                 const uint32_t* counts, uint32_t* out, uint32_t* scratch) {
-  if (m_cap <= 0) return;
-  const int64_t nb = (m_cap + kTileItems - 1) / kTileItems;
-  if (nb > kGatherScanTiles) {
-    launch_gather_counts(st, items, m_cap, dyn, counts, out);
-    scan_exclusive(st, out, out, m_cap, scratch);
-    return;
-  }
-  hipLaunchKernelGGL(gather_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, items, m_cap, dyn, counts, out,
-                     scratch);
-  hipLaunchKernelGGL(nb >= 64 ? gathered_scan_kernel<true> : gathered_scan_kernel<false>, dim3((unsigned)nb),
-                     dim3(kBlock), 0, st, out, m_cap, (const uint32_t*)scratch, out);
-}
+size_t tile_cone_bytes(int64_t ntiles) { return sizeof(float4) * kConeStride * (size_t)std::max<int64_t>(ntiles, 1); }
 
 void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,
                        float4* out, uint32_t* zero, int64_t nzero) {
@@ -880,12 +1013,12 @@ void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const f
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
-                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* hparts, int hpass,
+                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* twork, int hpass,
                    int hbits) {
   if (total_cap <= 0) return;
-  hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total_cap, (int64_t)kBlock * kExpandPer)), dim3(kBlock), 0, st,
-                     items, offs, m_cap, dyn_m, total_cap, dyn_total, rects, views, n, tcones, recs, op,
-                     op.cone_cull, tiles_out, items_out, hparts, hpass, hbits);
+  hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total_cap, kExpandSpan)), dim3(kBlock), 0, st, items, offs, m_cap,
+                     dyn_m, total_cap, dyn_total, rects, views, n, tcones, recs, op, op.cone_cull, tiles_out,
+                     items_out, twork, hpass, hbits);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,

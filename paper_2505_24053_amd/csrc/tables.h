@@ -40,28 +40,42 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
 // sort.hip
 int64_t scan_scratch_words(int64_t n);
 void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch);
-int64_t radix_work_words(int64_t n_cap);
-void radix_sort(hipStream_t st, const uint32_t* in_k, const uint32_t* in_v, const uint32_t* filter, bool drop,
-                int64_t n0_cap, const unsigned long long* dyn0, int64_t n1_cap, const unsigned long long* dyn1,
-                int shift0, int npass, uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint32_t* work,
-                unsigned long long* kept, unsigned long long* err,
-                const uint32_t* hparts = nullptr, int bits = 8, bool zeroed = false);
-// Words of a sort's work area (for up to nmax keys) that must start at zero;
-// radix_sort(..., zeroed = true) expects them cleared already.
-int64_t radix_zero_words(int64_t nmax);
-void launch_gather_counts(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
-                          const uint32_t* counts, uint32_t* out);
-// out = exclusive scan of counts[items[j]] (j < live count, 0 up to m_cap);
-// scratch: scan_scratch_words(m_cap) words
-void gather_scan(hipStream_t st, const uint32_t* items, int64_t m_cap, const unsigned long long* dyn,
-                 const uint32_t* counts, uint32_t* out, uint32_t* scratch);
-// also zero[0 .. nzero) = 0
+// Depth order of the visible items (four 8-bit passes over the depth keys;
+// pass 0 keeps items with counts[i] != 0 out of all n0 items, later passes
+// read the live visible count dyn1, or n1_cap): the items in depth order end
+// in vb, offs[j] = exclusive prefix of their tile counts.  work:
+// depth_work_words(n0) words whose first depth_zero_words(n0) are zero unless
+// `zeroed` is false (then the call clears them).
+int64_t depth_work_words(int64_t n0);
+int64_t depth_zero_words(int64_t n0);
+void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, int64_t n0, int64_t n1_cap,
+                 const unsigned long long* dyn1, uint32_t* work, bool zeroed, uint32_t* ka, uint32_t* va,
+                 uint32_t* kb, uint32_t* vb, uint32_t* offs, unsigned long long* err);
+// Work of the expansion and the tile sort for up to ecap entries:
+// tile_work_words(ecap) words whose first tile_zero_words(ecap) must be zero
+// before the expansion.
+int64_t tile_work_words(int64_t ecap);
+int64_t tile_zero_words(int64_t ecap);
+// Stable sort of the entries (tile ids tin, items iin; the live count dE, or
+// ecap) by `passes` digits of `bits` bits, leaving out the entries the
+// expansion marked as culled; the number kept goes to *kept.  Passes write
+// (at, ai), (bt, bi), (at, ai), ...  With hpass, the expansion counted the
+// digits of the first hpass passes into twork.
+void tile_sort(hipStream_t st, const uint32_t* tin, const uint32_t* iin, int64_t ecap,
+               const unsigned long long* dE, unsigned long long* kept, int passes, int bits, uint32_t* at,
+               uint32_t* ai, uint32_t* bt, uint32_t* bi, uint32_t* twork, int hpass, unsigned long long* err);
+// Bytes of the expansion's per-tile cull table; its launch also sets
+// zero[0 .. nzero) = 0.
+size_t tile_cone_bytes(int64_t ntiles);
 void launch_tile_cones(hipStream_t st, const ViewDev* views, int nviews, const float2* dtab, int64_t ntiles,
                        float4* out, uint32_t* zero, int64_t nzero);
+// Expansion of the depth-ordered items into their tile entries in depth
+// order; the culled ones get the tile id 0xffffffff.  With hpass, the kept
+// entries' tile digits are counted into the partial histograms of twork.
 void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, int64_t m_cap,
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
-                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* hparts, int hpass,
+                   const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* twork, int hpass,
                    int hbits);
 int hist_parts_words();
 // with list: also zeroes the 8 words of padding after the list
