@@ -5,7 +5,7 @@
 //      items, the last also writes the exclusive scan of the items' tile
 //      counts in depth order (the entry offsets);
 //   2. expansion of every item into (tile, item) entries in depth order,
-//      balanced over entries (8 per lane; owners found through LDS), with
+//      balanced over entries (4 per lane; owners found through LDS), with
 //      the contribution-cone cull marking the entries no ray can see;
 //   3. stable LSD radix sort of the entries by global tile id, so each tile's
 //      run stays in (depth key, item) order; the first pass leaves out the
@@ -469,7 +469,7 @@ int hist_parts_words() { return kHistCopies * kHistStride; }
 
 // ------------------------------------------------------------ expansion --
 
-constexpr int kExpandPer = 8;
+constexpr int kExpandPer = 4;
 constexpr int kExpandSpan = kBlock * kExpandPer;  // entries per expansion block
 constexpr int kConeStride = 5;                    // float4 per tile in the cull's table
 constexpr int kWaveSlots = kExpandSpan / 4 + kExpandSpan / 128;  // staging slots of one wave
@@ -534,15 +534,16 @@ __device__ __forceinline__ uint32_t small_quotient(uint32_t a, uint32_t b) {
 __device__ __forceinline__ int stage_slot(int i) { return i + (i >> 5); }
 
 // Each lane expands kExpandPer consecutive entries; the block stages its
-// 2048 entries in LDS and writes them back lane-striped so every store is
+// 1024 entries in LDS and writes them back lane-striped so every store is
 // coalesced.  With `cull`, an entry whose Gaussian's contribution cone meets
 // no ray of its tile gets the tile id kDropKey and is left out by the tile
-// sort.  Latency: one wave finds the owner of the block's first entry with a
-// 64-way search (a few dependent loads instead of ~log2 m), the owners'
-// offsets that can start inside the block are staged in LDS, where each lane
-// finds and walks its owners; the tile ids of all the lane's entries are
-// derived first, so each entry's tile cone is loaded one entry ahead of its
-// test.
+// sort.  The kernel is bound by chains of dependent loads, so blocks are
+// small (many waves in flight) and the chains short: one wave finds the
+// owner of the block's first entry with a 64-way search (a few dependent
+// loads instead of ~log2 m); the offsets and items of the owners that can
+// start inside the block are staged in LDS, where each lane finds and walks
+// its owners; the tile ids of all the lane's entries are derived first, so
+// their cull data are loaded together.
 __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restrict__ items,
                                                         const uint32_t* __restrict__ offs, int64_t m_cap,
                                                         const unsigned long long* __restrict__ dyn_m,
@@ -563,6 +564,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   __shared__ uint32_t s_tile[kSpan + kSpan / 32];  // slots spread by stage_slot
   __shared__ uint32_t s_item[kSpan + kSpan / 32];
   __shared__ uint32_t s_offs[kSpan + 1];  // offs[jlo + k]; past the last owner: 0xffffffff
+  __shared__ uint32_t s_own[kSpan + 1];   // items[jlo + k]
   __shared__ uint8_t s_keep[kSpan];        // verdicts of the exact cull test, per wave
   __shared__ uint32_t s_h[kHistPasses][256];  // this block's digit counts of the kept tile ids
   __shared__ int64_t s_jlo;
@@ -588,7 +590,10 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   // every owner of an entry of the block is one of jlo .. jlo + kSpan - 1
   const int64_t jlo = s_jlo;
   const int64_t S = min<int64_t>(kSpan + 1, m - jlo);
-  for (int k = threadIdx.x; k < kSpan + 1; k += kBlock) s_offs[k] = k < S ? offs[jlo + k] : 0xffffffffu;
+  for (int k = threadIdx.x; k < kSpan + 1; k += kBlock) {
+    s_offs[k] = k < S ? offs[jlo + k] : 0xffffffffu;
+    s_own[k] = k < S ? items[jlo + k] : 0u;
+  }
   __syncthreads();
 
   uint32_t run_d = 0u, run_n = 0u;  // run of equal upper digits along this lane's entries
@@ -618,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
         while ((int64_t)s_offs[jl + 1] <= e) ++jl;
         if (jl != cur) {
           cur = jl;
-          it = items[jlo + jl];
+          it = s_own[jl];
           const uint32_t local = (uint32_t)(e - (int64_t)s_offs[jl]);
           const uint2 r = rects[it];
           tx0 = (r.x & 0xffffu) >> 1;
