@@ -4,7 +4,10 @@
 // scene is read from HBM once per batch.  For every (Gaussian, view) item it
 // writes the half-tile rectangle, tile count and depth key (the association,
 // bit-exact IEEE single arithmetic in a fixed order, no contraction) and the
-// 64-byte render record (radiometric, free-form FP32).
+// 64-byte render record (radiometric, free-form FP32).  A single view gets
+// its colour in the same pass; a batch of views gets it from a second kernel
+// that reads each Gaussian's SH coefficients once per 8 views, so that the
+// association runs without the coefficients' registers.
 //
 // PBF (Sec. 3.2, App. D.1): with M = Rc R S and mu_c = Rc mu + t, a plane
 // through the camera y axis x = c z is tangent to the lambda-ellipsoid iff
@@ -48,7 +51,111 @@ __device__ __forceinline__ void block_add_totals(unsigned long long e, unsigned 
   }
 }
 
+// Views whose colour one pass of the SH coefficients serves.
+constexpr int kColourViews = 8;
+
+// The real SH basis functions of one band (degree) in direction (x, y, z),
+// the terms of that band in the full basis.  No contraction, so the values
+// do not depend on the code they are inlined into.
+template <int kBand>
+__device__ __forceinline__ void sh_band(float x, float y, float z, float B[7]) {
+#pragma clang fp contract(off)
+  if (kBand == 0) {
+    B[0] = 0.28209479177387814f;
+  } else if (kBand == 1) {
+    const float C1 = 0.4886025119029199f;
+    B[0] = -C1 * y; B[1] = C1 * z; B[2] = -C1 * x;
+  } else if (kBand == 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    B[0] = 1.0925484305920792f * x * y;
+    B[1] = -1.0925484305920792f * y * z;
+    B[2] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+    B[3] = -1.0925484305920792f * x * z;
+    B[4] = 0.5462742152960396f * (xx - yy);
+  } else {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    B[0] = -0.5900435899266435f * y * (3.0f * xx - yy);
+    B[1] = 2.890611442640554f * x * y * z;
+    B[2] = -0.4570457994644658f * y * (4.0f * zz - xx - yy);
+    B[3] = 0.3731763325901154f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    B[4] = -0.4570457994644658f * x * (4.0f * zz - xx - yy);
+    B[5] = 1.445305721320277f * z * (xx - yy);
+    B[6] = -0.5900435899266435f * x * (xx - 3.0f * yy);
+  }
+}
+
+// Adds band kBand of Gaussian g's colour in direction (x, y, z) to acc --
+// the one per-view sequence of operations of both colour paths, so that a
+// view renders the same bits alone and in a batch.
+template <int kBand, int kDeg>
+__device__ __forceinline__ void add_band(int64_t n, int64_t g, const float* __restrict__ sh, float x, float y,
+                                         float z, float acc[3]) {
+  if (kBand > kDeg) return;
+  constexpr int k0 = kBand * kBand, kn = 2 * kBand + 1;
+  float B[7];
+  sh_band<kBand>(x, y, z, B);
+#pragma unroll
+  for (int i = 0; i < kn; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = fmaf(B[i], sh[(int64_t)((k0 + i) * 3 + c) * n + g], acc[c]);
+}
+
+// Unit direction from view V's camera centre to the mean.
+__device__ __forceinline__ void view_direction(const ViewDev& V, const float mu[3], float& x, float& y, float& z) {
+#pragma clang fp contract(off)
+  const float dv[3] = {mu[0] - V.campos[0], mu[1] - V.campos[1], mu[2] - V.campos[2]};
+  const float dinv = rsqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  x = dv[0] * dinv;
+  y = dv[1] * dinv;
+  z = dv[2] * dinv;
+}
+
+// Band kBand of the colour of Gaussian g in the views v0 + vv with bit vv of
+// vis set: the band's coefficients are read once for all of them.
+template <int kBand, int kDeg>
+__device__ __forceinline__ void colour_band(int64_t n, int64_t g, const float mu[3], const float* __restrict__ sh,
+                                            const ViewDev* __restrict__ views, int v0, uint32_t vis,
+                                            float (*acc)[3]) {
+  if (kBand > kDeg) return;
+#pragma unroll
+  for (int vv = 0; vv < kColourViews; ++vv) {
+    if (!((vis >> vv) & 1u)) continue;
+    float x, y, z;
+    view_direction(views[v0 + vv], mu, x, y, z);
+    add_band<kBand, kDeg>(n, g, sh, x, y, z, acc[vv]);
+  }
+}
+
+// View-dependent colour (Eq. color's c_i: the SH expansion in the direction
+// from the camera centre to the mean, offset by 1/2 and clamped at 0) of
+// Gaussian g in the views v0 + vv with bit vv of vis set, written into their
+// records.  The coefficients are read one band at a time and each band
+// serves every view of the chunk, so they are never live beside the
+// association's state; per view the terms are added in coefficient order,
+// as a single-view evaluation would.
 template <int kDeg>
+__device__ __forceinline__ void chunk_colour(int64_t n, int64_t g, const float mu[3], const float* __restrict__ sh,
+                                             const ViewDev* __restrict__ views, int v0, uint32_t vis,
+                                             Record* __restrict__ recs) {
+  float acc[kColourViews][3];
+#pragma unroll
+  for (int vv = 0; vv < kColourViews; ++vv)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[vv][c] = 0.5f;
+  colour_band<0, kDeg>(n, g, mu, sh, views, v0, vis, acc);
+  colour_band<1, kDeg>(n, g, mu, sh, views, v0, vis, acc);
+  colour_band<2, kDeg>(n, g, mu, sh, views, v0, vis, acc);
+  colour_band<3, kDeg>(n, g, mu, sh, views, v0, vis, acc);
+#pragma unroll
+  for (int vv = 0; vv < kColourViews; ++vv) {
+    if (!((vis >> vv) & 1u)) continue;
+    Record* r = recs + (int64_t)(v0 + vv) * n + g;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r->rgb[c] = fmaxf(acc[vv][c], 0.0f);
+  }
+}
+
+template <int kDeg, bool kColour>
 __global__ __launch_bounds__(256) void preprocess_kernel(
     int64_t n, int32_t n_views, const float* __restrict__ mean, const float* __restrict__ scale,
     const float* __restrict__ quat, const float* __restrict__ opacity, const float* __restrict__ sh,
@@ -109,19 +216,21 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
       rec.lsig = __log2f(sigma);
       rec.c1 = F.r2;
       rec.qmax = op.lambda_mode == 1 ? op.kmax_fixed / F.r2 : INFINITY;
-      float dv[3] = {mu[0] - V.campos[0], mu[1] - V.campos[1], mu[2] - V.campos[2]};
-      const float dinv = rsqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-      const float vdir[3] = {dv[0] * dinv, dv[1] * dinv, dv[2] * dinv};
-      float B[16];
-      sh_basis(kDeg, vdir, B, nullptr);
-      constexpr int K = (kDeg + 1) * (kDeg + 1);
-      float acc[3] = {0.5f, 0.5f, 0.5f};
+      if (kColour) {
+        // the view-dependent colour (Eq. color's c_i): SH expansion in the
+        // direction from the camera centre to the mean, + 1/2, clamped at 0
+        float x, y, z;
+        view_direction(V, mu, x, y, z);
+        float acc[3] = {0.5f, 0.5f, 0.5f};
+        add_band<0, kDeg>(n, g, sh, x, y, z, acc);
+        add_band<1, kDeg>(n, g, sh, x, y, z, acc);
+        add_band<2, kDeg>(n, g, sh, x, y, z, acc);
+        add_band<3, kDeg>(n, g, sh, x, y, z, acc);
 #pragma unroll
-      for (int kk = 0; kk < K; ++kk)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] = fmaf(B[kk], sh[(int64_t)(kk * 3 + c) * n + g], acc[c]);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) rec.rgb[c] = fmaxf(acc[c], 0.0f);
+        for (int c = 0; c < 3; ++c) rec.rgb[c] = fmaxf(acc[c], 0.0f);
+      } else {
+        rec.rgb[0] = rec.rgb[1] = rec.rgb[2] = 0.0f;  // colour_kernel fills it in
+      }
       if (op.splat) {
         // splat record: the mean's BEAP angles and the conic of the local
         // affine footprint C = J Sigma_c J^T + dilation (C^-1 = [a b; b c]),
@@ -154,6 +263,28 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
                    totals + (totals_stride ? (int64_t)(n_views - 1) * totals_stride : 0));
 }
 
+// The colour of every visible (Gaussian, view) item of a batch, for a
+// preprocess launched without it: one lane per Gaussian, kColourViews views
+// per pass over its SH coefficients.  Kept out of the association kernel for
+// batches of views: there the coefficients' registers would halve its
+// occupancy (a 3M-Gaussian, 8-view batch: 1.9 ms with them, about 1.1 ms
+// without).
+template <int kDeg>
+__global__ __launch_bounds__(256) void colour_kernel(int64_t n, int32_t n_views, const float* __restrict__ mean,
+                                                     const float* __restrict__ sh, const ViewDev* __restrict__ views,
+                                                     const uint32_t* __restrict__ counts,
+                                                     Record* __restrict__ recs) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const float mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
+  for (int v0 = 0; v0 < n_views; v0 += kColourViews) {
+    uint32_t vis = 0u;
+    for (int vv = 0; vv < kColourViews && v0 + vv < n_views; ++vv)
+      if (counts[(int64_t)(v0 + vv) * n + g] != 0u) vis |= 1u << vv;
+    if (vis) chunk_colour<kDeg>(n, g, mu, sh, views, v0, vis, recs);
+  }
+}
+
 void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
                        const float* scale, const float* quat, const float* opacity, const float* sh,
                        const ViewDev* views, const Opts& op, const float* lam_tab, const float* edges,
@@ -161,9 +292,20 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
                        unsigned long long* totals, int totals_stride, const unsigned long long* err_in) {
   if (n == 0) return;
   const dim3 grid((unsigned)((n + 255) / 256));
+  // one view: the colour in the same pass; a batch of views: a second kernel
 #define GEER_PRE(D)                                                                                               \
-  hipLaunchKernelGGL(preprocess_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, scale, quat, opacity, sh,     \
-                     views, op, lam_tab, edges, recs, rects, keys, counts, totals, totals_stride, err_in)
+  do {                                                                                                            \
+    if (n_views == 1 || D == 0) {                                                                                 \
+      hipLaunchKernelGGL((preprocess_kernel<D, true>), grid, dim3(256), 0, st, n, n_views, mean, scale, quat,    \
+                         opacity, sh, views, op, lam_tab, edges, recs, rects, keys, counts, totals, totals_stride, \
+                         err_in);                                                                                 \
+    } else {                                                                                                      \
+      hipLaunchKernelGGL((preprocess_kernel<D, false>), grid, dim3(256), 0, st, n, n_views, mean, scale, quat,   \
+                         opacity, sh, views, op, lam_tab, edges, recs, rects, keys, counts, totals, totals_stride, \
+                         err_in);                                                                                 \
+      hipLaunchKernelGGL(colour_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, sh, views, counts, recs);   \
+    }                                                                                                             \
+  } while (0)
   switch (sh_degree) {
     case 0: GEER_PRE(0); break;
     case 1: GEER_PRE(1); break;
