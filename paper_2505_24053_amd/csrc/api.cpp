@@ -788,7 +788,7 @@ geer_status geer_render_backward(geer_ctx* c, const geer_frame* f, const float* 
   prof_mark(ps, 1, st);
   launch_preprocess_backward(st, f->n, f->nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh,
                              d_views, d_edges, f->lam, f->op, (const uint32_t*)f->counts.p, (const float*)acc.p,
-                             accumulate != 0, g_mean, g_scale, g_quat, g_opacity, g_sh);
+                             (const Record*)f->recs.p, accumulate != 0, g_mean, g_scale, g_quat, g_opacity, g_sh);
   prof_mark(ps, 2, st);
   if (ps) {
     prof_mark(ps, 3, st);
@@ -1470,8 +1470,8 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
     // Gaussian-wise backward once, summing every view
     launch_preprocess_backward(cs, n, n_views, scene->sh_degree, scene->mean, scene->scale, scene->quat,
                                scene->opacity, scene->sh, all_views,
-                               (const float*)P->meta, lt.dev, P->op, counts0, acc, 0, g_mean, g_scale, g_quat,
-                               g_opacity, g_sh);
+                               (const float*)P->meta, lt.dev, P->op, counts0, acc, recs0, 0, g_mean, g_scale,
+                               g_quat, g_opacity, g_sh);
     launch_sum_f32(cs, n_views, loss_views, loss);
     hipError_t e2 = hipStreamEndCapture(cs, &P->graph);
     e = e2 != hipSuccess ? e2 : hipGetLastError();

@@ -6,8 +6,8 @@
 // bit-exact IEEE single arithmetic in a fixed order, no contraction) and the
 // 64-byte render record (radiometric, free-form FP32).  A single view gets
 // its colour in the same pass; a batch of views gets it from a second kernel
-// that reads each Gaussian's SH coefficients once per 8 views, so that the
-// association runs without the coefficients' registers.
+// (one lane per item), so that the association runs without the
+// coefficients' registers.
 //
 // PBF (Sec. 3.2, App. D.1): with M = Rc R S and mu_c = Rc mu + t, a plane
 // through the camera y axis x = c z is tangent to the lambda-ellipsoid iff
@@ -50,9 +50,6 @@ __device__ __forceinline__ void block_add_totals(unsigned long long e, unsigned 
     if (tv) atomicAdd(&totals[1], tv);
   }
 }
-
-// Views whose colour one pass of the SH coefficients serves.
-constexpr int kColourViews = 8;
 
 // The real SH basis functions of one band (degree) in direction (x, y, z),
 // the terms of that band in the full basis.  No contraction, so the values
@@ -108,51 +105,6 @@ __device__ __forceinline__ void view_direction(const ViewDev& V, const float mu[
   x = dv[0] * dinv;
   y = dv[1] * dinv;
   z = dv[2] * dinv;
-}
-
-// Band kBand of the colour of Gaussian g in the views v0 + vv with bit vv of
-// vis set: the band's coefficients are read once for all of them.
-template <int kBand, int kDeg>
-__device__ __forceinline__ void colour_band(int64_t n, int64_t g, const float mu[3], const float* __restrict__ sh,
-                                            const ViewDev* __restrict__ views, int v0, uint32_t vis,
-                                            float (*acc)[3]) {
-  if (kBand > kDeg) return;
-#pragma unroll
-  for (int vv = 0; vv < kColourViews; ++vv) {
-    if (!((vis >> vv) & 1u)) continue;
-    float x, y, z;
-    view_direction(views[v0 + vv], mu, x, y, z);
-    add_band<kBand, kDeg>(n, g, sh, x, y, z, acc[vv]);
-  }
-}
-
-// View-dependent colour (Eq. color's c_i: the SH expansion in the direction
-// from the camera centre to the mean, offset by 1/2 and clamped at 0) of
-// Gaussian g in the views v0 + vv with bit vv of vis set, written into their
-// records.  The coefficients are read one band at a time and each band
-// serves every view of the chunk, so they are never live beside the
-// association's state; per view the terms are added in coefficient order,
-// as a single-view evaluation would.
-template <int kDeg>
-__device__ __forceinline__ void chunk_colour(int64_t n, int64_t g, const float mu[3], const float* __restrict__ sh,
-                                             const ViewDev* __restrict__ views, int v0, uint32_t vis,
-                                             Record* __restrict__ recs) {
-  float acc[kColourViews][3];
-#pragma unroll
-  for (int vv = 0; vv < kColourViews; ++vv)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[vv][c] = 0.5f;
-  colour_band<0, kDeg>(n, g, mu, sh, views, v0, vis, acc);
-  colour_band<1, kDeg>(n, g, mu, sh, views, v0, vis, acc);
-  colour_band<2, kDeg>(n, g, mu, sh, views, v0, vis, acc);
-  colour_band<3, kDeg>(n, g, mu, sh, views, v0, vis, acc);
-#pragma unroll
-  for (int vv = 0; vv < kColourViews; ++vv) {
-    if (!((vis >> vv) & 1u)) continue;
-    Record* r = recs + (int64_t)(v0 + vv) * n + g;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) r->rgb[c] = fmaxf(acc[vv][c], 0.0f);
-  }
 }
 
 template <int kDeg, bool kColour>
@@ -264,25 +216,32 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
 }
 
 // The colour of every visible (Gaussian, view) item of a batch, for a
-// preprocess launched without it: one lane per Gaussian, kColourViews views
-// per pass over its SH coefficients.  Kept out of the association kernel for
-// batches of views: there the coefficients' registers would halve its
-// occupancy (a 3M-Gaussian, 8-view batch: 1.9 ms with them, about 1.1 ms
-// without).
+// preprocess launched without it: one lane per item, the views of one
+// Gaussian on neighbouring lanes, so their loads of its SH coefficients are
+// the same addresses.  Kept out of the association kernel for batches of
+// views: there the coefficients' registers would halve its occupancy.
 template <int kDeg>
 __global__ __launch_bounds__(256) void colour_kernel(int64_t n, int32_t n_views, const float* __restrict__ mean,
                                                      const float* __restrict__ sh, const ViewDev* __restrict__ views,
                                                      const uint32_t* __restrict__ counts,
                                                      Record* __restrict__ recs) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n_views) return;
+  const int64_t g = t / n_views;
+  const int v = (int)(t - g * n_views);
+  const int64_t item = (int64_t)v * n + g;
+  if (counts[item] == 0u) return;
   const float mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
-  for (int v0 = 0; v0 < n_views; v0 += kColourViews) {
-    uint32_t vis = 0u;
-    for (int vv = 0; vv < kColourViews && v0 + vv < n_views; ++vv)
-      if (counts[(int64_t)(v0 + vv) * n + g] != 0u) vis |= 1u << vv;
-    if (vis) chunk_colour<kDeg>(n, g, mu, sh, views, v0, vis, recs);
-  }
+  float x, y, z;
+  view_direction(views[v], mu, x, y, z);
+  float acc[3] = {0.5f, 0.5f, 0.5f};
+  add_band<0, kDeg>(n, g, sh, x, y, z, acc);
+  add_band<1, kDeg>(n, g, sh, x, y, z, acc);
+  add_band<2, kDeg>(n, g, sh, x, y, z, acc);
+  add_band<3, kDeg>(n, g, sh, x, y, z, acc);
+  Record* r = recs + item;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r->rgb[c] = fmaxf(acc[c], 0.0f);
 }
 
 void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
@@ -303,7 +262,8 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
       hipLaunchKernelGGL((preprocess_kernel<D, false>), grid, dim3(256), 0, st, n, n_views, mean, scale, quat,   \
                          opacity, sh, views, op, lam_tab, edges, recs, rects, keys, counts, totals, totals_stride, \
                          err_in);                                                                                 \
-      hipLaunchKernelGGL(colour_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, sh, views, counts, recs);   \
+      hipLaunchKernelGGL(colour_kernel<D>, dim3((unsigned)((n * n_views + 255) / 256)), dim3(256), 0, st, n,     \
+                         n_views, mean, sh, views, counts, recs);                                                 \
     }                                                                                                             \
   } while (0)
   switch (sh_degree) {

@@ -124,8 +124,8 @@ void launch_render_backward(hipStream_t st, bool fixed_lambda, int64_t ntiles, i
 void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
                                 const float* scale, const float* quat, const float* opacity, const float* sh,
                                 const ViewDev* views, const float* edges, const float* lam_tab, const Opts& op,
-                                const uint32_t* counts, const float* acc, int accumulate, float* g_mean, float* g_scale, float* g_quat,
-                                float* g_opacity, float* g_sh);
+                                const uint32_t* counts, const float* acc, const Record* recs, int accumulate,
+                                float* g_mean, float* g_scale, float* g_quat, float* g_opacity, float* g_sh);
 
 // train.hip (raw parameter rows: mean 3, log scale 3, quaternion 4, opacity logit 1, SH 3K)
 void launch_activate(hipStream_t st, int64_t n, const float* raw, float* scale_out, float* opac_out);
