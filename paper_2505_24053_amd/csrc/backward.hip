@@ -466,37 +466,75 @@ __global__ __launch_bounds__(64 * kBackWaves) void render_backward_kernel(
 // ------------------------------------------------------------------------
 // Gaussian-wise stage
 
-// Colour part of one view's Gaussian-wise backward: the SH coefficients'
-// gradient (zero for a clamped channel) into dsh, and the view-direction
-// term into dmu.  a[1..3]: dL/dc of the item.
+// sum_k w_k grad B_k (x, y, z): the derivatives of the real SH basis (the
+// same ones sh_basis gives) contracted with w, without a derivative table.
 template <int kDeg>
-__device__ __forceinline__ void colour_grad(int64_t n, int64_t g, const float mu[3], const float* __restrict__ sh,
-                                            const ViewDev& V, const float a[16], float* dsh, float dmu[3]) {
+__device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const float w[16], float gv[3]) {
+  gv[0] = gv[1] = gv[2] = 0.0f;
+  if (kDeg < 1) return;
+  const float C1 = 0.4886025119029199f;
+  gv[0] -= C1 * w[3];
+  gv[1] -= C1 * w[1];
+  gv[2] += C1 * w[2];
+  if (kDeg < 2) return;
+  const float C20 = 1.0925484305920792f, C21 = -1.0925484305920792f, C22 = 0.31539156525252005f,
+              C23 = -1.0925484305920792f, C24 = 0.5462742152960396f;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  gv[0] += C20 * y * w[4] - 2.0f * C22 * x * w[6] + C23 * z * w[7] + 2.0f * C24 * x * w[8];
+  gv[1] += C20 * x * w[4] + C21 * z * w[5] - 2.0f * C22 * y * w[6] - 2.0f * C24 * y * w[8];
+  gv[2] += C21 * y * w[5] + 4.0f * C22 * z * w[6] + C23 * x * w[7];
+  if (kDeg < 3) return;
+  const float C30 = -0.5900435899266435f, C31 = 2.890611442640554f, C32 = -0.4570457994644658f,
+              C33 = 0.3731763325901154f, C34 = -0.4570457994644658f, C35 = 1.445305721320277f,
+              C36 = -0.5900435899266435f;
+  gv[0] += C30 * 6.0f * x * y * w[9] + C31 * y * z * w[10] - 2.0f * C32 * x * y * w[11] -
+           6.0f * C33 * x * z * w[12] + C34 * (4.0f * zz - 3.0f * xx - yy) * w[13] + 2.0f * C35 * x * z * w[14] +
+           C36 * (3.0f * xx - 3.0f * yy) * w[15];
+  gv[1] += C30 * (3.0f * xx - 3.0f * yy) * w[9] + C31 * x * z * w[10] + C32 * (4.0f * zz - xx - 3.0f * yy) * w[11] -
+           6.0f * C33 * y * z * w[12] - 2.0f * C34 * x * y * w[13] - 2.0f * C35 * y * z * w[14] -
+           6.0f * C36 * x * y * w[15];
+  gv[2] += C31 * x * y * w[10] + 8.0f * C32 * y * z * w[11] + C33 * (6.0f * zz - 3.0f * xx - 3.0f * yy) * w[12] +
+           8.0f * C34 * x * z * w[13] + C35 * (xx - yy) * w[14];
+}
+
+// Colour part of one view's Gaussian-wise backward: the SH coefficients'
+// gradient into dsh and the view-direction term into dmu.  dc: dL/dc of the
+// item's channels, zero where the forward clamped the colour (its record's
+// rgb = max(raw, 0) is > 0 exactly when raw > 0).  The direction term is the
+// gradient of sum_k w_k B_k with w_k = sum_c coef_kc dc_c, so each basis
+// derivative is used once and no derivative table is kept.
+template <int kDeg, typename ShPtr>
+__device__ __forceinline__ void colour_grad(int64_t n, int64_t g, const float mu[3], ShPtr sh,
+                                            const ViewDev& V, const float dc[3], float* dsh, float dmu[3]) {
   constexpr int K = (kDeg + 1) * (kDeg + 1);
   const float dv[3] = {mu[0] - V.campos[0], mu[1] - V.campos[1], mu[2] - V.campos[2]};
   const float dist = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
   const float vd[3] = {dv[0] / dist, dv[1] / dist, dv[2] / dist};
-  float B[16], dB[16][3];
-  sh_basis(kDeg, vd, B, dB);
-  float gv[3] = {0, 0, 0};
+  float B[16];
+  sh_basis(kDeg, vd, B, nullptr);
+  float w[16];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    float raw = 0.5f;
+  for (int k = 0; k < 16; ++k) {
+    w[k] = 0.0f;
+    if (k >= K) continue;
 #pragma unroll
-    for (int k = 0; k < K; ++k) raw = fmaf(B[k], sh[(int64_t)(k * 3 + c) * n + g], raw);
-    const float dc = raw > 0.0f ? a[1 + c] : 0.0f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      dsh[k * 3 + c] += B[k] * dc;
-      const float cf = sh[(int64_t)(k * 3 + c) * n + g] * dc;
-      gv[0] += cf * dB[k][0];
-      gv[1] += cf * dB[k][1];
-      gv[2] += cf * dB[k][2];
+    for (int c = 0; c < 3; ++c) {
+      dsh[k * 3 + c] += B[k] * dc[c];
+      w[k] += sh[(int64_t)(k * 3 + c) * n + g] * dc[c];
     }
   }
+  float gv[3];
+  sh_grad_dot<kDeg>(vd[0], vd[1], vd[2], w, gv);
   const float vg = vd[0] * gv[0] + vd[1] * gv[1] + vd[2] * gv[2];
 #pragma unroll
   for (int j = 0; j < 3; ++j) dmu[j] += (gv[j] - vd[j] * vg) / dist;
+}
+
+// dL/dc of an item's channels, zero where the forward clamped its colour.
+__device__ __forceinline__ void colour_dc(const Record& R, float a1, float a2, float a3, float dc[3]) {
+  dc[0] = R.rgb[0] > 0.0f ? a1 : 0.0f;
+  dc[1] = R.rgb[1] > 0.0f ? a2 : 0.0f;
+  dc[2] = R.rgb[2] > 0.0f ? a3 : 0.0f;
 }
 
 // The Gaussian-wise backward (App. C, second stage): per view the forward's
@@ -508,9 +546,9 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
     int64_t n, int32_t n_views, const float* __restrict__ mean, const float* __restrict__ scale,
     const float* __restrict__ quat, const float* __restrict__ opacity, const float* __restrict__ sh,
     const ViewDev* __restrict__ views, Opts op, const float* __restrict__ lam_tab, const float* __restrict__ edges,
-    const uint32_t* __restrict__ counts, const float* __restrict__ acc, int accumulate, float* __restrict__ g_mean,
-    float* __restrict__ g_scale, float* __restrict__ g_quat, float* __restrict__ g_opacity,
-    float* __restrict__ g_sh) {
+    const uint32_t* __restrict__ counts, const float* __restrict__ acc, const Record* __restrict__ recs,
+    int accumulate, float* __restrict__ g_mean, float* __restrict__ g_scale, float* __restrict__ g_quat,
+    float* __restrict__ g_opacity, float* __restrict__ g_sh) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const float mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
@@ -579,7 +617,11 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
     for (int j = 0; j < 3; ++j)
       dmu[j] -= R[j * 3 + 0] / s[0] * dou[0] + R[j * 3 + 1] / s[1] * dou[1] + R[j * 3 + 2] / s[2] * dou[2];
     dsig += a[0] / sigma;
-    if (kColour) colour_grad<kDeg>(n, g, mu, sh, Vw, a, dsh, dmu);
+    if (kColour) {
+      float dc[3];
+      colour_dc(recs[item], a[1], a[2], a[3], dc);
+      colour_grad<kDeg>(n, g, mu, sh, Vw, dc, dsh, dmu);
+    }
   }
   float ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0};
   if (any) {
@@ -622,37 +664,6 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
   }
 }
 
-// sum_k w_k grad B_k (x, y, z): the derivatives of the real SH basis (the
-// same ones sh_basis gives) contracted with w, without a derivative table.
-template <int kDeg>
-__device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const float w[16], float gv[3]) {
-  gv[0] = gv[1] = gv[2] = 0.0f;
-  if (kDeg < 1) return;
-  const float C1 = 0.4886025119029199f;
-  gv[0] -= C1 * w[3];
-  gv[1] -= C1 * w[1];
-  gv[2] += C1 * w[2];
-  if (kDeg < 2) return;
-  const float C20 = 1.0925484305920792f, C21 = -1.0925484305920792f, C22 = 0.31539156525252005f,
-              C23 = -1.0925484305920792f, C24 = 0.5462742152960396f;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  gv[0] += C20 * y * w[4] - 2.0f * C22 * x * w[6] + C23 * z * w[7] + 2.0f * C24 * x * w[8];
-  gv[1] += C20 * x * w[4] + C21 * z * w[5] - 2.0f * C22 * y * w[6] - 2.0f * C24 * y * w[8];
-  gv[2] += C21 * y * w[5] + 4.0f * C22 * z * w[6] + C23 * x * w[7];
-  if (kDeg < 3) return;
-  const float C30 = -0.5900435899266435f, C31 = 2.890611442640554f, C32 = -0.4570457994644658f,
-              C33 = 0.3731763325901154f, C34 = -0.4570457994644658f, C35 = 1.445305721320277f,
-              C36 = -0.5900435899266435f;
-  gv[0] += C30 * 6.0f * x * y * w[9] + C31 * y * z * w[10] - 2.0f * C32 * x * y * w[11] -
-           6.0f * C33 * x * z * w[12] + C34 * (4.0f * zz - 3.0f * xx - yy) * w[13] + 2.0f * C35 * x * z * w[14] +
-           C36 * (3.0f * xx - 3.0f * yy) * w[15];
-  gv[1] += C30 * (3.0f * xx - 3.0f * yy) * w[9] + C31 * x * z * w[10] + C32 * (4.0f * zz - xx - 3.0f * yy) * w[11] -
-           6.0f * C33 * y * z * w[12] - 2.0f * C34 * x * y * w[13] - 2.0f * C35 * y * z * w[14] -
-           6.0f * C36 * x * y * w[15];
-  gv[2] += C31 * x * y * w[10] + 8.0f * C32 * y * z * w[11] + C33 * (6.0f * zz - 3.0f * xx - 3.0f * yy) * w[12] +
-           8.0f * C34 * x * z * w[13] + C35 * (xx - yy) * w[14];
-}
-
 // The colour part of the Gaussian-wise backward for a batch of views, after
 // a preprocess_backward_kernel launched without it: the SH coefficients'
 // gradient is written (or, with accumulate, added) and the view-direction
@@ -686,31 +697,10 @@ __global__ __launch_bounds__(256) void colour_backward_kernel(int64_t n, int32_t
     const int64_t item = (int64_t)v * n + g;
     if (counts[item] == 0u) continue;
     const float4 A0 = reinterpret_cast<const float4*>(acc + item * kAcc)[0];
-    const float* rgb = recs[item].rgb;
-    const float dc[3] = {rgb[0] > 0.0f ? A0.y : 0.0f, rgb[1] > 0.0f ? A0.z : 0.0f, rgb[2] > 0.0f ? A0.w : 0.0f};
+    float dc[3];
+    colour_dc(recs[item], A0.y, A0.z, A0.w, dc);
     if (dc[0] == 0.0f && dc[1] == 0.0f && dc[2] == 0.0f) continue;
-    const ViewDev& V = views[v];
-    const float dv[3] = {mu[0] - V.campos[0], mu[1] - V.campos[1], mu[2] - V.campos[2]};
-    const float dist = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-    const float vd[3] = {dv[0] / dist, dv[1] / dist, dv[2] / dist};
-    float B[16];
-    sh_basis(kDeg, vd, B, nullptr);
-    float w[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      w[k] = 0.0f;
-      if (k >= K) continue;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        dsh[k * 3 + c] += B[k] * dc[c];
-        w[k] += shv[(int64_t)(k * 3 + c) * n + g] * dc[c];
-      }
-    }
-    float gv[3];
-    sh_grad_dot<kDeg>(vd[0], vd[1], vd[2], w, gv);
-    const float vg = vd[0] * gv[0] + vd[1] * gv[1] + vd[2] * gv[2];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) dmu[j] += (gv[j] - vd[j] * vg) / dist;
+    colour_grad<kDeg>(n, g, mu, shv, views[v], dc, dsh, dmu);
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j) g_mean[j * n + g] += dmu[j];
@@ -767,12 +757,12 @@ void launch_preprocess_backward(hipStream_t st, int64_t n, int32_t n_views, int3
   do {                                                                                                             \
     if (n_views == 1 || D == 0) {                                                                                  \
       hipLaunchKernelGGL((preprocess_backward_kernel<D, true>), grid, dim3(256), 0, st, n, n_views, mean, scale,  \
-                         quat, opacity, sh, views, op, lam_tab, edges, counts, acc, accumulate, g_mean, g_scale,    \
-                         g_quat, g_opacity, g_sh);                                                                 \
+                         quat, opacity, sh, views, op, lam_tab, edges, counts, acc, recs, accumulate, g_mean,       \
+                         g_scale, g_quat, g_opacity, g_sh);                                                        \
     } else {                                                                                                       \
       hipLaunchKernelGGL((preprocess_backward_kernel<D, false>), grid, dim3(256), 0, st, n, n_views, mean, scale, \
-                         quat, opacity, sh, views, op, lam_tab, edges, counts, acc, accumulate, g_mean, g_scale,    \
-                         g_quat, g_opacity, g_sh);                                                                 \
+                         quat, opacity, sh, views, op, lam_tab, edges, counts, acc, recs, accumulate, g_mean,       \
+                         g_scale, g_quat, g_opacity, g_sh);                                                        \
       hipLaunchKernelGGL(colour_backward_kernel<D>, grid, dim3(256), 0, st, n, n_views, mean, sh, views, counts,  \
                          acc, recs, accumulate, g_mean, g_sh);                                                    \
     }                                                                                                              \
