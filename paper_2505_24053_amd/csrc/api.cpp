@@ -320,6 +320,9 @@ struct FwdBufs {
                               // [6] heavy tiles, [7] stall flag of earlier eager forwards
   unsigned long long* err = nullptr;  // where the sorts flag a stall (null: stats[4])
   unsigned long long* sort_err() const { return err ? err : (unsigned long long*)(stats + 4); }
+  // radix passes take their chunks by atomic tickets: set where the forward
+  // may run beside look-back passes of other streams (render plans)
+  bool tickets = false;
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
   uint32_t* hist = nullptr;   // the depth order's work (depth_work_words)
   uint32_t* twork = nullptr;  // the expansion's and tile sort's work (tile_work_words)
@@ -359,7 +362,7 @@ void enqueue_depth_order(hipStream_t st, int64_t items, int64_t nvis_cap, const 
   if (nvis_cap <= 0) return;
   // items in depth order to b.vb, their entry offsets to b.cnt_sorted
   depth_order(st, b.keys, b.counts, items, nvis_cap, dV, b.hist, b.depth_work_zeroed, b.ka, b.va, b.kb, b.vb,
-              b.cnt_sorted, b.sort_err());
+              b.cnt_sorted, b.sort_err(), b.tickets);
 }
 
 // Second half: per-tile cones, expansion, tile sort and ranges.  dV / dE:
@@ -392,10 +395,10 @@ void enqueue_tile_lists(hipStream_t st, const Opts& op, int64_t n, int64_t items
     // two passes), which replaces the sort's histogram pass over the list
     const int hpass = hist_passes(ntiles);
     launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, b.tcones, b.recs, op, tin,
-                  iin, b.twork, hpass, td.bits);
-    tile_sort(st, tin, iin, ecap, dE, kept, passes, td.bits, at, ai, tin, iin, b.twork, hpass, err);
+                  iin, b.twork, hpass, td.bits, items, ntiles);
+    tile_sort(st, tin, iin, ecap, dE, kept, passes, td.bits, at, ai, tin, iin, b.twork, hpass, err, b.tickets);
     uint32_t* tfinal = (passes % 2 == 1) ? at : tin;
-    launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges, b.list);
+    launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges, b.list, err);
   } else {
     launch_fill_u32(st, b.list, 8, 0u);
     launch_ranges(st, nullptr, 0, nullptr, ntiles, b.ranges);
@@ -1142,6 +1145,7 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     b.depth_work_zeroed = true;
+    b.tickets = true;  // slots of a server replay plans on several streams at once
     enqueue_preprocess(cs, P->scene, n_views, P->op, lt.dev, b);
     enqueue_association(cs, P->op, P->n, items, std::max<int64_t>(items, 1), entry_capacity, P->ntiles, true, b);
     enqueue_render(cs, P->op, P->ntiles, n_views, b, rgb, depth, trans);

@@ -119,10 +119,16 @@ __device__ __forceinline__ int64_t dyn_count(int64_t n_cap, const unsigned long 
 //
 // The look-back spin is bounded and reports a stall through an error word
 // instead of hanging.  A block waits only on blocks with lower indices, and
-// each XCD dispatches the workgroups of a launch in index order, so the
-// lowest unfinished block is always resident and the walk always ends.  (A
-// per-block atomic ticket would serialise: tickets come one at a time off one
-// counter, which staggers the 692 blocks of a 2.8M-key pass over about 9 us.)
+// each XCD dispatches the workgroups of a launch in index order, so while
+// the pass has the device to itself the lowest unfinished block is always
+// resident and the walk always ends.  Kernels of other streams break that:
+// higher blocks of several passes can hold every slot while they wait on
+// lower blocks that are not dispatched.  Work that may run beside other
+// streams (render plans) therefore numbers the chunks by atomic tickets taken
+// as blocks start, so every block waited on is running.  (Tickets serialise:
+// they come one at a time off one counter, which staggers the 692 blocks of a
+// 2.8M-key pass over about 9 us, so eager forwards and training plans, one
+// association at a time, go without.)
 
 constexpr int kLookBack = 16;  // statuses read per look-back round
 constexpr int kOSPerSmall = 4;                  // keys per thread below kOSSmallKeys keys
@@ -244,7 +250,8 @@ struct PassArgs {
   int hcopies, hstride;
   unsigned long long* kept_out;  // with it, block 0 stores the number of keys sorted
   const uint32_t* whist;  // weighted pass: weight totals per digit
-  const uint32_t* wts;    // weighted pass: weight of value v
+  const uint32_t* wts;    // weighted pass: weight of value v (v < wts_n)
+  int64_t wts_n;
   void* status;           // this pass's status table, one row per block
   void* status_next;      // the next pass's table (row b cleared by block b), or null
   int next_row_words;     // u32 words of a row of the next pass's table
@@ -252,6 +259,7 @@ struct PassArgs {
   uint32_t* vals_out;
   uint32_t* wout;         // weighted pass: exclusive prefix of the weights in sorted order
   unsigned long long* err;
+  uint32_t* ticket;  // with it, a block's chunk is the ticket it takes off this counter (starts at 0)
 };
 
 template <bool kW>
@@ -292,7 +300,16 @@ __global__ __launch_bounds__(kBlock) void radix_pass_kernel(const PassArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // the grid is sized for the capacity: blocks past the live key count leave
   const int64_t n = dyn_count(a.n_cap, a.dyn);
-  const int64_t blk = blockIdx.x;
+  int64_t blk = blockIdx.x;
+  if (a.ticket) {
+    // chunks in the order blocks start: the walk then only ever waits on
+    // blocks that are running, also when kernels of other streams share the
+    // device (in-order dispatch holds within one kernel only)
+    __shared__ uint32_t s_ticket;
+    if (tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
+    __syncthreads();
+    blk = s_ticket;
+  }
   if (blk >= os_blocks(n, kItems)) return;
 #pragma unroll
   for (int q = 0; q < 4; ++q) s_cnt[q][tid] = 0u;
@@ -326,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void radix_pass_kernel(const PassArgs a) {
   }
   if (kWeighted) {
 #pragma unroll
-    for (int sl = 0; sl < kPer; ++sl) wt[sl] = a.wts[val[sl]];  // a weighted pass always has values
+    for (int sl = 0; sl < kPer; ++sl) wt[sl] = a.wts[min<int64_t>(val[sl], a.wts_n - 1)];  // values are set
   }
   uint32_t act = 0u;
 #pragma unroll
@@ -455,10 +472,13 @@ __global__ __launch_bounds__(kBlock) void radix_pass_kernel(const PassArgs a) {
     }
     __syncthreads();
   }
+  // (a stalled look-back or inputs a stalled pass left behind can put g past
+  // the keys; such keys are not written)
   for (uint32_t i = tid; i < ltotal; i += kBlock) {
     const uint32_t k = s_key[i];
     const uint32_t d = (k >> a.shift) & a.dmask;
     const uint32_t g = s_glob[d] + (i - s_loc[d]);
+    if ((int64_t)g >= n) continue;
     if (a.keys_out) a.keys_out[g] = k;
     a.vals_out[g] = s_val[i];
     if (kWeighted) a.wout[g] = s_wglob[d] + (s_wt[i] - s_wt[s_loc[d]]);
@@ -555,7 +575,8 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
                                                         const Record* __restrict__ recs, Opts op, int cull,
                                                         uint32_t* __restrict__ tiles_out,
                                                         uint32_t* __restrict__ items_out,
-                                                        uint32_t* __restrict__ hparts, int hpass, int hbits) {
+                                                        uint32_t* __restrict__ hparts, int hpass, int hbits,
+                                                        int64_t nitems, uint32_t ntiles) {
   constexpr int kSpan = kExpandSpan;
   const int64_t m = dyn_count(m_cap, dyn_m);
   const int64_t total = dyn_count(total_cap, dyn_total);
@@ -592,7 +613,9 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   const int64_t S = min<int64_t>(kSpan + 1, m - jlo);
   for (int k = threadIdx.x; k < kSpan + 1; k += kBlock) {
     s_offs[k] = k < S ? offs[jlo + k] : 0xffffffffu;
-    s_own[k] = k < S ? items[jlo + k] : 0u;
+    // item ids are clamped to the items there are, so that a depth order a
+    // stalled sort left inconsistent cannot send the reads out of bounds
+    s_own[k] = k < S ? (uint32_t)min<int64_t>(items[jlo + k], nitems - 1) : 0u;
   }
   __syncthreads();
 
@@ -606,6 +629,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
     // local owner of e0: last k with s_offs[k] <= e0; it is at most
     // e0 - block0, since every owner covers at least one entry
     int lo = 0, hi = cnt > 0 ? (int)min<int64_t>(S, (int64_t)threadIdx.x * kExpandPer + 1) : 0;
+    const int jmax = (int)S - 1;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if ((int64_t)s_offs[mid] <= e0) lo = mid; else hi = mid;
@@ -613,14 +637,14 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
     // tile ids and items of the lane's entries
     uint32_t tile[kExpandPer], item[kExpandPer];
     int jl = lo, cur = -1;
-    uint32_t it = 0, tx = 0, ty = 0, tx0 = 0, tx1 = 0, row = 0, base = 0;
+    uint32_t it = 0, tx = 0, ty = 0, tx0 = 0, tx1 = 0, ty1 = 0, row = 0, base = 0;
 #pragma unroll
     for (int k = 0; k < kExpandPer; ++k) {
       tile[k] = kDropKey;
       item[k] = 0u;
       if (k < cnt) {
         const int64_t e = e0 + k;
-        while ((int64_t)s_offs[jl + 1] <= e) ++jl;
+        while (jl < jmax && (int64_t)s_offs[jl + 1] <= e) ++jl;
         if (jl != cur) {
           cur = jl;
           it = s_own[jl];
@@ -629,6 +653,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
           tx0 = (r.x & 0xffffu) >> 1;
           tx1 = (r.x >> 16) >> 1;
           const uint32_t ty0 = (r.y & 0xffffu) >> 1;
+          ty1 = (r.y >> 16) >> 1;
           const uint32_t wt = tx1 - tx0 + 1u;
           const ViewDev& V = views[small_quotient(it, (uint32_t)n)];
           const uint32_t dy = small_quotient(local, wt);
@@ -640,7 +665,10 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
           tx = tx0;
           ++ty;
         }
-        tile[k] = base + ty * row + tx;
+        // an entry past its owner's rectangle (only offsets a stalled sort
+        // left behind make one) is dropped, so every tile id stays in the grid
+        const uint32_t tid_ = base + ty * row + tx;
+        tile[k] = (ty <= ty1 && tid_ < ntiles) ? tid_ : kDropKey;
         item[k] = it;
       }
     }
@@ -655,13 +683,15 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
       float4 cr[kExpandPer];
 #pragma unroll
       for (int k = 0; k < kExpandPer; ++k)
-        cr[k] = k < cnt ? tcones[kConeStride * (size_t)tile[k] + 4] : make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+        cr[k] = k < cnt && tile[k] != kDropKey ? tcones[kConeStride * (size_t)tile[k] + 4]
+                                               : make_float4(0.0f, 0.0f, 0.0f, -1.0f);
       uint32_t survive = 0u, cur = 0xffffffffu;
       int cls = 0;  // the item's verdict: 0 no ray reaches alpha_min, 1 every tile kept, 2 per tile
       float G[9] = {}, tau = 0.0f, lip = 0.0f;
 #pragma unroll
       for (int k = 0; k < kExpandPer; ++k) {
         if (k >= cnt) break;
+        if (tile[k] == kDropKey) continue;
         if (item[k] != cur) {
           cur = item[k];
           const float4* rp = reinterpret_cast<const float4*>(recs + cur);
@@ -788,8 +818,14 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
 __global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t* __restrict__ tiles, int64_t total_cap,
                                                         const unsigned long long* __restrict__ dyn,
                                                         int64_t ntiles, uint32_t* __restrict__ ranges,
-                                                        uint32_t* __restrict__ list) {
-  const int64_t total = dyn_count(total_cap, dyn);
+                                                        uint32_t* __restrict__ list,
+                                                        const unsigned long long* __restrict__ err) {
+  // A sort that stalled leaves a list in no order: every tile's range is then
+  // empty, so that nothing downstream reads the list (the outputs are
+  // reported invalid anyway).  The sort's kernels have all ended, so every
+  // block reads the same word.
+  const bool bad = err && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull;
+  const int64_t total = bad ? 0 : dyn_count(total_cap, dyn);
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const int64_t e0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (list && e0 < 8) list[total + e0] = 0u;
@@ -798,9 +834,11 @@ __global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t* __restri
     return;
   }
   // grid-stride: the grid is bounded, however large the capacity
+  // tile ids are clamped into the grid, so that even a list a stalled sort
+  // left inconsistent cannot send these writes out of bounds
   for (int64_t e = e0; e < total; e += stride) {
-    const int64_t cur = tiles[e];
-    const int64_t prev = e > 0 ? (int64_t)tiles[e - 1] : -1;
+    const int64_t cur = min((int64_t)tiles[e], ntiles - 1);
+    const int64_t prev = e > 0 ? min((int64_t)tiles[e - 1], ntiles - 1) : -1;
     for (int64_t t = prev + 1; t <= cur; ++t) ranges[t] = (uint32_t)e;
     if (e == total - 1)
       for (int64_t t = cur + 1; t <= ntiles; ++t) ranges[t] = (uint32_t)total;
@@ -878,13 +916,14 @@ int64_t depth_zero_words(int64_t n0) { return kWorkHead + 256 * depth_blocks(std
 
 void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, int64_t n0, int64_t n1_cap,
                  const unsigned long long* dyn1, uint32_t* work, bool zeroed, uint32_t* ka, uint32_t* va,
-                 uint32_t* kb, uint32_t* vb, uint32_t* offs, unsigned long long* err) {
+                 uint32_t* kb, uint32_t* vb, uint32_t* offs, unsigned long long* err, bool tickets) {
   if (n0 <= 0 || n1_cap <= 0) return;
   const int per = os_per(n0);
   const int items = kBlock * per;
   const int64_t nb0 = os_blocks(n0, items), nb1 = std::max<int64_t>(os_blocks(n1_cap, items), 1);
   uint32_t* ghist = work;
   uint32_t* whist = work + 4 * 256;
+  uint32_t* tk = work + 5 * 256;  // the passes' tickets (in the head, so they start at zero)
   uint32_t* t0 = work + kWorkHead;
   uint32_t* t1 = t0 + 256 * nb0;
   if (!zeroed)
@@ -913,6 +952,7 @@ void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, i
   p.status_next = t1;
   p.keys_out = ka;
   p.vals_out = va;
+  p.ticket = tickets ? tk : nullptr;
   hipLaunchKernelGGL(plain, dim3((unsigned)nb0), dim3(kBlock), 0, st, p);
   // passes 1 and 2 over the visible items: (ka, va) -> (kb, vb) -> (ka, va)
   p.filter = nullptr;
@@ -928,6 +968,7 @@ void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, i
     p.next_row_words = q == 1 ? 256 : 512;  // pass 3's rows are 64-bit
     p.keys_out = q == 1 ? kb : ka;
     p.vals_out = q == 1 ? vb : va;
+    p.ticket = tickets ? tk + q : nullptr;
     hipLaunchKernelGGL(plain, dim3((unsigned)nb1), dim3(kBlock), 0, st, p);
   }
   // pass 3, weighted by the tile counts: items in depth order to vb, their
@@ -938,11 +979,13 @@ void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, i
   p.ghist = ghist + 3 * 256;
   p.whist = whist;
   p.wts = counts;
+  p.wts_n = n0;
   p.status = t1;
   p.status_next = nullptr;
   p.keys_out = nullptr;
   p.vals_out = vb;
   p.wout = offs;
+  p.ticket = tickets ? tk + 3 : nullptr;
   hipLaunchKernelGGL(weighted, dim3((unsigned)nb1), dim3(kBlock), 0, st, p);
 }
 
@@ -960,7 +1003,8 @@ int64_t tile_work_words(int64_t ecap) { return tile_zero_words(ecap) + tile_rows
 
 void tile_sort(hipStream_t st, const uint32_t* tin, const uint32_t* iin, int64_t ecap,
                const unsigned long long* dE, unsigned long long* kept, int passes, int bits, uint32_t* at,
-               uint32_t* ai, uint32_t* bt, uint32_t* bi, uint32_t* twork, int hpass, unsigned long long* err) {
+               uint32_t* ai, uint32_t* bt, uint32_t* bi, uint32_t* twork, int hpass, unsigned long long* err,
+               bool tickets) {
   if (ecap <= 0 || passes <= 0) return;
   const int per = os_per(ecap);
   const unsigned nb = (unsigned)std::max<int64_t>(os_blocks(ecap, kBlock * per), 1);
@@ -1000,6 +1044,7 @@ void tile_sort(hipStream_t st, const uint32_t* tin, const uint32_t* iin, int64_t
     p.status_next = q + 1 < passes ? ((q % 2 == 0) ? t1 : t0) : nullptr;
     p.keys_out = ok;
     p.vals_out = ov;
+    p.ticket = tickets ? head + 5 * 256 + q : nullptr;  // in the head, cleared with it
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, p);
     sk = ok;
     sv = ov;
@@ -1019,15 +1064,15 @@ void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, 
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
                    const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* twork, int hpass,
-                   int hbits) {
+                   int hbits, int64_t nitems, int64_t ntiles) {
   if (total_cap <= 0) return;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total_cap, kExpandSpan)), dim3(kBlock), 0, st, items, offs, m_cap,
                      dyn_m, total_cap, dyn_total, rects, views, n, tcones, recs, op, op.cone_cull, tiles_out,
-                     items_out, twork, hpass, hbits);
+                     items_out, twork, hpass, hbits, std::max<int64_t>(nitems, 1), (uint32_t)ntiles);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
-                   int64_t ntiles, uint32_t* ranges, uint32_t* list) {
+                   int64_t ntiles, uint32_t* ranges, uint32_t* list, const unsigned long long* err) {
   if (total_cap <= 0 && !dyn) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(ntiles + 1, kBlock)), dim3(kBlock), 0, st, ranges, ntiles + 1,
                        0u);
@@ -1035,7 +1080,7 @@ void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, con
   }
   const int64_t g = std::max<int64_t>(total_cap, ntiles + 1);
   hipLaunchKernelGGL(ranges_kernel, dim3(std::min<unsigned>(grid_for(g, kBlock), 8192u)), dim3(kBlock), 0, st, tiles,
-                     total_cap, dyn, ntiles, ranges, list);
+                     total_cap, dyn, ntiles, ranges, list, err);
 }
 
 void launch_capacity_guard(hipStream_t st, unsigned long long* stats, int64_t cap) {

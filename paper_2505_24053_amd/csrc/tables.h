@@ -50,7 +50,7 @@ int64_t depth_work_words(int64_t n0);
 int64_t depth_zero_words(int64_t n0);
 void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, int64_t n0, int64_t n1_cap,
                  const unsigned long long* dyn1, uint32_t* work, bool zeroed, uint32_t* ka, uint32_t* va,
-                 uint32_t* kb, uint32_t* vb, uint32_t* offs, unsigned long long* err);
+                 uint32_t* kb, uint32_t* vb, uint32_t* offs, unsigned long long* err, bool tickets = false);
 // Work of the expansion and the tile sort for up to ecap entries:
 // tile_work_words(ecap) words whose first tile_zero_words(ecap) must be zero
 // before the expansion.
@@ -63,7 +63,8 @@ int64_t tile_zero_words(int64_t ecap);
 // digits of the first hpass passes into twork.
 void tile_sort(hipStream_t st, const uint32_t* tin, const uint32_t* iin, int64_t ecap,
                const unsigned long long* dE, unsigned long long* kept, int passes, int bits, uint32_t* at,
-               uint32_t* ai, uint32_t* bt, uint32_t* bi, uint32_t* twork, int hpass, unsigned long long* err);
+               uint32_t* ai, uint32_t* bt, uint32_t* bi, uint32_t* twork, int hpass, unsigned long long* err,
+               bool tickets = false);
 // Bytes of the expansion's per-tile cull table; its launch also sets
 // zero[0 .. nzero) = 0.
 size_t tile_cone_bytes(int64_t ntiles);
@@ -76,11 +77,13 @@ void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, 
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
                    const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* twork, int hpass,
-                   int hbits);
+                   int hbits, int64_t nitems, int64_t ntiles);
 int hist_parts_words();
-// with list: also zeroes the 8 words of padding after the list
+// with list: also zeroes the 8 words of padding after the list; with err:
+// every range is empty when the sort's error word is set
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,
-                   int64_t ntiles, uint32_t* ranges, uint32_t* list = nullptr);
+                   int64_t ntiles, uint32_t* ranges, uint32_t* list = nullptr,
+                   const unsigned long long* err = nullptr);
 void launch_zero2_u32(hipStream_t st, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2);
 void launch_capacity_guard(hipStream_t st, unsigned long long* stats, int64_t cap);
 void launch_fill_u32(hipStream_t st, uint32_t* p, int64_t n, uint32_t v);
