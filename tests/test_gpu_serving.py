@@ -213,3 +213,34 @@ def test_server_full_size_requests(R):
         compare_render(got, oracle.render(scene, r.cam, pix=pix), pix=pix)
     print("full-size serving: entries per tile %.0f" % per_tile, srv.stats, serve.latency_summary(done))
     srv.close()
+
+
+def test_server_saturated_full_size_three_slots(R):
+    """Saturated serving at the full size: 1M Gaussians, three slots, every
+    request queued at once, so the radix passes of different slots' plans run
+    on the device together.  No batch may report a stalled sort, and every
+    served result equals the same camera rendered alone."""
+    from paper_2505_24053_amd import serve
+
+    scene = synth.scene_box(1_000_000, seed=0)
+    sc = R.scene_from_numpy(scene)
+    cams = synth.workload_serving_requests(48, seed=9)
+    alone = {}
+    per_tile = 0.0
+    for i, c in enumerate(cams[:6]):
+        alone[i] = eager(R, sc, [c])
+        per_tile = max(per_tile, alone[i][3] / serve.tiles_of((c["width"], c["height"])))
+    srv = serve.Server(sc, {(c["width"], c["height"]) for c in cams}, entries_per_tile=2.0 * per_tile, slots=3,
+                       slot_views=2, max_views=4)
+    srv.prepare({(c["width"], c["height"]) for c in cams})
+    done = srv.run([serve.Request(i, c) for i, c in enumerate(cams)])
+    assert len(done) == len(cams)
+    # (a batch over its capacity is re-rendered eagerly and still compared)
+    assert srv.stats["stalls"] == 0, srv.stats
+    assert srv.stats["overlapped"] > 0, srv.stats
+    for r in done:
+        if r.rid in alone:
+            rgb, depth, trans, _ = alone[r.rid]
+            assert torch.equal(r.rgb, rgb) and torch.equal(r.depth, depth) and torch.equal(r.trans, trans), r.rid
+    print("saturated full-size serving", srv.stats, "overlap %.2f" % srv.device_overlap())
+    srv.close()
