@@ -323,6 +323,9 @@ struct FwdBufs {
   // radix passes take their chunks by atomic tickets: set where the forward
   // may run beside look-back passes of other streams (render plans)
   bool tickets = false;
+  // owners of the expansion's blocks, written by the depth order
+  uint32_t* owners = nullptr;
+  int64_t owners_n = 0;
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
   uint32_t* hist = nullptr;   // the depth order's work (depth_work_words)
   uint32_t* twork = nullptr;  // the expansion's and tile sort's work (tile_work_words)
@@ -362,7 +365,7 @@ void enqueue_depth_order(hipStream_t st, int64_t items, int64_t nvis_cap, const 
   if (nvis_cap <= 0) return;
   // items in depth order to b.vb, their entry offsets to b.cnt_sorted
   depth_order(st, b.keys, b.counts, items, nvis_cap, dV, b.hist, b.depth_work_zeroed, b.ka, b.va, b.kb, b.vb,
-              b.cnt_sorted, b.sort_err(), b.tickets);
+              b.cnt_sorted, b.owners, b.owners_n, b.sort_err(), b.tickets);
 }
 
 // Second half: per-tile cones, expansion, tile sort and ranges.  dV / dE:
@@ -395,7 +398,7 @@ void enqueue_tile_lists(hipStream_t st, const Opts& op, int64_t n, int64_t items
     // two passes), which replaces the sort's histogram pass over the list
     const int hpass = hist_passes(ntiles);
     launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, b.tcones, b.recs, op, tin,
-                  iin, b.twork, hpass, td.bits, items, ntiles);
+                  iin, b.twork, hpass, td.bits, items, ntiles, b.owners);
     tile_sort(st, tin, iin, ecap, dE, kept, passes, td.bits, at, ai, tin, iin, b.twork, hpass, err, b.tickets);
     uint32_t* tfinal = (passes % 2 == 1) ? at : tin;
     launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges, b.list, err);
@@ -615,9 +618,9 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   f->dtab_off = tab.dtab_off;
 
   // Temporaries of the sort; released at the end of the call.
-  Block ka, va, kb, vb, hist, twork, tiles_a, tiles_b, items_b, cnt_sorted, tcones;
+  Block ka, va, kb, vb, hist, twork, tiles_a, tiles_b, items_b, cnt_sorted, tcones, owners;
   auto cleanup = [&](geer_status st_) {
-    for (Block* b : {&ka, &va, &kb, &vb, &hist, &twork, &tiles_a, &tiles_b, &items_b, &cnt_sorted, &tcones})
+    for (Block* b : {&ka, &va, &kb, &vb, &hist, &twork, &tiles_a, &tiles_b, &items_b, &cnt_sorted, &tcones, &owners})
       release(c, *b);
     if (st_ != GEER_OK) {
       free_frame_buffers(f);
@@ -668,6 +671,12 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   TRY(acquire(c, 4 * (size_t)depth_work_words(it1), st, hist));
   TRY(acquire(c, 4 * it1, st, cnt_sorted));
   TRY(acquire(c, tile_cone_bytes(ntiles), st, tcones));
+  // owners of the expansion's blocks: the list is not sized yet, so the table
+  // is, for the most entries the items can make (each at most every tile)
+  const int64_t ebound = std::min<int64_t>(kMaxKeys, (int64_t)std::min<double>(1e18, (double)it1 * (double)ntiles));
+  TRY(acquire(c, 4 * (size_t)owner_words(ebound), st, owners));
+  b.owners = (uint32_t*)owners.p;
+  b.owners_n = owner_words(ebound);
   b.tcones = (float4*)tcones.p;
   b.ka = (uint32_t*)ka.p; b.va = (uint32_t*)va.p; b.kb = (uint32_t*)kb.p; b.vb = (uint32_t*)vb.p;
   b.hist = (uint32_t*)hist.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
@@ -981,7 +990,7 @@ geer_status geer_l1_loss(geer_ctx* c, int64_t pixels, const float* rgb, const fl
 struct PlanLayout {
   size_t meta = 0, recs = 0, rects = 0, keys = 0, counts = 0, stats = 0, ka = 0, va = 0, kb = 0, vb = 0, hist = 0,
          twork = 0, cnt_sorted = 0, tiles_a = 0, tiles_b = 0, items_b = 0, list = 0, ranges = 0, heavy_list = 0,
-         heavy_flag = 0, tcones = 0, total = 0;
+         heavy_flag = 0, tcones = 0, owners = 0, total = 0;
 };
 
 // pre_items (default: items) sizes the per-item outputs of the preprocess.
@@ -1016,12 +1025,13 @@ PlanLayout plan_layout(size_t meta_bytes, int64_t items, int64_t ecap, int64_t n
   L.heavy_list = put(4 * (size_t)heavy_list_words(ntiles));
   L.heavy_flag = put(4 * (size_t)ntiles);
   L.tcones = put(tile_cone_bytes(ntiles));
+  L.owners = put(4 * (size_t)owner_words(ecap));
   L.total = off;
   return L;
 }
 
 // Device pointers of a capacity-sized forward carved from the block at w.
-FwdBufs carve_plan(char* w, const PlanLayout& lay, const ViewTables& tab, int64_t ntiles) {
+FwdBufs carve_plan(char* w, const PlanLayout& lay, const ViewTables& tab, int64_t ntiles, int64_t ecap) {
   FwdBufs b;
   b.views = (const ViewDev*)(w + lay.meta);
   b.edges = (const float*)(w + lay.meta + tab.edges_off);
@@ -1046,6 +1056,8 @@ FwdBufs carve_plan(char* w, const PlanLayout& lay, const ViewTables& tab, int64_
   b.heavy_list = (uint32_t*)(w + lay.heavy_list);
   b.heavy_flag = (uint32_t*)(w + lay.heavy_flag);
   b.tcones = (float4*)(w + lay.tcones);
+  b.owners = (uint32_t*)(w + lay.owners);
+  b.owners_n = owner_words(ecap);
   b.hmax = heavy_capacity(ntiles);
   return b;
 }
@@ -1128,7 +1140,7 @@ geer_status geer_plan_create(geer_ctx* c, const geer_scene* scene, int32_t n_vie
     P->bytes = (int64_t)lay.total;
   }
   char* w = (char*)P->ws;
-  FwdBufs b = carve_plan(w, lay, tab, P->ntiles);
+  FwdBufs b = carve_plan(w, lay, tab, P->ntiles, entry_capacity);
   P->meta = w + lay.meta;
   P->stats = b.stats;
   for (int k = 0; k < 2; ++k) {
@@ -1212,7 +1224,7 @@ geer_status geer_render_static(geer_ctx* c, const geer_scene* scene, int32_t n_v
     HIP_TRY(c, hipStreamSynchronize(st));
     return GEER_OK;
   }
-  FwdBufs b = carve_plan(base, lay, tab, ntiles);
+  FwdBufs b = carve_plan(base, lay, tab, ntiles, ecap);
   b.depth_work_zeroed = true;
   HIP_TRY(c, hipMemcpyAsync(base + lay.meta, host.data(), meta_bytes, hipMemcpyHostToDevice, st));
   enqueue_preprocess(st, *scene, n_views, op, (const float*)(base + lay.meta + lam_off), b);
@@ -1414,6 +1426,8 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
   b.heavy_list = (uint32_t*)(w + F.heavy_list);
   b.heavy_flag = (uint32_t*)(w + F.heavy_flag);
   b.tcones = (float4*)(w + F.tcones);
+  b.owners = (uint32_t*)(w + F.owners);
+  b.owners_n = owner_words(entry_capacity);
   b.hmax = heavy_capacity(S.ntiles_max);
   b.nlast = (uint32_t*)(w + lay.nlast);
   b.tfinal = (float*)(w + lay.tfinal);

@@ -153,6 +153,9 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 // Work head: the digit counts of up to 4 passes, then the weighted counts of
 // the last pass's digits (padded).
 constexpr int kWorkHead = 5 * 256 + 64;
+// Entries per expansion block: the weighted depth pass records the owner of
+// every multiple of it, where an expansion block starts.
+constexpr int kOwnerSpan = 1024;
 
 __host__ __device__ __forceinline__ int64_t os_blocks(int64_t n, int items) { return (n + items - 1) / items; }
 
@@ -262,6 +265,10 @@ struct PassArgs {
   uint32_t* keys_out;     // null: keys are not written
   uint32_t* vals_out;
   uint32_t* wout;         // weighted pass: exclusive prefix of the weights in sorted order
+  // weighted pass, or null: owners[b] = the output position whose weight run
+  // [wout, wout + weight) holds b * kOwnerSpan, for b < owners_n
+  uint32_t* owners;
+  int64_t owners_n;
   unsigned long long* err;
   uint32_t* ticket;  // with it, a block's chunk is the ticket it takes off this counter (starts at 0)
 };
@@ -458,6 +465,7 @@ __global__ __launch_bounds__(kBlock) void radix_pass_kernel(const PassArgs a) {
     }
   }
   __syncthreads();
+  uint32_t wt_total = 0u;
   if (kWeighted) {
     // exclusive prefix of the weights in the block's sorted order (in place;
     // thread t scans kPer consecutive positions)
@@ -468,7 +476,6 @@ __global__ __launch_bounds__(kBlock) void radix_pass_kernel(const PassArgs a) {
       v[k] = i < ltotal ? s_wt[i] : 0u;
       s += v[k];
     }
-    uint32_t wt_total;
     uint32_t run = block_excl_scan256(s, s_w, wt_total);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -487,11 +494,23 @@ __global__ __launch_bounds__(kBlock) void radix_pass_kernel(const PassArgs a) {
     if ((int64_t)g >= n) continue;
     if (a.keys_out) a.keys_out[g] = k;
     a.vals_out[g] = s_val[i];
-    if (kWeighted) a.wout[g] = s_wglob[d] + (s_wt[i] - s_wt[s_loc[d]]);
+    if (kWeighted) {
+      const uint32_t o = s_wglob[d] + (s_wt[i] - s_wt[s_loc[d]]);
+      a.wout[g] = o;
+      if (a.owners) {
+        // the expansion blocks whose first entry is one of this key's
+        const uint32_t c = (i + 1 < ltotal ? s_wt[i + 1] : wt_total) - s_wt[i];
+        for (uint64_t b = ((uint64_t)o + kOwnerSpan - 1) / kOwnerSpan;
+             b * kOwnerSpan < (uint64_t)o + c && (int64_t)b < a.owners_n; ++b)
+          a.owners[b] = g;
+      }
+    }
   }
 }
 
 int hist_parts_words() { return kHistCopies * kHistStride; }
+
+int64_t owner_words(int64_t ecap) { return std::max<int64_t>(ecap, 1) / kOwnerSpan + 2; }
 
 // ------------------------------------------------------------ expansion --
 
@@ -582,8 +601,10 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
                                                         uint32_t* __restrict__ tiles_out,
                                                         uint32_t* __restrict__ items_out,
                                                         uint32_t* __restrict__ hparts, int hpass, int hbits,
-                                                        int64_t nitems, uint32_t ntiles) {
+                                                        int64_t nitems, uint32_t ntiles,
+                                                        const uint32_t* __restrict__ owners) {
   constexpr int kSpan = kExpandSpan;
+  static_assert(kSpan == kOwnerSpan, "the depth order records the owners of kOwnerSpan-entry blocks");
   const int64_t m = dyn_count(m_cap, dyn_m);
   const int64_t total = dyn_count(total_cap, dyn_total);
   const int64_t block0 = (int64_t)blockIdx.x * kSpan;
@@ -594,28 +615,14 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
   __shared__ uint32_t s_own[kSpan + 1];   // items[jlo + k]
   __shared__ uint8_t s_keep[kSpan];        // verdicts of the exact cull test, per wave
   __shared__ uint32_t s_h[kHistPasses][256];  // this block's digit counts of the kept tile ids
-  __shared__ int64_t s_jlo;
   if (hpass) {
 #pragma unroll
     for (int p = 0; p < kHistPasses; ++p) s_h[p][threadIdx.x] = 0u;
   }
-  if (threadIdx.x < 64) {
-    // owner of block0 (last j with offs[j] <= block0) in [lo, hi): each round
-    // probes 64 evenly spaced offsets; offs is increasing and offs[0] = 0
-    const int lane = threadIdx.x;
-    int64_t lo = 0, hi = m;
-    while (hi - lo > 1) {
-      const int64_t step = (hi - lo + 63) / 64;
-      const int64_t idx = lo + (int64_t)lane * step;
-      const uint64_t le = __builtin_amdgcn_ballot_w64(idx < hi && (int64_t)offs[idx] <= block0);
-      lo += (int64_t)(63 - __builtin_clzll(le)) * step;  // lane 0 always holds
-      hi = min(lo + step, hi);
-    }
-    if (lane == 0) s_jlo = lo;
-  }
-  __syncthreads();
-  // every owner of an entry of the block is one of jlo .. jlo + kSpan - 1
-  const int64_t jlo = s_jlo;
+  // owner of block0 (last j with offs[j] <= block0), recorded by the depth
+  // order's weighted pass (clamped, so that a stalled sort's leftovers stay in
+  // bounds); every owner of an entry of the block is one of jlo .. jlo + kSpan - 1
+  const int64_t jlo = min<int64_t>(owners[blockIdx.x], m - 1);
   const int64_t S = min<int64_t>(kSpan + 1, m - jlo);
   for (int k = threadIdx.x; k < kSpan + 1; k += kBlock) {
     s_offs[k] = k < S ? offs[jlo + k] : 0xffffffffu;
@@ -922,7 +929,8 @@ int64_t depth_zero_words(int64_t n0) { return kWorkHead + 256 * depth_blocks(std
 
 void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, int64_t n0, int64_t n1_cap,
                  const unsigned long long* dyn1, uint32_t* work, bool zeroed, uint32_t* ka, uint32_t* va,
-                 uint32_t* kb, uint32_t* vb, uint32_t* offs, unsigned long long* err, bool tickets) {
+                 uint32_t* kb, uint32_t* vb, uint32_t* offs, uint32_t* owners, int64_t owners_n,
+                 unsigned long long* err, bool tickets) {
   if (n0 <= 0 || n1_cap <= 0) return;
   const int per = os_per(n0);
   const int items = kBlock * per;
@@ -991,6 +999,8 @@ void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, i
   p.keys_out = nullptr;
   p.vals_out = vb;
   p.wout = offs;
+  p.owners = owners;
+  p.owners_n = owners_n;
   p.ticket = tickets ? tk + 3 : nullptr;
   hipLaunchKernelGGL(weighted, dim3((unsigned)nb1), dim3(kBlock), 0, st, p);
 }
@@ -1070,11 +1080,11 @@ void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, 
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
                    const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* twork, int hpass,
-                   int hbits, int64_t nitems, int64_t ntiles) {
+                   int hbits, int64_t nitems, int64_t ntiles, const uint32_t* owners) {
   if (total_cap <= 0) return;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(total_cap, kExpandSpan)), dim3(kBlock), 0, st, items, offs, m_cap,
                      dyn_m, total_cap, dyn_total, rects, views, n, tcones, recs, op, op.cone_cull, tiles_out,
-                     items_out, twork, hpass, hbits, std::max<int64_t>(nitems, 1), (uint32_t)ntiles);
+                     items_out, twork, hpass, hbits, std::max<int64_t>(nitems, 1), (uint32_t)ntiles, owners);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* tiles, int64_t total_cap, const unsigned long long* dyn,

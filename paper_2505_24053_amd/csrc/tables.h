@@ -50,7 +50,10 @@ int64_t depth_work_words(int64_t n0);
 int64_t depth_zero_words(int64_t n0);
 void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, int64_t n0, int64_t n1_cap,
                  const unsigned long long* dyn1, uint32_t* work, bool zeroed, uint32_t* ka, uint32_t* va,
-                 uint32_t* kb, uint32_t* vb, uint32_t* offs, unsigned long long* err, bool tickets = false);
+                 uint32_t* kb, uint32_t* vb, uint32_t* offs, uint32_t* owners, int64_t owners_n,
+                 unsigned long long* err, bool tickets = false);
+// words of the table of expansion-block owners for lists of up to ecap entries
+int64_t owner_words(int64_t ecap);
 // Work of the expansion and the tile sort for up to ecap entries:
 // tile_work_words(ecap) words whose first tile_zero_words(ecap) must be zero
 // before the expansion.
@@ -77,7 +80,7 @@ void launch_expand(hipStream_t st, const uint32_t* items, const uint32_t* offs, 
                    const unsigned long long* dyn_m, int64_t total_cap, const unsigned long long* dyn_total,
                    const uint2* rects, const ViewDev* views, int64_t n, const float4* tcones, const Record* recs,
                    const Opts& op, uint32_t* tiles_out, uint32_t* items_out, uint32_t* twork, int hpass,
-                   int hbits, int64_t nitems, int64_t ntiles);
+                   int hbits, int64_t nitems, int64_t ntiles, const uint32_t* owners);
 int hist_parts_words();
 // with list: also zeroes the 8 words of padding after the list; with err:
 // every range is empty when the sort's error word is set
