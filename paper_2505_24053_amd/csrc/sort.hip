@@ -311,17 +311,18 @@ __global__ __launch_bounds__(kBlock) void radix_pass_kernel(const PassArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // the grid is sized for the capacity: blocks past the live key count leave
   const int64_t n = dyn_count(a.n_cap, a.dyn);
+  if ((int64_t)blockIdx.x >= os_blocks(n, kItems)) return;
   int64_t blk = blockIdx.x;
   if (a.ticket) {
     // chunks in the order blocks start: the walk then only ever waits on
     // blocks that are running, also when kernels of other streams share the
-    // device (in-order dispatch holds within one kernel only)
+    // device (in-order dispatch holds within one kernel only).  Only the
+    // blocks of live chunks take one: they are as many as the chunks.
     __shared__ uint32_t s_ticket;
     if (tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
     __syncthreads();
     blk = s_ticket;
   }
-  if (blk >= os_blocks(n, kItems)) return;
 #pragma unroll
   for (int q = 0; q < 4; ++q) s_cnt[q][tid] = 0u;
   if (kWeighted) s_wsum[tid] = 0u;
