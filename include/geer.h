@@ -250,6 +250,14 @@ geer_status geer_check(geer_ctx* ctx, void* stream);
  * last launch (after waiting for it) as if a sort had stalled, so that the
  * reporting paths can be exercised without a device-side stall. */
 geer_status geer_debug_mark_stalled(geer_ctx* ctx, geer_plan* plan);
+/* Test hook: the number of polls after which the radix passes of later
+ * eager forwards on the context give up waiting (limit < 0: the default,
+ * about 2^22).  A small limit makes those passes give up for real, so that
+ * the handling of a stalled sort can be exercised with every kernel ending
+ * normally: such a forward's list is left unordered, its tile ranges are all
+ * empty (the frame renders background), and the stall is reported as
+ * described above.  Plans keep the limit they were captured with. */
+geer_status geer_debug_set_spin_limit(geer_ctx* ctx, int64_t limit);
 
 /* Frees the frame's device state (after any pending backward has completed). */
 void geer_frame_release(geer_frame* frame);

@@ -27,7 +27,7 @@ EXPORTS = ["geer_create", "geer_destroy", "geer_last_error", "geer_default_opts"
            "geer_frame_export", "geer_valid_mask", "geer_l1_loss", "geer_set_profiling", "geer_profile_read",
            "geer_plan_workspace_bytes", "geer_plan_create", "geer_train_plan_workspace_bytes",
            "geer_train_plan_create", "geer_plan_launch", "geer_plan_entries", "geer_plan_device_bytes", "geer_plan_destroy",
-           "geer_check", "geer_debug_mark_stalled", "geer_plan_get_stats",
+           "geer_check", "geer_debug_mark_stalled", "geer_debug_set_spin_limit", "geer_plan_get_stats",
            "geer_reproject", "geer_activate", "geer_adam_step", "geer_densify", "geer_render_static"]
 
 
@@ -140,6 +140,7 @@ def load():
         L.geer_plan_destroy.restype = None
         L.geer_check.argtypes = [V, V]
         L.geer_debug_mark_stalled.argtypes = [V, V]
+        L.geer_debug_set_spin_limit.argtypes = [V, C.c_int64]
         _lib = L
         return L
 

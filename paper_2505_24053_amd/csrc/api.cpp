@@ -68,6 +68,8 @@ struct geer_ctx {
   // gave up; reported (and cleared) by the next forward, geer_check or the
   // statistics of a frame.
   unsigned long long* dev_err = nullptr;
+  // look-back polls of the eager forwards' radix passes (a test hook lowers it)
+  uint32_t spin_limit = kDefaultSpinLimit;
   // Look-up of the allocation-free forward's fixed device array on this
   // device (geer_create).
   hipError_t static_init = hipErrorNotInitialized;
@@ -323,6 +325,7 @@ struct FwdBufs {
   // radix passes take their chunks by atomic tickets: set where the forward
   // may run beside look-back passes of other streams (render plans)
   bool tickets = false;
+  uint32_t spin_limit = kDefaultSpinLimit;
   // owners of the expansion's blocks, written by the depth order
   uint32_t* owners = nullptr;
   int64_t owners_n = 0;
@@ -365,7 +368,7 @@ void enqueue_depth_order(hipStream_t st, int64_t items, int64_t nvis_cap, const 
   if (nvis_cap <= 0) return;
   // items in depth order to b.vb, their entry offsets to b.cnt_sorted
   depth_order(st, b.keys, b.counts, items, nvis_cap, dV, b.hist, b.depth_work_zeroed, b.ka, b.va, b.kb, b.vb,
-              b.cnt_sorted, b.owners, b.owners_n, b.sort_err(), b.tickets);
+              b.cnt_sorted, b.owners, b.owners_n, b.sort_err(), b.tickets, b.spin_limit);
 }
 
 // Second half: per-tile cones, expansion, tile sort and ranges.  dV / dE:
@@ -399,7 +402,8 @@ void enqueue_tile_lists(hipStream_t st, const Opts& op, int64_t n, int64_t items
     const int hpass = hist_passes(ntiles);
     launch_expand(st, b.vb, b.cnt_sorted, nvis_cap, dV, ecap, dE, b.rects, b.views, n, b.tcones, b.recs, op, tin,
                   iin, b.twork, hpass, td.bits, items, ntiles, b.owners);
-    tile_sort(st, tin, iin, ecap, dE, kept, passes, td.bits, at, ai, tin, iin, b.twork, hpass, err, b.tickets);
+    tile_sort(st, tin, iin, ecap, dE, kept, passes, td.bits, at, ai, tin, iin, b.twork, hpass, err, b.tickets,
+              b.spin_limit);
     uint32_t* tfinal = (passes % 2 == 1) ? at : tin;
     launch_ranges(st, tfinal, ecap, kept, ntiles, b.ranges, b.list, err);
   } else {
@@ -682,6 +686,7 @@ geer_status geer_render(geer_ctx* c, const geer_scene* scene, int32_t n_views, c
   b.hist = (uint32_t*)hist.p; b.cnt_sorted = (uint32_t*)cnt_sorted.p;
   b.depth_work_zeroed = true;
   b.err = c->dev_err;
+  b.spin_limit = c->spin_limit;
   ProfSlot* ps = prof_slot(c);
   if (ps) ps->kind = 0;
   prof_mark(ps, 0, st);
@@ -1782,6 +1787,12 @@ geer_status geer_check(geer_ctx* c, void* stream) {
   if (!c) return GEER_ERR_INVALID_ARG;
   HIP_TRY(c, hipSetDevice(c->device));
   return take_stall(c, (hipStream_t)stream);
+}
+
+geer_status geer_debug_set_spin_limit(geer_ctx* c, int64_t limit) {
+  if (!c) return GEER_ERR_INVALID_ARG;
+  c->spin_limit = limit < 0 ? kDefaultSpinLimit : (uint32_t)std::min<int64_t>(limit, 0xffffffffll);
+  return GEER_OK;
 }
 
 geer_status geer_debug_mark_stalled(geer_ctx* c, geer_plan* P) {

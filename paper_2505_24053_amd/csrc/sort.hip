@@ -149,7 +149,6 @@ __host__ __device__ __forceinline__ int os_per(int64_t nmax) {
   return nmax < kOSSmallKeys ? kOSPerSmall : nmax < kOSBigKeys ? kOSPer : kOSPerBig;
 }
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
-constexpr uint32_t kSpinLimit = 1u << 22;
 // Work head: the digit counts of up to 4 passes, then the weighted counts of
 // the last pass's digits (padded).
 constexpr int kWorkHead = 5 * 256 + 64;
@@ -271,6 +270,7 @@ struct PassArgs {
   int64_t owners_n;
   unsigned long long* err;
   uint32_t* ticket;  // with it, a block's chunk is the ticket it takes off this counter (starts at 0)
+  uint32_t spin_limit;  // polls of the look-back before it gives up
 };
 
 template <bool kW>
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(kBlock) void radix_pass_kernel(const PassArgs a) {
     if (done) break;
     j -= q;
     if (q < kLookBack) {
-      if (++spins > kSpinLimit) {
+      if (++spins > a.spin_limit) {
         atomicOr(a.err, 1ull);
         break;
       }
@@ -931,7 +931,7 @@ int64_t depth_zero_words(int64_t n0) { return kWorkHead + 256 * depth_blocks(std
 void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, int64_t n0, int64_t n1_cap,
                  const unsigned long long* dyn1, uint32_t* work, bool zeroed, uint32_t* ka, uint32_t* va,
                  uint32_t* kb, uint32_t* vb, uint32_t* offs, uint32_t* owners, int64_t owners_n,
-                 unsigned long long* err, bool tickets) {
+                 unsigned long long* err, bool tickets, uint32_t spin_limit) {
   if (n0 <= 0 || n1_cap <= 0) return;
   const int per = os_per(n0);
   const int items = kBlock * per;
@@ -954,6 +954,7 @@ void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, i
                   : per == kOSPer  ? radix_pass_kernel<kOSPer, true>
                                    : radix_pass_kernel<kOSPerSmall, true>;
   PassArgs p{};
+  p.spin_limit = spin_limit;
   p.hcopies = 1;
   p.dmask = 255u;
   p.next_row_words = 256;
@@ -1021,7 +1022,7 @@ int64_t tile_work_words(int64_t ecap) { return tile_zero_words(ecap) + tile_rows
 void tile_sort(hipStream_t st, const uint32_t* tin, const uint32_t* iin, int64_t ecap,
                const unsigned long long* dE, unsigned long long* kept, int passes, int bits, uint32_t* at,
                uint32_t* ai, uint32_t* bt, uint32_t* bi, uint32_t* twork, int hpass, unsigned long long* err,
-               bool tickets) {
+               bool tickets, uint32_t spin_limit) {
   if (ecap <= 0 || passes <= 0) return;
   const int per = os_per(ecap);
   const unsigned nb = (unsigned)std::max<int64_t>(os_blocks(ecap, kBlock * per), 1);
@@ -1038,6 +1039,7 @@ void tile_sort(hipStream_t st, const uint32_t* tin, const uint32_t* iin, int64_t
               : per == kOSPer  ? radix_pass_kernel<kOSPer, false>
                                : radix_pass_kernel<kOSPerSmall, false>;
   PassArgs p{};
+  p.spin_limit = spin_limit;
   p.n_cap = ecap;
   p.dmask = (1u << bits) - 1u;
   p.hstride = kHistStride;

@@ -48,10 +48,13 @@ void scan_exclusive(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n
 // `zeroed` is false (then the call clears them).
 int64_t depth_work_words(int64_t n0);
 int64_t depth_zero_words(int64_t n0);
+// Polls of a radix pass's look-back before it gives up and sets the error
+// word (about a second of waiting).
+constexpr uint32_t kDefaultSpinLimit = 1u << 22;
 void depth_order(hipStream_t st, const uint32_t* keys, const uint32_t* counts, int64_t n0, int64_t n1_cap,
                  const unsigned long long* dyn1, uint32_t* work, bool zeroed, uint32_t* ka, uint32_t* va,
                  uint32_t* kb, uint32_t* vb, uint32_t* offs, uint32_t* owners, int64_t owners_n,
-                 unsigned long long* err, bool tickets = false);
+                 unsigned long long* err, bool tickets, uint32_t spin_limit);
 // words of the table of expansion-block owners for lists of up to ecap entries
 int64_t owner_words(int64_t ecap);
 // Work of the expansion and the tile sort for up to ecap entries:
@@ -67,7 +70,7 @@ int64_t tile_zero_words(int64_t ecap);
 void tile_sort(hipStream_t st, const uint32_t* tin, const uint32_t* iin, int64_t ecap,
                const unsigned long long* dE, unsigned long long* kept, int passes, int bits, uint32_t* at,
                uint32_t* ai, uint32_t* bt, uint32_t* bi, uint32_t* twork, int hpass, unsigned long long* err,
-               bool tickets = false);
+               bool tickets, uint32_t spin_limit);
 // Bytes of the expansion's per-tile cull table; its launch also sets
 // zero[0 .. nzero) = 0.
 size_t tile_cone_bytes(int64_t ntiles);

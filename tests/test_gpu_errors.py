@@ -1,10 +1,12 @@
 """Host-side reporting of a stalled association sort.
 
 Each radix pass waits on earlier blocks with a bounded spin; when it gives up
-the forward's outputs are invalid.  These tests do not make the device stall:
-they set the flag word from the host (geer_debug_mark_stalled) and check that
-every reporting path sees it -- the next eager forward, geer_check, a frame's
-statistics, a plan's status -- and that the server re-renders such a batch.
+the forward's outputs are invalid.  Most of these tests set the flag word from
+the host (geer_debug_mark_stalled) and check that every reporting path sees it
+-- the next eager forward, geer_check, a frame's statistics, a plan's status --
+and that the server re-renders such a batch.  One lowers the look-back limit
+from the host (geer_debug_set_spin_limit) so that the passes give up for real,
+with every kernel still ending, and checks that the damage is contained.
 """
 import numpy as np
 import pytest
@@ -100,3 +102,39 @@ def test_plan_status_and_server_rerender(R):
         torch.cuda.synchronize()
         assert torch.equal(r.rgb, alone) and torch.equal(r.depth, d) and torch.equal(r.trans, t)
     srv.close()
+
+
+def test_forced_stall_is_contained(R):
+    """A look-back limit of zero polls (set from the host) makes the radix
+    passes of an eager forward give up for real, while every kernel still
+    ends.  A pass that gives up leaves its output unordered: the frame must
+    then come back as background (every tile range emptied) and the stall be
+    reported; if no pass had to wait, the frame is the ordinary one.  The
+    next forward at the default limit renders as before."""
+    scene, cams = synth.workload_fisheye_forward(seed=4)
+    sc = R.scene_from_numpy(scene)
+    ref, ref_d, ref_t, _ = R.render(sc, cams)
+    torch.cuda.synchronize()
+    ctx = R.context(0)
+    L = _lib.load()
+    _lib.check(L.geer_debug_set_spin_limit(ctx, 0), ctx)
+    try:
+        rgb, depth, trans, _ = R.render(sc, cams)
+        torch.cuda.synchronize()
+    finally:
+        _lib.check(L.geer_debug_set_spin_limit(ctx, -1), ctx)
+    try:
+        R.check_errors()
+        stalled = False
+    except _lib.GeerError as e:
+        assert e.status == _lib.ERR_STALLED
+        stalled = True
+    if stalled:
+        assert not bool(rgb.any()) and not bool(depth.any()) and bool((trans == 1.0).all())
+    else:
+        assert torch.equal(rgb, ref) and torch.equal(depth, ref_d) and torch.equal(trans, ref_t)
+    print("forced stall:", stalled)
+    again, d2, t2, _ = R.render(sc, cams)
+    torch.cuda.synchronize()
+    R.check_errors()
+    assert torch.equal(again, ref) and torch.equal(d2, ref_d) and torch.equal(t2, ref_t)
