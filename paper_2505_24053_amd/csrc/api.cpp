@@ -1256,7 +1256,8 @@ geer_status geer_render_static(geer_ctx* c, const geer_scene* scene, int32_t n_v
 // forward and backward, the loss and the per-view statistics.
 struct TrainLayout {
   PlanLayout fwd;
-  size_t nlast = 0, tfinal = 0, dl = 0, acc = 0, partial = 0, loss_views = 0, stats = 0, mask = 0, total = 0;
+  size_t nlast = 0, tfinal = 0, dl = 0, acc = 0, partial = 0, loss_views = 0, stats = 0, mask = 0, list2 = 0,
+         ranges2 = 0, total = 0;
 };
 
 struct TrainShape {
@@ -1320,6 +1321,10 @@ TrainLayout train_layout(const TrainShape& S, int64_t n, int64_t ecap, int32_t n
   L.loss_views = put(4 * (size_t)n_views);
   L.stats = put(64 * (size_t)n_views);
   L.mask = put((size_t)S.npix_max);
+  // the second list and ranges: odd views' (the next view's association runs
+  // while the previous view's render and backward read the first)
+  L.list2 = put(4 * (size_t)(std::max<int64_t>(ecap, 1) + 8));
+  L.ranges2 = put(4 * (size_t)(S.ntiles_max + 1));
   L.total = off;
   return L;
 }
@@ -1452,8 +1457,22 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
 
   // Capture: per view, forward (keeping T_final and the last blended index),
   // weighted L1, backward accumulated into the gradients; then the loss sum.
-  hipStream_t cs = nullptr;
+  // The views' associations run on a second captured stream, one after the
+  // other, each as soon as its list buffers are free: view v's association
+  // overlaps view v - 1's render and backward (the two lists alternate).  So
+  // at most one look-back pass runs at a time, and no tickets are needed.
+  hipStream_t cs = nullptr, as = nullptr;
   PHIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  PHIP(hipStreamCreateWithFlags(&as, hipStreamNonBlocking));
+  std::vector<hipEvent_t> evs(2 * (size_t)n_views + 1, nullptr);
+  for (auto& ev : evs) PHIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  auto drop_streams = [&]() {
+    for (auto& ev : evs)
+      if (ev) (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(as);
+  };
+  uint32_t* const lists[2] = {b.list, (uint32_t*)(w + lay.list2)};
+  uint32_t* const rangess[2] = {b.ranges, (uint32_t*)(w + lay.ranges2)};
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     const double weight = 1.0 / (double)n_views;
@@ -1468,7 +1487,14 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
     Record* const recs0 = b.recs;
     uint2* const rects0 = b.rects;
     uint32_t *const keys0 = b.keys, *const counts0 = b.counts;
-    for (int v = 0; v < n_views; ++v) {
+    // the association stream forks off after the preprocess
+    auto ok = [&](hipError_t r) {
+      if (e == hipSuccess && r != hipSuccess) e = r;
+    };
+    ok(hipEventRecord(evs[0], cs));
+    ok(hipStreamWaitEvent(as, evs[0], 0));
+    for (int v = 0; v < n_views && e == hipSuccess; ++v) {
+      hipEvent_t assoc_done = evs[1 + 2 * v], bwd_done = evs[2 + 2 * v];
       const ViewTables& T = S.tabs[v];
       char* mv = (char*)P->meta + S.seg_off[v];
       b.views = (const ViewDev*)mv;
@@ -1482,13 +1508,20 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
       b.counts = counts0 + io;
       const int64_t po = S.pix_off[v];
       float* rgb_v = rgb + 3 * po;
-      enqueue_association(cs, P->op, n, n, n, entry_capacity, T.ntiles, true, b);
+      b.list = lists[v & 1];
+      b.ranges = rangess[v & 1];
+      // this list was last read by view v - 2's backward
+      if (v >= 2) ok(hipStreamWaitEvent(as, evs[2 + 2 * (v - 2)], 0));
+      enqueue_association(as, P->op, n, n, n, entry_capacity, T.ntiles, true, b);
+      ok(hipEventRecord(assoc_done, as));
+      ok(hipStreamWaitEvent(cs, assoc_done, 0));
       enqueue_render(cs, P->op, T.ntiles, 1, b, rgb_v, nullptr, nullptr);
       launch_l1(cs, T.npix, rgb_v, target + 3 * po, mask ? mask + po : ones, dl, loss_views + v, partial, scale,
                 weight);
       // ray-wise backward of this view into its own accumulator slice
       launch_render_backward(cs, P->op.lambda_mode == 1, T.ntiles, 1, b.views, b.dtab, P->op, b.heavy(), b.ranges,
                              b.list, b.rects, b.recs, b.nlast, b.tfinal, dl, acc + (size_t)v * (size_t)n * 16);
+      ok(hipEventRecord(bwd_done, cs));
     }
     // Gaussian-wise backward once, summing every view
     launch_preprocess_backward(cs, n, n_views, scene->sh_degree, scene->mean, scene->scale, scene->quat,
@@ -1497,10 +1530,11 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
                                g_quat, g_opacity, g_sh);
     launch_sum_f32(cs, n_views, loss_views, loss);
     hipError_t e2 = hipStreamEndCapture(cs, &P->graph);
-    e = e2 != hipSuccess ? e2 : hipGetLastError();
+    if (e == hipSuccess) e = e2 != hipSuccess ? e2 : hipGetLastError();
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
   (void)hipStreamDestroy(cs);
+  drop_streams();
   if (e != hipSuccess) return bail(fail(c, GEER_ERR_HIP, "graph capture: %s", hipGetErrorString(e)));
   *out = P;
   return GEER_OK;
