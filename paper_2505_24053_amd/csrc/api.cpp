@@ -348,7 +348,8 @@ struct FwdBufs {
 // Stage (a): zero the counters, then preprocess + PBF of every item.
 // With per_view_stats the counters of view v are the 8 words at b.stats + 8v.
 void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, const Opts& op, const float* lam,
-                        const FwdBufs& b, bool per_view_stats = false, const unsigned long long* err_in = nullptr) {
+                        const FwdBufs& b, bool per_view_stats = false, const unsigned long long* err_in = nullptr,
+                        bool defer_colour = false) {
   const int64_t nst = per_view_stats ? 16 * nviews : 16;
   if (b.depth_work_zeroed)
     launch_zero2_u32(st, (uint32_t*)b.stats, nst, b.hist, depth_zero_words(sc.n * nviews));
@@ -356,7 +357,7 @@ void enqueue_preprocess(hipStream_t st, const geer_scene& sc, int32_t nviews, co
     launch_fill_u32(st, (uint32_t*)b.stats, nst, 0u);
   launch_preprocess(st, sc.n, nviews, sc.sh_degree, sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh, b.views, op, lam,
                     b.edges, b.recs, b.rects, b.keys, b.counts, (unsigned long long*)b.stats, per_view_stats ? 8 : 0,
-                    err_in);
+                    err_in, defer_colour);
 }
 
 // Stage (b): association list; the tile-sorted list ends in b.list.
@@ -1482,17 +1483,20 @@ geer_status geer_train_plan_create(geer_ctx* c, const geer_scene* scene, int32_t
     b.views = all_views;
     b.edges = (const float*)P->meta;
     b.stats = P->stats;
-    enqueue_preprocess(cs, P->scene, n_views, P->op, lt.dev, b, true);
+    auto ok = [&](hipError_t r) {
+      if (e == hipSuccess && r != hipSuccess) e = r;
+    };
+    // the association stream forks off after the preprocess's geometry; the
+    // views' colour (the records' rgb, which no association kernel reads) and
+    // the accumulators' clear follow on this stream meanwhile
+    enqueue_preprocess(cs, P->scene, n_views, P->op, lt.dev, b, true, nullptr, true);
+    ok(hipEventRecord(evs[0], cs));
+    ok(hipStreamWaitEvent(as, evs[0], 0));
+    launch_colour(cs, n, n_views, scene->sh_degree, scene->mean, scene->sh, all_views, b.counts, b.recs);
     launch_zero_acc(cs, acc, b.counts, n * (int64_t)n_views);  // the visible items' accumulators
     Record* const recs0 = b.recs;
     uint2* const rects0 = b.rects;
     uint32_t *const keys0 = b.keys, *const counts0 = b.counts;
-    // the association stream forks off after the preprocess
-    auto ok = [&](hipError_t r) {
-      if (e == hipSuccess && r != hipSuccess) e = r;
-    };
-    ok(hipEventRecord(evs[0], cs));
-    ok(hipStreamWaitEvent(as, evs[0], 0));
     for (int v = 0; v < n_views && e == hipSuccess; ++v) {
       hipEvent_t assoc_done = evs[1 + 2 * v], bwd_done = evs[2 + 2 * v];
       const ViewTables& T = S.tabs[v];

@@ -244,11 +244,23 @@ __global__ __launch_bounds__(256) void colour_kernel(int64_t n, int32_t n_views,
   for (int c = 0; c < 3; ++c) r->rgb[c] = fmaxf(acc[c], 0.0f);
 }
 
+void launch_colour(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
+                   const float* sh, const ViewDev* views, const uint32_t* counts, Record* recs) {
+  if (n == 0 || n_views == 1 || sh_degree == 0) return;  // the association kernel gave the colour
+  const dim3 grid((unsigned)((n * n_views + 255) / 256));
+  switch (sh_degree) {
+    case 1: hipLaunchKernelGGL(colour_kernel<1>, grid, dim3(256), 0, st, n, n_views, mean, sh, views, counts, recs); break;
+    case 2: hipLaunchKernelGGL(colour_kernel<2>, grid, dim3(256), 0, st, n, n_views, mean, sh, views, counts, recs); break;
+    default: hipLaunchKernelGGL(colour_kernel<3>, grid, dim3(256), 0, st, n, n_views, mean, sh, views, counts, recs); break;
+  }
+}
+
 void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
                        const float* scale, const float* quat, const float* opacity, const float* sh,
                        const ViewDev* views, const Opts& op, const float* lam_tab, const float* edges,
                        Record* recs, uint2* rects, uint32_t* keys, uint32_t* counts,
-                       unsigned long long* totals, int totals_stride, const unsigned long long* err_in) {
+                       unsigned long long* totals, int totals_stride, const unsigned long long* err_in,
+                       bool defer_colour) {
   if (n == 0) return;
   const dim3 grid((unsigned)((n + 255) / 256));
   // one view: the colour in the same pass; a batch of views: a second kernel
@@ -262,8 +274,8 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
       hipLaunchKernelGGL((preprocess_kernel<D, false>), grid, dim3(256), 0, st, n, n_views, mean, scale, quat,   \
                          opacity, sh, views, op, lam_tab, edges, recs, rects, keys, counts, totals, totals_stride, \
                          err_in);                                                                                 \
-      hipLaunchKernelGGL(colour_kernel<D>, dim3((unsigned)((n * n_views + 255) / 256)), dim3(256), 0, st, n,     \
-                         n_views, mean, sh, views, counts, recs);                                                 \
+      if (!defer_colour)                                                                                          \
+        launch_colour(st, n, n_views, D, mean, sh, views, counts, recs);                                          \
     }                                                                                                             \
   } while (0)
   switch (sh_degree) {

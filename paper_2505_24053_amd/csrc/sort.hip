@@ -709,7 +709,10 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
         if (item[k] != cur) {
           cur = item[k];
           const float4* rp = reinterpret_cast<const float4*>(recs + cur);
-          const float4 p0 = rp[0], p1 = rp[1], p2 = rp[2], p3 = rp[3];
+          // the cull reads the record's geometry and qmax, never its rgb (which
+          // a batch's colour kernel may still be writing)
+          const float4 p0 = rp[0], p1 = rp[1], p2 = rp[2];
+          const float4 p3 = make_float4(0.0f, 0.0f, 0.0f, recs[cur].qmax);
           G[0] = p0.x; G[1] = p0.y; G[2] = p0.z; G[3] = p0.w;
           G[4] = p1.x; G[5] = p1.y; G[6] = p1.z; G[7] = p1.w; G[8] = p2.x;
           // the contribution threshold of the exact test, with its margins
@@ -765,7 +768,8 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(const uint32_t* __restri
           const float4* cp = tcones + kConeStride * (size_t)qt[q];
           const float4* rq = reinterpret_cast<const float4*>(recs + qi[q]);
           const float4 c0 = cp[0], c1 = cp[1], c2 = cp[2], c3 = cp[3];
-          const float4 p0 = rq[0], p1 = rq[1], p2 = rq[2], p3 = rq[3];
+          const float4 p0 = rq[0], p1 = rq[1], p2 = rq[2];
+          const float4 p3 = make_float4(0.0f, 0.0f, 0.0f, recs[qi[q]].qmax);
           QuadCone Q;
           Q.d[0][0] = c0.x; Q.d[0][1] = c0.y; Q.d[0][2] = c0.z;
           Q.d[1][0] = c1.x; Q.d[1][1] = c1.y; Q.d[1][2] = c1.z;

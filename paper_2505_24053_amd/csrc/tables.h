@@ -35,7 +35,12 @@ void launch_preprocess(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_de
                        const float* scale, const float* quat, const float* opacity, const float* sh,
                        const ViewDev* views, const Opts& op, const float* lam_tab, const float* edges,
                        Record* recs, uint2* rects, uint32_t* keys, uint32_t* counts, unsigned long long* totals,
-                       int totals_stride, const unsigned long long* err_in = nullptr);
+                       int totals_stride, const unsigned long long* err_in = nullptr, bool defer_colour = false);
+// The colour of a batch of views that launch_preprocess deferred (no-op when
+// it had none to defer: one view, or SH degree 0).  Touches only the records'
+// rgb, which the association never reads.
+void launch_colour(hipStream_t st, int64_t n, int32_t n_views, int32_t sh_degree, const float* mean,
+                   const float* sh, const ViewDev* views, const uint32_t* counts, Record* recs);
 
 // sort.hip
 int64_t scan_scratch_words(int64_t n);
