@@ -427,7 +427,12 @@ int32_t geer_profile_read(geer_ctx* ctx, geer_profile_record* out, int32_t max);
  * geer_plan_launch with new cameras (model, intrinsics, FoV, pose; the grid
  * sizes must match the plan's).  Results are identical to geer_render of the
  * same views.  A launch waits for the plan's previous launch; concurrent
- * batches use separate plans on separate streams.  The scene arrays and the
+ * batches use separate plans on separate streams.  A plan's radix passes
+ * take their chunks by atomic ticket as blocks start, so plans replayed on
+ * several streams at once never wait on each other's blocks.  (Eager forwards
+ * and training plans number chunks by block index: their sorts assume no
+ * other look-back pass runs beside them; if one does and a pass gives up, the
+ * stall is contained and reported as above.)  The scene arrays and the
  * outputs must stay allocated while the plan lives (the scene's values are
  * read by each launch).
  * When a batch's association list exceeds the capacity, that launch renders
@@ -450,7 +455,9 @@ geer_status geer_plan_create(geer_ctx* ctx, const geer_scene* scene, int32_t n_v
                              const geer_opts* opts, int64_t entry_capacity, void* workspace, int64_t workspace_bytes,
                              float* rgb, float* depth, float* trans, geer_plan** out);
 /* Training plans (batched training step).  One graph runs, for each view in
- * turn, the forward (keeping only each ray's final transmittance and last
+ * turn (the next view's association overlapping the current view's render
+ * and backward, one association at a time), the forward (keeping only each
+ * ray's final transmittance and last
  * blended entry), the L1 loss of that view against its target over the valid
  * rays (mask, or every ray when NULL), and the backward (App. C), so that the
  * gradient arrays receive the gradient of
